@@ -1,0 +1,248 @@
+/*
+ * graphreduce.h — C ABI of libgraphreduce, an MI355X (gfx950) implementation
+ * of the spectrum-preserving node aggregation of Zhao, Wang & Feng,
+ * "Nearly-Linear Time Spectral Graph Reduction for Scalable Graph
+ * Partitioning and Data Visualization" (arXiv 1812.08942), Phase A
+ * (Sec. 3.2), with the edge-weight derivatives that serve the constrained
+ * SGD edge scaling of Sec. 3.3.4 (Alg. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Graphs.  A weighted undirected graph G = (V, E, w) is passed as symmetric
+ *   CSR adjacency (the paper's A_G, Sec. 2.1): `row_ptr` int32[n+1] with
+ *   row_ptr[0] = 0, `col` int32[nnz], `w` float32[nnz].  Both directions of
+ *   every edge are stored with bit-identical weights; columns strictly
+ *   increase within a row; no self-loops; weights are positive and finite;
+ *   nnz < 2^31.  The Laplacian L = D - A (D = weighted degrees) is implicit.
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller
+ *   unless it is documented as host.  The library never allocates device
+ *   memory: scratch comes from the caller's workspace `ws` of `ws_bytes`
+ *   bytes (size it with gr_workspace_size).  Outputs have caller-allocated
+ *   upper-bound sizes.
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Work is
+ *   enqueued on it; an entry point returns only after the device-to-host
+ *   size reads it documents, otherwise asynchronously.
+ * Errors.  Every entry point returns GR_OK (0) or a negative GR_E* code and
+ *   sets a thread-local message readable with gr_last_error().  On error,
+ *   outputs are unspecified.  No C++ exception crosses the ABI.
+ * Determinism.  Identical inputs, parameters and seeds give bit-identical
+ *   outputs: no floating-point atomics are used anywhere.
+ * Vector storage.  Test-vector matrices X are node-major [n][K]: float32
+ *   (GR_F32, K a multiple of 4) or bfloat16 (GR_BF16, K a multiple of 8,
+ *   round-to-nearest-even on store); arithmetic is float32 in both cases.
+ *   1 <= K <= 64.
+ */
+#ifndef GRAPHREDUCE_H
+#define GRAPHREDUCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GR_OK 0
+#define GR_EINVAL (-1)   /* bad argument (null pointer, size, parameter)    */
+#define GR_ECSR (-2)     /* graph violates the CSR convention above         */
+#define GR_ECOLOUR (-3)  /* colouring invalid (edge inside one colour)      */
+#define GR_ENOMEM (-4)   /* workspace or output buffer too small            */
+#define GR_EHIP (-5)     /* a HIP runtime call failed (message has details) */
+#define GR_EUNSUP (-6)   /* unsupported K / dtype combination               */
+
+#define GR_F32 0
+#define GR_BF16 1
+
+/* gr_params.flags */
+#define GR_VALIDATE 1u     /* check the CSR convention on the device first     */
+#define GR_COLOUR_LDF 2u   /* greedy colouring in largest-degree-first order   */
+
+/* gr_result.warnings */
+#define GR_WNOPROGRESS 1u  /* a level could not shrink the graph; stopped early */
+
+typedef struct gr_graph {
+    int64_t n;              /* nodes                                */
+    int64_t nnz;            /* stored entries = 2 |E|               */
+    const int32_t* row_ptr; /* device int32[n+1]                    */
+    const int32_t* col;     /* device int32[nnz]                    */
+    const float* w;         /* device float32[nnz]                  */
+} gr_graph;
+
+typedef struct gr_params {
+    int32_t K;              /* test vectors (Sec. 3.2.1: K random vectors)   */
+    int32_t sweeps;         /* Gauss-Seidel sweeps ("a few", Sec. 3.2.1)     */
+    double ratio;           /* reduction ratio psi = |V| / |V_S| >= 1 (Alg. 2) */
+    uint64_t vec_seed;      /* seed of the test vectors; level l uses
+                               splitmix64 output l of this seed             */
+    uint64_t colour_seed;   /* seed of the greedy colouring priorities,
+                               per level as above                           */
+    int32_t vec_dtype;      /* GR_F32 or GR_BF16                              */
+    const int32_t* colours; /* optional device int32[n] colouring of level 0;
+                               NULL = greedy colouring                       */
+    int32_t n_colours;      /* number of colours in `colours`               */
+    int32_t max_levels;     /* 0 = no limit (stops at the target or when a
+                               level makes no progress)                     */
+    uint32_t flags;         /* GR_VALIDATE | GR_COLOUR_LDF                    */
+} gr_params;
+
+typedef struct gr_result {
+    int32_t* agg;           /* device int32[n]: final aggregate of each node   */
+    int32_t* c_row_ptr;     /* device int32[n+1] (upper bound): coarse CSR    */
+    int32_t* c_col;         /* device int32[nnz] (upper bound)                */
+    float* c_w;             /* device float32[nnz] (upper bound)              */
+    int64_t n_coarse;       /* out: coarse nodes                              */
+    int64_t nnz_coarse;     /* out: coarse stored entries                     */
+    int32_t levels;         /* out: levels run                                */
+    uint32_t warnings;      /* out: GR_W* bits                                */
+    int64_t level_n[32];    /* out: node count entering each level           */
+    int64_t level_nnz[32];  /* out: stored entries entering each level       */
+    int32_t level_colours[32]; /* out: colours used on each level            */
+} gr_result;
+
+/* Phases reported by the profiler (indices into gr_profile arrays). */
+#define GR_PHASE_COLOUR 0
+#define GR_PHASE_RELABEL 1
+#define GR_PHASE_INIT 2
+#define GR_PHASE_SMOOTH 3    /* one record per Gauss-Seidel colour step */
+#define GR_PHASE_AFFINITY 4
+#define GR_PHASE_AGGREGATE 5
+#define GR_PHASE_GALERKIN 6
+#define GR_PHASE_OTHER 7
+
+typedef struct gr_profile {
+    double phase_ms[8];       /* summed HIP-event time of the phase's records  */
+    double phase_max_ms[8];   /* longest single record                          */
+    double phase_bytes[8];    /* algorithmic (compulsory) bytes of the records  */
+    int64_t phase_launches[8];/* records (for SMOOTH: colour steps)            */
+    int64_t records;
+} gr_profile;
+
+/* Library version (major*10000 + minor*100 + patch) and status strings. */
+int gr_version(void);
+const char* gr_status_string(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* gr_last_error(void);
+
+/*
+ * gr_workspace_size — bytes of device workspace that every entry point of
+ * this header needs for a graph of n nodes and nnz stored entries, K test
+ * vectors of type `vec_dtype`.  Host outputs: *bytes.  GR_EINVAL for
+ * negative sizes, GR_EUNSUP for an unsupported K/dtype.
+ */
+int gr_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t vec_dtype, size_t* bytes);
+
+/*
+ * gr_reduce — the whole Phase A node reduction (Sec. 3.2) run level by level
+ * until at most T = ceil(n / ratio) nodes remain (the user-defined ratio psi
+ * of Alg. 2) or a level cannot shrink the graph.  Each level: colouring
+ * (prescribed on level 0 if given, else greedy), K centred random test
+ * vectors, `sweeps` multicolour Gauss-Seidel sweeps on L x = 0, per-edge
+ * affinity a_pq (Eq. of a_{p,q}), strongest-affinity aggregation, and the
+ * coarse Laplacian L_R = H_G^R L_G H_R^G with H_R^G = P (0/1 node-to-
+ * aggregate map) and H_G^R = P^T, formed by a sort and a segmented sum.
+ * Aggregate ids are numbered by each aggregate's smallest fine node.
+ * Outputs: res->agg (composed map), res->c_* (final coarse CSR, rows and
+ * columns ascending), the counts in *res.  Synchronises with the host a few
+ * times per level to read sizes.
+ */
+int gr_reduce(const gr_graph* g, const gr_params* p, gr_result* res, void* ws,
+              size_t ws_bytes, void* stream);
+
+/*
+ * gr_profile_start / gr_profile_stop — measurement aid.  After start, calls
+ * made on this thread record HIP events on their stream around each phase
+ * of gr_reduce (and each Gauss-Seidel colour step of gr_reduce/gr_smooth),
+ * with the compulsory bytes each one moves.  stop synchronises on the
+ * recorded events, fills *out (HOST) and turns recording off.
+ */
+int gr_profile_start(void);
+int gr_profile_stop(gr_profile* out);
+
+/* ---------------------------------------------------------------------
+ * Building blocks.  gr_reduce is made of these; they are exported for
+ * testing and for callers that want one step.
+ * ------------------------------------------------------------------- */
+
+/* gr_validate — checks the CSR convention on the device (GR_ECSR if it is
+ * violated).  Synchronises. */
+int gr_validate(const gr_graph* g, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_colour_greedy — greedy colouring (the multicolour order that makes
+ * Gauss-Seidel on L x = 0 reproducible, Sec. 3.2.1).  Nodes are ranked by
+ * priority (h(v), v), h(v) = splitmix64 output v of `seed` — or by
+ * (deg(v), h(v), v) when `largest_degree_first` — and each node takes the
+ * smallest colour missing among its higher-priority neighbours (computed by
+ * Jones-Plassmann rounds; the result equals the sequential greedy colouring
+ * in decreasing priority).  Output: colours int32[n] (device), *n_colours
+ * (HOST).  Synchronises.
+ */
+int gr_colour_greedy(const gr_graph* g, uint64_t seed, int32_t largest_degree_first,
+                     int32_t* colours, int32_t* n_colours, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * gr_init_vectors — K random test vectors orthogonal to the all-one vector
+ * (Sec. 3.2.1).  Entry (v,k): m = top 24 bits of splitmix64 output v*K + k of
+ * `seed`, x0 = (2m + 1 - 2^24) / 2^24 in (-1, 1); each column is then centred
+ * by its FP64 mean and stored as `dtype`.  X: device [n][K].
+ */
+int gr_init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, void* X,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_smooth — `sweeps` Gauss-Seidel relaxations of L x = 0 applied to all K
+ * columns of X in place (Sec. 3.2.1): within a sweep, colours 0..C-1 in
+ * order; each node v of the current colour with d_v > 0 becomes
+ * sum_j w_vj x_j / d_v.  `colours` is a valid colouring (device int32[n]);
+ * GR_ECOLOUR if a colour is out of range.  X: device [n][K] of `dtype`.
+ * Internally relabels the graph colour-major once per call.
+ */
+int gr_smooth(const gr_graph* g, const int32_t* colours, int32_t n_colours, int32_t K,
+              int32_t sweeps, int32_t dtype, void* X, void* ws, size_t ws_bytes,
+              void* stream);
+
+/*
+ * gr_affinity — spectral node affinity of every stored entry (Sec. 3.2.1,
+ * Eq. of a_{p,q}): a = (X_p . X_q)^2 / ((X_p . X_p)(X_q . X_q)), 0 when the
+ * denominator is 0, at most 1; and the algebraic distance d = 1 - a
+ * (Sec. 3.2.2), evaluated without cancellation as |u-w|^2 |u+w|^2 / 4 on the
+ * normalised rows u, w so that it stays accurate where a rounds to 1 in
+ * float32.  Both are bit-symmetric: value(p,q) == value(q,p).  Outputs:
+ * a float32[nnz] and dist float32[nnz] (either may be NULL), best int32[n]
+ * = the neighbour minimising (d, index) — the largest affinity, ties to the
+ * smaller index — or -1 without neighbours, dbest float32[n] its distance
+ * (may be NULL).
+ */
+int gr_affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, float* a,
+                float* dist, int32_t* best, float* dbest, void* stream);
+
+/*
+ * gr_aggregate — strongest-affinity aggregation (Sec. 3.2.2: nodes with large
+ * affinity, i.e. small algebraic distance, are aggregated).  From `dist`
+ * (float32[nnz], symmetric) the forest F = {v, best(v)}, best(v) = argmin
+ * (d, index), is formed; if n - |F| >= target all of F is accepted,
+ * otherwise its first n - target edges in the order (smaller distance,
+ * smaller min endpoint, smaller max endpoint).  Aggregates are connected
+ * components of the accepted edges numbered by smallest member.  Outputs:
+ * agg int32[n] (device), *n_coarse (HOST).  Synchronises.
+ */
+int gr_aggregate(const gr_graph* g, const float* dist, int64_t target, int32_t* agg,
+                 int64_t* n_coarse, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_galerkin — coarse Laplacian L_R = P^T L_G P (Sec. 3.2.2) for the
+ * aggregate map `agg` (int32[n], values in [0, n_coarse)).  Output CSR:
+ * c_row_ptr int32[n_coarse+1], c_col int32[<= nnz], c_w float32[<= nnz]
+ * with W[I,J] = sum of w_vj over stored (v,j), agg(v)=I != agg(j)=J, summed
+ * in float32 in a fixed order.  *nnz_coarse is HOST.  Synchronises.
+ */
+int gr_galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c_row_ptr,
+                int32_t* c_col, float* c_w, int64_t* nnz_coarse, void* ws, size_t ws_bytes,
+                void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAPHREDUCE_H */

@@ -239,9 +239,10 @@ int or_smooth(int64_t n, const int32_t *row_ptr, const int32_t *col,
  * (X_p, X_q) = sum_k x_p^(k) x_q^(k).  The norm bars around the scalar
  * inner product are read as an absolute value.  A zero denominator gives 0,
  * and the value is clamped to at most 1 (Cauchy-Schwarz makes it <= 1 in
- * exact arithmetic).  One value per stored entry. */
+ * exact arithmetic).  One value per stored entry.  The algebraic distance
+ * d = 1 - a (Sec. 3.2.2) is returned alongside when `d` is non-null. */
 void or_affinity(int64_t n, const int32_t *row_ptr, const int32_t *col,
-                 int32_t K, const double *X, double *a)
+                 int32_t K, const double *X, double *a, double *d)
 {
     for (int64_t v = 0; v < n; ++v) {
         const double *xv = X + v * K;
@@ -257,47 +258,48 @@ void or_affinity(int64_t n, const int32_t *row_ptr, const int32_t *col,
             double den = nv * nj;
             double r = den == 0.0 ? 0.0 : (c * c) / den;
             a[e] = r > 1.0 ? 1.0 : r;
+            if (d) d[e] = 1.0 - a[e];
         }
     }
 }
 
-/* Strongest neighbour: best(v) maximises (a_vj, -j) over the neighbours of
- * v, i.e. the largest affinity with ties to the smaller index; -1 for a node
- * without neighbours.  "Nodes with large affinity should be aggregated
- * together" (Sec. 3.2.2); the rule that picks the partner is this build's
- * reading. */
+/* Strongest neighbour: "nodes with large affinity or small algebraic
+ * distance should be aggregated together" (Sec. 3.2.2).  best(v) minimises
+ * (d_vj, j) over the neighbours of v, i.e. the smallest algebraic distance
+ * (largest affinity) with ties to the smaller index; -1 without neighbours.
+ * The rule that picks the partner is this build's reading. */
 void or_best(int64_t n, const int32_t *row_ptr, const int32_t *col,
-             const double *a, int32_t *best)
+             const double *d, int32_t *best)
 {
     for (int64_t v = 0; v < n; ++v) {
         int32_t b = -1;
-        double ba = -1.0;
+        double bd = 0.0;
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
-            if (a[e] > ba) { ba = a[e]; b = col[e]; } /* columns ascend: first max wins */
+            if (b < 0 || d[e] < bd) { bd = d[e]; b = col[e]; } /* columns ascend: first min wins */
         best[v] = b;
     }
 }
 
 /* ------------------------------------------------------ aggregation */
 /* Aggregation rule (reading of Sec. 3.2.2 with the reduction ratio of
- * Alg. 2):
+ * Alg. 2), on algebraic distances d = 1 - a:
  *  1. F = the edges {v, best(v)}; a mutual pair is one edge.  F is a forest:
  *     around a pointer cycle of length >= 3 the edge keys would strictly
- *     increase, which a total order forbids.
- *  2. Edges are ordered by the total order: larger affinity first, then the
- *     smaller min(p,q), then the smaller max(p,q).
+ *     decrease, which a total order forbids.
+ *  2. Edges are ordered by the total order: smaller distance (larger
+ *     affinity) first, then the smaller min(p,q), then the smaller max(p,q).
  *  3. If n - |F| >= target, every edge of F is accepted; otherwise only the
  *     first n - target edges in that order.  Each accepted forest edge
  *     joins two components, so exactly max(target, n - |F|) aggregates form.
  *  4. Aggregates are the connected components of the accepted edges,
  *     numbered 0, 1, ... in increasing order of their smallest member.
- * The affinity of an edge is the value stored at entry (v, best(v)). */
-typedef struct { double a; int32_t lo, hi; } or_fedge;
+ * The distance of an edge is the value stored at entry (v, best(v)). */
+typedef struct { double d; int32_t lo, hi; } or_fedge;
 
 static int fedge_cmp(const void *x, const void *y)
 {
     const or_fedge *p = (const or_fedge *)x, *q = (const or_fedge *)y;
-    if (p->a != q->a) return p->a > q->a ? -1 : 1;
+    if (p->d != q->d) return p->d < q->d ? -1 : 1;
     if (p->lo != q->lo) return p->lo < q->lo ? -1 : 1;
     if (p->hi != q->hi) return p->hi < q->hi ? -1 : 1;
     return 0;
@@ -313,11 +315,11 @@ static int32_t uf_find(int32_t *par, int32_t x)
 }
 
 int or_aggregate(int64_t n, const int32_t *row_ptr, const int32_t *col,
-                 const double *a, int64_t target, int32_t *best, int32_t *agg,
+                 const double *d, int64_t target, int32_t *best, int32_t *agg,
                  int64_t *n_coarse, int64_t *n_forest, int64_t *n_accepted)
 {
     if (target < 1) target = 1;
-    or_best(n, row_ptr, col, a, best);
+    or_best(n, row_ptr, col, d, best);
     or_fedge *F = (or_fedge *)malloc(sizeof(or_fedge) * (size_t)(n > 0 ? n : 1));
     int32_t *par = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t *minm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
@@ -327,10 +329,10 @@ int or_aggregate(int64_t n, const int32_t *row_ptr, const int32_t *col,
         int32_t b = best[v];
         if (b < 0) continue;
         if (best[b] == v && b < v) continue; /* mutual pair: keep once */
-        double av = -1.0;
+        double dv = 2.0;
         for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
-            if (col[e] == b) { av = a[e]; break; }
-        F[nf].a = av;
+            if (col[e] == b) { dv = d[e]; break; }
+        F[nf].d = dv;
         F[nf].lo = (int32_t)(v < b ? v : b);
         F[nf].hi = (int32_t)(v < b ? b : v);
         ++nf;

@@ -55,7 +55,8 @@ def lib():
         L.or_smooth.argtypes = [_i64, _i32p, _i32p, _f64p, _i32p, _i32, _i32,
                                 _i32, _f64p, _i32]
         L.or_affinity.restype = None
-        L.or_affinity.argtypes = [_i64, _i32p, _i32p, _i32, _f64p, _f64p]
+        L.or_affinity.argtypes = [_i64, _i32p, _i32p, _i32, _f64p, _f64p,
+                                  ctypes.c_void_p]
         L.or_best.restype = None
         L.or_best.argtypes = [_i64, _i32p, _i32p, _f64p, _i32p]
         L.or_aggregate.restype = ctypes.c_int
@@ -143,17 +144,25 @@ def smooth(n, row_ptr, col, w, colours, n_colours, X, sweeps, bf16=False):
     return X
 
 
-def affinity(n, row_ptr, col, X):
+def affinity(n, row_ptr, col, X, with_distance=False):
+    """Per-entry affinities a (and the algebraic distances d = 1 - a)."""
     X = _af64(X)
     a = np.empty(int(row_ptr[-1]), np.float64)
+    d = np.empty(int(row_ptr[-1]), np.float64) if with_distance else None
     lib().or_affinity(n, _ai32(row_ptr), _ai32(col), X.shape[1], X.reshape(-1),
-                      a)
-    return a
+                      a, d.ctypes.data if d is not None else None)
+    return (a, d) if with_distance else a
 
 
-def best(n, row_ptr, col, a):
+def distance(n, row_ptr, col, X):
+    """Algebraic distances d = 1 - a per stored entry (Sec. 3.2.2)."""
+    return affinity(n, row_ptr, col, X, with_distance=True)[1]
+
+
+def best(n, row_ptr, col, d):
+    """Strongest neighbour: argmin (d, j)."""
     b = np.empty(n, np.int32)
-    lib().or_best(n, _ai32(row_ptr), _ai32(col), _af64(a), b)
+    lib().or_best(n, _ai32(row_ptr), _ai32(col), _af64(d), b)
     return b
 
 
@@ -166,13 +175,13 @@ class AggResult:
     n_accepted: int
 
 
-def aggregate(n, row_ptr, col, a, target) -> AggResult:
-    """Aggregation of one level from per-entry affinities `a` (any float
-    array; promoted exactly to float64)."""
+def aggregate(n, row_ptr, col, d, target) -> AggResult:
+    """Aggregation of one level from per-entry algebraic distances `d`
+    (any float array; promoted exactly to float64)."""
     agg = np.empty(n, np.int32)
     b = np.empty(n, np.int32)
     nc, nf, na = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
-    _check(lib().or_aggregate(n, _ai32(row_ptr), _ai32(col), _af64(a),
+    _check(lib().or_aggregate(n, _ai32(row_ptr), _ai32(col), _af64(d),
                               int(target), b, agg, ctypes.byref(nc),
                               ctypes.byref(nf), ctypes.byref(na)),
            "aggregate")
@@ -270,8 +279,8 @@ def reduce(n, row_ptr, col, w, K, sweeps, ratio, vec_seed, colour_seed,
                                        largest_degree_first)
         X = init_vectors(cur_n, K, level_seed(vec_seed, ell))
         X = smooth(cur_n, rp, cl, ww, cols_, nc_, X, sweeps, bf16=bf16)
-        a = affinity(cur_n, rp, cl, X)
-        ag = aggregate(cur_n, rp, cl, a, T)
+        d = distance(cur_n, rp, cl, X)
+        ag = aggregate(cur_n, rp, cl, d, T)
         c_rp, c_col, c_w = galerkin(cur_n, rp, cl, ww, ag.agg, ag.n_coarse)
         levels.append(Level(cur_n, int(rp[-1]), nc_, ag.n_coarse,
                             ag.n_forest, ag.n_accepted))
@@ -319,7 +328,12 @@ def laplacian_eigs(n, row_ptr, col, w, count=10, dense_limit=20000):
     ncomp = n_components(n, row_ptr, col)
     want = ncomp + count
     if n <= dense_limit:
-        lam = np.linalg.eigvalsh(laplacian_dense(n, row_ptr, col, w))
+        import scipy.linalg as sl
+
+        L = laplacian_dense(n, row_ptr, col, w)
+        hi = min(n - 1, want - 1)
+        lam = sl.eigh(L, eigvals_only=True, subset_by_index=(0, hi),
+                      overwrite_a=True, check_finite=False)
     else:
         import scipy.sparse as sp
         import scipy.sparse.linalg as sla

@@ -1,0 +1,367 @@
+// extern "C" entry points of libgraphreduce and the multilevel driver of
+// Phase A (Sec. 3.2; the reduction ratio psi of Alg. 2).  Argument checks
+// happen here, on the host, before any kernel sees a pointer or a size.
+#include "gr_internal.hpp"
+
+#include <math.h>
+#include <string.h>
+
+namespace gr {
+const char* last_error();
+void clear_error();
+
+static int check_graph_args(const gr_graph* g) {
+    if (!g) return set_error(GR_EINVAL, "graph is NULL");
+    if (g->n < 0 || g->nnz < 0) return set_error(GR_EINVAL, "negative n or nnz");
+    if (g->n >= (int64_t(1) << 31) - 1 || g->nnz >= (int64_t(1) << 31) - 1)
+        return set_error(GR_EINVAL, "n and nnz must be below 2^31 - 1");
+    if (!g->row_ptr) return set_error(GR_EINVAL, "row_ptr is NULL");
+    if (g->nnz > 0 && (!g->col || !g->w)) return set_error(GR_EINVAL, "col or w is NULL");
+    return GR_OK;
+}
+
+static int check_vec_args(int32_t K, int32_t dtype) {
+    if (dtype != GR_F32 && dtype != GR_BF16) return set_error(GR_EUNSUP, "unknown dtype %d", dtype);
+    if (K < 1 || K > 64) return set_error(GR_EUNSUP, "K must lie in [1, 64]");
+    int bytes = K * (dtype == GR_BF16 ? 2 : 4);
+    if (bytes % 16) return set_error(GR_EUNSUP, "K=%d: rows must be a multiple of 16 bytes "
+                                                "(K %% 4 == 0 for float32, K %% 8 == 0 for bfloat16)", K);
+    return GR_OK;
+}
+
+static int check_aligned(const void* p, const char* what) {
+    if (((uintptr_t)p) & 15) return set_error(GR_EINVAL, "%s must be 16-byte aligned", what);
+    return GR_OK;
+}
+
+static size_t vec_bytes(int64_t n, int32_t K, int32_t dtype) {
+    return (size_t)n * (size_t)K * (dtype == GR_BF16 ? 2 : 4);
+}
+
+// Upper bound of the workspace every entry point may carve (see each
+// function's takes; 256-byte alignment slack included).
+static size_t plan_bytes(int64_t n, int64_t nnz, int32_t K, int32_t dtype) {
+    const size_t N = (size_t)n + 1, M = (size_t)nnz + 1;
+    auto sort_scratch = [](size_t m) { return 2 * 256 * 4 * (m / 2048 + 1) + m / 64 + 256 * 1024; };
+    size_t persistent = 4 * N                                  // colours
+                        + 4 * N * 3 + 8 * M                    // relabelled graph
+                        + vec_bytes(n, K, dtype) + 256         // X
+                        + 4 * N * 4                            // best, abest, agg (two)
+                        + 2 * (4 * N + 8 * M)                  // coarse ping-pong
+                        + (M / 32 + 1) * (24 + 4 * (size_t)(K + 4) + 4) + 12 * N;  // chunks
+    size_t relabel = 36 * N + 8 * 1024 + sort_scratch(N);
+    size_t colour = 8 * N + 1024;
+    size_t agg = 24 * N + 44 * N + sort_scratch(N);
+    size_t gal = 8 * M + 4 * N + 36 * M + sort_scratch(M);
+    size_t temp = relabel;
+    if (colour > temp) temp = colour;
+    if (agg > temp) temp = agg;
+    if (gal > temp) temp = gal;
+    size_t total = persistent + temp;
+    return total + total / 16 + (17u << 20);
+}
+
+static void copy_params(const gr_params* p, gr_params* q) { memcpy(q, p, sizeof(*q)); }
+
+__global__ void k_iota_i32(int32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+// agg_orig[perm[r]] = aggp[r]
+__global__ void k_unpermute(const int32_t* __restrict__ aggp, const int32_t* __restrict__ perm,
+                            int64_t n, int32_t* __restrict__ agg) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) agg[perm[r]] = aggp[r];
+}
+
+// total[v] = lvl[total[v]]
+__global__ void k_compose(const int32_t* __restrict__ lvl, int64_t n0, int32_t* __restrict__ total) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n0) total[v] = lvl[total[v]];
+}
+
+// strongest neighbour from per-entry algebraic distances: argmin (d, j),
+// one thread per row
+__global__ void k_best_from_d(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              const float* __restrict__ d, int64_t n, int32_t* __restrict__ best,
+                              float* __restrict__ dbest) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t b = -1;
+    float bd = 1.0f;
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+        if (b < 0 || d[e] < bd) { bd = d[e]; b = col[e]; }  // columns ascend: first min wins
+    best[v] = b;
+    dbest[v] = bd;
+}
+
+}  // namespace gr
+
+using namespace gr;
+
+extern "C" {
+
+int gr_version(void) { return 10000; }
+
+const char* gr_status_string(int s) {
+    switch (s) {
+        case GR_OK: return "ok";
+        case GR_EINVAL: return "invalid argument";
+        case GR_ECSR: return "malformed CSR graph";
+        case GR_ECOLOUR: return "invalid colouring";
+        case GR_ENOMEM: return "workspace or output too small";
+        case GR_EHIP: return "HIP runtime error";
+        case GR_EUNSUP: return "unsupported K / dtype";
+    }
+    return "unknown status";
+}
+
+const char* gr_last_error(void) { return last_error(); }
+
+int gr_profile_start(void) {
+    clear_error();
+    prof::start();
+    return GR_OK;
+}
+
+int gr_profile_stop(gr_profile* out) {
+    clear_error();
+    if (!out) return set_error(GR_EINVAL, "out is NULL");
+    return prof::stop(out);
+}
+
+int gr_workspace_size(int64_t n, int64_t nnz, int32_t K, int32_t vec_dtype, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || nnz < 0) return set_error(GR_EINVAL, "negative size");
+    GR_TRY(check_vec_args(K, vec_dtype));
+    *bytes = plan_bytes(n, nnz, K, vec_dtype);
+    return GR_OK;
+}
+
+int gr_validate(const gr_graph* g, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!ws) return set_error(GR_EINVAL, "workspace is NULL");
+    Arena A(ws, ws_bytes);
+    return validate_graph(g, A, S(stream));
+}
+
+int gr_colour_greedy(const gr_graph* g, uint64_t seed, int32_t ldf, int32_t* colours,
+                     int32_t* n_colours, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!colours || !n_colours || !ws) return set_error(GR_EINVAL, "NULL output or workspace");
+    Arena A(ws, ws_bytes);
+    return colour_jp(g, seed, ldf ? 1 : 0, colours, n_colours, A, S(stream));
+}
+
+int gr_init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, void* X, void* ws,
+                    size_t ws_bytes, void* stream) {
+    clear_error();
+    if (n < 0) return set_error(GR_EINVAL, "negative n");
+    GR_TRY(check_vec_args(K, dtype));
+    if (n > 0 && (!X || !ws)) return set_error(GR_EINVAL, "NULL X or workspace");
+    Arena A(ws, ws_bytes);
+    return init_vectors(n, K, seed, dtype, nullptr, X, A, S(stream));
+}
+
+int gr_smooth(const gr_graph* g, const int32_t* colours, int32_t n_colours, int32_t K,
+              int32_t sweeps, int32_t dtype, void* X, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    GR_TRY(check_vec_args(K, dtype));
+    if (sweeps < 0) return set_error(GR_EINVAL, "sweeps must be >= 0");
+    if (n_colours < 0 || (g->n > 0 && n_colours < 1)) return set_error(GR_EINVAL, "bad n_colours");
+    if (g->n == 0 || sweeps == 0) return GR_OK;
+    if (!colours || !X || !ws) return set_error(GR_EINVAL, "NULL colours, X or workspace");
+    GR_TRY(check_aligned(X, "X"));
+    hipStream_t st = S(stream);
+    Arena A(ws, ws_bytes);
+    GR_TRY(validate_colouring(g, colours, n_colours, A, st));
+    OrderedGraph og;
+    GR_TRY(order_by_colour(g, colours, n_colours, K, dtype, &og, A, st));
+    // permute X into colour-major rows, smooth, permute back
+    size_t vb = vec_bytes(g->n, K, dtype);
+    char* Xp = A.take<char>(vb);
+    if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (smooth)");
+    GR_TRY(permute_rows(X, Xp, og.perm, g->n, (size_t)K * (dtype == GR_BF16 ? 2 : 4), 0, st));
+    GR_TRY(smooth_ordered(&og, K, sweeps, dtype, Xp, st));
+    GR_TRY(permute_rows(Xp, X, og.perm, g->n, (size_t)K * (dtype == GR_BF16 ? 2 : 4), 1, st));
+    return GR_OK;
+}
+
+int gr_affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, float* a,
+                float* dist, int32_t* best, float* dbest, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    GR_TRY(check_vec_args(K, dtype));
+    if (g->n == 0) return GR_OK;
+    if (!X || !best) return set_error(GR_EINVAL, "NULL X or best");
+    GR_TRY(check_aligned(X, "X"));
+    return affinity(g, K, dtype, X, nullptr, a, dist, best, dbest, S(stream));
+}
+
+int gr_aggregate(const gr_graph* g, const float* dist, int64_t target, int32_t* agg,
+                 int64_t* n_coarse, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!n_coarse) return set_error(GR_EINVAL, "n_coarse is NULL");
+    *n_coarse = 0;
+    if (g->n == 0) return GR_OK;
+    if ((g->nnz > 0 && !dist) || !agg || !ws)
+        return set_error(GR_EINVAL, "NULL dist, agg or workspace");
+    hipStream_t st = S(stream);
+    Arena A(ws, ws_bytes);
+    int32_t* best = A.take<int32_t>(g->n);
+    float* dbest = A.take<float>(g->n);
+    if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (aggregate)");
+    hipLaunchKernelGGL(k_best_from_d, dim3(blocks_for(g->n, 256)), dim3(256), 0, st, g->row_ptr,
+                       g->col, dist, g->n, best, dbest);
+    GR_LAUNCHED("best from d");
+    return aggregate(g, best, dbest, nullptr, target, agg, n_coarse, nullptr, A, st);
+}
+
+int gr_galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c_row_ptr,
+                int32_t* c_col, float* c_w, int64_t* nnz_coarse, void* ws, size_t ws_bytes,
+                void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!nnz_coarse) return set_error(GR_EINVAL, "nnz_coarse is NULL");
+    if (n_coarse < 0 || n_coarse > g->n || (g->n > 0 && n_coarse < 1))
+        return set_error(GR_EINVAL, "n_coarse out of range");
+    if (!c_row_ptr || !ws || (g->n > 0 && !agg) || (g->nnz > 0 && (!c_col || !c_w)))
+        return set_error(GR_EINVAL, "NULL argument");
+    Arena A(ws, ws_bytes);
+    return galerkin(g, agg, n_coarse, c_row_ptr, c_col, c_w, nnz_coarse, A, S(stream));
+}
+
+int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws, size_t ws_bytes,
+              void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!p_in || !res) return set_error(GR_EINVAL, "NULL params or result");
+    gr_params p;
+    copy_params(p_in, &p);
+    GR_TRY(check_vec_args(p.K, p.vec_dtype));
+    if (p.sweeps < 0) return set_error(GR_EINVAL, "sweeps must be >= 0");
+    if (!(p.ratio >= 1.0) || !isfinite(p.ratio)) return set_error(GR_EINVAL, "ratio must be >= 1");
+    if (p.max_levels < 0) return set_error(GR_EINVAL, "max_levels must be >= 0");
+    if (p.colours && p.n_colours < 1) return set_error(GR_EINVAL, "n_colours must be >= 1");
+    if (!res->agg || !res->c_row_ptr || (g->nnz > 0 && (!res->c_col || !res->c_w)) || !ws)
+        return set_error(GR_EINVAL, "NULL output or workspace");
+    res->n_coarse = 0;
+    res->nnz_coarse = 0;
+    res->levels = 0;
+    res->warnings = 0;
+    hipStream_t st = S(stream);
+    Arena A(ws, ws_bytes);
+    const int64_t n0 = g->n;
+    if (p.flags & GR_VALIDATE) GR_TRY(validate_graph(g, A, st));
+    A.used = 0;
+    const int64_t target = (int64_t)ceil((double)n0 / p.ratio) < 1 ? 1
+                                                                      : (int64_t)ceil((double)n0 / p.ratio);
+    const int ldf = (p.flags & GR_COLOUR_LDF) ? 1 : 0;
+    // persistent buffers sized for level 0
+    int32_t* colours = A.take<int32_t>(n0 + 1);
+    void* X = A.take<char>(vec_bytes(n0, p.K, p.vec_dtype) + 256);
+    int32_t* best = A.take<int32_t>(n0 + 1);
+    float* dbest = A.take<float>(n0 + 1);
+    int32_t* aggp = A.take<int32_t>(n0 + 1);
+    int32_t* aggl = A.take<int32_t>(n0 + 1);
+    int32_t* gbuf_rp[2] = {A.take<int32_t>(n0 + 1), A.take<int32_t>(n0 + 1)};
+    int32_t* gbuf_col[2] = {A.take<int32_t>(g->nnz + 1), A.take<int32_t>(g->nnz + 1)};
+    float* gbuf_w[2] = {A.take<float>(g->nnz + 1), A.take<float>(g->nnz + 1)};
+    if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (%zu bytes given)", ws_bytes);
+    if (n0 > 0) {
+        hipLaunchKernelGGL(k_iota_i32, dim3(blocks_for(n0, 256)), dim3(256), 0, st, res->agg, n0);
+        GR_LAUNCHED("iota");
+    }
+    gr_graph cur = *g;
+    int which = 0;
+    int level = 0;
+    const size_t level_mark = A.used;
+    while (cur.n > target) {
+        if (p.max_levels > 0 && level >= p.max_levels) break;
+        A.used = level_mark;
+        const uint64_t vseed = splitmix64(p.vec_seed, (uint64_t)level);
+        const uint64_t cseed = splitmix64(p.colour_seed, (uint64_t)level);
+        int32_t nc = 0;
+        const int32_t* col_use = colours;
+        const bool pr = prof::on();
+        const double xs = p.vec_dtype == GR_BF16 ? 2.0 : 4.0;
+        if (pr) prof::begin(st);
+        if (level == 0 && p.colours) {
+            GR_TRY(validate_colouring(&cur, p.colours, p.n_colours, A, st));
+            col_use = p.colours;
+            nc = p.n_colours;
+        } else {
+            GR_TRY(colour_jp(&cur, cseed, ldf, colours, &nc, A, st));
+        }
+        if (pr) prof::end(st, prof::COLOUR, 0.0, 1);
+        if (level < 32) {
+            res->level_n[level] = cur.n;
+            res->level_nnz[level] = cur.nnz;
+            res->level_colours[level] = nc;
+        }
+        OrderedGraph og;
+        if (pr) prof::begin(st);
+        GR_TRY(order_by_colour(&cur, col_use, nc, p.K, p.vec_dtype, &og, A, st));
+        if (pr) prof::end(st, prof::RELABEL, 0.0, 1);
+        if (pr) prof::begin(st);
+        GR_TRY(init_vectors(cur.n, p.K, vseed, p.vec_dtype, og.perm, X, A, st));
+        if (pr) prof::end(st, prof::INIT, (double)cur.n * p.K * xs + 4.0 * cur.n, 1);
+        GR_TRY(smooth_ordered(&og, p.K, p.sweeps, p.vec_dtype, X, st));
+        if (pr) prof::begin(st);
+        GR_TRY(affinity(&og.g, p.K, p.vec_dtype, X, og.perm, nullptr, nullptr, best, dbest, st));
+        // compulsory bytes: CSR columns, each vector row once, ids, best + abest
+        if (pr)
+            prof::end(st, prof::AFFINITY,
+                      4.0 * (cur.n + 1) + 4.0 * cur.nnz + (double)cur.n * p.K * xs + 12.0 * cur.n,
+                      1);
+        int64_t ncoarse = 0, nforest = 0;
+        if (pr) prof::begin(st);
+        GR_TRY(aggregate(&og.g, best, dbest, og.perm, target, aggp, &ncoarse, &nforest, A, st));
+        hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(cur.n, 256)), dim3(256), 0, st, aggp,
+                           og.perm, cur.n, aggl);
+        GR_LAUNCHED("unpermute");
+        if (pr) prof::end(st, prof::AGGREGATE, 0.0, 1);
+        gr_graph next;
+        next.n = ncoarse;
+        next.row_ptr = gbuf_rp[which];
+        next.col = gbuf_col[which];
+        next.w = gbuf_w[which];
+        int64_t nnzc = 0;
+        if (pr) prof::begin(st);
+        GR_TRY(galerkin(&og.g, aggp, ncoarse, gbuf_rp[which], gbuf_col[which], gbuf_w[which], &nnzc,
+                        A, st));
+        if (pr) prof::end(st, prof::GALERKIN, 0.0, 1);
+        next.nnz = nnzc;
+        hipLaunchKernelGGL(k_compose, dim3(blocks_for(n0, 256)), dim3(256), 0, st, aggl, n0,
+                           res->agg);
+        GR_LAUNCHED("compose");
+        ++level;
+        bool stuck = ncoarse == cur.n;
+        cur = next;
+        which ^= 1;
+        if (stuck) {
+            res->warnings |= GR_WNOPROGRESS;
+            break;
+        }
+    }
+    // final coarse graph into the caller's buffers
+    GR_HIP(hipMemcpyAsync(res->c_row_ptr, cur.row_ptr, sizeof(int32_t) * (cur.n + 1),
+                          hipMemcpyDeviceToDevice, st));
+    if (cur.nnz > 0) {
+        GR_HIP(hipMemcpyAsync(res->c_col, cur.col, sizeof(int32_t) * cur.nnz, hipMemcpyDeviceToDevice,
+                              st));
+        GR_HIP(hipMemcpyAsync(res->c_w, cur.w, sizeof(float) * cur.nnz, hipMemcpyDeviceToDevice, st));
+    }
+    res->n_coarse = cur.n;
+    res->nnz_coarse = cur.nnz;
+    res->levels = level;
+    return GR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Internal declarations shared by the HIP sources of libgraphreduce.
+// gfx950 (CDNA4) only: wave64, 64 KiB+ LDS per workgroup, IEEE fp32 division.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <vector>
+
+#include "graphreduce.h"
+
+namespace gr {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ errors
+int set_error(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+
+#define GR_TRY(expr)                 \
+    do {                             \
+        int _rc = (expr);            \
+        if (_rc != GR_OK) return _rc; \
+    } while (0)
+
+#define GR_HIP(expr) GR_TRY(::gr::check_hip((expr), #expr))
+#define GR_LAUNCHED(what) GR_TRY(::gr::check_hip(hipGetLastError(), what))
+
+// ------------------------------------------------------------- profiling
+// Optional HIP-event timing of phases and kernels on the caller's stream
+// (enabled by gr_profile_start on the calling thread; off by default).
+namespace prof {
+enum Phase { COLOUR = 0, RELABEL, INIT, SMOOTH, AFFINITY, AGGREGATE, GALERKIN, OTHER, NPHASE };
+bool on();
+void begin(hipStream_t st);
+void end(hipStream_t st, int phase, double bytes, int64_t launches);
+void start();
+int stop(gr_profile* out);
+}  // namespace prof
+
+// ------------------------------------------------------------- workspace
+// Bump allocator over a caller-provided device buffer.  Every carve is
+// 256-byte aligned.  `base == nullptr` runs in sizing mode: nothing is
+// dereferenced, only `used` grows, so the same code computes workspace sizes.
+struct Arena {
+    char* base;
+    size_t cap;
+    size_t used;
+    bool overflow;
+    Arena(void* b, size_t c) : base((char*)b), cap(c), used(0), overflow(false) {}
+    template <class T>
+    T* take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        size_t bytes = count * sizeof(T);
+        used = off + ((bytes + 255) & ~size_t(255));
+        if (used > cap) overflow = true;
+        if (!base || overflow) return nullptr;
+        return reinterpret_cast<T*>(base + off);
+    }
+    bool sizing() const { return base == nullptr; }
+};
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline unsigned blocks_for(int64_t n, int per_block) {
+    int64_t b = (n + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ----------------------------------------------------------- device math
+// SplitMix64 (Steele, Lea & Flood 2014): output i of the generator seeded
+// with s is the variant-13 finaliser applied to s + (i + 1) * 0x9E3779B97F4A7C15.
+__host__ __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// bfloat16 storage: round-to-nearest-even from binary32, NaN kept quiet.
+__device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------- primitives
+// Exclusive prefix sum of int32 values (deterministic).  Writes n outputs
+// and, when `total` is non-null, the grand total to device memory.
+int scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total,
+                       Arena& ws, hipStream_t st);
+// Same for int64.
+int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total,
+                       Arena& ws, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+// Results land in keys_out/vals_out; the inputs are used as scratch.
+int radix_sort_pairs(uint64_t* keys_in, uint32_t* vals_in, uint64_t* keys_out,
+                     uint32_t* vals_out, int64_t n, int bits, Arena& ws, hipStream_t st);
+
+// Deterministic FP64 sum of n values into *out (device).
+int sum_f64(const double* in, int64_t n, double* out, Arena& ws, hipStream_t st);
+
+int fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+
+inline int bits_for(int64_t n) {  // bits needed to hold values in [0, n)
+    int b = 0;
+    while (b < 63 && (int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+// --------------------------------------------------------------- phase A
+int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st);
+int colour_jp(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
+              int32_t* n_colours_host, Arena& ws, hipStream_t st);
+int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colours,
+                       Arena& ws, hipStream_t st);
+
+// One chunk of a long row: entries [e0, e1) of `row`; the row's chunks are
+// first .. first+count-1 (self is this chunk's own index).
+struct ChunkDesc {
+    int32_t row, e0, e1, first, count, self;
+};
+
+// Colour-major relabel: new row r holds old node perm[r]; rows of colour c
+// are [class_ptr[c], class_ptr[c+1]), with the long rows (degree above the
+// split threshold) first: [class_ptr[c], long_end[c]).  Long rows are cut
+// into chunks (chunk_ptr[c] .. chunk_ptr[c+1]) for the smoothing kernel.
+// Host copies of the boundaries are kept for launch planning.
+struct OrderedGraph {
+    gr_graph g;          // relabelled CSR (device pointers into the arena)
+    int32_t* perm;       // [n] new -> old
+    int32_t* iperm;      // [n] old -> new
+    int32_t n_colours;
+    std::vector<int64_t> class_ptr_h;   // host [C+1]
+    std::vector<int64_t> long_end_h;    // host [C]
+    std::vector<int64_t> class_nnz_h;   // host [C]: stored entries per colour
+    std::vector<int64_t> normal_nnz_h;  // host [C]: entries of the normal rows
+    std::vector<int64_t> chunk_ptr_h;   // host [C+1]
+    int64_t n_chunks;
+    int32_t chunk_entries;
+    ChunkDesc* chunks;   // device [n_chunks]
+    float* partial;      // device [n_chunks][K+4]
+    int32_t* counter;    // device [n_chunks] (tickets, indexed by a row's first chunk)
+    double mean_deg;
+};
+int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours, int32_t K,
+                    int32_t dtype, OrderedGraph* out, Arena& ws, hipStream_t st);
+
+// dst[r] = src[perm[r]] (inverse = 0) or dst[perm[r]] = src[r] (inverse = 1),
+// rows of row_bytes (a multiple of 16) bytes.
+int permute_rows(const void* src, void* dst, const int32_t* perm, int64_t n, size_t row_bytes,
+                 int inverse, hipStream_t st);
+
+int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32_t* ids,
+                 void* X, Arena& ws, hipStream_t st);
+int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dtype,
+                   void* X, hipStream_t st);
+// a (affinity) and dist (algebraic distance d = 1 - a) per entry are
+// optional; best = argmin (d, id) per row, dbest its distance.
+int affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, const int32_t* ids,
+             float* a, float* dist, int32_t* best, float* dbest, hipStream_t st);
+
+// ---------------------------------------------------- aggregation / RAP
+int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const int32_t* ids,
+              int64_t target, int32_t* agg, int64_t* n_coarse, int64_t* n_forest,
+              Arena& ws, hipStream_t st);
+int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c_row_ptr,
+             int32_t* c_col, float* c_w, int64_t* nnz_coarse, Arena& ws, hipStream_t st);
+
+int degree_stats(const gr_graph* g, int32_t* max_deg, Arena& ws, hipStream_t st);
+
+}  // namespace gr

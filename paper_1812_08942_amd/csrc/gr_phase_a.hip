@@ -1,0 +1,1005 @@
+// Phase A of the spectral reduction (Sec. 3.2): graph checks, greedy
+// colouring, colour-major relabel, random test vectors, multicolour
+// Gauss-Seidel smoothing and the per-edge spectral affinity.
+//
+// Layout.  Test vectors are node-major rows of K values; a row is split into
+// Q 16-byte chunks (4 float32 or 8 bfloat16 values).  A row-group of L = Q*P
+// lanes handles one CSR row: lane (p, q) walks neighbours p, p+P, ... and
+// accumulates chunk q, and the P partial sums are combined by a fixed xor
+// shuffle tree.  Every reduction order is therefore a function of (Q, P)
+// only, which keeps results bit-reproducible.
+#include "gr_internal.hpp"
+
+namespace gr {
+
+constexpr int kLongRow = 128;     // rows above this degree are split into chunks
+constexpr int kThreads = 256;
+
+// ------------------------------------------------------------- validation
+__global__ void k_check_rowptr(const int32_t* __restrict__ rp, int64_t n, int64_t nnz,
+                               int32_t* __restrict__ bad) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > n) return;
+    int32_t x = rp[v];
+    bool ok = x >= 0 && x <= nnz;
+    if (v == 0) ok = ok && x == 0;
+    if (v == n) ok = ok && x == nnz;
+    if (v < n) ok = ok && rp[v + 1] >= x;
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ void k_check_entries(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const float* __restrict__ w, int64_t n, int32_t* __restrict__ bad) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t e0 = rp[v], e1 = rp[v + 1];
+    int flags = 0;
+    for (int32_t e = e0; e < e1; ++e) {
+        int32_t j = col[e];
+        float wv = w[e];
+        if (j < 0 || j >= n || j == v) { flags |= 2; break; }
+        if (e > e0 && col[e - 1] >= j) { flags |= 4; break; }
+        if (!(wv > 0.0f) || !isfinite(wv)) { flags |= 8; break; }
+        // partner entry (j, v) with bit-identical weight
+        int32_t lo = rp[j], hi = rp[j + 1] - 1, f = -1;
+        while (lo <= hi) {
+            int32_t mid = lo + ((hi - lo) >> 1);
+            int32_t c = col[mid];
+            if (c == (int32_t)v) { f = mid; break; }
+            if (c < (int32_t)v) lo = mid + 1; else hi = mid - 1;
+        }
+        if (f < 0 || __float_as_uint(w[f]) != __float_as_uint(wv)) { flags |= 16; break; }
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
+    int32_t* bad = ws.take<int32_t>(1);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (validate)");
+    GR_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(g->n + 1, kThreads)), dim3(kThreads), 0, st,
+                       g->row_ptr, g->n, g->nnz, bad);
+    GR_LAUNCHED("check row_ptr");
+    int32_t hb = 0;
+    GR_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    if (hb) return set_error(GR_ECSR, "row_ptr is not a monotone offset array with row_ptr[0]=0, row_ptr[n]=nnz");
+    if (g->n > 0) {
+        hipLaunchKernelGGL(k_check_entries, dim3(blocks_for(g->n, kThreads)), dim3(kThreads), 0, st,
+                           g->row_ptr, g->col, g->w, g->n, bad);
+        GR_LAUNCHED("check entries");
+        GR_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+    }
+    if (hb & 2) return set_error(GR_ECSR, "column index out of range or self-loop");
+    if (hb & 4) return set_error(GR_ECSR, "columns not strictly increasing within a row");
+    if (hb & 8) return set_error(GR_ECSR, "weight not positive and finite");
+    if (hb & 16) return set_error(GR_ECSR, "graph not symmetric (missing or unequal reverse entry)");
+    return GR_OK;
+}
+
+// -------------------------------------------------------------- colouring
+// Priority of node v: (deg(v) if largest-degree-first, h(v), v) compared
+// lexicographically, h(v) = splitmix64 output v of the colour seed.
+struct Prio {
+    uint32_t deg;
+    uint64_t h;
+    int32_t v;
+};
+__device__ inline Prio prio_of(const int32_t* rp, int32_t v, uint64_t seed, int ldf) {
+    Prio p;
+    p.deg = ldf ? (uint32_t)(rp[v + 1] - rp[v]) : 0u;
+    p.h = splitmix64(seed, (uint64_t)v);
+    p.v = v;
+    return p;
+}
+__device__ inline bool higher(const Prio& a, const Prio& b) {
+    if (a.deg != b.deg) return a.deg > b.deg;
+    if (a.h != b.h) return a.h > b.h;
+    return a.v > b.v;
+}
+
+// One Jones-Plassmann round over the worklist in[0 .. *nin): a node all of
+// whose uncoloured neighbours have lower priority takes the smallest colour
+// missing among its (necessarily higher-priority) coloured neighbours; the
+// others go to `out`.  Each colour word is written once (from -1 to its final
+// value), so a plain load returns either -1 or the final colour; a stale -1
+// only postpones a node to a later round.  cursor[v] remembers where the
+// readiness scan of v stopped: entries before it are coloured or of lower
+// priority for good, so every row is scanned O(1) times in total.
+// Counters rotate over three slots: this round reads cnt[k % 3], appends to
+// cnt[(k+1) % 3] and clears cnt[(k+2) % 3] (read by the previous round).
+__global__ void k_jp_round(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           uint64_t seed, int ldf, int32_t* colours, int32_t* __restrict__ cursor,
+                           const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                           int32_t* __restrict__ cnt, int k) {
+    const int32_t nin = cnt[k % 3];
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) cnt[(k + 2) % 3] = 0;
+    if (t >= nin) return;
+    const int32_t v = in[t];
+    const Prio pv = prio_of(rp, v, seed, ldf);
+    const int32_t e1 = rp[v + 1];
+    for (int32_t e = cursor[v]; e < e1; ++e) {
+        int32_t j = col[e];
+        if (colours[j] < 0 && higher(prio_of(rp, j, seed, ldf), pv)) {
+            cursor[v] = e;
+            out[atomicAdd(&cnt[(k + 1) % 3], 1)] = v;
+            return;
+        }
+    }
+    // ready: smallest colour missing among the neighbours, by windows of 256.
+    // A higher-priority neighbour read as uncoloured here (never expected,
+    // since it was read as coloured above) defers v instead of guessing.
+    const int32_t e0 = rp[v];
+    int32_t c = -1;
+    for (int32_t base = 0; c < 0; base += 256) {
+        uint64_t used[4] = {0, 0, 0, 0};
+        for (int32_t e = e0; e < e1; ++e) {
+            int32_t j = col[e];
+            int32_t cj = colours[j];
+            if (cj < 0) {
+                if (higher(prio_of(rp, j, seed, ldf), pv)) {
+                    cursor[v] = e0;
+                    out[atomicAdd(&cnt[(k + 1) % 3], 1)] = v;
+                    return;
+                }
+            } else if (cj >= base && cj < base + 256) {
+                used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
+            }
+        }
+        for (int w = 0; w < 4 && c < 0; ++w)
+            if (~used[w]) c = base + w * 64 + __ffsll((unsigned long long)~used[w]) - 1;
+    }
+    colours[v] = c;
+}
+
+__global__ void k_jp_init(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ colours,
+                          int32_t* __restrict__ cursor, int32_t* __restrict__ work,
+                          int32_t* __restrict__ cnt) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) {
+        cnt[0] = (int32_t)n;
+        cnt[1] = 0;
+        cnt[2] = 0;
+    }
+    if (v >= n) return;
+    colours[v] = -1;
+    cursor[v] = rp[v];
+    work[v] = (int32_t)v;
+}
+
+__global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t m = -1;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) m = max(m, x[i]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
+}
+
+int colour_jp(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours, int32_t* n_colours_host,
+              Arena& ws, hipStream_t st) {
+    const int64_t n = g->n;
+    *n_colours_host = 0;
+    if (n == 0) return GR_OK;
+    size_t mark = ws.used;
+    int32_t* wk[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
+    int32_t* cursor = ws.take<int32_t>(n);
+    int32_t* cnt = ws.take<int32_t>(4);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
+    hipLaunchKernelGGL(k_jp_init, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, g->row_ptr,
+                       n, colours, cursor, wk[0], cnt);
+    GR_LAUNCHED("jp init");
+    // rounds in batches; the grid of a batch is sized by the last count read
+    // back (worklists only shrink), the kernels read the exact count
+    const int kBatch = 8;
+    int32_t left = (int32_t)n;
+    int64_t k = 0;
+    while (left > 0) {
+        if (k > n + kBatch) return set_error(GR_EHIP, "colouring did not converge");
+        for (int b = 0; b < kBatch; ++b, ++k) {
+            hipLaunchKernelGGL(k_jp_round, dim3(blocks_for(left, kThreads)), dim3(kThreads), 0, st,
+                               g->row_ptr, g->col, seed, ldf, colours, cursor, wk[k & 1],
+                               wk[(k + 1) & 1], cnt, (int)(k % 3));
+            GR_LAUNCHED("jp round");
+        }
+        int32_t now = 0;
+        GR_HIP(hipMemcpyAsync(&now, cnt + (k % 3), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+        if (now >= left && now > 0) return set_error(GR_EHIP, "colouring made no progress");
+        left = now;
+    }
+    GR_HIP(hipMemsetAsync(cnt + 3, 0xff, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kThreads), 0, st, colours, n, cnt + 3);
+    GR_LAUNCHED("max colour");
+    int32_t mx = -1;
+    GR_HIP(hipMemcpyAsync(&mx, cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    *n_colours_host = mx + 1;
+    ws.used = mark;
+    return GR_OK;
+}
+
+__global__ void k_check_colouring(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                  const int32_t* __restrict__ colours, int64_t n, int32_t nc,
+                                  int32_t* bad) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t c = colours[v];
+    int f = 0;
+    if (c < 0 || c >= nc) f = 1;
+    else
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (colours[col[e]] == c) { f = 2; break; }
+    if (f) atomicOr(bad, f);
+}
+
+int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colours, Arena& ws,
+                       hipStream_t st) {
+    if (g->n == 0) return GR_OK;
+    size_t mark = ws.used;
+    int32_t* bad = ws.take<int32_t>(1);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small");
+    GR_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_check_colouring, dim3(blocks_for(g->n, kThreads)), dim3(kThreads), 0, st,
+                       g->row_ptr, g->col, colours, g->n, n_colours, bad);
+    GR_LAUNCHED("check colouring");
+    int32_t hb = 0;
+    GR_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    ws.used = mark;
+    if (hb & 1) return set_error(GR_ECOLOUR, "colour out of range [0, %d)", n_colours);
+    if (hb & 2) return set_error(GR_ECOLOUR, "an edge joins two nodes of one colour");
+    return GR_OK;
+}
+
+// ------------------------------------------------------- colour-major order
+// Rows are relabelled by the key (colour, long?0:1, old id): the rows of one
+// colour become a contiguous range with the long rows (degree > kLongRow)
+// first.  Long rows are later split into chunks handled by one workgroup
+// each, so a hub's latency no longer bounds a whole colour step.
+__global__ void k_bucket_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ colours,
+                              int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t deg = rp[v + 1] - rp[v];
+    uint64_t b = (uint64_t)colours[v] * 2u + (deg > kLongRow ? 0u : 1u);
+    keys[v] = b;
+    vals[v] = (uint32_t)v;
+}
+
+// first and one-past-last row of every bucket present in the sorted keys
+__global__ void k_bucket_bounds(const uint64_t* __restrict__ keys, int64_t n,
+                                int32_t* __restrict__ bfirst, int32_t* __restrict__ bend) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) bfirst[k] = (int32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) bend[k] = (int32_t)(i + 1);
+}
+
+__global__ void k_perm_degrees(const int32_t* __restrict__ rp, const uint32_t* __restrict__ perm,
+                               int64_t n, int32_t* __restrict__ iperm, int32_t* __restrict__ deg) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int32_t v = (int32_t)perm[r];
+    iperm[v] = (int32_t)r;
+    deg[r] = rp[v + 1] - rp[v];
+}
+
+// one wave per new row: copy the old row's entries with relabelled columns
+__global__ void k_perm_entries(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const float* __restrict__ w, const uint32_t* __restrict__ perm,
+                               const int32_t* __restrict__ iperm, const int32_t* __restrict__ nrp,
+                               int64_t n, int32_t* __restrict__ ncol, float* __restrict__ nw) {
+    int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    int lane = threadIdx.x & (kWave - 1);
+    if (r >= n) return;
+    int32_t v = (int32_t)perm[r];
+    int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[r];
+    for (int32_t e = e0 + lane; e < e1; e += kWave) {
+        ncol[o + (e - e0)] = iperm[col[e]];
+        nw[o + (e - e0)] = w[e];
+    }
+}
+
+// per bucket: rows, and stored entries (from the relabelled row pointers)
+__global__ void k_bucket_sizes(const int32_t* __restrict__ bfirst, const int32_t* __restrict__ bend,
+                               const int32_t* __restrict__ nrp, int32_t nb,
+                               int64_t* __restrict__ out) {
+    int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    int32_t f = bfirst[b], e = bend[b];
+    out[2 * b] = f >= 0 ? (int64_t)(e - f) : 0;
+    out[2 * b + 1] = f >= 0 ? (int64_t)(nrp[e] - nrp[f]) : 0;
+}
+
+// long rows of the relabelled graph, compacted: their row ids and extents
+__global__ void k_long_rows(const int32_t* __restrict__ nrp, const int32_t* __restrict__ bfirst,
+                            const int32_t* __restrict__ bend, int32_t n_colours,
+                            const int32_t* __restrict__ long_off, int32_t* __restrict__ out) {
+    int32_t c = blockIdx.y;
+    if (c >= n_colours) return;
+    int32_t f = bfirst[2 * c], e = bend[2 * c];
+    if (f < 0) return;
+    for (int32_t r = f + blockIdx.x * blockDim.x + threadIdx.x; r < e; r += gridDim.x * blockDim.x) {
+        int32_t o = long_off[c] + (r - f);
+        out[3 * o] = r;
+        out[3 * o + 1] = nrp[r];
+        out[3 * o + 2] = nrp[r + 1];
+    }
+}
+
+int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours, int32_t K,
+                    int32_t dtype, OrderedGraph* og, Arena& ws, hipStream_t st) {
+    const int64_t n = g->n, nnz = g->nnz;
+    const int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
+    const int CH = 1024 / Q;  // entries per chunk of a long row
+    og->n_colours = n_colours;
+    og->chunk_entries = CH;
+    og->perm = ws.take<int32_t>(n);
+    og->iperm = ws.take<int32_t>(n);
+    int32_t* nrp = ws.take<int32_t>(n + 1);
+    int32_t* ncol = ws.take<int32_t>(nnz);
+    float* nw = ws.take<float>(nnz);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (relabel)");
+    size_t mark = ws.used;
+    const int32_t nb = 2 * n_colours;
+    uint64_t* k0 = ws.take<uint64_t>(n);
+    uint32_t* v0 = ws.take<uint32_t>(n);
+    uint64_t* k1 = ws.take<uint64_t>(n);
+    int32_t* bfirst = ws.take<int32_t>(nb + 1);
+    int32_t* bend = ws.take<int32_t>(nb + 1);
+    int64_t* sizes = ws.take<int64_t>(2 * (int64_t)nb + 2);
+    int32_t* deg = ws.take<int32_t>(n + 1);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (relabel)");
+    GR_TRY(fill_i32(bfirst, -1, nb + 1, st));
+    GR_TRY(fill_i32(bend, -1, nb + 1, st));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bucket_keys, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st,
+                           g->row_ptr, colours, n, k0, v0);
+        GR_LAUNCHED("bucket keys");
+    }
+    GR_TRY(radix_sort_pairs(k0, v0, k1, (uint32_t*)og->perm, n, bits_for(nb), ws, st));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bucket_bounds, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st,
+                           (const uint64_t*)k1, n, bfirst, bend);
+        GR_LAUNCHED("bucket bounds");
+        hipLaunchKernelGGL(k_perm_degrees, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st,
+                           g->row_ptr, (const uint32_t*)og->perm, n, og->iperm, deg);
+        GR_LAUNCHED("perm degrees");
+    }
+    GR_TRY(scan_exclusive_i32(deg, nrp, n, nrp + n, ws, st));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_perm_entries, dim3(blocks_for(n * kWave, kThreads)), dim3(kThreads), 0,
+                           st, g->row_ptr, g->col, g->w, (const uint32_t*)og->perm, og->iperm, nrp,
+                           n, ncol, nw);
+        GR_LAUNCHED("perm entries");
+    }
+    // bucket sizes (rows, entries) on the host
+    std::vector<int64_t> hs(2 * (size_t)nb);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_bucket_sizes, dim3(blocks_for(nb, kThreads)), dim3(kThreads), 0, st,
+                           bfirst, bend, nrp, nb, sizes);
+        GR_LAUNCHED("bucket sizes");
+        GR_HIP(hipMemcpyAsync(hs.data(), sizes, sizeof(int64_t) * 2 * nb, hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+    }
+    og->class_ptr_h.assign((size_t)n_colours + 1, 0);
+    og->long_end_h.assign((size_t)n_colours, 0);
+    og->class_nnz_h.assign((size_t)n_colours, 0);
+    og->normal_nnz_h.assign((size_t)n_colours, 0);
+    std::vector<int32_t> long_off(n_colours + 1, 0);
+    int64_t total = 0, nlong = 0;
+    for (int c = 0; c < n_colours; ++c) {
+        og->class_ptr_h[c] = total;
+        og->long_end_h[c] = total + hs[4 * c];
+        og->class_nnz_h[c] = hs[4 * c + 1] + hs[4 * c + 3];
+        og->normal_nnz_h[c] = hs[4 * c + 3];
+        long_off[c] = (int32_t)nlong;
+        nlong += hs[4 * c];
+        total += hs[4 * c] + hs[4 * c + 2];
+    }
+    long_off[n_colours] = (int32_t)nlong;
+    og->class_ptr_h[n_colours] = total;
+    if (total != n) return set_error(GR_ECOLOUR, "colouring does not cover every node");
+    // chunk table of the long rows: (row, e0, e1, first chunk of the row, chunks of the row)
+    og->chunk_ptr_h.assign((size_t)n_colours + 1, 0);
+    og->n_chunks = 0;
+    og->chunks = nullptr;
+    og->partial = nullptr;
+    og->counter = nullptr;
+    if (nlong > 0) {
+        int32_t* loff = ws.take<int32_t>(n_colours + 1);
+        int32_t* lrows = ws.take<int32_t>(3 * nlong);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
+        GR_HIP(hipMemcpy(loff, long_off.data(), sizeof(int32_t) * (n_colours + 1),
+                         hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_long_rows, dim3(8, n_colours), dim3(kThreads), 0, st, nrp, bfirst, bend,
+                           n_colours, loff, lrows);
+        GR_LAUNCHED("long rows");
+        std::vector<int32_t> hl(3 * (size_t)nlong);
+        GR_HIP(hipMemcpyAsync(hl.data(), lrows, sizeof(int32_t) * 3 * nlong, hipMemcpyDeviceToHost,
+                              st));
+        GR_HIP(hipStreamSynchronize(st));
+        std::vector<ChunkDesc> tab;
+        for (int c = 0; c < n_colours; ++c) {
+            og->chunk_ptr_h[c] = (int64_t)tab.size();
+            for (int32_t t = long_off[c]; t < long_off[c + 1]; ++t) {
+                int32_t r = hl[3 * t], e0 = hl[3 * t + 1], e1 = hl[3 * t + 2];
+                int32_t cnt = (e1 - e0 + CH - 1) / CH;
+                int32_t first = (int32_t)tab.size();
+                for (int32_t k = 0; k < cnt; ++k)
+                    tab.push_back(ChunkDesc{r, e0 + k * CH, min(e1, e0 + (k + 1) * CH), first, cnt,
+                                            first + k});
+            }
+        }
+        og->chunk_ptr_h[n_colours] = (int64_t)tab.size();
+        og->n_chunks = (int64_t)tab.size();
+        ws.used = mark;  // the temporaries above are dead; the chunk data persists
+        og->chunks = ws.take<ChunkDesc>(og->n_chunks);
+        og->partial = ws.take<float>(og->n_chunks * (size_t)(K + 4));
+        og->counter = ws.take<int32_t>(og->n_chunks);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (chunks)");
+        GR_HIP(hipMemcpy(og->chunks, tab.data(), sizeof(ChunkDesc) * tab.size(),
+                         hipMemcpyHostToDevice));
+        GR_HIP(hipMemsetAsync(og->counter, 0, sizeof(int32_t) * og->n_chunks, st));
+        mark = ws.used;
+    }
+    og->g.n = n;
+    og->g.nnz = nnz;
+    og->g.row_ptr = nrp;
+    og->g.col = ncol;
+    og->g.w = nw;
+    og->mean_deg = n > 0 ? (double)nnz / (double)n : 0.0;
+    ws.used = mark;
+    return GR_OK;
+}
+
+// ------------------------------------------------------------ row moves
+__global__ void k_permute_rows(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                               const int32_t* __restrict__ perm, int64_t n, int64_t q, int inverse) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * q) return;
+    int64_t r = i / q, c = i - r * q;
+    int64_t o = perm[r];
+    if (inverse) dst[o * q + c] = src[r * q + c];
+    else dst[r * q + c] = src[o * q + c];
+}
+
+int permute_rows(const void* src, void* dst, const int32_t* perm, int64_t n, size_t row_bytes,
+                 int inverse, hipStream_t st) {
+    if (n == 0) return GR_OK;
+    int64_t q = (int64_t)(row_bytes / 16);
+    hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(n * q, kThreads)), dim3(kThreads), 0, st,
+                       (const uint4*)src, (uint4*)dst, perm, n, q, inverse);
+    GR_LAUNCHED("permute rows");
+    return GR_OK;
+}
+
+// ------------------------------------------------------------ test vectors
+__device__ inline double rand_entry(uint64_t seed, uint64_t idx) {
+    uint64_t r = splitmix64(seed, idx);
+    int64_t m = (int64_t)(r >> 40);
+    return (double)(2 * m + 1 - (1ll << 24)) * (1.0 / 16777216.0);
+}
+
+constexpr int kInitBlocks = 240;
+
+__global__ void __launch_bounds__(kThreads) k_init_colsum(int64_t n, int32_t K, uint64_t seed,
+                                                          const int32_t* __restrict__ ids,
+                                                          double* __restrict__ part) {
+    // grid (kInitBlocks, K): block (b, k) sums column k over rows b, b+B, ...
+    const int k = blockIdx.y;
+    double s = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * kThreads) {
+        int64_t id = ids ? ids[r] : r;
+        s += rand_entry(seed, (uint64_t)id * (uint64_t)K + (uint64_t)k);
+    }
+    __shared__ double wsum[kThreads / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) t += wsum[w];
+        part[(int64_t)k * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+__global__ void k_init_mean(const double* __restrict__ part, int nb, int64_t n, int32_t K,
+                            double* __restrict__ mean) {
+    int k = threadIdx.x;
+    if (k >= K) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[(int64_t)k * nb + b];
+    mean[k] = t / (double)n;
+}
+
+__global__ void k_init_write(int64_t n, int32_t K, uint64_t seed, const int32_t* __restrict__ ids,
+                             const double* __restrict__ mean, int dtype, void* __restrict__ X) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * K) return;
+    int64_t r = i / K;
+    int k = (int)(i - r * K);
+    int64_t id = ids ? ids[r] : r;
+    double x = rand_entry(seed, (uint64_t)id * (uint64_t)K + (uint64_t)k) - mean[k];
+    float f = (float)x;
+    if (dtype == GR_BF16) ((uint16_t*)X)[i] = f32_to_bf16(f);
+    else ((float*)X)[i] = f;
+}
+
+int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32_t* ids, void* X,
+                 Arena& ws, hipStream_t st) {
+    if (n == 0) return GR_OK;
+    size_t mark = ws.used;
+    double* part = ws.take<double>((size_t)kInitBlocks * K);
+    double* mean = ws.take<double>(K);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (init)");
+    hipLaunchKernelGGL(k_init_colsum, dim3(kInitBlocks, K), dim3(kThreads), 0, st, n, K, seed, ids,
+                       part);
+    GR_LAUNCHED("init colsum");
+    hipLaunchKernelGGL(k_init_mean, dim3(1), dim3(64), 0, st, (const double*)part, kInitBlocks, n, K,
+                       mean);
+    GR_LAUNCHED("init mean");
+    hipLaunchKernelGGL(k_init_write, dim3(blocks_for(n * K, kThreads)), dim3(kThreads), 0, st, n, K,
+                       seed, ids, (const double*)mean, dtype, X);
+    GR_LAUNCHED("init write");
+    ws.used = mark;
+    return GR_OK;
+}
+
+// ------------------------------------------------------------- chunk I/O
+// A chunk is 16 bytes of a row: E = 4 float32 or 8 bfloat16 values.
+template <int DT> struct Chunk;
+template <> struct Chunk<GR_F32> {
+    static constexpr int E = 4;
+    __device__ static inline void load(const void* X, int64_t row, int K, int q, float* v) {
+        float4 t = *reinterpret_cast<const float4*>((const float*)X + row * K + q * 4);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+    __device__ static inline void store(void* X, int64_t row, int K, int q, const float* v) {
+        float4 t = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<float4*>((float*)X + row * K + q * 4) = t;
+    }
+};
+template <> struct Chunk<GR_BF16> {
+    static constexpr int E = 8;
+    __device__ static inline void load(const void* X, int64_t row, int K, int q, float* v) {
+        uint4 t = *reinterpret_cast<const uint4*>((const uint16_t*)X + row * K + q * 8);
+        uint32_t u[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = __uint_as_float(u[i] << 16);
+            v[2 * i + 1] = __uint_as_float(u[i] & 0xffff0000u);
+        }
+    }
+    __device__ static inline void store(void* X, int64_t row, int K, int q, const float* v) {
+        uint32_t u[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            u[i] = (uint32_t)f32_to_bf16(v[2 * i]) | ((uint32_t)f32_to_bf16(v[2 * i + 1]) << 16);
+        *reinterpret_cast<uint4*>((uint16_t*)X + row * K + q * 8) = make_uint4(u[0], u[1], u[2], u[3]);
+    }
+};
+
+// ----------------------------------------------------------- GS colour step
+// One Gauss-Seidel colour step (Sec. 3.2.1): every node v of the colour with
+// d_v > 0 becomes sum_j w_vj x_j / d_v.  One launch per step; block roles:
+//  * blocks [0, n_chunks): one chunk (<= CH entries) of a long row each.  The
+//    block writes its partial sums (K values and the weight sum) and takes a
+//    ticket; the block that draws the last ticket of the row adds the
+//    partials in chunk order (a fixed order) and stores the row.  Nothing
+//    waits, so no block can stall another.
+//  * the remaining blocks: normal rows, L = Q*P lanes per row, U = 4
+//    neighbours per lane per round so that four gathers are in flight.
+constexpr int kU = 4;
+
+template <int Q, int P, int DT>
+__device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                      const float* __restrict__ w, void* __restrict__ X, int32_t K,
+                                      int64_t r_lo, int64_t r_hi, int64_t rblock) {
+    constexpr int L = Q * P;
+    constexpr int RPW = kWave / L;
+    constexpr int E = Chunk<DT>::E;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int l = lane % L;
+    const int p = l / Q, q = l % Q;
+    const int64_t wave = (rblock * kThreads + threadIdx.x) / kWave;
+    const int64_t r = r_lo + wave * RPW + lane / L;
+    if (r >= r_hi) return;  // whole row-groups leave together
+    const int32_t e0 = rp[r], e1 = rp[r + 1];
+    float acc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc[i] = 0.0f;
+    float d = 0.0f;
+    for (int32_t e = e0 + p; e < e1; e += kU * P) {
+        int32_t j[kU];
+        float wt[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            int32_t eu = e + u * P;
+            bool ok = eu < e1;
+            j[u] = ok ? col[eu] : (int32_t)r;   // out of range: weight 0, own row
+            wt[u] = ok ? w[eu] : 0.0f;
+        }
+        float x[kU][E];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) Chunk<DT>::load(X, j[u], K, q, x[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt[u], x[u][i], acc[i]);
+            d += wt[u];
+        }
+    }
+#pragma unroll
+    for (int off = Q; off < L; off <<= 1) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
+        d += __shfl_xor(d, off, kWave);
+    }
+    if (p == 0 && d > 0.0f) {
+        float y[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) y[i] = acc[i] / d;
+        Chunk<DT>::store(X, r, K, q, y);
+    }
+}
+
+template <int Q, int DT>
+__device__ inline void gs_long_chunk(const int32_t* __restrict__ col, const float* __restrict__ w,
+                                     void* __restrict__ X, int32_t K, const ChunkDesc& cd,
+                                     float* __restrict__ partial, int32_t* __restrict__ counter) {
+    constexpr int E = Chunk<DT>::E;
+    constexpr int P = kThreads / Q;
+    constexpr int NW = kThreads / kWave;
+    __shared__ float sacc[NW][Q][E];
+    __shared__ float sd[NW];
+    __shared__ int last;
+    const int t = threadIdx.x;
+    const int p = t / Q, q = t % Q;
+    float acc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc[i] = 0.0f;
+    float d = 0.0f;
+    {
+        int32_t j[kU];
+        float wt[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            int32_t e = cd.e0 + p + u * P;
+            bool ok = e < cd.e1;
+            j[u] = ok ? col[e] : cd.row;
+            wt[u] = ok ? w[e] : 0.0f;
+        }
+        float x[kU][E];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) Chunk<DT>::load(X, j[u], K, q, x[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt[u], x[u][i], acc[i]);
+            d += wt[u];
+        }
+    }
+#pragma unroll
+    for (int off = Q; off < kWave; off <<= 1) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
+        d += __shfl_xor(d, off, kWave);
+    }
+    const int wid = t / kWave, lane = t & (kWave - 1);
+    if (lane < Q) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) sacc[wid][lane][i] = acc[i];
+        if (lane == 0) sd[wid] = d;
+    }
+    __syncthreads();
+    float* mine = partial + (size_t)cd.self * (K + 4);
+    if (t < Q) {
+        float y[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) y[i] = 0.0f;
+        for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+            for (int i = 0; i < E; ++i) y[i] += sacc[ww][t][i];
+#pragma unroll
+        for (int i = 0; i < E; ++i) mine[t * E + i] = y[i];
+    }
+    if (t == 0) {
+        float dd = 0.0f;
+        for (int ww = 0; ww < NW; ++ww) dd += sd[ww];
+        mine[K] = dd;
+    }
+    // publish the partial, then take a ticket; the last block of the row
+    // reduces the partials of all its chunks in chunk order
+    __threadfence();
+    __syncthreads();
+    if (t == 0) {
+        int prev = atomicAdd(&counter[cd.first], 1);
+        last = (prev == cd.count - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (t < Q) {
+        float y[E];
+        float dd = 0.0f;
+#pragma unroll
+        for (int i = 0; i < E; ++i) y[i] = 0.0f;
+        for (int32_t k = 0; k < cd.count; ++k) {
+            const float* pk = partial + (size_t)(cd.first + k) * (K + 4);
+#pragma unroll
+            for (int i = 0; i < E; ++i) y[i] += __builtin_nontemporal_load(pk + t * E + i);
+            dd += __builtin_nontemporal_load(pk + K);
+        }
+        if (dd > 0.0f) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) y[i] = y[i] / dd;
+            Chunk<DT>::store(X, cd.row, K, t, y);
+        }
+    }
+    if (t == 0) counter[cd.first] = 0;  // ready for the next step over this colour
+}
+
+template <int Q, int P, int DT>
+__global__ void __launch_bounds__(kThreads) k_gs_step(const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ w,
+                                                      void* __restrict__ X, int32_t K,
+                                                      const ChunkDesc* __restrict__ chunks,
+                                                      int64_t c_lo, int64_t n_chunks,
+                                                      float* __restrict__ partial,
+                                                      int32_t* __restrict__ counter, int64_t r_lo,
+                                                      int64_t r_hi) {
+    const int64_t b = blockIdx.x;
+    if (b < n_chunks) {
+        ChunkDesc cd = chunks[c_lo + b];
+        gs_long_chunk<Q, DT>(col, w, X, K, cd, partial, counter);
+    } else {
+        gs_normal_rows<Q, P, DT>(rp, col, w, X, K, r_lo, r_hi, b - n_chunks);
+    }
+}
+
+template <int Q, int DT>
+static int launch_gs_step(int P, const OrderedGraph* og, void* X, int K, int c, hipStream_t st) {
+    const int64_t lo = og->class_ptr_h[c], le = og->long_end_h[c], hi = og->class_ptr_h[c + 1];
+    const int64_t c_lo = og->chunk_ptr_h[c], nch = og->chunk_ptr_h[c + 1] - c_lo;
+    (void)lo;
+    const int64_t rows = hi - le;
+    const int L = Q * P;
+    const int64_t waves = (rows * L + kWave - 1) / kWave;
+    const int64_t rblocks = rows > 0 ? (waves * kWave + kThreads - 1) / kThreads : 0;
+    const int64_t grid = nch + rblocks;
+    if (grid == 0) return GR_OK;
+#define GR_GS(PP)                                                                               \
+    case PP:                                                                                   \
+        if constexpr (Q * PP <= kWave)                                                         \
+            hipLaunchKernelGGL((k_gs_step<Q, PP, DT>), dim3((unsigned)grid), dim3(kThreads), 0, \
+                               st, og->g.row_ptr, og->g.col, og->g.w, X, K, og->chunks, c_lo,    \
+                               nch, og->partial, og->counter, le, hi);                          \
+        break;
+    switch (P) {
+        GR_GS(1) GR_GS(2) GR_GS(4) GR_GS(8) GR_GS(16) GR_GS(32) GR_GS(64)
+        default: return set_error(GR_EINVAL, "bad lane split");
+    }
+#undef GR_GS
+    GR_LAUNCHED("gs step");
+    return GR_OK;
+}
+
+// lanes per row for normal rows: about a quarter of the mean degree (each
+// lane takes four neighbours per round), a power of two, at most a wave
+static int pick_p(int Q, double mean_deg) {
+    int P = 1;
+    while (P * kU < mean_deg && Q * P * 2 <= kWave) P *= 2;
+    return P;
+}
+
+template <int Q, int DT>
+static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, hipStream_t st) {
+    const bool pr = prof::on();
+    const int xs = DT == GR_BF16 ? 2 : 4;
+    std::vector<int> Ps(og->n_colours);
+    for (int c = 0; c < og->n_colours; ++c) {
+        int64_t rows = og->class_ptr_h[c + 1] - og->long_end_h[c];
+        Ps[c] = pick_p(Q, rows > 0 ? (double)og->normal_nnz_h[c] / (double)rows : 1.0);
+    }
+    for (int s = 0; s < sweeps; ++s)
+        for (int c = 0; c < og->n_colours; ++c) {
+            int64_t lo = og->class_ptr_h[c], hi = og->class_ptr_h[c + 1];
+            if (hi == lo) continue;
+            if (pr) prof::begin(st);
+            GR_TRY((launch_gs_step<Q, DT>(Ps[c], og, X, K, c, st)));
+            if (pr) {
+                // compulsory bytes of this colour step: its CSR rows, plus one
+                // read and one write of each updated vector row
+                double rows = (double)(hi - lo);
+                double bytes = 4.0 * (rows + 1) + 8.0 * (double)og->class_nnz_h[c] +
+                               2.0 * rows * K * xs;
+                prof::end(st, prof::SMOOTH, bytes, 1);
+            }
+        }
+    return GR_OK;
+}
+
+int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dtype, void* X,
+                   hipStream_t st) {
+    if (og->g.n == 0 || sweeps == 0) return GR_OK;
+    int bytes = K * (dtype == GR_BF16 ? 2 : 4);
+    int Q = bytes / 16;
+    if (og->n_chunks > 0 && og->chunk_entries != 1024 / Q)
+        return set_error(GR_EINVAL, "graph ordered for a different vector width");
+    if (dtype == GR_BF16) {
+        switch (Q) {
+            case 1: return smooth_q<1, GR_BF16>(og, K, sweeps, X, st);
+            case 2: return smooth_q<2, GR_BF16>(og, K, sweeps, X, st);
+            case 4: return smooth_q<4, GR_BF16>(og, K, sweeps, X, st);
+            case 8: return smooth_q<8, GR_BF16>(og, K, sweeps, X, st);
+        }
+    } else {
+        switch (Q) {
+            case 1: return smooth_q<1, GR_F32>(og, K, sweeps, X, st);
+            case 2: return smooth_q<2, GR_F32>(og, K, sweeps, X, st);
+            case 4: return smooth_q<4, GR_F32>(og, K, sweeps, X, st);
+            case 8: return smooth_q<8, GR_F32>(og, K, sweeps, X, st);
+            case 16: return smooth_q<16, GR_F32>(og, K, sweeps, X, st);
+        }
+    }
+    return set_error(GR_EUNSUP, "unsupported K=%d for this dtype", K);
+}
+
+// ---------------------------------------------------------------- affinity
+// Sum of the Q partial sums of a row-group, fixed xor tree over q.
+template <int Q>
+__device__ inline float qsum(float v) {
+#pragma unroll
+    for (int off = 1; off < Q; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <int E>
+__device__ inline float chunk_dot(const float* a, const float* b) {
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < E; ++i) s = __fmaf_rn(a[i], b[i], s);
+    return s;
+}
+
+// (d, id) ordering of candidates: smaller algebraic distance, then smaller id.
+__device__ inline bool closer(float d1, int32_t id1, float d2, int32_t id2) {
+    return d1 < d2 || (d1 == d2 && id1 < id2);
+}
+
+// Per row-group: a = (x_v . x_j)^2 / (|x_v|^2 |x_j|^2) and the algebraic
+// distance d = 1 - a.  d is formed without cancellation as
+// |u - w|^2 |u + w|^2 / 4 on the normalised rows u = x_v/|x_v|, w = x_j/|x_j|
+// (equal to 1 - cos^2 in exact arithmetic), so that it keeps its relative
+// accuracy where a itself rounds to 1 in float32.  Both quantities are
+// computed by the same code for (v, j) and (j, v), hence bit-symmetric.
+template <int Q, int P, int DT>
+__global__ void __launch_bounds__(kThreads) k_affinity(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const void* __restrict__ X, int32_t K,
+                                                       int64_t n, const int32_t* __restrict__ ids,
+                                                       float* __restrict__ a,
+                                                       float* __restrict__ dist,
+                                                       int32_t* __restrict__ best,
+                                                       float* __restrict__ dbest) {
+    constexpr int L = Q * P;
+    constexpr int RPW = kWave / L;
+    constexpr int E = Chunk<DT>::E;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int l = lane % L;
+    const int p = l / Q, q = l % Q;
+    const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+    const int64_t r = wave * RPW + lane / L;
+    if (r >= n) return;
+    float xv[E], uv[E];
+    Chunk<DT>::load(X, r, K, q, xv);
+    const float nv = qsum<Q>(chunk_dot<E>(xv, xv));
+    const float sv = sqrtf(nv);
+#pragma unroll
+    for (int i = 0; i < E; ++i) uv[i] = nv > 0.0f ? xv[i] / sv : 0.0f;
+    const int32_t e0 = rp[r], e1 = rp[r + 1];
+    float bd = 2.0f;
+    int32_t bj = -1, bid = 0x7fffffff;
+    // every lane of the row-group runs the same trip count so the q-sums
+    // (shuffles) stay converged; lanes past the end use a dummy column
+    const int32_t trips = (e1 - e0 + P - 1) / P;
+    for (int32_t t = 0; t < trips; ++t) {
+        int32_t e = e0 + p + t * P;
+        bool ok = e < e1;
+        int32_t j = ok ? col[e] : (int32_t)r;
+        float xj[E];
+        Chunk<DT>::load(X, j, K, q, xj);
+        float c = qsum<Q>(chunk_dot<E>(xv, xj));
+        float nj = qsum<Q>(chunk_dot<E>(xj, xj));
+        float sj = sqrtf(nj);
+        float dm = 0.0f, dp = 0.0f;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            float uj = nj > 0.0f ? xj[i] / sj : 0.0f;
+            float m = uv[i] - uj, s2 = uv[i] + uj;
+            dm = __fmaf_rn(m, m, dm);
+            dp = __fmaf_rn(s2, s2, dp);
+        }
+        dm = qsum<Q>(dm);
+        dp = qsum<Q>(dp);
+        float den = nv * nj;
+        float av = den == 0.0f ? 0.0f : fminf(1.0f, (c * c) / den);
+        float dv = den == 0.0f ? 1.0f : fminf(1.0f, dm * dp * 0.25f);
+        if (ok) {
+            if (q == 0) {
+                if (a) a[e] = av;
+                if (dist) dist[e] = dv;
+            }
+            int32_t jid = ids ? ids[j] : j;
+            if (closer(dv, jid, bd, bid)) { bd = dv; bj = j; bid = jid; }
+        }
+    }
+    // combine the P candidates of the row-group (ties: smaller id)
+#pragma unroll
+    for (int off = Q; off < L; off <<= 1) {
+        float od = __shfl_xor(bd, off, kWave);
+        int32_t oj = __shfl_xor(bj, off, kWave);
+        int32_t oid = __shfl_xor(bid, off, kWave);
+        if (oj >= 0 && (bj < 0 || closer(od, oid, bd, bid))) { bd = od; bj = oj; bid = oid; }
+    }
+    if (l == 0) {
+        best[r] = bj;
+        if (dbest) dbest[r] = bj >= 0 ? bd : 1.0f;
+    }
+}
+
+template <int Q, int DT>
+static int launch_aff(const gr_graph* g, int K, const void* X, const int32_t* ids, float* a,
+                      float* dist, int32_t* best, float* dbest, hipStream_t st) {
+    int P = 1;
+    double md = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
+    while (P * 2 <= md * 0.75 && Q * P * 2 <= kWave) P *= 2;
+    int64_t waves = (g->n * Q * P + kWave - 1) / kWave;
+    dim3 grid(blocks_for(waves * kWave, kThreads));
+#define GR_AF(PP)                                                                              \
+    case PP:                                                                                  \
+        if constexpr (Q * PP <= kWave)                                                        \
+            hipLaunchKernelGGL((k_affinity<Q, PP, DT>), grid, dim3(kThreads), 0, st, g->row_ptr, \
+                               g->col, X, K, g->n, ids, a, dist, best, dbest);                 \
+        break;
+    switch (P) {
+        GR_AF(1) GR_AF(2) GR_AF(4) GR_AF(8) GR_AF(16) GR_AF(32) GR_AF(64)
+        default: return set_error(GR_EINVAL, "bad lane split");
+    }
+#undef GR_AF
+    GR_LAUNCHED("affinity");
+    return GR_OK;
+}
+
+int affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, const int32_t* ids,
+             float* a, float* dist, int32_t* best, float* dbest, hipStream_t st) {
+    if (g->n == 0) return GR_OK;
+    int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
+    if (dtype == GR_BF16) {
+        switch (Q) {
+            case 1: return launch_aff<1, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
+            case 2: return launch_aff<2, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
+            case 4: return launch_aff<4, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
+            case 8: return launch_aff<8, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
+        }
+    } else {
+        switch (Q) {
+            case 1: return launch_aff<1, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
+            case 2: return launch_aff<2, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
+            case 4: return launch_aff<4, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
+            case 8: return launch_aff<8, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
+            case 16: return launch_aff<16, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
+        }
+    }
+    return set_error(GR_EUNSUP, "unsupported K=%d for this dtype", K);
+}
+
+}  // namespace gr

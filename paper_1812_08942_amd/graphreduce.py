@@ -1,0 +1,375 @@
+"""Python binding of libgraphreduce (the C ABI declared in
+include/graphreduce.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device arrays
+are torch tensors on a ROCm device; the current torch stream is passed as the
+hipStream_t.  Functions keep the C names; the `reduce` helper wraps
+gr_reduce with output allocation.  If the library is not built, importing
+this module raises ImportError — there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgraphreduce.so")
+
+GR_OK = 0
+GR_F32 = 0
+GR_BF16 = 1
+GR_VALIDATE = 1
+GR_COLOUR_LDF = 2
+GR_WNOPROGRESS = 1
+
+
+class gr_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("w", ctypes.c_void_p)]
+
+
+class gr_params(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("ratio", ctypes.c_double), ("vec_seed", ctypes.c_uint64),
+                ("colour_seed", ctypes.c_uint64), ("vec_dtype", ctypes.c_int32),
+                ("colours", ctypes.c_void_p), ("n_colours", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class gr_result(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_void_p), ("c_row_ptr", ctypes.c_void_p),
+                ("c_col", ctypes.c_void_p), ("c_w", ctypes.c_void_p),
+                ("n_coarse", ctypes.c_int64), ("nnz_coarse", ctypes.c_int64),
+                ("levels", ctypes.c_int32), ("warnings", ctypes.c_uint32),
+                ("level_n", ctypes.c_int64 * 32),
+                ("level_nnz", ctypes.c_int64 * 32),
+                ("level_colours", ctypes.c_int32 * 32)]
+
+
+class gr_profile(ctypes.Structure):
+    _fields_ = [("phase_ms", ctypes.c_double * 8),
+                ("phase_max_ms", ctypes.c_double * 8),
+                ("phase_bytes", ctypes.c_double * 8),
+                ("phase_launches", ctypes.c_int64 * 8),
+                ("records", ctypes.c_int64)]
+
+
+PHASES = ("colour", "relabel", "init", "smooth", "affinity", "aggregate",
+          "galerkin", "other")
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+_G = ctypes.POINTER(gr_graph)
+
+_SIGNATURES = {
+    "gr_version": ([], ctypes.c_int),
+    "gr_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "gr_last_error": ([], ctypes.c_char_p),
+    "gr_workspace_size": ([_I64, _I64, _I32, _I32, ctypes.POINTER(_SZ)],
+                          ctypes.c_int),
+    "gr_reduce": ([_G, ctypes.POINTER(gr_params), ctypes.POINTER(gr_result),
+                   _P, _SZ, _P], ctypes.c_int),
+    "gr_validate": ([_G, _P, _SZ, _P], ctypes.c_int),
+    "gr_profile_start": ([], ctypes.c_int),
+    "gr_profile_stop": ([ctypes.POINTER(gr_profile)], ctypes.c_int),
+    "gr_colour_greedy": ([_G, _U64, _I32, _P, ctypes.POINTER(_I32), _P, _SZ,
+                          _P], ctypes.c_int),
+    "gr_init_vectors": ([_I64, _I32, _U64, _I32, _P, _P, _SZ, _P],
+                        ctypes.c_int),
+    "gr_smooth": ([_G, _P, _I32, _I32, _I32, _I32, _P, _P, _SZ, _P],
+                  ctypes.c_int),
+    "gr_affinity": ([_G, _I32, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "gr_aggregate": ([_G, _P, _I64, _P, ctypes.POINTER(_I64), _P, _SZ, _P],
+                     ctypes.c_int),
+    "gr_galerkin": ([_G, _P, _I64, _P, _P, _P, ctypes.POINTER(_I64), _P, _SZ,
+                     _P], ctypes.c_int),
+}
+
+_lib = None
+
+
+def load():
+    """The loaded library; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGNATURES)
+
+
+class GraphReduceError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != GR_OK:
+        L = load()
+        raise GraphReduceError(rc, (L.gr_last_error() or b"").decode()
+                               or L.gr_status_string(rc).decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ graphs
+
+@dataclasses.dataclass
+class DeviceGraph:
+    """Symmetric CSR adjacency on the device (int32 / int32 / float32)."""
+
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    w: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.col.numel()
+
+    def c(self) -> gr_graph:
+        for t, dt in ((self.row_ptr, torch.int32), (self.col, torch.int32),
+                      (self.w, torch.float32)):
+            if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("graph arrays must be contiguous device "
+                                 "int32/int32/float32 tensors")
+        return gr_graph(self.n, self.nnz, self.row_ptr.data_ptr(),
+                        self.col.data_ptr() if self.nnz else None,
+                        self.w.data_ptr() if self.nnz else None)
+
+    @staticmethod
+    def from_numpy(row_ptr, col, w, device="cuda"):
+        import numpy as np
+
+        return DeviceGraph(
+            torch.from_numpy(np.ascontiguousarray(row_ptr, np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(col, np.int32)).to(device),
+            torch.from_numpy(np.ascontiguousarray(w, np.float32)).to(device))
+
+
+def vec_dtype_code(dtype) -> int:
+    if dtype in (GR_F32, "f32", torch.float32):
+        return GR_F32
+    if dtype in (GR_BF16, "bf16", torch.bfloat16):
+        return GR_BF16
+    raise ValueError(f"unsupported vector dtype {dtype}")
+
+
+def torch_dtype(code: int):
+    return torch.bfloat16 if code == GR_BF16 else torch.float32
+
+
+_ws_cache: dict = {}
+
+
+def workspace(n, nnz, K=8, dtype=GR_F32, device="cuda") -> torch.Tensor:
+    """Device workspace sized by gr_workspace_size (cached per device)."""
+    nbytes = gr_workspace_size(n, nnz, K, dtype)
+    key = str(torch.device(device))
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+# ------------------------------------------------------------ C functions
+
+def gr_version() -> int:
+    return load().gr_version()
+
+
+def gr_status_string(code: int) -> str:
+    return load().gr_status_string(code).decode()
+
+
+def gr_last_error() -> str:
+    return (load().gr_last_error() or b"").decode()
+
+
+def gr_profile_start():
+    _check(load().gr_profile_start())
+
+
+def gr_profile_stop() -> dict:
+    """Per-phase HIP-event totals recorded since gr_profile_start."""
+    pr = gr_profile()
+    _check(load().gr_profile_stop(ctypes.byref(pr)))
+    return {name: {"ms": pr.phase_ms[i], "max_ms": pr.phase_max_ms[i],
+                   "bytes": pr.phase_bytes[i],
+                   "launches": int(pr.phase_launches[i])}
+            for i, name in enumerate(PHASES)}
+
+
+def gr_workspace_size(n, nnz, K, dtype=GR_F32) -> int:
+    out = _SZ(0)
+    _check(load().gr_workspace_size(n, nnz, K, vec_dtype_code(dtype),
+                                    ctypes.byref(out)))
+    return int(out.value)
+
+
+def gr_validate(g: DeviceGraph, ws=None):
+    ws = ws if ws is not None else workspace(g.n, g.nnz)
+    cg = g.c()
+    _check(load().gr_validate(ctypes.byref(cg), _ptr(ws), ws.numel(),
+                              _stream()))
+
+
+def gr_colour_greedy(g: DeviceGraph, seed: int, largest_degree_first=False,
+                     ws=None):
+    ws = ws if ws is not None else workspace(g.n, g.nnz)
+    colours = torch.empty(max(g.n, 1), dtype=torch.int32,
+                          device=g.row_ptr.device)
+    nc = _I32(0)
+    cg = g.c()
+    _check(load().gr_colour_greedy(ctypes.byref(cg), seed & (2**64 - 1),
+                                   int(bool(largest_degree_first)),
+                                   _ptr(colours), ctypes.byref(nc), _ptr(ws),
+                                   ws.numel(), _stream()))
+    return colours[:g.n], int(nc.value)
+
+
+def gr_init_vectors(n, K, seed, dtype=GR_F32, device="cuda", ws=None):
+    code = vec_dtype_code(dtype)
+    ws = ws if ws is not None else workspace(n, 0, K, code, device)
+    X = torch.empty((max(n, 1), K), dtype=torch_dtype(code), device=device)
+    _check(load().gr_init_vectors(n, K, seed & (2**64 - 1), code, _ptr(X),
+                                  _ptr(ws), ws.numel(), _stream()))
+    return X[:n]
+
+
+def gr_smooth(g: DeviceGraph, colours, n_colours, X, sweeps, ws=None):
+    """Smooths X ([n, K] float32 or bfloat16 device tensor) in place."""
+    code = vec_dtype_code(X.dtype)
+    K = X.shape[1]
+    ws = ws if ws is not None else workspace(g.n, g.nnz, K, code)
+    if not X.is_contiguous() or X.shape[0] != g.n:
+        raise ValueError("X must be a contiguous [n, K] tensor")
+    cg = g.c()
+    _check(load().gr_smooth(ctypes.byref(cg), _ptr(colours), n_colours, K,
+                            sweeps, code, _ptr(X), _ptr(ws), ws.numel(),
+                            _stream()))
+    return X
+
+
+def gr_affinity(g: DeviceGraph, X, want_a=True, want_d=True):
+    """Returns (a, d, best, dbest): per-entry affinities and algebraic
+    distances, the strongest neighbour of each node and its distance."""
+    code = vec_dtype_code(X.dtype)
+    dev = g.row_ptr.device
+    a = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev) \
+        if want_a else None
+    d = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev) \
+        if want_d else None
+    best = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    dbest = torch.empty(max(g.n, 1), dtype=torch.float32, device=dev)
+    if not X.is_contiguous() or X.shape[0] != g.n:
+        raise ValueError("X must be a contiguous [n, K] tensor")
+    cg = g.c()
+    _check(load().gr_affinity(ctypes.byref(cg), X.shape[1], code, _ptr(X),
+                              _ptr(a), _ptr(d), _ptr(best), _ptr(dbest),
+                              _stream()))
+    return ((a[:g.nnz] if a is not None else None),
+            (d[:g.nnz] if d is not None else None), best[:g.n], dbest[:g.n])
+
+
+def gr_aggregate(g: DeviceGraph, dist, target, ws=None):
+    """Aggregation from per-entry algebraic distances `dist`."""
+    ws = ws if ws is not None else workspace(g.n, g.nnz)
+    agg = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.row_ptr.device)
+    nc = _I64(0)
+    cg = g.c()
+    _check(load().gr_aggregate(ctypes.byref(cg), _ptr(dist), int(target),
+                               _ptr(agg), ctypes.byref(nc), _ptr(ws),
+                               ws.numel(), _stream()))
+    return agg[:g.n], int(nc.value)
+
+
+def gr_galerkin(g: DeviceGraph, agg, n_coarse, ws=None):
+    ws = ws if ws is not None else workspace(g.n, g.nnz)
+    dev = g.row_ptr.device
+    c_rp = torch.empty(n_coarse + 1, dtype=torch.int32, device=dev)
+    c_col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    c_w = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev)
+    m = _I64(0)
+    cg = g.c()
+    _check(load().gr_galerkin(ctypes.byref(cg), _ptr(agg), int(n_coarse),
+                              _ptr(c_rp), _ptr(c_col), _ptr(c_w),
+                              ctypes.byref(m), _ptr(ws), ws.numel(),
+                              _stream()))
+    k = int(m.value)
+    return DeviceGraph(c_rp, c_col[:k].clone(), c_w[:k].clone())
+
+
+@dataclasses.dataclass
+class ReduceOut:
+    agg: torch.Tensor
+    coarse: DeviceGraph
+    levels: int
+    warnings: int
+    level_n: list
+    level_nnz: list
+    level_colours: list
+
+
+def gr_reduce(g: DeviceGraph, K, sweeps, ratio, vec_seed, colour_seed,
+              dtype=GR_F32, colours=None, n_colours=0, max_levels=0,
+              validate=False, largest_degree_first=False, ws=None,
+              out=None) -> ReduceOut:
+    """graph_reduce(csr, K, sweeps, ratio) -> aggregate ids + coarse CSR."""
+    code = vec_dtype_code(dtype)
+    ws = ws if ws is not None else workspace(g.n, g.nnz, K, code)
+    dev = g.row_ptr.device
+    if out is None:
+        out = (torch.empty(max(g.n, 1), dtype=torch.int32, device=dev),
+               torch.empty(g.n + 1, dtype=torch.int32, device=dev),
+               torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev))
+    agg, c_rp, c_col, c_w = out
+    p = gr_params(K, sweeps, float(ratio), vec_seed & (2**64 - 1),
+                  colour_seed & (2**64 - 1), code,
+                  colours.data_ptr() if colours is not None else None,
+                  int(n_colours), int(max_levels),
+                  (GR_VALIDATE if validate else 0)
+                  | (GR_COLOUR_LDF if largest_degree_first else 0))
+    r = gr_result(agg.data_ptr(), c_rp.data_ptr(), c_col.data_ptr(),
+                  c_w.data_ptr())
+    cg = g.c()
+    _check(load().gr_reduce(ctypes.byref(cg), ctypes.byref(p), ctypes.byref(r),
+                            _ptr(ws), ws.numel(), _stream()))
+    nc, m = int(r.n_coarse), int(r.nnz_coarse)
+    L = int(r.levels)
+    return ReduceOut(agg[:g.n], DeviceGraph(c_rp[:nc + 1], c_col[:m], c_w[:m]),
+                     L, int(r.warnings), list(r.level_n[:min(L, 32)]),
+                     list(r.level_nnz[:min(L, 32)]),
+                     list(r.level_colours[:min(L, 32)]))

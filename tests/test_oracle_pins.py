@@ -271,6 +271,7 @@ def test_aggregate_by_hand_path():
     a = np.array([ea[(min(v, j), max(v, j))]
                   for v in range(6)
                   for j in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]])
+    a = 1.0 - a    # decisions are taken on the algebraic distance d = 1 - a
     # best: 0->1, 1->0, 2->3, 3->2 (tie .7/.7 to the smaller index), 4->3,
     # 5->4.  Forest {0,1}, {2,3}, {3,4}, {4,5}: |F| = 4, n - |F| = 2
     r = O.aggregate(6, g.row_ptr, g.col, a, 1)
@@ -295,9 +296,9 @@ def test_aggregate_invariants():
         c, nc = _colour(g)
         X = O.smooth(g.n, g.row_ptr, g.col, wd(g), c, nc,
                      O.init_vectors(g.n, 8, 2), 5)
-        a = O.affinity(g.n, g.row_ptr, g.col, X)
+        d = O.distance(g.n, g.row_ptr, g.col, X)
         for T in (1, max(1, g.n // 3), g.n):
-            r = O.aggregate(g.n, g.row_ptr, g.col, a, T)
+            r = O.aggregate(g.n, g.row_ptr, g.col, d, T)
             assert r.n_coarse == max(T, g.n - r.n_forest)
             assert r.agg.min() == 0 and r.agg.max() == r.n_coarse - 1
             # ids in order of first appearance (smallest member)
