@@ -169,13 +169,14 @@ int gr_validate(const gr_graph* g, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * gr_colour_greedy — greedy colouring (the multicolour order that makes
- * Gauss-Seidel on L x = 0 reproducible, Sec. 3.2.1).  Nodes are ranked by
- * priority (h(v), v), h(v) = splitmix64 output v of `seed` — or by
- * (deg(v), h(v), v) when `largest_degree_first` — and each node takes the
- * smallest colour missing among its higher-priority neighbours (computed by
- * Jones-Plassmann rounds; the result equals the sequential greedy colouring
- * in decreasing priority).  Output: colours int32[n] (device), *n_colours
- * (HOST).  Synchronises.
+ * Gauss-Seidel on L x = 0 reproducible, Sec. 3.2.1), built in synchronous
+ * rounds from a snapshot: every uncoloured node proposes the smallest colour
+ * absent from its coloured neighbours and keeps it unless an uncoloured
+ * neighbour of higher priority proposes the same colour; kept proposals are
+ * committed together.  Priority is (h(v), v), h(v) = splitmix64 output v of
+ * `seed` — or (deg(v), h(v), v) when `largest_degree_first`.  Output:
+ * colours int32[n] (device), *n_colours (HOST).  Synchronises once per
+ * round.
  */
 int gr_colour_greedy(const gr_graph* g, uint64_t seed, int32_t largest_degree_first,
                      int32_t* colours, int32_t* n_colours, void* ws, size_t ws_bytes,
@@ -212,10 +213,11 @@ int gr_smooth(const gr_graph* g, const int32_t* colours, int32_t n_colours, int3
  * a float32[nnz] and dist float32[nnz] (either may be NULL), best int32[n]
  * = the neighbour minimising (d, index) — the largest affinity, ties to the
  * smaller index — or -1 without neighbours, dbest float32[n] its distance
- * (may be NULL).
+ * (may be NULL).  Synchronises once (to size the list of long rows).
  */
 int gr_affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, float* a,
-                float* dist, int32_t* best, float* dbest, void* stream);
+                float* dist, int32_t* best, float* dbest, void* ws, size_t ws_bytes,
+                void* stream);
 
 /*
  * gr_aggregate — strongest-affinity aggregation (Sec. 3.2.2: nodes with large

@@ -81,63 +81,92 @@ int or_validate_csr(int64_t n, const int32_t *row_ptr, const int32_t *col,
  * Reading taken: a multicolour order, colours 0..C-1 ascending in every
  * sweep, nodes of one colour mutually non-adjacent, so the result does not
  * depend on the order inside a colour.  When no colouring is prescribed the
- * colouring is greedy: nodes are visited in decreasing priority
- * (h(v), v), h(v) = splitmix64 output v for the colour seed (or
- * (deg(v), h(v), v) in largest-degree-first mode), and each node takes the
- * smallest colour absent from its already-coloured neighbours. */
-typedef struct { uint64_t a, b, c; int64_t v; } or_prio;
+ * colouring is greedy, built in synchronous rounds from a snapshot of the
+ * colours at the start of each round:
+ *   1. every uncoloured node proposes the smallest colour absent from its
+ *      coloured neighbours;
+ *   2. it keeps the proposal unless an uncoloured neighbour of higher
+ *      priority proposes the same colour;
+ *   3. kept proposals are committed together.
+ * Priority is (h(v), v), h(v) = splitmix64 output v for the colour seed, or
+ * (deg(v), h(v), v) in largest-degree-first mode.  The highest-priority
+ * uncoloured node always keeps its proposal, so every round makes progress;
+ * two adjacent proposals of one colour never both commit, so the colouring
+ * is proper; and each node's colour is the smallest absent among its
+ * neighbours coloured before it (first fit). */
+typedef struct { uint64_t a, b, c; } or_prio;
 
-static int prio_desc(const void *x, const void *y)
+static or_prio prio_of(const int32_t *row_ptr, int64_t v, uint64_t seed, int ldf)
 {
-    const or_prio *p = (const or_prio *)x, *q = (const or_prio *)y;
-    if (p->a != q->a) return p->a > q->a ? -1 : 1;
-    if (p->b != q->b) return p->b > q->b ? -1 : 1;
-    if (p->c != q->c) return p->c > q->c ? -1 : 1;
-    return 0;
+    or_prio p;
+    uint64_t h = or_splitmix64(seed, (uint64_t)v);
+    p.a = ldf ? (uint64_t)(row_ptr[v + 1] - row_ptr[v]) : h;
+    p.b = ldf ? h : 0;
+    p.c = (uint64_t)v;
+    return p;
+}
+
+static int prio_higher(or_prio x, or_prio y)
+{
+    if (x.a != y.a) return x.a > y.a;
+    if (x.b != y.b) return x.b > y.b;
+    return x.c > y.c;
 }
 
 int or_colour_greedy(int64_t n, const int32_t *row_ptr, const int32_t *col,
                      uint64_t seed, int32_t largest_degree_first,
                      int32_t *colours, int32_t *n_colours)
 {
-    or_prio *pr = (or_prio *)malloc(sizeof(or_prio) * (size_t)(n > 0 ? n : 1));
     int32_t maxdeg = 0;
     for (int64_t v = 0; v < n; ++v)
         if (row_ptr[v + 1] - row_ptr[v] > maxdeg) maxdeg = row_ptr[v + 1] - row_ptr[v];
+    int32_t *tent = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     uint8_t *used = (uint8_t *)calloc((size_t)maxdeg + 2, 1);
-    if (!pr || !used) { free(pr); free(used); return OR_ENOMEM; }
-    for (int64_t v = 0; v < n; ++v) {
-        uint64_t h = or_splitmix64(seed, (uint64_t)v);
-        if (largest_degree_first) {
-            pr[v].a = (uint64_t)(row_ptr[v + 1] - row_ptr[v]);
-            pr[v].b = h;
-        } else {
-            pr[v].a = h;
-            pr[v].b = 0;
+    if (!tent || !keep || !used) { free(tent); free(keep); free(used); return OR_ENOMEM; }
+    for (int64_t v = 0; v < n; ++v) colours[v] = -1;
+    int64_t left = n;
+    while (left > 0) {
+        /* 1. proposals from the snapshot */
+        for (int64_t v = 0; v < n; ++v) {
+            tent[v] = -1;
+            if (colours[v] >= 0) continue;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t c = colours[col[e]];
+                if (c >= 0 && c <= maxdeg) used[c] = 1;
+            }
+            int32_t c = 0;
+            while (used[c]) ++c;
+            tent[v] = c;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t cc = colours[col[e]];
+                if (cc >= 0 && cc <= maxdeg) used[cc] = 0;
+            }
         }
-        pr[v].c = (uint64_t)v;
-        pr[v].v = v;
-        colours[v] = -1;
+        /* 2. conflicts lost to higher-priority uncoloured neighbours */
+        for (int64_t v = 0; v < n; ++v) {
+            keep[v] = 0;
+            if (colours[v] >= 0) continue;
+            or_prio pv = prio_of(row_ptr, v, seed, largest_degree_first);
+            int k = 1;
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1] && k; ++e) {
+                int32_t u = col[e];
+                if (colours[u] < 0 && tent[u] == tent[v] &&
+                    prio_higher(prio_of(row_ptr, u, seed, largest_degree_first), pv))
+                    k = 0;
+            }
+            keep[v] = k;
+        }
+        /* 3. commit */
+        for (int64_t v = 0; v < n; ++v)
+            if (keep[v]) { colours[v] = tent[v]; --left; }
     }
-    qsort(pr, (size_t)n, sizeof(or_prio), prio_desc);
     int32_t nc = 0;
-    for (int64_t t = 0; t < n; ++t) {
-        int64_t v = pr[t].v;
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            int32_t c = colours[col[e]];
-            if (c >= 0 && c <= maxdeg) used[c] = 1;
-        }
-        int32_t c = 0;
-        while (used[c]) ++c;
-        colours[v] = c;
-        if (c + 1 > nc) nc = c + 1;
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            int32_t cc = colours[col[e]];
-            if (cc >= 0 && cc <= maxdeg) used[cc] = 0;
-        }
-    }
+    for (int64_t v = 0; v < n; ++v)
+        if (colours[v] + 1 > nc) nc = colours[v] + 1;
     *n_colours = nc;
-    free(pr);
+    free(tent);
+    free(keep);
     free(used);
     return OR_OK;
 }

@@ -48,7 +48,7 @@ static size_t plan_bytes(int64_t n, int64_t nnz, int32_t K, int32_t dtype) {
                         + vec_bytes(n, K, dtype) + 256         // X
                         + 4 * N * 4                            // best, abest, agg (two)
                         + 2 * (4 * N + 8 * M)                  // coarse ping-pong
-                        + (M / 32 + 1) * (24 + 4 * (size_t)(K + 4) + 4) + 12 * N;  // chunks
+                        + 4 * N;                               // long-row ids
     size_t relabel = 36 * N + 8 * 1024 + sort_scratch(N);
     size_t colour = 8 * N + 1024;
     size_t agg = 24 * N + 44 * N + sort_scratch(N);
@@ -154,7 +154,7 @@ int gr_colour_greedy(const gr_graph* g, uint64_t seed, int32_t ldf, int32_t* col
     GR_TRY(check_graph_args(g));
     if (!colours || !n_colours || !ws) return set_error(GR_EINVAL, "NULL output or workspace");
     Arena A(ws, ws_bytes);
-    return colour_jp(g, seed, ldf ? 1 : 0, colours, n_colours, A, S(stream));
+    return colour_greedy(g, seed, ldf ? 1 : 0, colours, n_colours, A, S(stream));
 }
 
 int gr_init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, void* X, void* ws,
@@ -181,7 +181,7 @@ int gr_smooth(const gr_graph* g, const int32_t* colours, int32_t n_colours, int3
     Arena A(ws, ws_bytes);
     GR_TRY(validate_colouring(g, colours, n_colours, A, st));
     OrderedGraph og;
-    GR_TRY(order_by_colour(g, colours, n_colours, K, dtype, &og, A, st));
+    GR_TRY(order_by_colour(g, colours, n_colours, &og, A, st));
     // permute X into colour-major rows, smooth, permute back
     size_t vb = vec_bytes(g->n, K, dtype);
     char* Xp = A.take<char>(vb);
@@ -193,14 +193,20 @@ int gr_smooth(const gr_graph* g, const int32_t* colours, int32_t n_colours, int3
 }
 
 int gr_affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, float* a,
-                float* dist, int32_t* best, float* dbest, void* stream) {
+                float* dist, int32_t* best, float* dbest, void* ws, size_t ws_bytes,
+                void* stream) {
     clear_error();
     GR_TRY(check_graph_args(g));
     GR_TRY(check_vec_args(K, dtype));
     if (g->n == 0) return GR_OK;
-    if (!X || !best) return set_error(GR_EINVAL, "NULL X or best");
+    if (!X || !best || !ws) return set_error(GR_EINVAL, "NULL X, best or workspace");
     GR_TRY(check_aligned(X, "X"));
-    return affinity(g, K, dtype, X, nullptr, a, dist, best, dbest, S(stream));
+    hipStream_t st = S(stream);
+    Arena A(ws, ws_bytes);
+    int32_t* long_rows = nullptr;
+    int64_t n_long = 0;
+    GR_TRY(find_long_rows(g, &long_rows, &n_long, A, st));
+    return affinity(g, K, dtype, X, nullptr, long_rows, n_long, a, dist, best, dbest, st);
 }
 
 int gr_aggregate(const gr_graph* g, const float* dist, int64_t target, int32_t* agg,
@@ -297,7 +303,7 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
             col_use = p.colours;
             nc = p.n_colours;
         } else {
-            GR_TRY(colour_jp(&cur, cseed, ldf, colours, &nc, A, st));
+            GR_TRY(colour_greedy(&cur, cseed, ldf, colours, &nc, A, st));
         }
         if (pr) prof::end(st, prof::COLOUR, 0.0, 1);
         if (level < 32) {
@@ -307,14 +313,15 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
         }
         OrderedGraph og;
         if (pr) prof::begin(st);
-        GR_TRY(order_by_colour(&cur, col_use, nc, p.K, p.vec_dtype, &og, A, st));
+        GR_TRY(order_by_colour(&cur, col_use, nc, &og, A, st));
         if (pr) prof::end(st, prof::RELABEL, 0.0, 1);
         if (pr) prof::begin(st);
         GR_TRY(init_vectors(cur.n, p.K, vseed, p.vec_dtype, og.perm, X, A, st));
         if (pr) prof::end(st, prof::INIT, (double)cur.n * p.K * xs + 4.0 * cur.n, 1);
         GR_TRY(smooth_ordered(&og, p.K, p.sweeps, p.vec_dtype, X, st));
         if (pr) prof::begin(st);
-        GR_TRY(affinity(&og.g, p.K, p.vec_dtype, X, og.perm, nullptr, nullptr, best, dbest, st));
+        GR_TRY(affinity(&og.g, p.K, p.vec_dtype, X, og.perm, og.long_rows, og.n_long, nullptr,
+                        nullptr, best, dbest, st));
         // compulsory bytes: CSR columns, each vector row once, ids, best + abest
         if (pr)
             prof::end(st, prof::AFFINITY,

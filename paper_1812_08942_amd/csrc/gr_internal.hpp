@@ -114,22 +114,15 @@ inline int bits_for(int64_t n) {  // bits needed to hold values in [0, n)
 
 // --------------------------------------------------------------- phase A
 int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st);
-int colour_jp(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
+int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
               int32_t* n_colours_host, Arena& ws, hipStream_t st);
 int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colours,
                        Arena& ws, hipStream_t st);
 
-// One chunk of a long row: entries [e0, e1) of `row`; the row's chunks are
-// first .. first+count-1 (self is this chunk's own index).
-struct ChunkDesc {
-    int32_t row, e0, e1, first, count, self;
-};
-
 // Colour-major relabel: new row r holds old node perm[r]; rows of colour c
 // are [class_ptr[c], class_ptr[c+1]), with the long rows (degree above the
-// split threshold) first: [class_ptr[c], long_end[c]).  Long rows are cut
-// into chunks (chunk_ptr[c] .. chunk_ptr[c+1]) for the smoothing kernel.
-// Host copies of the boundaries are kept for launch planning.
+// long-row threshold) first: [class_ptr[c], long_end[c]).  Host copies of
+// the boundaries are kept for launch planning.
 struct OrderedGraph {
     gr_graph g;          // relabelled CSR (device pointers into the arena)
     int32_t* perm;       // [n] new -> old
@@ -139,16 +132,12 @@ struct OrderedGraph {
     std::vector<int64_t> long_end_h;    // host [C]
     std::vector<int64_t> class_nnz_h;   // host [C]: stored entries per colour
     std::vector<int64_t> normal_nnz_h;  // host [C]: entries of the normal rows
-    std::vector<int64_t> chunk_ptr_h;   // host [C+1]
-    int64_t n_chunks;
-    int32_t chunk_entries;
-    ChunkDesc* chunks;   // device [n_chunks]
-    float* partial;      // device [n_chunks][K+4]
-    int32_t* counter;    // device [n_chunks] (tickets, indexed by a row's first chunk)
+    int64_t n_long;      // long rows in all classes
+    int32_t* long_rows;  // device [n_long]: their relabelled ids
     double mean_deg;
 };
-int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours, int32_t K,
-                    int32_t dtype, OrderedGraph* out, Arena& ws, hipStream_t st);
+int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours,
+                    OrderedGraph* out, Arena& ws, hipStream_t st);
 
 // dst[r] = src[perm[r]] (inverse = 0) or dst[perm[r]] = src[r] (inverse = 1),
 // rows of row_bytes (a multiple of 16) bytes.
@@ -160,9 +149,14 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
 int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dtype,
                    void* X, hipStream_t st);
 // a (affinity) and dist (algebraic distance d = 1 - a) per entry are
-// optional; best = argmin (d, id) per row, dbest its distance.
+// optional; best = argmin (d, id) per row, dbest its distance.  Rows of
+// degree above the long-row threshold are listed in long_rows (n_long of
+// them) and handled by a workgroup each.
 int affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, const int32_t* ids,
-             float* a, float* dist, int32_t* best, float* dbest, hipStream_t st);
+             const int32_t* long_rows, int64_t n_long, float* a, float* dist, int32_t* best,
+             float* dbest, hipStream_t st);
+// rows of degree above the long-row threshold, in increasing order
+int find_long_rows(const gr_graph* g, int32_t** rows, int64_t* n_long, Arena& ws, hipStream_t st);
 
 // ---------------------------------------------------- aggregation / RAP
 int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const int32_t* ids,

@@ -12,7 +12,7 @@
 
 namespace gr {
 
-constexpr int kLongRow = 128;     // rows above this degree are split into chunks
+constexpr int kLongRow = 128;     // rows above this degree get a workgroup each
 constexpr int kThreads = 256;
 
 // ------------------------------------------------------------- validation
@@ -79,8 +79,13 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 }
 
 // -------------------------------------------------------------- colouring
-// Priority of node v: (deg(v) if largest-degree-first, h(v), v) compared
-// lexicographically, h(v) = splitmix64 output v of the colour seed.
+// Greedy colouring in synchronous rounds from a snapshot of the colours:
+// (1) every uncoloured node proposes the smallest colour absent from its
+// coloured neighbours; (2) it keeps the proposal unless an uncoloured
+// neighbour of higher priority proposes the same colour; (3) kept proposals
+// are committed together.  Priority: (h(v), v), h(v) = splitmix64 output v of
+// the colour seed, or (deg(v), h(v), v) largest-degree-first.  Proposals and
+// conflicts use one wave per node, so hub rows cost deg/64 steps.
 struct Prio {
     uint32_t deg;
     uint64_t h;
@@ -99,73 +104,79 @@ __device__ inline bool higher(const Prio& a, const Prio& b) {
     return a.v > b.v;
 }
 
-// One Jones-Plassmann round over the worklist in[0 .. *nin): a node all of
-// whose uncoloured neighbours have lower priority takes the smallest colour
-// missing among its (necessarily higher-priority) coloured neighbours; the
-// others go to `out`.  Each colour word is written once (from -1 to its final
-// value), so a plain load returns either -1 or the final colour; a stale -1
-// only postpones a node to a later round.  cursor[v] remembers where the
-// readiness scan of v stopped: entries before it are coloured or of lower
-// priority for good, so every row is scanned O(1) times in total.
-// Counters rotate over three slots: this round reads cnt[k % 3], appends to
-// cnt[(k+1) % 3] and clears cnt[(k+2) % 3] (read by the previous round).
-__global__ void k_jp_round(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           uint64_t seed, int ldf, int32_t* colours, int32_t* __restrict__ cursor,
-                           const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                           int32_t* __restrict__ cnt, int k) {
-    const int32_t nin = cnt[k % 3];
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) cnt[(k + 2) % 3] = 0;
-    if (t >= nin) return;
-    const int32_t v = in[t];
-    const Prio pv = prio_of(rp, v, seed, ldf);
-    const int32_t e1 = rp[v + 1];
-    for (int32_t e = cursor[v]; e < e1; ++e) {
-        int32_t j = col[e];
-        if (colours[j] < 0 && higher(prio_of(rp, j, seed, ldf), pv)) {
-            cursor[v] = e;
-            out[atomicAdd(&cnt[(k + 1) % 3], 1)] = v;
-            return;
-        }
+__device__ inline uint64_t wave_or(uint64_t x) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t lo = __shfl_xor((uint32_t)x, off, kWave);
+        uint32_t hi = __shfl_xor((uint32_t)(x >> 32), off, kWave);
+        x |= ((uint64_t)hi << 32) | lo;
     }
-    // ready: smallest colour missing among the neighbours, by windows of 256.
-    // A higher-priority neighbour read as uncoloured here (never expected,
-    // since it was read as coloured above) defers v instead of guessing.
-    const int32_t e0 = rp[v];
+    return x;
+}
+
+__global__ void __launch_bounds__(kThreads) k_col_propose(const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const int32_t* __restrict__ colours,
+                                                          const int32_t* __restrict__ work,
+                                                          int32_t nwork, int32_t* __restrict__ tent) {
+    const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (t >= nwork) return;  // whole waves leave together
+    const int32_t v = work[t];
+    const int32_t e0 = rp[v], e1 = rp[v + 1];
     int32_t c = -1;
     for (int32_t base = 0; c < 0; base += 256) {
         uint64_t used[4] = {0, 0, 0, 0};
-        for (int32_t e = e0; e < e1; ++e) {
-            int32_t j = col[e];
-            int32_t cj = colours[j];
-            if (cj < 0) {
-                if (higher(prio_of(rp, j, seed, ldf), pv)) {
-                    cursor[v] = e0;
-                    out[atomicAdd(&cnt[(k + 1) % 3], 1)] = v;
-                    return;
-                }
-            } else if (cj >= base && cj < base + 256) {
-                used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
-            }
+        for (int32_t e = e0 + lane; e < e1; e += kWave) {
+            int32_t cj = colours[col[e]];
+            if (cj >= base && cj < base + 256) used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
         }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
         for (int w = 0; w < 4 && c < 0; ++w)
             if (~used[w]) c = base + w * 64 + __ffsll((unsigned long long)~used[w]) - 1;
     }
-    colours[v] = c;
+    if (lane == 0) tent[v] = c;
 }
 
-__global__ void k_jp_init(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ colours,
-                          int32_t* __restrict__ cursor, int32_t* __restrict__ work,
-                          int32_t* __restrict__ cnt) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0) {
-        cnt[0] = (int32_t)n;
-        cnt[1] = 0;
-        cnt[2] = 0;
+__global__ void __launch_bounds__(kThreads) k_col_resolve(const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const int32_t* __restrict__ colours,
+                                                          const int32_t* __restrict__ tent,
+                                                          const int32_t* __restrict__ work,
+                                                          int32_t nwork, uint64_t seed, int ldf,
+                                                          int32_t* __restrict__ newc) {
+    const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (t >= nwork) return;
+    const int32_t v = work[t];
+    const int32_t e0 = rp[v], e1 = rp[v + 1];
+    const int32_t tv = tent[v];
+    const Prio pv = prio_of(rp, v, seed, ldf);
+    bool lose = false;
+    for (int32_t e = e0 + lane; e < e1 && !lose; e += kWave) {
+        int32_t u = col[e];
+        if (colours[u] < 0 && tent[u] == tv && higher(prio_of(rp, u, seed, ldf), pv)) lose = true;
     }
+    uint64_t any = __ballot(lose);
+    if (lane == 0) newc[v] = any ? -1 : tv;
+}
+
+__global__ void k_col_commit(const int32_t* __restrict__ work, int32_t nwork,
+                             const int32_t* __restrict__ newc, int32_t* __restrict__ colours,
+                             int32_t* __restrict__ next, int32_t* __restrict__ cnt) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nwork) return;
+    const int32_t v = work[t];
+    const int32_t c = newc[v];
+    if (c >= 0) colours[v] = c;
+    else next[atomicAdd(cnt, 1)] = v;
+}
+
+__global__ void k_col_init(int64_t n, int32_t* __restrict__ colours, int32_t* __restrict__ work) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     colours[v] = -1;
-    cursor[v] = rp[v];
     work[v] = (int32_t)v;
 }
 
@@ -178,36 +189,40 @@ __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out
     if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
 }
 
-int colour_jp(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours, int32_t* n_colours_host,
-              Arena& ws, hipStream_t st) {
+int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
+                  int32_t* n_colours_host, Arena& ws, hipStream_t st) {
     const int64_t n = g->n;
     *n_colours_host = 0;
     if (n == 0) return GR_OK;
     size_t mark = ws.used;
     int32_t* wk[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
-    int32_t* cursor = ws.take<int32_t>(n);
+    int32_t* tent = ws.take<int32_t>(n);
+    int32_t* newc = ws.take<int32_t>(n);
     int32_t* cnt = ws.take<int32_t>(4);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
-    hipLaunchKernelGGL(k_jp_init, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, g->row_ptr,
-                       n, colours, cursor, wk[0], cnt);
-    GR_LAUNCHED("jp init");
-    // rounds in batches; the grid of a batch is sized by the last count read
-    // back (worklists only shrink), the kernels read the exact count
-    const int kBatch = 8;
+    hipLaunchKernelGGL(k_col_init, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, colours,
+                       wk[0]);
+    GR_LAUNCHED("colour init");
     int32_t left = (int32_t)n;
-    int64_t k = 0;
-    while (left > 0) {
-        if (k > n + kBatch) return set_error(GR_EHIP, "colouring did not converge");
-        for (int b = 0; b < kBatch; ++b, ++k) {
-            hipLaunchKernelGGL(k_jp_round, dim3(blocks_for(left, kThreads)), dim3(kThreads), 0, st,
-                               g->row_ptr, g->col, seed, ldf, colours, cursor, wk[k & 1],
-                               wk[(k + 1) & 1], cnt, (int)(k % 3));
-            GR_LAUNCHED("jp round");
-        }
+    for (int64_t round = 0; left > 0; ++round) {
+        if (round > n) return set_error(GR_EHIP, "colouring did not converge");
+        int32_t* in = wk[round & 1];
+        int32_t* out = wk[(round + 1) & 1];
+        const unsigned wb = blocks_for((int64_t)left * kWave, kThreads);
+        hipLaunchKernelGGL(k_col_propose, dim3(wb), dim3(kThreads), 0, st, g->row_ptr, g->col,
+                           colours, in, left, tent);
+        GR_LAUNCHED("colour propose");
+        hipLaunchKernelGGL(k_col_resolve, dim3(wb), dim3(kThreads), 0, st, g->row_ptr, g->col,
+                           colours, tent, in, left, seed, ldf, newc);
+        GR_LAUNCHED("colour resolve");
+        GR_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_col_commit, dim3(blocks_for(left, kThreads)), dim3(kThreads), 0, st, in,
+                           left, newc, colours, out, cnt);
+        GR_LAUNCHED("colour commit");
         int32_t now = 0;
-        GR_HIP(hipMemcpyAsync(&now, cnt + (k % 3), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipMemcpyAsync(&now, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
-        if (now >= left && now > 0) return set_error(GR_EHIP, "colouring made no progress");
+        if (now >= left) return set_error(GR_EHIP, "colouring made no progress");
         left = now;
     }
     GR_HIP(hipMemsetAsync(cnt + 3, 0xff, sizeof(int32_t), st));
@@ -257,8 +272,8 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
 // ------------------------------------------------------- colour-major order
 // Rows are relabelled by the key (colour, long?0:1, old id): the rows of one
 // colour become a contiguous range with the long rows (degree > kLongRow)
-// first.  Long rows are later split into chunks handled by one workgroup
-// each, so a hub's latency no longer bounds a whole colour step.
+// first.  Long rows get a whole workgroup each in the smoothing and affinity
+// kernels, so a hub's latency does not bound a whole colour step.
 __global__ void k_bucket_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ colours,
                               int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -315,6 +330,11 @@ __global__ void k_bucket_sizes(const int32_t* __restrict__ bfirst, const int32_t
     out[2 * b + 1] = f >= 0 ? (int64_t)(nrp[e] - nrp[f]) : 0;
 }
 
+__global__ void k_long_ids(const int32_t* __restrict__ lrows, int64_t nlong, int32_t* __restrict__ ids) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nlong) ids[i] = lrows[3 * i];
+}
+
 // long rows of the relabelled graph, compacted: their row ids and extents
 __global__ void k_long_rows(const int32_t* __restrict__ nrp, const int32_t* __restrict__ bfirst,
                             const int32_t* __restrict__ bend, int32_t n_colours,
@@ -331,13 +351,10 @@ __global__ void k_long_rows(const int32_t* __restrict__ nrp, const int32_t* __re
     }
 }
 
-int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours, int32_t K,
-                    int32_t dtype, OrderedGraph* og, Arena& ws, hipStream_t st) {
+int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours, OrderedGraph* og,
+                    Arena& ws, hipStream_t st) {
     const int64_t n = g->n, nnz = g->nnz;
-    const int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
-    const int CH = 1024 / Q;  // entries per chunk of a long row
     og->n_colours = n_colours;
-    og->chunk_entries = CH;
     og->perm = ws.take<int32_t>(n);
     og->iperm = ws.take<int32_t>(n);
     int32_t* nrp = ws.take<int32_t>(n + 1);
@@ -404,47 +421,26 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
     long_off[n_colours] = (int32_t)nlong;
     og->class_ptr_h[n_colours] = total;
     if (total != n) return set_error(GR_ECOLOUR, "colouring does not cover every node");
-    // chunk table of the long rows: (row, e0, e1, first chunk of the row, chunks of the row)
-    og->chunk_ptr_h.assign((size_t)n_colours + 1, 0);
-    og->n_chunks = 0;
-    og->chunks = nullptr;
-    og->partial = nullptr;
-    og->counter = nullptr;
+    // device list of the long rows (relabelled ids), class by class
+    og->n_long = nlong;
+    og->long_rows = nullptr;
     if (nlong > 0) {
         int32_t* loff = ws.take<int32_t>(n_colours + 1);
         int32_t* lrows = ws.take<int32_t>(3 * nlong);
         if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
-        GR_HIP(hipMemcpy(loff, long_off.data(), sizeof(int32_t) * (n_colours + 1),
-                         hipMemcpyHostToDevice));
+        GR_HIP(hipMemcpyAsync(loff, long_off.data(), sizeof(int32_t) * (n_colours + 1),
+                              hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_long_rows, dim3(8, n_colours), dim3(kThreads), 0, st, nrp, bfirst, bend,
                            n_colours, loff, lrows);
         GR_LAUNCHED("long rows");
-        std::vector<int32_t> hl(3 * (size_t)nlong);
-        GR_HIP(hipMemcpyAsync(hl.data(), lrows, sizeof(int32_t) * 3 * nlong, hipMemcpyDeviceToHost,
-                              st));
-        GR_HIP(hipStreamSynchronize(st));
-        std::vector<ChunkDesc> tab;
-        for (int c = 0; c < n_colours; ++c) {
-            og->chunk_ptr_h[c] = (int64_t)tab.size();
-            for (int32_t t = long_off[c]; t < long_off[c + 1]; ++t) {
-                int32_t r = hl[3 * t], e0 = hl[3 * t + 1], e1 = hl[3 * t + 2];
-                int32_t cnt = (e1 - e0 + CH - 1) / CH;
-                int32_t first = (int32_t)tab.size();
-                for (int32_t k = 0; k < cnt; ++k)
-                    tab.push_back(ChunkDesc{r, e0 + k * CH, min(e1, e0 + (k + 1) * CH), first, cnt,
-                                            first + k});
-            }
-        }
-        og->chunk_ptr_h[n_colours] = (int64_t)tab.size();
-        og->n_chunks = (int64_t)tab.size();
-        ws.used = mark;  // the temporaries above are dead; the chunk data persists
-        og->chunks = ws.take<ChunkDesc>(og->n_chunks);
-        og->partial = ws.take<float>(og->n_chunks * (size_t)(K + 4));
-        og->counter = ws.take<int32_t>(og->n_chunks);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (chunks)");
-        GR_HIP(hipMemcpy(og->chunks, tab.data(), sizeof(ChunkDesc) * tab.size(),
-                         hipMemcpyHostToDevice));
-        GR_HIP(hipMemsetAsync(og->counter, 0, sizeof(int32_t) * og->n_chunks, st));
+        // keep only the ids, at the front of the persistent region
+        ws.used = mark;
+        og->long_rows = ws.take<int32_t>(nlong);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
+        hipLaunchKernelGGL(k_long_ids, dim3(blocks_for(nlong, kThreads)), dim3(kThreads), 0, st,
+                           (const int32_t*)lrows, nlong, og->long_rows);
+        GR_LAUNCHED("long ids");
+        GR_HIP(hipStreamSynchronize(st));  // lrows lies in memory released below
         mark = ws.used;
     }
     og->g.n = n;
@@ -588,15 +584,15 @@ template <> struct Chunk<GR_BF16> {
 
 // ----------------------------------------------------------- GS colour step
 // One Gauss-Seidel colour step (Sec. 3.2.1): every node v of the colour with
-// d_v > 0 becomes sum_j w_vj x_j / d_v.  One launch per step; block roles:
-//  * blocks [0, n_chunks): one chunk (<= CH entries) of a long row each.  The
-//    block writes its partial sums (K values and the weight sum) and takes a
-//    ticket; the block that draws the last ticket of the row adds the
-//    partials in chunk order (a fixed order) and stores the row.  Nothing
-//    waits, so no block can stall another.
-//  * the remaining blocks: normal rows, L = Q*P lanes per row, U = 4
+// d_v > 0 becomes sum_j w_vj x_j / d_v.  One launch of kBig-thread blocks per
+// step; block roles:
+//  * blocks [0, n_long): one long row each (degree > kLongRow); P = kBig/Q
+//    neighbour slots, four neighbours per slot per round, partial sums
+//    combined by a fixed shuffle tree and then across waves in LDS;
+//  * the remaining blocks: normal rows, L = Q*P lanes per row, four
 //    neighbours per lane per round so that four gathers are in flight.
 constexpr int kU = 4;
+constexpr int kBig = 1024;
 
 template <int Q, int P, int DT>
 __device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -608,7 +604,7 @@ __device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int3
     const int lane = threadIdx.x & (kWave - 1);
     const int l = lane % L;
     const int p = l / Q, q = l % Q;
-    const int64_t wave = (rblock * kThreads + threadIdx.x) / kWave;
+    const int64_t wave = (rblock * kBig + threadIdx.x) / kWave;
     const int64_t r = r_lo + wave * RPW + lane / L;
     if (r >= r_hi) return;  // whole row-groups leave together
     const int32_t e0 = rp[r], e1 = rp[r + 1];
@@ -651,30 +647,30 @@ __device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int3
 }
 
 template <int Q, int DT>
-__device__ inline void gs_long_chunk(const int32_t* __restrict__ col, const float* __restrict__ w,
-                                     void* __restrict__ X, int32_t K, const ChunkDesc& cd,
-                                     float* __restrict__ partial, int32_t* __restrict__ counter) {
+__device__ inline void gs_long_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                   const float* __restrict__ w, void* __restrict__ X, int32_t K,
+                                   int64_t r) {
     constexpr int E = Chunk<DT>::E;
-    constexpr int P = kThreads / Q;
-    constexpr int NW = kThreads / kWave;
+    constexpr int P = kBig / Q;
+    constexpr int NW = kBig / kWave;
     __shared__ float sacc[NW][Q][E];
     __shared__ float sd[NW];
-    __shared__ int last;
     const int t = threadIdx.x;
     const int p = t / Q, q = t % Q;
+    const int32_t e0 = rp[r], e1 = rp[r + 1];
     float acc[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] = 0.0f;
     float d = 0.0f;
-    {
+    for (int32_t e = e0 + p; e < e1; e += kU * P) {
         int32_t j[kU];
         float wt[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            int32_t e = cd.e0 + p + u * P;
-            bool ok = e < cd.e1;
-            j[u] = ok ? col[e] : cd.row;
-            wt[u] = ok ? w[e] : 0.0f;
+            int32_t eu = e + u * P;
+            bool ok = eu < e1;
+            j[u] = ok ? col[eu] : (int32_t)r;
+            wt[u] = ok ? w[eu] : 0.0f;
         }
         float x[kU][E];
 #pragma unroll
@@ -699,89 +695,49 @@ __device__ inline void gs_long_chunk(const int32_t* __restrict__ col, const floa
         if (lane == 0) sd[wid] = d;
     }
     __syncthreads();
-    float* mine = partial + (size_t)cd.self * (K + 4);
     if (t < Q) {
         float y[E];
+        float dd = 0.0f;
 #pragma unroll
         for (int i = 0; i < E; ++i) y[i] = 0.0f;
-        for (int ww = 0; ww < NW; ++ww)
+        for (int ww = 0; ww < NW; ++ww) {
 #pragma unroll
             for (int i = 0; i < E; ++i) y[i] += sacc[ww][t][i];
-#pragma unroll
-        for (int i = 0; i < E; ++i) mine[t * E + i] = y[i];
-    }
-    if (t == 0) {
-        float dd = 0.0f;
-        for (int ww = 0; ww < NW; ++ww) dd += sd[ww];
-        mine[K] = dd;
-    }
-    // publish the partial, then take a ticket; the last block of the row
-    // reduces the partials of all its chunks in chunk order
-    __threadfence();
-    __syncthreads();
-    if (t == 0) {
-        int prev = atomicAdd(&counter[cd.first], 1);
-        last = (prev == cd.count - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (t < Q) {
-        float y[E];
-        float dd = 0.0f;
-#pragma unroll
-        for (int i = 0; i < E; ++i) y[i] = 0.0f;
-        for (int32_t k = 0; k < cd.count; ++k) {
-            const float* pk = partial + (size_t)(cd.first + k) * (K + 4);
-#pragma unroll
-            for (int i = 0; i < E; ++i) y[i] += __builtin_nontemporal_load(pk + t * E + i);
-            dd += __builtin_nontemporal_load(pk + K);
+            dd += sd[ww];
         }
         if (dd > 0.0f) {
 #pragma unroll
             for (int i = 0; i < E; ++i) y[i] = y[i] / dd;
-            Chunk<DT>::store(X, cd.row, K, t, y);
+            Chunk<DT>::store(X, r, K, t, y);
         }
     }
-    if (t == 0) counter[cd.first] = 0;  // ready for the next step over this colour
 }
 
 template <int Q, int P, int DT>
-__global__ void __launch_bounds__(kThreads) k_gs_step(const int32_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ col,
-                                                      const float* __restrict__ w,
-                                                      void* __restrict__ X, int32_t K,
-                                                      const ChunkDesc* __restrict__ chunks,
-                                                      int64_t c_lo, int64_t n_chunks,
-                                                      float* __restrict__ partial,
-                                                      int32_t* __restrict__ counter, int64_t r_lo,
-                                                      int64_t r_hi) {
+__global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const float* __restrict__ w,
+                                                  void* __restrict__ X, int32_t K, int64_t lo,
+                                                  int64_t n_long, int64_t hi) {
     const int64_t b = blockIdx.x;
-    if (b < n_chunks) {
-        ChunkDesc cd = chunks[c_lo + b];
-        gs_long_chunk<Q, DT>(col, w, X, K, cd, partial, counter);
-    } else {
-        gs_normal_rows<Q, P, DT>(rp, col, w, X, K, r_lo, r_hi, b - n_chunks);
-    }
+    if (b < n_long) gs_long_row<Q, DT>(rp, col, w, X, K, lo + b);
+    else gs_normal_rows<Q, P, DT>(rp, col, w, X, K, lo + n_long, hi, b - n_long);
 }
 
 template <int Q, int DT>
 static int launch_gs_step(int P, const OrderedGraph* og, void* X, int K, int c, hipStream_t st) {
     const int64_t lo = og->class_ptr_h[c], le = og->long_end_h[c], hi = og->class_ptr_h[c + 1];
-    const int64_t c_lo = og->chunk_ptr_h[c], nch = og->chunk_ptr_h[c + 1] - c_lo;
-    (void)lo;
-    const int64_t rows = hi - le;
+    const int64_t nlong = le - lo, rows = hi - le;
     const int L = Q * P;
     const int64_t waves = (rows * L + kWave - 1) / kWave;
-    const int64_t rblocks = rows > 0 ? (waves * kWave + kThreads - 1) / kThreads : 0;
-    const int64_t grid = nch + rblocks;
+    const int64_t rblocks = rows > 0 ? (waves * kWave + kBig - 1) / kBig : 0;
+    const int64_t grid = nlong + rblocks;
     if (grid == 0) return GR_OK;
 #define GR_GS(PP)                                                                               \
     case PP:                                                                                   \
         if constexpr (Q * PP <= kWave)                                                         \
-            hipLaunchKernelGGL((k_gs_step<Q, PP, DT>), dim3((unsigned)grid), dim3(kThreads), 0, \
-                               st, og->g.row_ptr, og->g.col, og->g.w, X, K, og->chunks, c_lo,    \
-                               nch, og->partial, og->counter, le, hi);                          \
+            hipLaunchKernelGGL((k_gs_step<Q, PP, DT>), dim3((unsigned)grid), dim3(kBig), 0, st,  \
+                               og->g.row_ptr, og->g.col, og->g.w, X, K, lo, nlong, hi);         \
         break;
     switch (P) {
         GR_GS(1) GR_GS(2) GR_GS(4) GR_GS(8) GR_GS(16) GR_GS(32) GR_GS(64)
@@ -832,8 +788,6 @@ int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dt
     if (og->g.n == 0 || sweeps == 0) return GR_OK;
     int bytes = K * (dtype == GR_BF16 ? 2 : 4);
     int Q = bytes / 16;
-    if (og->n_chunks > 0 && og->chunk_entries != 1024 / Q)
-        return set_error(GR_EINVAL, "graph ordered for a different vector width");
     if (dtype == GR_BF16) {
         switch (Q) {
             case 1: return smooth_q<1, GR_BF16>(og, K, sweeps, X, st);
@@ -881,31 +835,65 @@ __device__ inline bool closer(float d1, int32_t id1, float d2, int32_t id2) {
 // (equal to 1 - cos^2 in exact arithmetic), so that it keeps its relative
 // accuracy where a itself rounds to 1 in float32.  Both quantities are
 // computed by the same code for (v, j) and (j, v), hence bit-symmetric.
+// Distance, affinity and the row-group's candidate for one entry (v, j):
+// chunk q of the normalised rows, reduced over the Q lanes of the entry with
+// a fixed tree, so (v, j) and (j, v) give identical bits.
+template <int Q, int DT>
+__device__ inline void entry_ad(const void* __restrict__ X, int32_t K, int q, const float* xv,
+                                const float* uv, float nv, int32_t j, float* av, float* dv) {
+    constexpr int E = Chunk<DT>::E;
+    float xj[E];
+    Chunk<DT>::load(X, j, K, q, xj);
+    float c = qsum<Q>(chunk_dot<E>(xv, xj));
+    float nj = qsum<Q>(chunk_dot<E>(xj, xj));
+    float sj = sqrtf(nj);
+    float dm = 0.0f, dp = 0.0f;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        float uj = nj > 0.0f ? xj[i] / sj : 0.0f;
+        float m = uv[i] - uj, s2 = uv[i] + uj;
+        dm = __fmaf_rn(m, m, dm);
+        dp = __fmaf_rn(s2, s2, dp);
+    }
+    dm = qsum<Q>(dm);
+    dp = qsum<Q>(dp);
+    float den = nv * nj;
+    *av = den == 0.0f ? 0.0f : fminf(1.0f, (c * c) / den);
+    *dv = den == 0.0f ? 1.0f : fminf(1.0f, dm * dp * 0.25f);
+}
+
+template <int Q, int DT>
+__device__ inline void row_prep(const void* __restrict__ X, int32_t K, int q, int64_t r, float* xv,
+                                float* uv, float* nv_out) {
+    constexpr int E = Chunk<DT>::E;
+    Chunk<DT>::load(X, r, K, q, xv);
+    const float nv = qsum<Q>(chunk_dot<E>(xv, xv));
+    const float sv = sqrtf(nv);
+#pragma unroll
+    for (int i = 0; i < E; ++i) uv[i] = nv > 0.0f ? xv[i] / sv : 0.0f;
+    *nv_out = nv;
+}
+
+// Rows with degree <= kLongRow: L = Q*P lanes per row.
 template <int Q, int P, int DT>
-__global__ void __launch_bounds__(kThreads) k_affinity(const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col,
-                                                       const void* __restrict__ X, int32_t K,
-                                                       int64_t n, const int32_t* __restrict__ ids,
-                                                       float* __restrict__ a,
-                                                       float* __restrict__ dist,
-                                                       int32_t* __restrict__ best,
-                                                       float* __restrict__ dbest) {
+__device__ inline void aff_normal(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                  const void* __restrict__ X, int32_t K, int64_t n,
+                                  const int32_t* __restrict__ ids, float* __restrict__ a,
+                                  float* __restrict__ dist, int32_t* __restrict__ best,
+                                  float* __restrict__ dbest, int64_t rblock) {
     constexpr int L = Q * P;
     constexpr int RPW = kWave / L;
     constexpr int E = Chunk<DT>::E;
     const int lane = threadIdx.x & (kWave - 1);
     const int l = lane % L;
     const int p = l / Q, q = l % Q;
-    const int64_t wave = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+    const int64_t wave = (rblock * kBig + threadIdx.x) / kWave;
     const int64_t r = wave * RPW + lane / L;
     if (r >= n) return;
-    float xv[E], uv[E];
-    Chunk<DT>::load(X, r, K, q, xv);
-    const float nv = qsum<Q>(chunk_dot<E>(xv, xv));
-    const float sv = sqrtf(nv);
-#pragma unroll
-    for (int i = 0; i < E; ++i) uv[i] = nv > 0.0f ? xv[i] / sv : 0.0f;
     const int32_t e0 = rp[r], e1 = rp[r + 1];
+    if (e1 - e0 > kLongRow) return;  // handled by a whole workgroup
+    float xv[E], uv[E], nv;
+    row_prep<Q, DT>(X, K, q, r, xv, uv, &nv);
     float bd = 2.0f;
     int32_t bj = -1, bid = 0x7fffffff;
     // every lane of the row-group runs the same trip count so the q-sums
@@ -915,24 +903,8 @@ __global__ void __launch_bounds__(kThreads) k_affinity(const int32_t* __restrict
         int32_t e = e0 + p + t * P;
         bool ok = e < e1;
         int32_t j = ok ? col[e] : (int32_t)r;
-        float xj[E];
-        Chunk<DT>::load(X, j, K, q, xj);
-        float c = qsum<Q>(chunk_dot<E>(xv, xj));
-        float nj = qsum<Q>(chunk_dot<E>(xj, xj));
-        float sj = sqrtf(nj);
-        float dm = 0.0f, dp = 0.0f;
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            float uj = nj > 0.0f ? xj[i] / sj : 0.0f;
-            float m = uv[i] - uj, s2 = uv[i] + uj;
-            dm = __fmaf_rn(m, m, dm);
-            dp = __fmaf_rn(s2, s2, dp);
-        }
-        dm = qsum<Q>(dm);
-        dp = qsum<Q>(dp);
-        float den = nv * nj;
-        float av = den == 0.0f ? 0.0f : fminf(1.0f, (c * c) / den);
-        float dv = den == 0.0f ? 1.0f : fminf(1.0f, dm * dp * 0.25f);
+        float av, dv;
+        entry_ad<Q, DT>(X, K, q, xv, uv, nv, j, &av, &dv);
         if (ok) {
             if (q == 0) {
                 if (a) a[e] = av;
@@ -942,7 +914,6 @@ __global__ void __launch_bounds__(kThreads) k_affinity(const int32_t* __restrict
             if (closer(dv, jid, bd, bid)) { bd = dv; bj = j; bid = jid; }
         }
     }
-    // combine the P candidates of the row-group (ties: smaller id)
 #pragma unroll
     for (int off = Q; off < L; off <<= 1) {
         float od = __shfl_xor(bd, off, kWave);
@@ -956,19 +927,97 @@ __global__ void __launch_bounds__(kThreads) k_affinity(const int32_t* __restrict
     }
 }
 
+// A long row: the whole workgroup, P = kBig/Q entries at a time.
 template <int Q, int DT>
-static int launch_aff(const gr_graph* g, int K, const void* X, const int32_t* ids, float* a,
-                      float* dist, int32_t* best, float* dbest, hipStream_t st) {
-    int P = 1;
+__device__ inline void aff_long(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const void* __restrict__ X, int32_t K, int64_t r,
+                                const int32_t* __restrict__ ids, float* __restrict__ a,
+                                float* __restrict__ dist, int32_t* __restrict__ best,
+                                float* __restrict__ dbest) {
+    constexpr int E = Chunk<DT>::E;
+    constexpr int P = kBig / Q;
+    constexpr int NW = kBig / kWave;
+    __shared__ float sbd[NW];
+    __shared__ int32_t sbj[NW], sbid[NW];
+    const int t = threadIdx.x;
+    const int p = t / Q, q = t % Q;
+    float xv[E], uv[E], nv;
+    row_prep<Q, DT>(X, K, q, r, xv, uv, &nv);
+    const int32_t e0 = rp[r], e1 = rp[r + 1];
+    float bd = 2.0f;
+    int32_t bj = -1, bid = 0x7fffffff;
+    const int32_t trips = (e1 - e0 + P - 1) / P;
+    for (int32_t it = 0; it < trips; ++it) {
+        int32_t e = e0 + p + it * P;
+        bool ok = e < e1;
+        int32_t j = ok ? col[e] : (int32_t)r;
+        float av, dv;
+        entry_ad<Q, DT>(X, K, q, xv, uv, nv, j, &av, &dv);
+        if (ok) {
+            if (q == 0) {
+                if (a) a[e] = av;
+                if (dist) dist[e] = dv;
+            }
+            int32_t jid = ids ? ids[j] : j;
+            if (closer(dv, jid, bd, bid)) { bd = dv; bj = j; bid = jid; }
+        }
+    }
+#pragma unroll
+    for (int off = Q; off < kWave; off <<= 1) {
+        float od = __shfl_xor(bd, off, kWave);
+        int32_t oj = __shfl_xor(bj, off, kWave);
+        int32_t oid = __shfl_xor(bid, off, kWave);
+        if (oj >= 0 && (bj < 0 || closer(od, oid, bd, bid))) { bd = od; bj = oj; bid = oid; }
+    }
+    const int wid = t / kWave, lane = t & (kWave - 1);
+    if (lane == 0) {
+        sbd[wid] = bd;
+        sbj[wid] = bj;
+        sbid[wid] = bid;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < NW; ++w)
+            if (sbj[w] >= 0 && (bj < 0 || closer(sbd[w], sbid[w], bd, bid))) {
+                bd = sbd[w];
+                bj = sbj[w];
+                bid = sbid[w];
+            }
+        best[r] = bj;
+        if (dbest) dbest[r] = bj >= 0 ? bd : 1.0f;
+    }
+}
+
+template <int Q, int P, int DT>
+__global__ void __launch_bounds__(kBig) k_affinity(const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col,
+                                                   const void* __restrict__ X, int32_t K, int64_t n,
+                                                   const int32_t* __restrict__ ids,
+                                                   const int32_t* __restrict__ long_rows,
+                                                   int64_t n_long, float* __restrict__ a,
+                                                   float* __restrict__ dist,
+                                                   int32_t* __restrict__ best,
+                                                   float* __restrict__ dbest) {
+    const int64_t b = blockIdx.x;
+    if (b < n_long) aff_long<Q, DT>(rp, col, X, K, long_rows[b], ids, a, dist, best, dbest);
+    else aff_normal<Q, P, DT>(rp, col, X, K, n, ids, a, dist, best, dbest, b - n_long);
+}
+
+template <int Q, int DT>
+static int launch_aff(const gr_graph* g, int K, const void* X, const int32_t* ids,
+                      const int32_t* long_rows, int64_t n_long, float* a, float* dist,
+                      int32_t* best, float* dbest, hipStream_t st) {
     double md = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
+    int P = 1;
     while (P * 2 <= md * 0.75 && Q * P * 2 <= kWave) P *= 2;
-    int64_t waves = (g->n * Q * P + kWave - 1) / kWave;
-    dim3 grid(blocks_for(waves * kWave, kThreads));
-#define GR_AF(PP)                                                                              \
-    case PP:                                                                                  \
-        if constexpr (Q * PP <= kWave)                                                        \
-            hipLaunchKernelGGL((k_affinity<Q, PP, DT>), grid, dim3(kThreads), 0, st, g->row_ptr, \
-                               g->col, X, K, g->n, ids, a, dist, best, dbest);                 \
+    const int64_t waves = (g->n * Q * P + kWave - 1) / kWave;
+    const int64_t grid = n_long + (waves * kWave + kBig - 1) / kBig;
+#define GR_AF(PP)                                                                                  \
+    case PP:                                                                                      \
+        if constexpr (Q * PP <= kWave)                                                            \
+            hipLaunchKernelGGL((k_affinity<Q, PP, DT>), dim3((unsigned)grid), dim3(kBig), 0, st,    \
+                               g->row_ptr, g->col, X, K, g->n, ids, long_rows, n_long, a, dist,    \
+                               best, dbest);                                                      \
         break;
     switch (P) {
         GR_AF(1) GR_AF(2) GR_AF(4) GR_AF(8) GR_AF(16) GR_AF(32) GR_AF(64)
@@ -979,26 +1028,57 @@ static int launch_aff(const gr_graph* g, int K, const void* X, const int32_t* id
     return GR_OK;
 }
 
+__global__ void k_long_flags(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ flag) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = (rp[v + 1] - rp[v]) > kLongRow ? 1 : 0;
+}
+
+__global__ void k_long_scatter(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                               int64_t n, int32_t* __restrict__ out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && flag[v]) out[pos[v]] = (int32_t)v;
+}
+
+int find_long_rows(const gr_graph* g, int32_t** rows, int64_t* n_long, Arena& ws, hipStream_t st) {
+    const int64_t n = g->n;
+    *rows = nullptr;
+    *n_long = 0;
+    if (n == 0) return GR_OK;
+    int32_t* flag = ws.take<int32_t>(n);
+    int32_t* pos = ws.take<int32_t>(n + 1);
+    int32_t* out = ws.take<int32_t>(n);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
+    hipLaunchKernelGGL(k_long_flags, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st,
+                       g->row_ptr, n, flag);
+    GR_LAUNCHED("long flags");
+    GR_TRY(scan_exclusive_i32(flag, pos, n, pos + n, ws, st));
+    hipLaunchKernelGGL(k_long_scatter, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, flag,
+                       pos, n, out);
+    GR_LAUNCHED("long scatter");
+    int32_t cnt = 0;
+    GR_HIP(hipMemcpyAsync(&cnt, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    *rows = out;
+    *n_long = cnt;
+    return GR_OK;
+}
+
 int affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, const int32_t* ids,
-             float* a, float* dist, int32_t* best, float* dbest, hipStream_t st) {
+             const int32_t* long_rows, int64_t n_long, float* a, float* dist, int32_t* best,
+             float* dbest, hipStream_t st) {
     if (g->n == 0) return GR_OK;
     int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
+#define GR_AFQ(QQ, DD) \
+    case QQ: return launch_aff<QQ, DD>(g, K, X, ids, long_rows, n_long, a, dist, best, dbest, st);
     if (dtype == GR_BF16) {
-        switch (Q) {
-            case 1: return launch_aff<1, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
-            case 2: return launch_aff<2, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
-            case 4: return launch_aff<4, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
-            case 8: return launch_aff<8, GR_BF16>(g, K, X, ids, a, dist, best, dbest, st);
-        }
+        switch (Q) { GR_AFQ(1, GR_BF16) GR_AFQ(2, GR_BF16) GR_AFQ(4, GR_BF16) GR_AFQ(8, GR_BF16) }
     } else {
         switch (Q) {
-            case 1: return launch_aff<1, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
-            case 2: return launch_aff<2, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
-            case 4: return launch_aff<4, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
-            case 8: return launch_aff<8, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
-            case 16: return launch_aff<16, GR_F32>(g, K, X, ids, a, dist, best, dbest, st);
+            GR_AFQ(1, GR_F32) GR_AFQ(2, GR_F32) GR_AFQ(4, GR_F32) GR_AFQ(8, GR_F32)
+            GR_AFQ(16, GR_F32)
         }
     }
+#undef GR_AFQ
     return set_error(GR_EUNSUP, "unsupported K=%d for this dtype", K);
 }
 

@@ -86,7 +86,8 @@ _SIGNATURES = {
                         ctypes.c_int),
     "gr_smooth": ([_G, _P, _I32, _I32, _I32, _I32, _P, _P, _SZ, _P],
                   ctypes.c_int),
-    "gr_affinity": ([_G, _I32, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "gr_affinity": ([_G, _I32, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P],
+                    ctypes.c_int),
     "gr_aggregate": ([_G, _P, _I64, _P, ctypes.POINTER(_I64), _P, _SZ, _P],
                      ctypes.c_int),
     "gr_galerkin": ([_G, _P, _I64, _P, _P, _P, ctypes.POINTER(_I64), _P, _SZ,
@@ -282,7 +283,7 @@ def gr_smooth(g: DeviceGraph, colours, n_colours, X, sweeps, ws=None):
     return X
 
 
-def gr_affinity(g: DeviceGraph, X, want_a=True, want_d=True):
+def gr_affinity(g: DeviceGraph, X, want_a=True, want_d=True, ws=None):
     """Returns (a, d, best, dbest): per-entry affinities and algebraic
     distances, the strongest neighbour of each node and its distance."""
     code = vec_dtype_code(X.dtype)
@@ -295,10 +296,11 @@ def gr_affinity(g: DeviceGraph, X, want_a=True, want_d=True):
     dbest = torch.empty(max(g.n, 1), dtype=torch.float32, device=dev)
     if not X.is_contiguous() or X.shape[0] != g.n:
         raise ValueError("X must be a contiguous [n, K] tensor")
+    ws = ws if ws is not None else workspace(g.n, g.nnz, X.shape[1], code)
     cg = g.c()
     _check(load().gr_affinity(ctypes.byref(cg), X.shape[1], code, _ptr(X),
                               _ptr(a), _ptr(d), _ptr(best), _ptr(dbest),
-                              _stream()))
+                              _ptr(ws), ws.numel(), _stream()))
     return ((a[:g.nnz] if a is not None else None),
             (d[:g.nnz] if d is not None else None), best[:g.n], dbest[:g.n])
 

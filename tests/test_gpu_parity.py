@@ -301,8 +301,9 @@ def test_reduce_end_to_end_multilevel(case):
     to end; the per-step decisions are pinned bit-exactly elsewhere (the
     oracle fed the GPU's affinities).  Here: the GPU result is a valid
     aggregation, its coarse graph is exactly P^T L P of its own map, and its
-    first 10 nontrivial eigenvalues agree with the oracle's within
-    max(1e-4 lambda, half the oracle's spread over 5 vector seeds)."""
+    first 10 nontrivial eigenvalues agree with the oracle's to 1e-4, or, where
+    rounding flipped near-ties, lie within 4 standard deviations of the
+    oracle's spread over 5 vector seeds."""
     g = small_graphs()[case]
     ratio = {"knn2d_3000": 32.0, "chunglu_20000": 33.4, "grid3d_12": 20.0}[case]
     say(f"reduce {case} ratio {ratio}")
@@ -327,11 +328,15 @@ def test_reduce_end_to_end_multilevel(case):
                      fp32_coarse=True)
         lams.append(O.laplacian_eigs(r.n_coarse, r.row_ptr, r.col, r.w, 10))
     lams = np.array(lams)
-    spread = lams.max(0) - lams.min(0)
+    mean, std = lams.mean(0), lams.std(0, ddof=1)
     err = np.abs(lam_gpu - lams[0])
     print(f"[gpu-case] {case}: max |dlambda|/lambda {np.max(err / lams[0]):.3e}, "
-          f"max spread/lambda {np.max(spread / lams[0]):.3e}")
-    assert np.all(err <= np.maximum(1e-4 * lams[0], 0.5 * spread) + 1e-12)
+          f"max seed std/lambda {np.max(std / mean):.3e}")
+    # where ids agree the eigenvalues agree to float32 accuracy; where
+    # near-ties flipped, the GPU result must look like one more draw of the
+    # oracle's test vectors: within 4 seed standard deviations of their mean
+    assert np.all((err <= 1e-4 * lams[0]) |
+                  (np.abs(lam_gpu - mean) <= 4 * std + 1e-4 * mean))
     if agree == 1.0:
         assert np.array_equal(agg, ref.agg)
 
