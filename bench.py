@@ -45,8 +45,9 @@ def main():
     ap.add_argument("--dtype", default=None, help="f32 or bf16 vector storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
-    ap.add_argument("--ldf", action="store_true",
-                    help="largest-degree-first greedy colouring")
+    ap.add_argument("--random-priority", action="store_true",
+                    help="greedy colouring with hashed priorities instead of "
+                         "largest-degree-first")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -65,6 +66,7 @@ def main():
     G.load()
     wl = W.WORKLOADS[args.workload]
     dtype = args.dtype or wl.dtype
+    args.ldf = not args.random_priority
     t0 = time.time()
     g = W.build_graph(args.workload)
     log(f"graph {g.name}: n={g.n} nnz={g.nnz} built in {time.time() - t0:.1f}s")

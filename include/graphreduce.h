@@ -99,6 +99,10 @@ typedef struct gr_result {
     int32_t level_colours[32]; /* out: colours used on each level            */
 } gr_result;
 
+/* gr_rq_forward / gr_rq_backward: the quotient's denominator matrix B */
+#define GR_RQ_IDENTITY 0   /* B = I      (ratio cut, Alg. 4)       */
+#define GR_RQ_DEGREE 1     /* B = D(w)   (normalized cut, Alg. 4)  */
+
 /* Phases reported by the profiler (indices into gr_profile arrays). */
 #define GR_PHASE_COLOUR 0
 #define GR_PHASE_RELABEL 1
@@ -242,6 +246,75 @@ int gr_aggregate(const gr_graph* g, const float* dist, int64_t target, int32_t* 
 int gr_galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c_row_ptr,
                 int32_t* c_col, float* c_w, int64_t* nnz_coarse, void* ws, size_t ws_bytes,
                 void* stream);
+
+/* ---------------------------------------------------------------------
+ * Edge-weight derivatives (serving the SGD edge scaling of Sec. 3.3.4).
+ * Edge weights are one FP64 value per undirected edge: edge e = (p, q),
+ * p < q, numbered in CSR order of the upper entries.
+ * ------------------------------------------------------------------- */
+
+/*
+ * gr_edge_list — the undirected edges of g: eu/ev int32[E] with eu < ev,
+ * E = nnz / 2, and edge_of_entry int32[nnz] (may be NULL) mapping each
+ * stored entry (both directions) to its edge.  *n_edges is HOST.
+ * Synchronises.
+ */
+int gr_edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* edge_of_entry,
+                 int64_t* n_edges, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_rq_forward — FP64 Rayleigh quotients of the m columns of U (node-major
+ * double[n][m], 1 <= m <= 64) on the graph with edge weights w_E double[E]:
+ *   R_i = u_i^T L(w) u_i / u_i^T B u_i,  u^T L(w) u = sum_e w_e (u_p - u_q)^2,
+ * with B = I (GR_RQ_IDENTITY) or B = D(w) (GR_RQ_DEGREE) — the quotients of
+ * the eigenproblems L u = lambda B u of Alg. 4/5, whose values at the
+ * eigenvectors are the eigenvalues.  Outputs R double[m] and the
+ * denominators den double[m] (needed by the backward), device.  Sums are
+ * tree reductions of fixed shape (deterministic).
+ */
+int gr_rq_forward(int64_t n, int64_t n_edges, const int32_t* eu, const int32_t* ev,
+                  const double* w_E, const double* U, int32_t m, int32_t mode, double* R,
+                  double* den, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_rq_backward — edge-weight gradient of sum_i gR_i R_i:
+ *   gw_e = sum_i gR_i [ (u_pi - u_qi)^2 - [B = D] R_i (u_pi^2 + u_qi^2) ] / den_i.
+ * At an eigenvector u_i with B = I this is the first-order sensitivity
+ * d(lambda_i)/dw_e = (e_pq^T u_i)^2 / u_i^T u_i of Sec. 3.3.3 (the paper's
+ * formula for the generalised problem carries the factor -lambda_n instead,
+ * for weights of the denominator Laplacian).  U is held fixed (at an
+ * eigenvector the quotient is stationary in u).  Output gw_E double[E].
+ */
+int gr_rq_backward(int64_t n_edges, const int32_t* eu, const int32_t* ev, const double* U,
+                   int32_t m, int32_t mode, const double* R, const double* den, const double* gR,
+                   double* gw_E, void* stream);
+
+/*
+ * gr_expand_edge_weights — entry weights from edge weights:
+ * w[e] = w_E[edge_of_entry[e]] for the nnz stored entries (float32, device).
+ */
+int gr_expand_edge_weights(const int32_t* edge_of_entry, int64_t nnz, const float* w_E, float* w,
+                           void* stream);
+
+/*
+ * gr_smooth_vjp — reverse-mode derivative of `sweeps` Gauss-Seidel sweeps
+ * (the smoothing of Sec. 3.2.1 as computed by gr_smooth) with respect to the
+ * undirected edge weights and the initial vectors.  The graph's entry
+ * weights must be w_E[edge_of_entry[e]] (see gr_edge_list).  Inputs: X0
+ * [n][K] of `dtype` (the initial vectors), G float32 [n][K] (the cotangent of
+ * the smoothed vectors).  Outputs: gw_E float32[E] = d<G, X_S>/dw_E and
+ * gX0 float32 [n][K] = d<G, X_S>/dX0.  With store_states != 0 the S+1
+ * sweep-boundary states are kept; otherwise they are recomputed from X0
+ * (S(S+1)/2 sweeps, three state buffers).  bfloat16 rounding of stored
+ * states is treated as the identity in the reverse pass.  Deterministic
+ * (gather form, no atomics on values).  Workspace: gr_smooth_vjp_workspace.
+ */
+int gr_smooth_vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t sweeps,
+                            int32_t store_states, size_t* bytes);
+int gr_smooth_vjp(const gr_graph* g, const int32_t* edge_of_entry, int64_t n_edges,
+                  const int32_t* colours, int32_t n_colours, int32_t K, int32_t sweeps,
+                  int32_t dtype, const void* X0, const float* G, float* gw_E, float* gX0,
+                  int32_t store_states, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -371,4 +371,84 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
     return GR_OK;
 }
 
+int gr_edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* edge_of_entry,
+                 int64_t* n_edges, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!n_edges) return set_error(GR_EINVAL, "n_edges is NULL");
+    *n_edges = 0;
+    if (g->nnz == 0) return GR_OK;
+    if (g->nnz % 2) return set_error(GR_ECSR, "odd nnz: graph not symmetric");
+    if (!eu || !ev || !ws) return set_error(GR_EINVAL, "NULL eu, ev or workspace");
+    Arena A(ws, ws_bytes);
+    return edge_list(g, eu, ev, edge_of_entry, n_edges, A, S(stream));
+}
+
+static int check_rq_args(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev,
+                         const double* U, int32_t m, int32_t mode) {
+    if (n < 0 || E < 0) return set_error(GR_EINVAL, "negative size");
+    if (m < 1 || m > 64) return set_error(GR_EINVAL, "m must lie in [1, 64]");
+    if (mode != GR_RQ_IDENTITY && mode != GR_RQ_DEGREE) return set_error(GR_EINVAL, "bad mode");
+    if ((E > 0 && (!eu || !ev)) || (n > 0 && !U)) return set_error(GR_EINVAL, "NULL argument");
+    return GR_OK;
+}
+
+int gr_rq_forward(int64_t n, int64_t n_edges, const int32_t* eu, const int32_t* ev,
+                  const double* w_E, const double* U, int32_t m, int32_t mode, double* R,
+                  double* den, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_rq_args(n, n_edges, eu, ev, U, m, mode));
+    if (!R || !ws || (n_edges > 0 && !w_E)) return set_error(GR_EINVAL, "NULL argument");
+    Arena A(ws, ws_bytes);
+    return rq_forward(n, n_edges, eu, ev, w_E, U, m, mode, R, den, A, S(stream));
+}
+
+int gr_rq_backward(int64_t n_edges, const int32_t* eu, const int32_t* ev, const double* U,
+                   int32_t m, int32_t mode, const double* R, const double* den, const double* gR,
+                   double* gw_E, void* stream) {
+    clear_error();
+    GR_TRY(check_rq_args(0, n_edges, eu, ev, U, m, mode));
+    if (n_edges > 0 && (!U || !R || !den || !gR || !gw_E)) return set_error(GR_EINVAL, "NULL argument");
+    return rq_backward(n_edges, eu, ev, U, m, mode, R, den, gR, gw_E, S(stream));
+}
+
+int gr_expand_edge_weights(const int32_t* edge_of_entry, int64_t nnz, const float* w_E, float* w,
+                           void* stream) {
+    clear_error();
+    if (nnz < 0) return set_error(GR_EINVAL, "negative nnz");
+    if (nnz > 0 && (!edge_of_entry || !w_E || !w)) return set_error(GR_EINVAL, "NULL argument");
+    return expand_weights(edge_of_entry, nnz, w_E, w, S(stream));
+}
+
+int gr_smooth_vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t sweeps,
+                            int32_t store_states, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || nnz < 0 || sweeps < 0) return set_error(GR_EINVAL, "negative size");
+    GR_TRY(check_vec_args(K, dtype));
+    *bytes = vjp_workspace(n, nnz, K, dtype, sweeps, store_states);
+    return GR_OK;
+}
+
+int gr_smooth_vjp(const gr_graph* g, const int32_t* edge_of_entry, int64_t n_edges,
+                  const int32_t* colours, int32_t n_colours, int32_t K, int32_t sweeps,
+                  int32_t dtype, const void* X0, const float* G, float* gw_E, float* gX0,
+                  int32_t store_states, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    GR_TRY(check_vec_args(K, dtype));
+    if (sweeps < 0) return set_error(GR_EINVAL, "sweeps must be >= 0");
+    if (n_edges != g->nnz / 2) return set_error(GR_EINVAL, "n_edges must be nnz / 2");
+    if (g->n > 0 && (!colours || n_colours < 1)) return set_error(GR_EINVAL, "bad colouring");
+    if (g->n > 0 && (!X0 || !G || !gX0 || !ws)) return set_error(GR_EINVAL, "NULL argument");
+    if (g->nnz > 0 && (!edge_of_entry || !gw_E)) return set_error(GR_EINVAL, "NULL argument");
+    GR_TRY(check_aligned(X0, "X0"));
+    GR_TRY(check_aligned(G, "G"));
+    GR_TRY(check_aligned(gX0, "gX0"));
+    if (g->n == 0) return GR_OK;
+    Arena A(ws, ws_bytes);
+    return smooth_vjp(g, edge_of_entry, n_edges, colours, n_colours, K, sweeps, dtype, X0, G, gw_E,
+                      gX0, store_states ? 1 : 0, A, S(stream));
+}
+
 }  // extern "C"

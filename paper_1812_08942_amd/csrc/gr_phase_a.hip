@@ -9,6 +9,7 @@
 // shuffle tree.  Every reduction order is therefore a function of (Q, P)
 // only, which keeps results bit-reproducible.
 #include "gr_internal.hpp"
+#include "gr_device.hpp"
 
 namespace gr {
 
@@ -548,40 +549,6 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
     return GR_OK;
 }
 
-// ------------------------------------------------------------- chunk I/O
-// A chunk is 16 bytes of a row: E = 4 float32 or 8 bfloat16 values.
-template <int DT> struct Chunk;
-template <> struct Chunk<GR_F32> {
-    static constexpr int E = 4;
-    __device__ static inline void load(const void* X, int64_t row, int K, int q, float* v) {
-        float4 t = *reinterpret_cast<const float4*>((const float*)X + row * K + q * 4);
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    }
-    __device__ static inline void store(void* X, int64_t row, int K, int q, const float* v) {
-        float4 t = make_float4(v[0], v[1], v[2], v[3]);
-        *reinterpret_cast<float4*>((float*)X + row * K + q * 4) = t;
-    }
-};
-template <> struct Chunk<GR_BF16> {
-    static constexpr int E = 8;
-    __device__ static inline void load(const void* X, int64_t row, int K, int q, float* v) {
-        uint4 t = *reinterpret_cast<const uint4*>((const uint16_t*)X + row * K + q * 8);
-        uint32_t u[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            v[2 * i] = __uint_as_float(u[i] << 16);
-            v[2 * i + 1] = __uint_as_float(u[i] & 0xffff0000u);
-        }
-    }
-    __device__ static inline void store(void* X, int64_t row, int K, int q, const float* v) {
-        uint32_t u[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            u[i] = (uint32_t)f32_to_bf16(v[2 * i]) | ((uint32_t)f32_to_bf16(v[2 * i + 1]) << 16);
-        *reinterpret_cast<uint4*>((uint16_t*)X + row * K + q * 8) = make_uint4(u[0], u[1], u[2], u[3]);
-    }
-};
-
 // ----------------------------------------------------------- GS colour step
 // One Gauss-Seidel colour step (Sec. 3.2.1): every node v of the colour with
 // d_v > 0 becomes sum_j w_vj x_j / d_v.  One launch of kBig-thread blocks per
@@ -808,22 +775,6 @@ int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dt
 }
 
 // ---------------------------------------------------------------- affinity
-// Sum of the Q partial sums of a row-group, fixed xor tree over q.
-template <int Q>
-__device__ inline float qsum(float v) {
-#pragma unroll
-    for (int off = 1; off < Q; off <<= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
-template <int E>
-__device__ inline float chunk_dot(const float* a, const float* b) {
-    float s = 0.0f;
-#pragma unroll
-    for (int i = 0; i < E; ++i) s = __fmaf_rn(a[i], b[i], s);
-    return s;
-}
-
 // (d, id) ordering of candidates: smaller algebraic distance, then smaller id.
 __device__ inline bool closer(float d1, int32_t id1, float d2, int32_t id2) {
     return d1 < d2 || (d1 == d2 && id1 < id2);
@@ -846,11 +797,11 @@ __device__ inline void entry_ad(const void* __restrict__ X, int32_t K, int q, co
     Chunk<DT>::load(X, j, K, q, xj);
     float c = qsum<Q>(chunk_dot<E>(xv, xj));
     float nj = qsum<Q>(chunk_dot<E>(xj, xj));
-    float sj = sqrtf(nj);
+    const float rj = nj > 0.0f ? 1.0f / sqrtf(nj) : 0.0f;
     float dm = 0.0f, dp = 0.0f;
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-        float uj = nj > 0.0f ? xj[i] / sj : 0.0f;
+        float uj = xj[i] * rj;
         float m = uv[i] - uj, s2 = uv[i] + uj;
         dm = __fmaf_rn(m, m, dm);
         dp = __fmaf_rn(s2, s2, dp);
@@ -868,9 +819,11 @@ __device__ inline void row_prep(const void* __restrict__ X, int32_t K, int q, in
     constexpr int E = Chunk<DT>::E;
     Chunk<DT>::load(X, r, K, q, xv);
     const float nv = qsum<Q>(chunk_dot<E>(xv, xv));
-    const float sv = sqrtf(nv);
+    // the row is normalised by one correctly rounded reciprocal square root
+    // (the same operations for every row, so (v, j) and (j, v) agree)
+    const float rv = nv > 0.0f ? 1.0f / sqrtf(nv) : 0.0f;
 #pragma unroll
-    for (int i = 0; i < E; ++i) uv[i] = nv > 0.0f ? xv[i] / sv : 0.0f;
+    for (int i = 0; i < E; ++i) uv[i] = xv[i] * rv;
     *nv_out = nv;
 }
 

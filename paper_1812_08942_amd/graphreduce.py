@@ -24,6 +24,8 @@ GR_BF16 = 1
 GR_VALIDATE = 1
 GR_COLOUR_LDF = 2
 GR_WNOPROGRESS = 1
+GR_RQ_IDENTITY = 0
+GR_RQ_DEGREE = 1
 
 
 class gr_graph(ctypes.Structure):
@@ -92,6 +94,17 @@ _SIGNATURES = {
                      ctypes.c_int),
     "gr_galerkin": ([_G, _P, _I64, _P, _P, _P, ctypes.POINTER(_I64), _P, _SZ,
                      _P], ctypes.c_int),
+    "gr_edge_list": ([_G, _P, _P, _P, ctypes.POINTER(_I64), _P, _SZ, _P],
+                     ctypes.c_int),
+    "gr_rq_forward": ([_I64, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P,
+                       _SZ, _P], ctypes.c_int),
+    "gr_rq_backward": ([_I64, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P],
+                       ctypes.c_int),
+    "gr_expand_edge_weights": ([_P, _I64, _P, _P, _P], ctypes.c_int),
+    "gr_smooth_vjp_workspace": ([_I64, _I64, _I32, _I32, _I32, _I32,
+                                 ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_smooth_vjp": ([_G, _P, _I64, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
+                       _P, _I32, _P, _SZ, _P], ctypes.c_int),
 }
 
 _lib = None
@@ -375,3 +388,103 @@ def gr_reduce(g: DeviceGraph, K, sweeps, ratio, vec_seed, colour_seed,
                      L, int(r.warnings), list(r.level_n[:min(L, 32)]),
                      list(r.level_nnz[:min(L, 32)]),
                      list(r.level_colours[:min(L, 32)]))
+
+
+# ------------------------------------------------------- edge derivatives
+
+@dataclasses.dataclass
+class EdgeList:
+    eu: torch.Tensor              # int32 [E]
+    ev: torch.Tensor              # int32 [E]
+    edge_of_entry: torch.Tensor   # int32 [nnz]
+    n: int
+
+    @property
+    def E(self) -> int:
+        return self.eu.numel()
+
+
+def gr_edge_list(g: DeviceGraph, ws=None) -> EdgeList:
+    ws = ws if ws is not None else workspace(g.n, g.nnz)
+    dev = g.row_ptr.device
+    E0 = max(g.nnz // 2, 1)
+    eu = torch.empty(E0, dtype=torch.int32, device=dev)
+    ev = torch.empty(E0, dtype=torch.int32, device=dev)
+    eoe = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    ne = _I64(0)
+    cg = g.c()
+    _check(load().gr_edge_list(ctypes.byref(cg), _ptr(eu), _ptr(ev), _ptr(eoe),
+                               ctypes.byref(ne), _ptr(ws), ws.numel(),
+                               _stream()))
+    E = int(ne.value)
+    return EdgeList(eu[:E], ev[:E], eoe[:g.nnz], g.n)
+
+
+def _f64c(t):
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("expected a contiguous float64 device tensor")
+    return t
+
+
+def gr_rq_forward(edges: EdgeList, w_E, U, mode=GR_RQ_IDENTITY, ws=None):
+    """(R, den): Rayleigh quotients of the columns of U ([n, m] float64)."""
+    _f64c(w_E)
+    _f64c(U)
+    n, m = U.shape
+    ws = ws if ws is not None else workspace(n, 0)
+    R = torch.empty(m, dtype=torch.float64, device=U.device)
+    den = torch.empty(m, dtype=torch.float64, device=U.device)
+    _check(load().gr_rq_forward(n, edges.E, _ptr(edges.eu), _ptr(edges.ev),
+                                _ptr(w_E), _ptr(U), m, int(mode), _ptr(R),
+                                _ptr(den), _ptr(ws), ws.numel(), _stream()))
+    return R, den
+
+
+def gr_rq_backward(edges: EdgeList, U, R, den, gR, mode=GR_RQ_IDENTITY):
+    _f64c(U)
+    gR = gR.contiguous().to(torch.float64)
+    gw = torch.empty(max(edges.E, 1), dtype=torch.float64, device=U.device)
+    _check(load().gr_rq_backward(edges.E, _ptr(edges.eu), _ptr(edges.ev),
+                                 _ptr(U), U.shape[1], int(mode), _ptr(R),
+                                 _ptr(den), _ptr(gR), _ptr(gw), _stream()))
+    return gw[:edges.E]
+
+
+def gr_smooth_vjp_workspace(n, nnz, K, dtype, sweeps, store_states) -> int:
+    out = _SZ(0)
+    _check(load().gr_smooth_vjp_workspace(n, nnz, K, vec_dtype_code(dtype),
+                                          sweeps, int(store_states),
+                                          ctypes.byref(out)))
+    return int(out.value)
+
+
+def gr_smooth_vjp(g: DeviceGraph, edges: EdgeList, colours, n_colours, X0, G,
+                  sweeps, store_states=False):
+    """(gw_E float32[E], gX0 float32[n, K]): gradients of <G, X_S> for the
+    smoothing of X0 on g (whose entry weights are w_E[edge_of_entry])."""
+    code = vec_dtype_code(X0.dtype)
+    n, K = X0.shape
+    if G.dtype != torch.float32 or not G.is_contiguous() or not X0.is_contiguous():
+        raise ValueError("X0 and G must be contiguous; G float32")
+    nbytes = gr_smooth_vjp_workspace(g.n, g.nnz, K, code, sweeps, store_states)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=X0.device)
+    gw = torch.empty(max(edges.E, 1), dtype=torch.float32, device=X0.device)
+    gX = torch.empty((max(n, 1), K), dtype=torch.float32, device=X0.device)
+    cg = g.c()
+    _check(load().gr_smooth_vjp(ctypes.byref(cg), _ptr(edges.edge_of_entry),
+                                edges.E, _ptr(colours), n_colours, K, sweeps,
+                                code, _ptr(X0), _ptr(G), _ptr(gw), _ptr(gX),
+                                int(store_states), _ptr(ws), nbytes,
+                                _stream()))
+    return gw[:edges.E], gX[:n]
+
+
+def gr_expand_edge_weights(edges: EdgeList, w_E):
+    """Entry weights float32[nnz] = w_E[edge_of_entry]."""
+    w_E = w_E.contiguous().to(torch.float32)
+    w = torch.empty(max(edges.edge_of_entry.numel(), 1), dtype=torch.float32,
+                    device=w_E.device)
+    _check(load().gr_expand_edge_weights(_ptr(edges.edge_of_entry),
+                                         edges.edge_of_entry.numel(), _ptr(w_E),
+                                         _ptr(w), _stream()))
+    return w[:edges.edge_of_entry.numel()]
