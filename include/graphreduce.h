@@ -292,9 +292,11 @@ int gr_rq_backward(int64_t n_edges, const int32_t* eu, const int32_t* ev, const 
 /*
  * gr_expand_edge_weights — entry weights from edge weights:
  * w[e] = w_E[edge_of_entry[e]] for the nnz stored entries (float32, device).
+ * GR_EINVAL if an id lies outside [0, n_edges) (such entries are never
+ * dereferenced).  Synchronises.
  */
-int gr_expand_edge_weights(const int32_t* edge_of_entry, int64_t nnz, const float* w_E, float* w,
-                           void* stream);
+int gr_expand_edge_weights(const int32_t* edge_of_entry, int64_t nnz, int64_t n_edges,
+                           const float* w_E, float* w, void* stream);
 
 /*
  * gr_smooth_vjp — reverse-mode derivative of `sweeps` Gauss-Seidel sweeps

@@ -412,12 +412,12 @@ int gr_rq_backward(int64_t n_edges, const int32_t* eu, const int32_t* ev, const 
     return rq_backward(n_edges, eu, ev, U, m, mode, R, den, gR, gw_E, S(stream));
 }
 
-int gr_expand_edge_weights(const int32_t* edge_of_entry, int64_t nnz, const float* w_E, float* w,
-                           void* stream) {
+int gr_expand_edge_weights(const int32_t* edge_of_entry, int64_t nnz, int64_t n_edges,
+                           const float* w_E, float* w, void* stream) {
     clear_error();
-    if (nnz < 0) return set_error(GR_EINVAL, "negative nnz");
+    if (nnz < 0 || n_edges < 0) return set_error(GR_EINVAL, "negative size");
     if (nnz > 0 && (!edge_of_entry || !w_E || !w)) return set_error(GR_EINVAL, "NULL argument");
-    return expand_weights(edge_of_entry, nnz, w_E, w, S(stream));
+    return expand_weights(edge_of_entry, nnz, n_edges, w_E, w, S(stream));
 }
 
 int gr_smooth_vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t sweeps,

@@ -70,17 +70,48 @@ int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t
     return GR_OK;
 }
 
-__global__ void k_expand_weights(const int32_t* __restrict__ eoe, int64_t nnz,
+// set when a caller-supplied edge id lies outside [0, E); the offending
+// entry is never dereferenced
+__device__ int32_t g_bad_edge_id;
+
+__global__ void k_expand_weights(const int32_t* __restrict__ eoe, int64_t nnz, int64_t E,
                                  const float* __restrict__ wE, float* __restrict__ w) {
     int64_t e = (int64_t)blockIdx.x * kA + threadIdx.x;
-    if (e < nnz) w[e] = wE[eoe[e]];
+    if (e >= nnz) return;
+    int32_t k = eoe[e];
+    if (k >= 0 && k < E) {
+        w[e] = wE[k];
+    } else {
+        w[e] = 0.0f;
+        g_bad_edge_id = 1;
+    }
 }
 
-int expand_weights(const int32_t* eoe, int64_t nnz, const float* wE, float* w, hipStream_t st) {
-    if (nnz == 0) return GR_OK;
-    hipLaunchKernelGGL(k_expand_weights, dim3(blocks_for(nnz, kA)), dim3(kA), 0, st, eoe, nnz, wE, w);
-    GR_LAUNCHED("expand weights");
+static int reset_bad_edge_flag(hipStream_t st) {
+    int32_t zero = 0;
+    GR_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_bad_edge_id), &zero, sizeof(int32_t), 0,
+                                  hipMemcpyHostToDevice, st));
+    GR_HIP(hipStreamSynchronize(st));
     return GR_OK;
+}
+
+static int check_bad_edge_flag(hipStream_t st) {
+    int32_t bad = 0;
+    GR_HIP(hipMemcpyFromSymbolAsync(&bad, HIP_SYMBOL(g_bad_edge_id), sizeof(int32_t), 0,
+                                    hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    if (bad) return set_error(GR_EINVAL, "edge_of_entry holds ids outside [0, n_edges)");
+    return GR_OK;
+}
+
+int expand_weights(const int32_t* eoe, int64_t nnz, int64_t E, const float* wE, float* w,
+                   hipStream_t st) {
+    if (nnz == 0) return GR_OK;
+    GR_TRY(reset_bad_edge_flag(st));
+    hipLaunchKernelGGL(k_expand_weights, dim3(blocks_for(nnz, kA)), dim3(kA), 0, st, eoe, nnz, E, wE,
+                       w);
+    GR_LAUNCHED("expand weights");
+    return check_bad_edge_flag(st);
 }
 
 // ------------------------------------------------------- Rayleigh quotients
@@ -410,14 +441,15 @@ __global__ void __launch_bounds__(256) k_vjp_segs(const int32_t* __restrict__ re
 // whose original row is the smaller endpoint
 __global__ void k_edge_slots(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                              const int32_t* __restrict__ eoe, const int32_t* __restrict__ perm,
-                             int64_t n, int32_t* __restrict__ slots) {
+                             int64_t n, int64_t E, int32_t* __restrict__ slots) {
     int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     int lane = threadIdx.x & (kWave - 1);
     if (r >= n) return;
     const int32_t orow = perm[r];
     for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) {
         int32_t k = eoe[e];
-        slots[2 * k + (orow < perm[col[e]] ? 0 : 1)] = e;
+        if (k >= 0 && k < E) slots[2 * k + (orow < perm[col[e]] ? 0 : 1)] = e;
+        else g_bad_edge_id = 1;
     }
 }
 
@@ -633,9 +665,12 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
 #undef GR_VJ
     GR_TRY(permute_rows(xbar, gX0, og.perm, n, (size_t)K * 4, 1, st));
     if (E > 0) {
+        GR_TRY(fill_i32(slots, 0, 2 * E, st));  // unmatched slots read entry 0, never garbage
+        GR_TRY(reset_bad_edge_flag(st));
         hipLaunchKernelGGL(k_edge_slots, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
-                           og.g.row_ptr, og.g.col, (const int32_t*)eoe_s, og.perm, n, slots);
+                           og.g.row_ptr, og.g.col, (const int32_t*)eoe_s, og.perm, n, E, slots);
         GR_LAUNCHED("edge slots");
+        GR_TRY(check_bad_edge_flag(st));
         hipLaunchKernelGGL(k_edge_grad, dim3(blocks_for(E, 256)), dim3(256), 0, st,
                            (const int32_t*)slots, (const float*)ge, E, gw);
         GR_LAUNCHED("edge grad");

@@ -171,7 +171,8 @@ int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t
 int rq_forward(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev, const double* w,
                const double* U, int32_t m, int32_t mode, double* R, double* den, Arena& ws,
                hipStream_t st);
-int expand_weights(const int32_t* eoe, int64_t nnz, const float* wE, float* w, hipStream_t st);
+int expand_weights(const int32_t* eoe, int64_t nnz, int64_t E, const float* wE, float* w,
+                   hipStream_t st);
 size_t vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t S, int32_t store);
 int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* colours, int32_t C,
                int32_t K, int32_t S, int32_t dtype, const void* X0, const float* Gc, float* gw,

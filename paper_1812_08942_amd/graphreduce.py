@@ -100,7 +100,7 @@ _SIGNATURES = {
                        _SZ, _P], ctypes.c_int),
     "gr_rq_backward": ([_I64, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P],
                        ctypes.c_int),
-    "gr_expand_edge_weights": ([_P, _I64, _P, _P, _P], ctypes.c_int),
+    "gr_expand_edge_weights": ([_P, _I64, _I64, _P, _P, _P], ctypes.c_int),
     "gr_smooth_vjp_workspace": ([_I64, _I64, _I32, _I32, _I32, _I32,
                                  ctypes.POINTER(_SZ)], ctypes.c_int),
     "gr_smooth_vjp": ([_G, _P, _I64, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
@@ -485,6 +485,6 @@ def gr_expand_edge_weights(edges: EdgeList, w_E):
     w = torch.empty(max(edges.edge_of_entry.numel(), 1), dtype=torch.float32,
                     device=w_E.device)
     _check(load().gr_expand_edge_weights(_ptr(edges.edge_of_entry),
-                                         edges.edge_of_entry.numel(), _ptr(w_E),
-                                         _ptr(w), _stream()))
+                                         edges.edge_of_entry.numel(), edges.E,
+                                         _ptr(w_E), _ptr(w), _stream()))
     return w[:edges.edge_of_entry.numel()]
