@@ -318,6 +318,53 @@ int gr_smooth_vjp(const gr_graph* g, const int32_t* edge_of_entry, int64_t n_edg
                   int32_t dtype, const void* X0, const float* G, float* gw_E, float* gX0,
                   int32_t store_states, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Constrained-SGD edge scaling (Alg. 1, Sec. 3.3.4), FP64.
+ * ------------------------------------------------------------------- */
+#define GR_SGD_MAX_ITER 64
+
+typedef struct gr_sgd_params {
+    double alpha;       /* momentum coefficient                               */
+    double eta_scale;   /* eta_max = eta_scale * mean(w_P) / max|s^(1)|        */
+    double eps;         /* stop when (lambda_n^(k-1) - lambda_n^(k)) / lambda_n^(k) < eps */
+    double delta_bar;   /* lambda_1 may fall at most to lambda_1^(0) * delta_bar */
+    int32_t k_max;      /* iteration limit, <= GR_SGD_MAX_ITER                 */
+    int32_t t;          /* generalised power iterations per h_t (the paper: 2) */
+    uint64_t seed;      /* h_0 = one column of the test-vector generator       */
+    int32_t cg_max_iter;/* 0 = 20000                                           */
+    double cg_tol;      /* relative residual of the L_P solves; 0 = 1e-13      */
+} gr_sgd_params;
+
+typedef struct gr_sgd_report {
+    int32_t iterations;              /* weight updates applied             */
+    int32_t n_lambda;                /* entries of lambda_n                */
+    int32_t cg_iterations_max;       /* longest L_P solve                  */
+    double lambda_n[GR_SGD_MAX_ITER];     /* h_t^T L_G h_t per iteration  */
+    double lambda_1[GR_SGD_MAX_ITER + 1]; /* min_p d_G(p)/d_P(p) after each */
+} gr_sgd_report;
+
+/*
+ * gr_sgd_scale — Alg. 1 (Sec. 3.3.4) on the GPU in FP64.  G: the original
+ * graph (float32 weights).  P: a subgraph on the same n nodes (CSR
+ * structure; its weight array is ignored) with its edge list p_eu/p_ev
+ * (E = p_edges, eu < ev) and p_edge_of_entry (see gr_edge_list).  w_P:
+ * double[E] on the device, scaled in place.  Per iteration: h_t from t
+ * generalised power iterations h <- L_P^+ L_G h (L_P solves by
+ * Jacobi-preconditioned CG), normalised to h^T L_P h = 1;
+ * lambda_n = h^T L_G h; s_e = -lambda_n (h_p - h_q)^2; dw <- alpha dw - eta s;
+ * per-node caps cap_p = d_G(p)/(lambda_1 Delta) - d_P(p),
+ * Delta = delta_bar^(1/k_max), shared in proportion where the edges at p ask
+ * for more (all edges are updated at once: the parallel reading of the
+ * paper's edge-by-edge lines); w += dw; eta <- (lambda_n/lambda_n^(0)) eta_max;
+ * lambda_1 = min_p d_G(p)/d_P(p).  *report is HOST.  Synchronises every CG
+ * check and iteration.  Workspace: gr_sgd_workspace.
+ */
+int gr_sgd_workspace(int64_t n, int64_t nnz_g, int64_t nnz_p, int64_t p_edges, size_t* bytes);
+int gr_sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* p_edge_of_entry,
+                 int64_t p_edges, const int32_t* p_eu, const int32_t* p_ev, double* w_P,
+                 const gr_sgd_params* params, gr_sgd_report* report, void* ws, size_t ws_bytes,
+                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

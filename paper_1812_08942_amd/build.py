@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgraphreduce.so")
 SOURCES = ["gr_prims.hip", "gr_phase_a.hip", "gr_aggregate.hip", "gr_autograd.hip",
-           "gr_api.hip"]
+           "gr_sgd.hip", "gr_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -28,6 +28,7 @@ def sources():
 
 def build(force: bool = True, verbose: bool = False) -> str:
     deps = sources() + [os.path.join(CSRC, "gr_internal.hpp"),
+                        os.path.join(CSRC, "gr_device.hpp"),
                         os.path.join(INCLUDE, "graphreduce.h")]
     if not force and os.path.exists(LIB) and \
             os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):

@@ -451,4 +451,37 @@ int gr_smooth_vjp(const gr_graph* g, const int32_t* edge_of_entry, int64_t n_edg
                       gX0, store_states ? 1 : 0, A, S(stream));
 }
 
+int gr_sgd_workspace(int64_t n, int64_t nnz_g, int64_t nnz_p, int64_t p_edges, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || nnz_g < 0 || nnz_p < 0 || p_edges < 0) return set_error(GR_EINVAL, "negative size");
+    *bytes = sgd_workspace(n, nnz_g, nnz_p, p_edges);
+    return GR_OK;
+}
+
+int gr_sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* p_edge_of_entry,
+                 int64_t p_edges, const int32_t* p_eu, const int32_t* p_ev, double* w_P,
+                 const gr_sgd_params* params, gr_sgd_report* report, void* ws, size_t ws_bytes,
+                 void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(G));
+    if (!P) return set_error(GR_EINVAL, "P is NULL");
+    if (P->n != G->n) return set_error(GR_EINVAL, "P must have the nodes of G");
+    if (P->nnz < 0 || !P->row_ptr || (P->nnz > 0 && !P->col))
+        return set_error(GR_EINVAL, "bad P arrays");
+    if (!params || !report || !ws) return set_error(GR_EINVAL, "NULL argument");
+    if (p_edges != P->nnz / 2) return set_error(GR_EINVAL, "p_edges must be nnz(P) / 2");
+    if (p_edges > 0 && (!p_edge_of_entry || !p_eu || !p_ev || !w_P))
+        return set_error(GR_EINVAL, "NULL P edge arrays");
+    if (params->k_max < 1 || params->k_max > GR_SGD_MAX_ITER)
+        return set_error(GR_EINVAL, "k_max must lie in [1, %d]", GR_SGD_MAX_ITER);
+    if (params->t < 1) return set_error(GR_EINVAL, "t must be >= 1");
+    if (!(params->delta_bar > 0.0 && params->delta_bar <= 1.0))
+        return set_error(GR_EINVAL, "delta_bar must lie in (0, 1]");
+    memset(report, 0, sizeof(*report));
+    if (G->n == 0 || p_edges == 0) return GR_OK;
+    Arena A(ws, ws_bytes);
+    return sgd_scale(G, P, p_edge_of_entry, p_edges, p_eu, p_ev, w_P, params, report, A, S(stream));
+}
+
 }  // extern "C"

@@ -173,6 +173,10 @@ int rq_forward(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev, const
                hipStream_t st);
 int expand_weights(const int32_t* eoe, int64_t nnz, int64_t E, const float* wE, float* w,
                    hipStream_t st);
+size_t sgd_workspace(int64_t n, int64_t nnzG, int64_t nnzP, int64_t E);
+int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t E,
+              const int32_t* eu, const int32_t* ev, double* wP, const gr_sgd_params* prm,
+              gr_sgd_report* rep, Arena& ws, hipStream_t st);
 size_t vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t S, int32_t store);
 int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* colours, int32_t C,
                int32_t K, int32_t S, int32_t dtype, const void* X0, const float* Gc, float* gw,

@@ -60,6 +60,24 @@ class gr_profile(ctypes.Structure):
                 ("records", ctypes.c_int64)]
 
 
+GR_SGD_MAX_ITER = 64
+
+
+class gr_sgd_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("eta_scale", ctypes.c_double),
+                ("eps", ctypes.c_double), ("delta_bar", ctypes.c_double),
+                ("k_max", ctypes.c_int32), ("t", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("cg_max_iter", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double)]
+
+
+class gr_sgd_report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("n_lambda", ctypes.c_int32),
+                ("cg_iterations_max", ctypes.c_int32),
+                ("lambda_n", ctypes.c_double * GR_SGD_MAX_ITER),
+                ("lambda_1", ctypes.c_double * (GR_SGD_MAX_ITER + 1))]
+
+
 PHASES = ("colour", "relabel", "init", "smooth", "affinity", "aggregate",
           "galerkin", "other")
 
@@ -100,6 +118,11 @@ _SIGNATURES = {
                        _SZ, _P], ctypes.c_int),
     "gr_rq_backward": ([_I64, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P],
                        ctypes.c_int),
+    "gr_sgd_workspace": ([_I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)],
+                         ctypes.c_int),
+    "gr_sgd_scale": ([_G, _G, _P, _I64, _P, _P, _P,
+                      ctypes.POINTER(gr_sgd_params),
+                      ctypes.POINTER(gr_sgd_report), _P, _SZ, _P], ctypes.c_int),
     "gr_expand_edge_weights": ([_P, _I64, _I64, _P, _P, _P], ctypes.c_int),
     "gr_smooth_vjp_workspace": ([_I64, _I64, _I32, _I32, _I32, _I32,
                                  ctypes.POINTER(_SZ)], ctypes.c_int),
@@ -488,3 +511,32 @@ def gr_expand_edge_weights(edges: EdgeList, w_E):
                                          edges.edge_of_entry.numel(), edges.E,
                                          _ptr(w_E), _ptr(w), _stream()))
     return w[:edges.edge_of_entry.numel()]
+
+
+def gr_sgd_workspace(n, nnz_g, nnz_p, p_edges) -> int:
+    out = _SZ(0)
+    _check(load().gr_sgd_workspace(n, nnz_g, nnz_p, p_edges, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gr_sgd_scale(G_graph: DeviceGraph, P_graph: DeviceGraph, p_edges: EdgeList,
+                 w_P, alpha=0.9, eta_scale=0.1, eps=1e-3, delta_bar=0.5,
+                 k_max=20, t=2, seed=1, cg_max_iter=0, cg_tol=0.0):
+    """Alg. 1 edge scaling: scales w_P (float64 [E_P], device) in place;
+    returns the report as a dict."""
+    _f64c(w_P)
+    nbytes = gr_sgd_workspace(G_graph.n, G_graph.nnz, P_graph.nnz, p_edges.E)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=w_P.device)
+    prm = gr_sgd_params(alpha, eta_scale, eps, delta_bar, k_max, t,
+                        seed & (2**64 - 1), cg_max_iter, cg_tol)
+    rep = gr_sgd_report()
+    cgG, cgP = G_graph.c(), P_graph.c()
+    _check(load().gr_sgd_scale(ctypes.byref(cgG), ctypes.byref(cgP),
+                               _ptr(p_edges.edge_of_entry), p_edges.E,
+                               _ptr(p_edges.eu), _ptr(p_edges.ev), _ptr(w_P),
+                               ctypes.byref(prm), ctypes.byref(rep), _ptr(ws),
+                               nbytes, _stream()))
+    return {"iterations": int(rep.iterations),
+            "lambda_n": list(rep.lambda_n[:rep.n_lambda]),
+            "lambda_1": list(rep.lambda_1[:rep.iterations + 1]),
+            "cg_iterations_max": int(rep.cg_iterations_max)}

@@ -238,3 +238,44 @@ def test_smoothed_vectors_autograd():
                             Gc.cpu().numpy().astype(np.float64), 5)
     assert np.max(np.abs(wE.grad.cpu().numpy() - rgw)) <= 1e-4 * np.max(np.abs(rgw))
     assert np.max(np.abs(X0.grad.cpu().numpy() - rgX)) <= 1e-4 * np.max(np.abs(rgX))
+
+
+# ----------------------------------------------- Alg. 1 constrained SGD
+
+@pytest.mark.parametrize("case", ["er_200", "gmm_reduced"])
+def test_sgd_scale_matches_oracle(case):
+    """Alg. 1 on the GPU (CG solves) against the FP64 oracle (dense solves):
+    lambda_n and lambda_1 histories and the scaled weights agree to 1e-7."""
+    from oracle import sgd as S
+
+    dev = _dev()
+    G = _G()
+    if case == "er_200":
+        g = W.random_weighted(200, 0.05, seed=12)
+    else:
+        big = W.gmm_knn(n_per=300, dim=784, n_comp=10, k=10, seed=4)
+        r = O.reduce(big.n, big.row_ptr, big.col, big.w.astype(np.float64), 16,
+                     5, 16.0, 14, 24, fp32_coarse=True)
+        g = W.Graph(r.n_coarse, r.row_ptr, r.col, r.w.astype(np.float32), "gmm_red")
+    say(f"sgd {case} n={g.n}")
+    eoe, eu, ev = O.edge_index(g.n, g.row_ptr, g.col)
+    w = np.zeros(eu.size)
+    w[eoe] = g.w
+    keep = W.spanning_sparsifier(g.n, eu, ev, w, 0.1)
+    pg = W.csr_from_edges(g.n, eu[keep], ev[keep], w[keep])
+    prm = S.SgdParams(k_max=12, eps=1e-4)
+    ref = S.sgd_scale(g.n, eu, ev, w, eu[keep], ev[keep], w[keep], prm)
+    dG = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    dP = G.DeviceGraph.from_numpy(pg.row_ptr, pg.col, pg.w, dev)
+    pel = G.gr_edge_list(dP)
+    assert np.array_equal(pel.eu.cpu().numpy(), eu[keep])
+    wP = torch.from_numpy(w[keep].copy()).to(dev)
+    rep = G.gr_sgd_scale(dG, dP, pel, wP, k_max=12, eps=1e-4, cg_tol=1e-14)
+    print(f"[gpu-case] sgd {case}: iterations {rep['iterations']}, "
+          f"lambda_n {rep['lambda_n'][0]:.6g} -> {rep['lambda_n'][-1]:.6g}, "
+          f"cg max {rep['cg_iterations_max']}")
+    assert rep["iterations"] == ref.iterations
+    assert np.allclose(rep["lambda_n"], ref.lambda_n, rtol=1e-7)
+    assert np.allclose(rep["lambda_1"], ref.lambda_1, rtol=1e-9)
+    assert np.allclose(wP.cpu().numpy(), ref.w_P, rtol=1e-7)
+    assert ref.lambda_n[-1] < ref.lambda_n[0]

@@ -507,3 +507,68 @@ def test_rayleigh_gradient_hellmann_feynman():
             / (2 * h) @ gR
         assert abs(fd - gwd[e]) < 1e-7
     assert Rd.shape == (4,)
+
+
+# -------------------------------------------------- Alg. 1 edge scaling
+
+def _sgd_setup(seed=3, n=60):
+    g = G.random_weighted(n, 0.15, seed=seed)
+    eoe, eu, ev = O.edge_index(g.n, g.row_ptr, g.col)
+    w = np.zeros(eu.size)
+    w[eoe] = g.w
+    keep = G.spanning_sparsifier(g.n, eu, ev, w, 0.1)
+    return g, eu, ev, w, keep
+
+
+def test_sgd_constraint_monotone_weights_and_falling_lambda_n():
+    """Alg. 1: weights only grow, lambda_1 (the degree-ratio estimate) stays
+    above lambda_1^(0) * Delta_bar, and the dense generalised lambda_n of
+    (L_G, L_P) falls."""
+    import scipy.linalg as sl
+    from oracle import sgd as S
+
+    g, eu, ev, w, keep = _sgd_setup()
+    p = S.SgdParams(k_max=15)
+    r = S.sgd_scale(g.n, eu, ev, w, eu[keep], ev[keep], w[keep], p)
+    assert r.iterations >= 2
+    assert np.all(r.w_P >= w[keep] - 1e-15)
+    lam1_0 = r.lambda_1[0]
+    assert np.all(np.array(r.lambda_1) >= lam1_0 * p.delta_bar * (1 - 1e-12))
+
+    def gen_lmax(wp):
+        Lg = S._lap(g.n, eu, ev, w)
+        Lp = S._lap(g.n, eu[keep], ev[keep], wp)
+        J = np.ones((g.n, g.n)) / g.n
+        return sl.eigh(Lg + J, Lp + J, eigvals_only=True)[-1]
+
+    assert gen_lmax(r.w_P) < gen_lmax(w[keep])
+
+
+def test_sgd_power_vector_and_sensitivity_against_dense_eigen():
+    """h_t approaches the dominant generalised eigenvector, and the
+    sensitivity -lambda_n (e_pq^T u_n)^2 (u_n^T L_P u_n = 1) matches finite
+    differences of the dense generalised lambda_n (Sec. 3.3.4)."""
+    import scipy.linalg as sl
+    from oracle import sgd as S
+
+    g, eu, ev, w, keep = _sgd_setup(seed=5, n=40)
+    pe, pv = eu[keep], ev[keep]
+    Lg = S._lap(g.n, eu, ev, w)
+    J = np.ones((g.n, g.n)) / g.n
+
+    def gen(wp):
+        return sl.eigh(Lg + J, S._lap(g.n, pe, pv, wp) + J)
+
+    lam, U = gen(w[keep])
+    u = U[:, -1] / np.sqrt(U[:, -1] @ S._lap(g.n, pe, pv, w[keep]) @ U[:, -1])
+    h = S.power_vector(Lg, S._lap(g.n, pe, pv, w[keep]),
+                       O.init_vectors(g.n, 1, 7)[:, 0], 60)
+    assert abs(abs(h @ S._lap(g.n, pe, pv, w[keep]) @ u) - 1.0) < 1e-6
+    sens = -lam[-1] * (u[pe] - u[pv]) ** 2
+    for e in range(0, len(keep), max(1, len(keep) // 8)):
+        hh = 1e-6 * w[keep][e]
+        wp, wm = w[keep].copy(), w[keep].copy()
+        wp[e] += hh
+        wm[e] -= hh
+        fd = (gen(wp)[0][-1] - gen(wm)[0][-1]) / (2 * hh)
+        assert abs(fd - sens[e]) <= 1e-5 * max(1.0, abs(fd))

@@ -368,6 +368,35 @@ def chung_lu(n: int = 434_000, mean_deg: float = 73.7, beta: float = 2.5,
     return csr_from_edges(n, u, v, w, f"chung_lu_{n}")
 
 
+# ----------------------------------------------------- subgraph for Alg. 1
+
+def spanning_sparsifier(n, eu, ev, w, frac=0.1):
+    """A spectrally similar subgraph P for tests: the maximum-weight spanning
+    forest (Kruskal, ties by edge index) plus the heaviest `frac` of the
+    remaining edges.  Returns the indices of the chosen edges, ascending."""
+    order = np.lexsort((np.arange(len(w)), -np.asarray(w)))
+    par = np.arange(n)
+
+    def find(x):
+        while par[x] != x:
+            par[x] = par[par[x]]
+            x = par[x]
+        return x
+
+    tree = np.zeros(len(w), bool)
+    for e in order:
+        a, b = find(eu[e]), find(ev[e])
+        if a != b:
+            par[max(a, b)] = min(a, b)
+            tree[e] = True
+    rest = order[~tree[order]]
+    extra = rest[:int(round(frac * len(rest)))]
+    keep = np.zeros(len(w), bool)
+    keep[tree] = True
+    keep[extra] = True
+    return np.nonzero(keep)[0]
+
+
 # ---------------------------------------------------------------- workloads
 
 @dataclasses.dataclass(frozen=True)
