@@ -319,6 +319,47 @@ int gr_smooth_vjp(const gr_graph* g, const int32_t* edge_of_entry, int64_t n_edg
                   int32_t store_states, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * FP64 Laplacian eigenvalues (the spectrum a reduced graph should keep:
+ * its first nontrivial eigenvalues, Sec. 5, Fig. 5).
+ * ------------------------------------------------------------------- */
+#define GR_EIG_AUTO 0      /* LOBPCG when max degree > 16 x mean degree   */
+#define GR_EIG_CHEBYSHEV 1 /* Chebyshev-filtered subspace iteration       */
+#define GR_EIG_LOBPCG 2    /* LOBPCG, Jacobi (D^-1) preconditioner        */
+
+typedef struct gr_eig_report {
+    int32_t iterations;        /* outer iterations                          */
+    int32_t block;             /* block width m                             */
+    double residual;           /* max ||L x_i - theta_i x_i|| of the wanted  */
+    double lambda_max_bound;   /* b = 2 max degree >= lambda_max            */
+    int32_t cholesky_warnings; /* 1 if an orthonormalisation lost rank      */
+    int32_t method;            /* GR_EIG_CHEBYSHEV or GR_EIG_LOBPCG used    */
+    int32_t restarts;          /* LOBPCG bases rebuilt without P            */
+} gr_eig_report;
+
+/*
+ * gr_laplacian_eigs — the n_eig (1..32) smallest eigenvalues of L = D - A
+ * restricted to the vectors orthogonal to the all-one vector (for a
+ * connected graph lambda_2 .. lambda_{n_eig+1}; a graph with c components
+ * reports c - 1 zeros first), in FP64.  Both methods keep a block of
+ * m > n_eig orthonormal vectors and stop when every wanted Ritz pair has
+ * residual <= tol * b (b = 2 max degree) or after max_iter iterations:
+ *  - GR_EIG_CHEBYSHEV: m = n_eig + max(8, n_eig) (<= 64), each iteration
+ *    applies the Chebyshev polynomial of [a, b] (a = the largest Ritz
+ *    value) of degree <= `degree` (capped so no direction grows by more
+ *    than 1e6), then Rayleigh-Ritz;
+ *  - GR_EIG_LOBPCG: m = min(n_eig + 8, 21), Rayleigh-Ritz over
+ *    [X, D^{-1} R, P]; needs n_eig <= 19 and n >= 12 m (GR_EUNSUP else).
+ * Where n - 1 < m the block spans the whole complement and entries past
+ * n - 1 are NaN.  Output eig double[n_eig] is HOST; report (may be NULL)
+ * is HOST.  Synchronises once or twice per iteration.  Workspace:
+ * gr_eig_workspace (about 32 n * 64 bytes).
+ */
+int gr_eig_workspace(int64_t n, int32_t n_eig, size_t* bytes);
+int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+                      int32_t max_iter, int32_t degree, uint64_t seed, double* eig,
+                      gr_eig_report* report, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------
  * Constrained-SGD edge scaling (Alg. 1, Sec. 3.3.4), FP64.
  * ------------------------------------------------------------------- */
 #define GR_SGD_MAX_ITER 64

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgraphreduce.so")
 SOURCES = ["gr_prims.hip", "gr_phase_a.hip", "gr_aggregate.hip", "gr_autograd.hip",
-           "gr_sgd.hip", "gr_api.hip"]
+           "gr_sgd.hip", "gr_eigen.hip", "gr_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

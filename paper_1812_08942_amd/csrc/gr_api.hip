@@ -451,6 +451,33 @@ int gr_smooth_vjp(const gr_graph* g, const int32_t* edge_of_entry, int64_t n_edg
                       gX0, store_states ? 1 : 0, A, S(stream));
 }
 
+int gr_eig_workspace(int64_t n, int32_t n_eig, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || n_eig < 1 || n_eig > 32) return set_error(GR_EINVAL, "bad size");
+    *bytes = eig_workspace(n, n_eig);
+    return GR_OK;
+}
+
+int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+                      int32_t max_iter, int32_t degree, uint64_t seed, double* eig,
+                      gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (n_eig < 1 || n_eig > 32) return set_error(GR_EINVAL, "n_eig must lie in [1, 32]");
+    if (method < GR_EIG_AUTO || method > GR_EIG_LOBPCG) return set_error(GR_EINVAL, "unknown method");
+    if (!(tol > 0.0) || max_iter < 0 || degree < 1 || degree > 2000)
+        return set_error(GR_EINVAL, "bad tol, max_iter or degree");
+    if (!eig || !ws) return set_error(GR_EINVAL, "NULL argument");
+    if (report) memset(report, 0, sizeof(*report));
+    if (g->n < 2) {
+        for (int i = 0; i < n_eig; ++i) eig[i] = NAN;
+        return GR_OK;
+    }
+    Arena A(ws, ws_bytes);
+    return laplacian_eigs(g, n_eig, method, tol, max_iter, degree, seed, eig, report, A, S(stream));
+}
+
 int gr_sgd_workspace(int64_t n, int64_t nnz_g, int64_t nnz_p, int64_t p_edges, size_t* bytes) {
     clear_error();
     if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");

@@ -55,14 +55,14 @@ bool on() { return g_on; }
 
 void begin(hipStream_t st) {
     g_open = get_event();
-    if (g_open) hipEventRecord(g_open, st);
+    if (g_open) (void)hipEventRecord(g_open, st);
 }
 
 void end(hipStream_t st, int phase, double bytes, int64_t launches) {
     if (!g_open) return;
     hipEvent_t e = get_event();
     if (!e) return;
-    hipEventRecord(e, st);
+    (void)hipEventRecord(e, st);
     g_recs.push_back(Rec{phase, g_open, e, bytes, launches});
     g_open = nullptr;
 }

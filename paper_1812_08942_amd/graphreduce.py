@@ -71,6 +71,14 @@ class gr_sgd_params(ctypes.Structure):
                 ("cg_tol", ctypes.c_double)]
 
 
+class gr_eig_report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("residual", ctypes.c_double),
+                ("lambda_max_bound", ctypes.c_double),
+                ("cholesky_warnings", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("restarts", ctypes.c_int32)]
+
+
 class gr_sgd_report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("n_lambda", ctypes.c_int32),
                 ("cg_iterations_max", ctypes.c_int32),
@@ -118,6 +126,11 @@ _SIGNATURES = {
                        _SZ, _P], ctypes.c_int),
     "gr_rq_backward": ([_I64, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P],
                        ctypes.c_int),
+    "gr_eig_workspace": ([_I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_laplacian_eigs": ([_G, _I32, _I32, ctypes.c_double, _I32, _I32, _U64,
+                           ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(gr_eig_report), _P, _SZ, _P],
+                          ctypes.c_int),
     "gr_sgd_workspace": ([_I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)],
                          ctypes.c_int),
     "gr_sgd_scale": ([_G, _G, _P, _I64, _P, _P, _P,
@@ -540,3 +553,39 @@ def gr_sgd_scale(G_graph: DeviceGraph, P_graph: DeviceGraph, p_edges: EdgeList,
             "lambda_n": list(rep.lambda_n[:rep.n_lambda]),
             "lambda_1": list(rep.lambda_1[:rep.iterations + 1]),
             "cg_iterations_max": int(rep.cg_iterations_max)}
+
+
+def gr_eig_workspace(n, n_eig) -> int:
+    out = _SZ(0)
+    _check(load().gr_eig_workspace(n, n_eig, ctypes.byref(out)))
+    return int(out.value)
+
+
+GR_EIG_AUTO, GR_EIG_CHEBYSHEV, GR_EIG_LOBPCG = 0, 1, 2
+EIG_METHODS = {"auto": GR_EIG_AUTO, "chebyshev": GR_EIG_CHEBYSHEV,
+               "lobpcg": GR_EIG_LOBPCG}
+
+
+def gr_laplacian_eigs(g: DeviceGraph, n_eig=10, method="auto", tol=1e-12,
+                      max_iter=1000, degree=80, seed=1):
+    """The n_eig smallest Laplacian eigenvalues on the complement of the
+    constant vector (FP64, GPU).  Returns (numpy array, report dict)."""
+    import numpy as np
+
+    nbytes = gr_eig_workspace(g.n, n_eig)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.row_ptr.device)
+    out = (ctypes.c_double * n_eig)()
+    rep = gr_eig_report()
+    cg = g.c()
+    _check(load().gr_laplacian_eigs(ctypes.byref(cg), n_eig, EIG_METHODS[method],
+                                    float(tol), int(max_iter), int(degree),
+                                    seed & (2**64 - 1), out, ctypes.byref(rep),
+                                    _ptr(ws), nbytes, _stream()))
+    names = {GR_EIG_CHEBYSHEV: "chebyshev", GR_EIG_LOBPCG: "lobpcg"}
+    return np.array(out[:], dtype=np.float64), {
+        "iterations": int(rep.iterations), "block": int(rep.block),
+        "residual": float(rep.residual),
+        "lambda_max_bound": float(rep.lambda_max_bound),
+        "cholesky_warnings": int(rep.cholesky_warnings),
+        "method": names.get(int(rep.method), "none"),
+        "restarts": int(rep.restarts)}

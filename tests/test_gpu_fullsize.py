@@ -1,0 +1,244 @@
+"""Parity at the benchmark's full sizes, in the configuration the benchmark
+runs: the power-law graph (434,000 nodes, about 32M stored entries, K = 16
+float32 vectors, largest-degree-first greedy colouring) step by step
+against the oracle, and the 256^3 grid (16.7M nodes, 100M entries, K = 32
+bfloat16 vectors, parity colouring) through properties the oracle can check
+at that size.  Each step is fed the GPU's own input for it (so a rounding
+difference upstream cannot hide or fake a mismatch downstream):
+colouring, aggregation ids and coarse structure bit-exact, floats within
+the tolerances of the small-size parity tests.  The one-level gr_reduce
+(the entry point the benchmark times) must reproduce the step-by-step
+aggregation bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import graphs as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def _G():
+    from paper_1812_08942_amd import graphreduce as G
+    return G
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _adj(g):
+    import scipy.sparse as sp
+    return sp.csr_matrix((g.w.astype(np.float64), g.col, g.row_ptr),
+                         shape=(g.n, g.n))
+
+
+def _smooth_scale(g, X):
+    """max(|X_vk|, sum_j w_vj |X_jk| / d_v) per element."""
+    A = _adj(g)
+    d = np.asarray(A.sum(axis=1)).ravel()
+    d[d == 0] = 1.0
+    return np.maximum(np.abs(X), (A @ np.abs(X)) / d[:, None])
+
+
+def _check_valid_aggregation(g, agg, n_c):
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as cg
+    assert agg.min() == 0 and agg.max() == n_c - 1
+    first = np.unique(agg, return_index=True)[1]
+    assert np.all(np.diff(first) > 0)          # numbered by smallest member
+    rows = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.row_ptr))
+    keep = agg[rows] == agg[g.col]
+    A = sp.csr_matrix((np.ones(int(keep.sum()), np.int8),
+                       (rows[keep], g.col[keep])), shape=(g.n, g.n))
+    assert cg.connected_components(A, directed=False)[0] == n_c
+
+
+def _check_distance(d, rd):
+    assert np.all(np.abs(d - rd) <= 2e-6 * np.sqrt(rd) + 1e-5 * rd + 1e-12), \
+        f"worst {np.max(np.abs(d - rd) / (np.sqrt(rd) + 1e-30))}"
+
+
+@pytest.fixture(scope="module")
+def power_law():
+    return W.build_graph("chunglu434k"), W.WORKLOADS["chunglu434k"]
+
+
+@pytest.fixture(scope="module")
+def grid256():
+    return W.build_graph("grid256"), W.WORKLOADS["grid256"]
+
+
+@pytest.mark.timeout(900)
+def test_power_law_full_size_level0_steps(power_law):
+    g, wl = power_law
+    dev, G = _dev(), _G()
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    w64 = g.w.astype(np.float64)
+    cseed, vseed = O.level_seed(wl.colour_seed, 0), O.level_seed(wl.vec_seed, 0)
+    T = O.target_size(g.n, wl.ratio)
+
+    say(f"full-size colouring {g.name} n={g.n} nnz={g.nnz} (LDF)")
+    col, nc = G.gr_colour_greedy(dg, cseed, True)
+    rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, cseed, True)
+    assert nc == rnc and np.array_equal(col.cpu().numpy(), rc)
+
+    say(f"full-size init K={wl.K}")
+    X = G.gr_init_vectors(g.n, wl.K, vseed, "f32", dev)
+    X0 = O.init_vectors(g.n, wl.K, vseed)
+    assert np.max(np.abs(X.cpu().numpy() - X0)) <= 2.0**-24 * np.max(np.abs(X0))
+
+    say(f"full-size smoothing sweeps={wl.sweeps}")
+    X0q = X.cpu().numpy().astype(np.float64)
+    G.gr_smooth(dg, col, nc, X, wl.sweeps)
+    got = X.cpu().numpy()
+    ref = O.smooth(g.n, g.row_ptr, g.col, w64, rc, rnc, X0q, wl.sweeps)
+    err = np.abs(got - ref)
+    scale = _smooth_scale(g, ref)
+    assert np.all(err <= 1e-5 * scale + 1e-30), np.max(err / (scale + 1e-30))
+
+    say("full-size affinity / distance on the GPU's vectors")
+    _, d, best, _ = G.gr_affinity(dg, X, want_a=False)
+    dn = d.cpu().numpy()
+    _check_distance(dn, O.distance(g.n, g.row_ptr, g.col, got.astype(np.float64)))
+    assert np.array_equal(best.cpu().numpy(), O.best(g.n, g.row_ptr, g.col, dn))
+
+    say(f"full-size aggregation T={T}")
+    agg, n_c = G.gr_aggregate(dg, d, T)
+    ra = O.aggregate(g.n, g.row_ptr, g.col, dn, T)
+    agg = agg.cpu().numpy()
+    assert n_c == ra.n_coarse and np.array_equal(agg, ra.agg)
+
+    say(f"full-size Galerkin n_c={n_c}")
+    cg = G.gr_galerkin(dg, torch.from_numpy(agg).to(dev), n_c)
+    rp, cl, cw = O.galerkin(g.n, g.row_ptr, g.col, w64, agg, n_c)
+    assert np.array_equal(cg.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(cg.col.cpu().numpy(), cl)
+    assert np.allclose(cg.w.cpu().numpy(), cw, rtol=1e-5, atol=0)
+
+    say("one-level gr_reduce reproduces the steps")
+    out = G.gr_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed,
+                      wl.colour_seed, largest_degree_first=True, max_levels=1)
+    assert out.levels == 1 and out.coarse.n == n_c
+    assert np.array_equal(out.agg.cpu().numpy(), agg)
+    assert np.array_equal(out.coarse.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(out.coarse.col.cpu().numpy(), cl)
+    # its Galerkin sums run over the colour-major relabelled entries, in
+    # another order: float32 sums agree to rounding, not bit for bit
+    assert np.allclose(out.coarse.w.cpu().numpy(), cw, rtol=1e-5, atol=0)
+
+
+@pytest.mark.timeout(900)
+def test_power_law_full_size_multilevel_and_eigenvalues(power_law):
+    g, wl = power_law
+    dev, G = _dev(), _G()
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    T = O.target_size(g.n, wl.ratio)
+    say(f"full-size gr_reduce {g.name} T={T}")
+    outs = [G.gr_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed,
+                        wl.colour_seed, largest_degree_first=True)
+            for _ in range(2)]
+    a0, a1 = (o.agg.cpu().numpy() for o in outs)
+    assert np.array_equal(a0, a1)                      # deterministic
+    out = outs[0]
+    n_c = out.coarse.n
+    assert n_c == T or (n_c > T and out.warnings)
+    _check_valid_aggregation(g, a0, n_c)
+    rp, cl, cw = O.galerkin(g.n, g.row_ptr, g.col, g.w.astype(np.float64), a0, n_c)
+    crp, ccl = out.coarse.row_ptr.cpu().numpy(), out.coarse.col.cpu().numpy()
+    ccw = out.coarse.w.cpu().numpy()
+    assert np.array_equal(crp, rp) and np.array_equal(ccl, cl)
+    assert np.allclose(ccw, cw, rtol=1e-5, atol=0)
+
+    say(f"eigenvalues of the reduced graph n={n_c} nnz={cl.size}")
+    lam, rep = G.gr_laplacian_eigs(out.coarse, 10)
+    say(f"  {rep}")
+    ref = O.laplacian_eigs(n_c, crp, ccl, ccw, 10)
+    assert np.allclose(lam, ref, rtol=1e-9, atol=0), (lam, ref)
+
+
+@pytest.mark.timeout(900)
+def test_grid256_full_size_bf16(grid256):
+    g, wl = grid256
+    dev, G = _dev(), _G()
+    assert wl.dtype == "bf16"
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    colours = torch.from_numpy(g.colours).to(dev)
+    vseed = O.level_seed(wl.vec_seed, 0)
+    T = O.target_size(g.n, wl.ratio)
+
+    say(f"full-size bf16 init {g.name} n={g.n} nnz={g.nnz} K={wl.K}")
+    X = G.gr_init_vectors(g.n, wl.K, vseed, "bf16", dev)
+    X0 = O.init_vectors(g.n, wl.K, vseed)
+    # round-to-nearest-even of the centred value; the centring mean may
+    # differ in its last bits, so at most one bf16 step anywhere
+    assert np.max(np.abs(X.float().cpu().numpy() - X0)) <= 2.0**-8 * np.max(np.abs(X0))
+    del X0
+
+    say(f"full-size bf16 smoothing sweeps={wl.sweeps}")
+    G.gr_smooth(dg, colours, g.n_colours, X, wl.sweeps)
+    Xs = X.float().cpu().numpy()
+    assert np.all(np.isfinite(Xs))
+    # the last colour step leaves every node of the last colour at the
+    # weighted mean of its (final) neighbours, rounded to bfloat16
+    rng = np.random.default_rng(11)
+    last = np.flatnonzero(g.colours == g.n_colours - 1)
+    v = np.sort(rng.choice(last, 200_000, replace=False))
+    A = _adj(g)[v]
+    dv = np.asarray(A.sum(axis=1)).ravel()
+    t = (A @ Xs.astype(np.float64)) / dv[:, None]
+    mag = (A @ np.abs(Xs).astype(np.float64)) / dv[:, None]
+    assert np.all(np.abs(Xs[v] - t) <= 2.0**-7 * np.abs(t) + 2.0**-20 * mag + 1e-30)
+
+    say("full-size affinity / distance on the GPU's bf16 vectors")
+    _, d, best, _ = G.gr_affinity(dg, X, want_a=False)
+    dn = d.cpu().numpy()
+    _check_distance(dn, O.distance(g.n, g.row_ptr, g.col, Xs.astype(np.float64)))
+    assert np.array_equal(best.cpu().numpy(), O.best(g.n, g.row_ptr, g.col, dn))
+    del Xs
+
+    say(f"full-size aggregation T={T}")
+    agg, n_c = G.gr_aggregate(dg, d, T)
+    ra = O.aggregate(g.n, g.row_ptr, g.col, dn, T)
+    agg = agg.cpu().numpy()
+    assert n_c == ra.n_coarse and np.array_equal(agg, ra.agg)
+
+    say(f"full-size Galerkin n_c={n_c}")
+    cg = G.gr_galerkin(dg, torch.from_numpy(agg).to(dev), n_c)
+    rp, cl, cw = O.galerkin(g.n, g.row_ptr, g.col, g.w.astype(np.float64), agg, n_c)
+    assert np.array_equal(cg.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(cg.col.cpu().numpy(), cl)
+    assert np.allclose(cg.w.cpu().numpy(), cw, rtol=1e-5, atol=0)
+
+
+@pytest.mark.timeout(900)
+def test_grid256_full_size_reduce(grid256):
+    g, wl = grid256
+    dev, G = _dev(), _G()
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    colours = torch.from_numpy(g.colours).to(dev)
+    T = O.target_size(g.n, wl.ratio)
+    say(f"full-size gr_reduce {g.name} bf16 K={wl.K} T={T}")
+    out = G.gr_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed, wl.colour_seed,
+                      dtype="bf16", colours=colours, n_colours=g.n_colours)
+    agg = out.agg.cpu().numpy()
+    n_c = out.coarse.n
+    assert n_c == T or (n_c > T and out.warnings)
+    _check_valid_aggregation(g, agg, n_c)
+    rp, cl, cw = O.galerkin(g.n, g.row_ptr, g.col, g.w.astype(np.float64), agg, n_c)
+    crp, ccl = out.coarse.row_ptr.cpu().numpy(), out.coarse.col.cpu().numpy()
+    ccw = out.coarse.w.cpu().numpy()
+    assert np.array_equal(crp, rp) and np.array_equal(ccl, cl)
+    assert np.allclose(ccw, cw, rtol=1e-5, atol=0)
+    say(f"eigenvalues of the reduced grid n={n_c}")
+    lam, rep = G.gr_laplacian_eigs(out.coarse, 10)
+    say(f"  {rep}")
+    ref = O.laplacian_eigs(n_c, crp, ccl, ccw, 10)
+    assert np.allclose(lam, ref, rtol=1e-9, atol=0), (lam, ref)
