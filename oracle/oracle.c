@@ -81,19 +81,11 @@ int or_validate_csr(int64_t n, const int32_t *row_ptr, const int32_t *col,
  * Reading taken: a multicolour order, colours 0..C-1 ascending in every
  * sweep, nodes of one colour mutually non-adjacent, so the result does not
  * depend on the order inside a colour.  When no colouring is prescribed the
- * colouring is greedy, built in synchronous rounds from a snapshot of the
- * colours at the start of each round:
- *   1. every uncoloured node proposes the smallest colour absent from its
- *      coloured neighbours;
- *   2. it keeps the proposal unless an uncoloured neighbour of higher
- *      priority proposes the same colour;
- *   3. kept proposals are committed together.
- * Priority is (h(v), v), h(v) = splitmix64 output v for the colour seed, or
- * (deg(v), h(v), v) in largest-degree-first mode.  The highest-priority
- * uncoloured node always keeps its proposal, so every round makes progress;
- * two adjacent proposals of one colour never both commit, so the colouring
- * is proper; and each node's colour is the smallest absent among its
- * neighbours coloured before it (first fit). */
+ * colouring is sequential greedy (first fit) in decreasing priority: every
+ * node takes the smallest colour absent among its neighbours of higher
+ * priority, which are all coloured before it.  Priority is (h(v), v),
+ * h(v) = splitmix64 output v for the colour seed, or (deg(v), h(v), v) in
+ * largest-degree-first mode (the order of Welsh and Powell). */
 typedef struct { uint64_t a, b, c; } or_prio;
 
 static or_prio prio_of(const int32_t *row_ptr, int64_t v, uint64_t seed, int ldf)
@@ -106,11 +98,13 @@ static or_prio prio_of(const int32_t *row_ptr, int64_t v, uint64_t seed, int ldf
     return p;
 }
 
-static int prio_higher(or_prio x, or_prio y)
+static int prio_cmp_desc(const void *x, const void *y)
 {
-    if (x.a != y.a) return x.a > y.a;
-    if (x.b != y.b) return x.b > y.b;
-    return x.c > y.c;
+    const or_prio *p = (const or_prio *)x, *q = (const or_prio *)y;
+    if (p->a != q->a) return p->a > q->a ? -1 : 1;
+    if (p->b != q->b) return p->b > q->b ? -1 : 1;
+    if (p->c != q->c) return p->c > q->c ? -1 : 1;
+    return 0;
 }
 
 int or_colour_greedy(int64_t n, const int32_t *row_ptr, const int32_t *col,
@@ -120,53 +114,32 @@ int or_colour_greedy(int64_t n, const int32_t *row_ptr, const int32_t *col,
     int32_t maxdeg = 0;
     for (int64_t v = 0; v < n; ++v)
         if (row_ptr[v + 1] - row_ptr[v] > maxdeg) maxdeg = row_ptr[v + 1] - row_ptr[v];
-    int32_t *tent = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    int32_t *keep = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    or_prio *order = (or_prio *)malloc(sizeof(or_prio) * (size_t)(n > 0 ? n : 1));
     uint8_t *used = (uint8_t *)calloc((size_t)maxdeg + 2, 1);
-    if (!tent || !keep || !used) { free(tent); free(keep); free(used); return OR_ENOMEM; }
-    for (int64_t v = 0; v < n; ++v) colours[v] = -1;
-    int64_t left = n;
-    while (left > 0) {
-        /* 1. proposals from the snapshot */
-        for (int64_t v = 0; v < n; ++v) {
-            tent[v] = -1;
-            if (colours[v] >= 0) continue;
-            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-                int32_t c = colours[col[e]];
-                if (c >= 0 && c <= maxdeg) used[c] = 1;
-            }
-            int32_t c = 0;
-            while (used[c]) ++c;
-            tent[v] = c;
-            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-                int32_t cc = colours[col[e]];
-                if (cc >= 0 && cc <= maxdeg) used[cc] = 0;
-            }
-        }
-        /* 2. conflicts lost to higher-priority uncoloured neighbours */
-        for (int64_t v = 0; v < n; ++v) {
-            keep[v] = 0;
-            if (colours[v] >= 0) continue;
-            or_prio pv = prio_of(row_ptr, v, seed, largest_degree_first);
-            int k = 1;
-            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1] && k; ++e) {
-                int32_t u = col[e];
-                if (colours[u] < 0 && tent[u] == tent[v] &&
-                    prio_higher(prio_of(row_ptr, u, seed, largest_degree_first), pv))
-                    k = 0;
-            }
-            keep[v] = k;
-        }
-        /* 3. commit */
-        for (int64_t v = 0; v < n; ++v)
-            if (keep[v]) { colours[v] = tent[v]; --left; }
+    if (!order || !used) { free(order); free(used); return OR_ENOMEM; }
+    for (int64_t v = 0; v < n; ++v) {
+        colours[v] = -1;
+        order[v] = prio_of(row_ptr, v, seed, largest_degree_first);
     }
+    qsort(order, (size_t)n, sizeof(or_prio), prio_cmp_desc);
     int32_t nc = 0;
-    for (int64_t v = 0; v < n; ++v)
-        if (colours[v] + 1 > nc) nc = colours[v] + 1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = (int64_t)order[i].c;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t c = colours[col[e]];
+            if (c >= 0 && c <= maxdeg) used[c] = 1;
+        }
+        int32_t c = 0;
+        while (used[c]) ++c;
+        colours[v] = c;
+        if (c + 1 > nc) nc = c + 1;
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t cc = colours[col[e]];
+            if (cc >= 0 && cc <= maxdeg) used[cc] = 0;
+        }
+    }
     *n_colours = nc;
-    free(tent);
-    free(keep);
+    free(order);
     free(used);
     return OR_OK;
 }
@@ -407,7 +380,8 @@ static int int_cmp(const void *x, const void *y)
  * again a Laplacian: its off-diagonal weights are
  *   W[I,J] = sum of w_vj over stored (v,j) with agg(v) = I, agg(j) = J, I != J,
  * while edges inside an aggregate cancel against the diagonal.  Output is
- * CSR with rows and columns ascending and FP64 weights.  `c_row_ptr` has
+ * CSR with rows and columns ascending and FP64 weights, (I, J) and (J, I)
+ * bitwise equal (each computed once, as the upper one).  `c_row_ptr` has
  * n_c + 1 entries; `c_col`/`c_w` must hold nnz entries (an upper bound). */
 int or_galerkin(int64_t n, const int32_t *row_ptr, const int32_t *col,
                 const double *w, const int32_t *agg, int64_t n_c,
@@ -460,6 +434,20 @@ int or_galerkin(int64_t n, const int32_t *row_ptr, const int32_t *col,
         }
         c_row_ptr[I + 1] = (int32_t)out;
     }
+    /* L_R is symmetric: the weight of (I, J), I > J, is by definition the
+     * same sum as that of (J, I); store the upper one's value in both so the
+     * two directions carry identical bits */
+    for (int64_t I = 0; I < n_c; ++I)
+        for (int32_t t = c_row_ptr[I]; t < c_row_ptr[I + 1]; ++t) {
+            int32_t J = c_col[t];
+            if (J >= I) break;
+            int32_t lo = c_row_ptr[J], hi = c_row_ptr[J + 1] - 1;
+            while (lo <= hi) {
+                int32_t mid = lo + (hi - lo) / 2;
+                if (c_col[mid] == I) { c_w[t] = c_w[mid]; break; }
+                if (c_col[mid] < I) lo = mid + 1; else hi = mid - 1;
+            }
+        }
     *nnz_c = out;
     free(cnt); free(members); free(acc); free(mark); free(touched);
     return OR_OK;

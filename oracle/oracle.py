@@ -110,6 +110,9 @@ def validate_csr(n, row_ptr, col, w) -> int:
 
 
 def colour_greedy(n, row_ptr, col, seed, largest_degree_first=False):
+    """Sequential greedy (first-fit) colouring in decreasing priority
+    (h(v), v), or (deg(v), h(v), v) largest-degree-first; h = splitmix64
+    output v of `seed`."""
     colours = np.empty(n, np.int32)
     nc = ctypes.c_int32(0)
     _check(lib().or_colour_greedy(n, _ai32(row_ptr), _ai32(col),

@@ -1,6 +1,7 @@
 // Strongest-affinity aggregation and the Galerkin collapse P^T L P
 // (Sec. 3.2.2).  All integer work; the only floating-point arithmetic is the
-// coarse weight sum, done sequentially per (I, J) run in sorted order.
+// coarse weight sum, done once per unordered aggregate pair in a fixed
+// (sorted, tiled) order.
 #include "gr_internal.hpp"
 
 namespace gr {
@@ -197,14 +198,18 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
 }
 
 // ---------------------------------------------------------------- Galerkin
-// flag[e] = 1 for entries joining two different aggregates; 8 lanes per row.
+// The coarse weights are summed once per unordered aggregate pair: only
+// stored entries (v, j) with agg(v) < agg(j) (each fine edge between two
+// aggregates exactly once) enter the sort, and every summed (I, J) is then
+// written to both (I, J) and (J, I), so both directions carry equal bits.
+// flag[e] = 1 for such entries; 8 lanes per row.
 __global__ void k_rap_flags(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                             const int32_t* __restrict__ agg, int64_t n, int32_t* __restrict__ flag) {
     int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
     int l = threadIdx.x & 7;
     if (v >= n) return;
     int32_t I = agg[v];
-    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) flag[e] = agg[col[e]] != I;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) flag[e] = agg[col[e]] > I;
 }
 
 __global__ void k_rap_scatter(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -218,7 +223,7 @@ __global__ void k_rap_scatter(const int32_t* __restrict__ rp, const int32_t* __r
     int32_t e1 = rp[v + 1];
     for (int32_t e = rp[v] + l; e < e1; e += 8) {
         int32_t J = agg[col[e]];
-        if ((uint64_t)J != I) {
+        if ((uint64_t)J > I) {
             int32_t s = pos[e];
             keys[s] = (I << jbits) | (uint64_t)J;
             vals[s] = __float_as_uint(w[e]);
@@ -299,10 +304,13 @@ __global__ void __launch_bounds__(kT) k_seg_tile(const uint32_t* __restrict__ va
     }
 }
 
-// pass 2: one thread per run adds the run's pieces in tile order
+// pass 2: one thread per run adds the run's pieces in tile order; the run's
+// key (I << jbits | J, I < J) and sum go to ukey / uw, and its mirrored key
+// (J << jbits | I) with the run index to mkey / midx for the second sort
 __global__ void k_seg_runs(const uint64_t* __restrict__ keys, const int32_t* __restrict__ start,
                            const float* __restrict__ piece, int64_t runs, int64_t m, int jbits,
-                           int32_t* __restrict__ c_col, float* __restrict__ c_w) {
+                           uint64_t* __restrict__ ukey, float* __restrict__ uw,
+                           uint64_t* __restrict__ mkey, uint32_t* __restrict__ midx) {
     int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= runs) return;
     int64_t s = start[r];
@@ -312,27 +320,62 @@ __global__ void k_seg_runs(const uint64_t* __restrict__ keys, const int32_t* __r
         int64_t pe = min(e, (t + 1) * (int64_t)kSegTile) - 1;
         acc += piece[pe];
     }
-    uint64_t k = keys[s];
-    c_col[r] = (int32_t)(k & ((1ull << jbits) - 1));
-    c_w[r] = acc;
+    const uint64_t k = keys[s];
+    const uint64_t mask = (1ull << jbits) - 1;
+    ukey[r] = k;
+    uw[r] = acc;
+    mkey[r] = ((k & mask) << jbits) | (k >> jbits);
+    midx[r] = (uint32_t)r;
 }
 
-// first and one-past-last run of every coarse row
-__global__ void k_row_bounds(const uint64_t* __restrict__ keys, const int32_t* __restrict__ start,
-                             int64_t runs, int jbits, int32_t* __restrict__ rfirst,
-                             int32_t* __restrict__ rend) {
+// first and one-past-last position of every row in a key array sorted by
+// row (row = key >> jbits)
+__global__ void k_row_bounds(const uint64_t* __restrict__ keys, int64_t cnt, int jbits,
+                             int32_t* __restrict__ rfirst, int32_t* __restrict__ rend) {
     int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (r >= runs) return;
-    uint64_t I = keys[start[r]] >> jbits;
-    if (r == 0 || (keys[start[r - 1]] >> jbits) != I) rfirst[I] = (int32_t)r;
-    if (r == runs - 1 || (keys[start[r + 1]] >> jbits) != I) rend[I] = (int32_t)(r + 1);
+    if (r >= cnt) return;
+    uint64_t I = keys[r] >> jbits;
+    if (r == 0 || (keys[r - 1] >> jbits) != I) rfirst[I] = (int32_t)r;
+    if (r == cnt - 1 || (keys[r + 1] >> jbits) != I) rend[I] = (int32_t)(r + 1);
 }
 
-__global__ void k_row_counts(const int32_t* __restrict__ rfirst, const int32_t* __restrict__ rend,
+// coarse row I = [lower part: mirrored entries (I, J < I)] ++ [upper part:
+// summed runs (I, J > I)]; both parts already ascending in J
+__global__ void k_row_counts(const int32_t* __restrict__ ufirst, const int32_t* __restrict__ uend,
+                             const int32_t* __restrict__ lfirst, const int32_t* __restrict__ lend,
                              int64_t n_c, int32_t* __restrict__ cnt) {
     int64_t I = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (I >= n_c) return;
-    cnt[I] = rfirst[I] >= 0 ? rend[I] - rfirst[I] : 0;
+    cnt[I] = (ufirst[I] >= 0 ? uend[I] - ufirst[I] : 0) + (lfirst[I] >= 0 ? lend[I] - lfirst[I] : 0);
+}
+
+__global__ void k_place_upper(const uint64_t* __restrict__ ukey, const float* __restrict__ uw,
+                              int64_t runs, int jbits, const int32_t* __restrict__ c_row_ptr,
+                              const int32_t* __restrict__ ufirst, const int32_t* __restrict__ lfirst,
+                              const int32_t* __restrict__ lend, int32_t* __restrict__ c_col,
+                              float* __restrict__ c_w) {
+    int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (r >= runs) return;
+    const uint64_t k = ukey[r];
+    const int64_t I = (int64_t)(k >> jbits);
+    const int32_t nlow = lfirst[I] >= 0 ? lend[I] - lfirst[I] : 0;
+    const int64_t p = (int64_t)c_row_ptr[I] + nlow + (r - ufirst[I]);
+    c_col[p] = (int32_t)(k & ((1ull << jbits) - 1));
+    c_w[p] = uw[r];
+}
+
+__global__ void k_place_lower(const uint64_t* __restrict__ mkey, const uint32_t* __restrict__ midx,
+                              const float* __restrict__ uw, int64_t runs, int jbits,
+                              const int32_t* __restrict__ c_row_ptr,
+                              const int32_t* __restrict__ lfirst, int32_t* __restrict__ c_col,
+                              float* __restrict__ c_w) {
+    int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (t >= runs) return;
+    const uint64_t k = mkey[t];
+    const int64_t J = (int64_t)(k >> jbits);
+    const int64_t p = (int64_t)c_row_ptr[J] + (t - lfirst[J]);
+    c_col[p] = (int32_t)(k & ((1ull << jbits) - 1));
+    c_w[p] = uw[midx[t]];
 }
 
 int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_ptr,
@@ -344,8 +387,10 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     int32_t* pos = ws.take<int32_t>(nnz + 1);
     int32_t* small = ws.take<int32_t>(4);
     int32_t* row_cnt = ws.take<int32_t>(n_c + 1);
-    int32_t* rfirst = ws.take<int32_t>(n_c + 1);
-    int32_t* rend = ws.take<int32_t>(n_c + 1);
+    int32_t* ufirst = ws.take<int32_t>(n_c + 1);
+    int32_t* uend = ws.take<int32_t>(n_c + 1);
+    int32_t* lfirst = ws.take<int32_t>(n_c + 1);
+    int32_t* lend = ws.take<int32_t>(n_c + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin)");
     int32_t m = 0;
     if (nnz > 0) {
@@ -357,8 +402,10 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         GR_HIP(hipStreamSynchronize(st));
     }
     int32_t runs = 0;
-    GR_TRY(fill_i32(rfirst, -1, n_c + 1, st));
-    GR_TRY(fill_i32(rend, -1, n_c + 1, st));
+    GR_TRY(fill_i32(ufirst, -1, n_c + 1, st));
+    GR_TRY(fill_i32(uend, -1, n_c + 1, st));
+    GR_TRY(fill_i32(lfirst, -1, n_c + 1, st));
+    GR_TRY(fill_i32(lend, -1, n_c + 1, st));
     if (m > 0) {
         const int jbits = bits_for(n_c);
         uint64_t* k0 = ws.take<uint64_t>(m);
@@ -386,21 +433,41 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         GR_LAUNCHED("segment tiles");
         GR_HIP(hipMemcpyAsync(&runs, small + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
+        // the unsorted keys are no longer needed: the runs' keys reuse k0
+        uint64_t* ukey = k0;
+        uint64_t* mk0 = ws.take<uint64_t>(runs);
+        uint32_t* mi0 = ws.take<uint32_t>(runs);
+        uint64_t* mk1 = ws.take<uint64_t>(runs);
+        uint32_t* mi1 = ws.take<uint32_t>(runs);
+        float* uw = ws.take<float>(runs);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin mirror)");
         const unsigned nbr = blocks_for(runs, kT);
         hipLaunchKernelGGL(k_seg_runs, dim3(nbr), dim3(kT), 0, st, k1, start, piece, (int64_t)runs,
-                           (int64_t)m, jbits, c_col, c_w);
+                           (int64_t)m, jbits, ukey, uw, mk0, mi0);
         GR_LAUNCHED("segment runs");
-        hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, k1, start, (int64_t)runs, jbits,
-                           rfirst, rend);
-        GR_LAUNCHED("row bounds");
+        GR_TRY(radix_sort_pairs(mk0, mi0, mk1, mi1, runs, 2 * jbits, ws, st));
+        hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, ukey, (int64_t)runs, jbits,
+                           ufirst, uend);
+        GR_LAUNCHED("upper row bounds");
+        hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, mk1, (int64_t)runs, jbits,
+                           lfirst, lend);
+        GR_LAUNCHED("lower row bounds");
+        if (n_c > 0) {
+            hipLaunchKernelGGL(k_row_counts, dim3(blocks_for(n_c, kT)), dim3(kT), 0, st, ufirst,
+                               uend, lfirst, lend, n_c, row_cnt);
+            GR_LAUNCHED("row counts");
+        }
+        GR_TRY(scan_exclusive_i32(row_cnt, c_row_ptr, n_c, c_row_ptr + n_c, ws, st));
+        hipLaunchKernelGGL(k_place_upper, dim3(nbr), dim3(kT), 0, st, ukey, uw, (int64_t)runs, jbits,
+                           c_row_ptr, ufirst, lfirst, lend, c_col, c_w);
+        GR_LAUNCHED("place upper");
+        hipLaunchKernelGGL(k_place_lower, dim3(nbr), dim3(kT), 0, st, mk1, mi1, uw, (int64_t)runs,
+                           jbits, c_row_ptr, lfirst, c_col, c_w);
+        GR_LAUNCHED("place lower");
+    } else {
+        GR_TRY(fill_i32(c_row_ptr, 0, n_c + 1, st));
     }
-    if (n_c > 0) {
-        hipLaunchKernelGGL(k_row_counts, dim3(blocks_for(n_c, kT)), dim3(kT), 0, st, rfirst, rend,
-                           n_c, row_cnt);
-        GR_LAUNCHED("row counts");
-    }
-    GR_TRY(scan_exclusive_i32(row_cnt, c_row_ptr, n_c, c_row_ptr + n_c, ws, st));
-    *nnz_coarse = runs;
+    *nnz_coarse = 2 * (int64_t)runs;
     ws.used = mark;
     return GR_OK;
 }

@@ -80,13 +80,17 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 }
 
 // -------------------------------------------------------------- colouring
-// Greedy colouring in synchronous rounds from a snapshot of the colours:
-// (1) every uncoloured node proposes the smallest colour absent from its
-// coloured neighbours; (2) it keeps the proposal unless an uncoloured
-// neighbour of higher priority proposes the same colour; (3) kept proposals
-// are committed together.  Priority: (h(v), v), h(v) = splitmix64 output v of
-// the colour seed, or (deg(v), h(v), v) largest-degree-first.  Proposals and
-// conflicts use one wave per node, so hub rows cost deg/64 steps.
+// Sequential greedy colouring in decreasing priority (every node takes the
+// smallest colour absent among its higher-priority neighbours), computed in
+// Jones-Plassmann rounds: a node is coloured once all its higher-priority
+// neighbours are, so the result does not depend on timing.  Priority:
+// (h(v), v), h(v) = splitmix64 output v of the colour seed, or
+// (deg(v), h(v), v) largest-degree-first.  One pass counts each node's
+// higher-priority neighbours; each round colours the ready nodes (one wave
+// per node) and counts down their lower-priority neighbours, which join the
+// next round's frontier when their count reaches zero.  Every edge is read
+// a constant number of times over all rounds; rounds run in batches with
+// one host synchronisation per batch.
 struct Prio {
     uint32_t deg;
     uint64_t h;
@@ -115,70 +119,130 @@ __device__ inline uint64_t wave_or(uint64_t x) {
     return x;
 }
 
-__global__ void __launch_bounds__(kThreads) k_col_propose(const int32_t* __restrict__ rp,
-                                                          const int32_t* __restrict__ col,
-                                                          const int32_t* __restrict__ colours,
-                                                          const int32_t* __restrict__ work,
-                                                          int32_t nwork, int32_t* __restrict__ tent) {
-    const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (t >= nwork) return;  // whole waves leave together
-    const int32_t v = work[t];
-    const int32_t e0 = rp[v], e1 = rp[v + 1];
-    int32_t c = -1;
-    for (int32_t base = 0; c < 0; base += 256) {
-        uint64_t used[4] = {0, 0, 0, 0};
-        for (int32_t e = e0 + lane; e < e1; e += kWave) {
-            int32_t cj = colours[col[e]];
-            if (cj >= base && cj < base + 256) used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
-        }
-#pragma unroll
-        for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
-        for (int w = 0; w < 4 && c < 0; ++w)
-            if (~used[w]) c = base + w * 64 + __ffsll((unsigned long long)~used[w]) - 1;
-    }
-    if (lane == 0) tent[v] = c;
+constexpr int kJpThreads = 1024;   // block of a round
+constexpr int kJpWaves = kJpThreads / kWave;
+constexpr int32_t kJpBig = 512;    // degree above which a whole block takes a node
+
+// frontier lists come in pairs: nodes of degree <= kJpBig (one wave each)
+// and above (one block each); sizes[2 r] and sizes[2 r + 1] count round r's
+__device__ inline void jp_append(const int32_t* rp, int32_t u, int32_t* small, int32_t* big,
+                                 int32_t* sizes2) {
+    if (rp[u + 1] - rp[u] > kJpBig) big[atomicAdd(&sizes2[1], 1)] = u;
+    else small[atomicAdd(&sizes2[0], 1)] = u;
 }
 
-__global__ void __launch_bounds__(kThreads) k_col_resolve(const int32_t* __restrict__ rp,
-                                                          const int32_t* __restrict__ col,
-                                                          const int32_t* __restrict__ colours,
-                                                          const int32_t* __restrict__ tent,
-                                                          const int32_t* __restrict__ work,
-                                                          int32_t nwork, uint64_t seed, int ldf,
-                                                          int32_t* __restrict__ newc) {
+// cnt[v] = number of higher-priority neighbours; nodes without any form the
+// first frontier (order of appends is irrelevant to the result)
+__global__ void __launch_bounds__(kThreads) k_jp_count(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col, int64_t n,
+                                                       uint64_t seed, int ldf,
+                                                       int32_t* __restrict__ cnt,
+                                                       int32_t* __restrict__ small,
+                                                       int32_t* __restrict__ big,
+                                                       int32_t* __restrict__ sizes) {
     const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    if (t >= nwork) return;
-    const int32_t v = work[t];
-    const int32_t e0 = rp[v], e1 = rp[v + 1];
-    const int32_t tv = tent[v];
+    if (t >= n) return;  // whole waves leave together
+    const int32_t v = (int32_t)t;
     const Prio pv = prio_of(rp, v, seed, ldf);
-    bool lose = false;
-    for (int32_t e = e0 + lane; e < e1 && !lose; e += kWave) {
-        int32_t u = col[e];
-        if (colours[u] < 0 && tent[u] == tv && higher(prio_of(rp, u, seed, ldf), pv)) lose = true;
+    int32_t c = 0;
+    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave)
+        c += higher(prio_of(rp, col[e], seed, ldf), pv) ? 1 : 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if (lane == 0) {
+        cnt[v] = c;
+        if (c == 0) jp_append(rp, v, small, big, sizes);
     }
-    uint64_t any = __ballot(lose);
-    if (lane == 0) newc[v] = any ? -1 : tv;
 }
 
-__global__ void k_col_commit(const int32_t* __restrict__ work, int32_t nwork,
-                             const int32_t* __restrict__ newc, int32_t* __restrict__ colours,
-                             int32_t* __restrict__ next, int32_t* __restrict__ cnt) {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nwork) return;
-    const int32_t v = work[t];
-    const int32_t c = newc[v];
-    if (c >= 0) colours[v] = c;
-    else next[atomicAdd(cnt, 1)] = v;
+// bits of the colours of neighbours col[e], e = e0 + i*stride (i >= 0,
+// e < e1), that fall in the window [base, base + 256)
+__device__ inline void window_bits(const int32_t* __restrict__ col,
+                                   const int32_t* __restrict__ colours, int32_t e0, int32_t e1,
+                                   int32_t stride, int32_t base, uint64_t used[4]) {
+    used[0] = used[1] = used[2] = used[3] = 0;
+    for (int32_t e = e0; e < e1; e += stride) {
+        int32_t cj = colours[col[e]];
+        if (cj >= base && cj < base + 256) used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
 }
 
-__global__ void k_col_init(int64_t n, int32_t* __restrict__ colours, int32_t* __restrict__ work) {
+__device__ inline int32_t first_free(const uint64_t used[4], int32_t base) {
+    for (int w = 0; w < 4; ++w)
+        if (~used[w]) return base + w * 64 + __ffsll((unsigned long long)~used[w]) - 1;
+    return -1;
+}
+
+// one round: colour the frontier of round r (the coloured neighbours of a
+// frontier node are exactly its higher-priority ones) and count down the
+// lower-priority neighbours, appending those that become ready to round
+// r + 1's lists.  Large nodes first, one block each; then small nodes, one
+// wave each; both grid-stride.
+__global__ void __launch_bounds__(kJpThreads) k_jp_round(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, uint64_t seed, int ldf,
+    const int32_t* __restrict__ in_small, const int32_t* __restrict__ in_big,
+    int32_t* __restrict__ out_small, int32_t* __restrict__ out_big, int32_t* __restrict__ sizes,
+    int32_t r, int32_t* __restrict__ cnt, int32_t* __restrict__ colours) {
+    __shared__ uint64_t part[kJpWaves][4];
+    __shared__ int32_t found;
+    const int32_t n_small = sizes[2 * r], n_big = sizes[2 * r + 1];
+    int32_t* next = sizes + 2 * (r + 1);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    for (int32_t t = blockIdx.x; t < n_big; t += gridDim.x) {
+        const int32_t v = in_big[t];
+        const int32_t e0 = rp[v], e1 = rp[v + 1];
+        int32_t c = -1;
+        for (int32_t base = 0; c < 0; base += 256) {
+            uint64_t used[4];
+            window_bits(col, colours, e0 + (int32_t)threadIdx.x, e1, kJpThreads, base, used);
+            if (lane == 0)
+                for (int w = 0; w < 4; ++w) part[wave][w] = used[w];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint64_t all[4] = {0, 0, 0, 0};
+                for (int k = 0; k < kJpWaves; ++k)
+                    for (int w = 0; w < 4; ++w) all[w] |= part[k][w];
+                found = first_free(all, base);
+            }
+            __syncthreads();
+            c = found;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) colours[v] = c;
+        const Prio pv = prio_of(rp, v, seed, ldf);
+        for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += kJpThreads) {
+            const int32_t u = col[e];
+            if (higher(pv, prio_of(rp, u, seed, ldf)) && atomicSub(&cnt[u], 1) == 1)
+                jp_append(rp, u, out_small, out_big, next);
+        }
+    }
+    const int64_t nwaves = (int64_t)gridDim.x * kJpWaves;
+    for (int64_t t = (int64_t)blockIdx.x * kJpWaves + wave; t < n_small; t += nwaves) {
+        const int32_t v = in_small[t];
+        const int32_t e0 = rp[v], e1 = rp[v + 1];
+        int32_t c = -1;
+        for (int32_t base = 0; c < 0; base += 256) {
+            uint64_t used[4];
+            window_bits(col, colours, e0 + lane, e1, kWave, base, used);
+            c = first_free(used, base);
+        }
+        if (lane == 0) colours[v] = c;
+        const Prio pv = prio_of(rp, v, seed, ldf);
+        for (int32_t e = e0 + lane; e < e1; e += kWave) {
+            const int32_t u = col[e];
+            if (higher(pv, prio_of(rp, u, seed, ldf)) && atomicSub(&cnt[u], 1) == 1)
+                jp_append(rp, u, out_small, out_big, next);
+        }
+    }
+}
+
+__global__ void k_col_fill(int64_t n, int32_t* __restrict__ colours) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    colours[v] = -1;
-    work[v] = (int32_t)v;
+    if (v < n) colours[v] = -1;
 }
 
 __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out) {
@@ -190,48 +254,52 @@ __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out
     if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
 }
 
+constexpr int kJpBatch = 48;    // rounds between host synchronisations
+constexpr int kJpBlocks = 256;  // grid of a round (4096 waves, grid-stride)
+
 int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
                   int32_t* n_colours_host, Arena& ws, hipStream_t st) {
     const int64_t n = g->n;
     *n_colours_host = 0;
     if (n == 0) return GR_OK;
     size_t mark = ws.used;
-    int32_t* wk[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
-    int32_t* tent = ws.take<int32_t>(n);
-    int32_t* newc = ws.take<int32_t>(n);
-    int32_t* cnt = ws.take<int32_t>(4);
+    int32_t* small[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
+    int32_t* big[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
+    int32_t* cnt = ws.take<int32_t>(n);
+    // frontier sizes of rounds [0, n + 1] (a round colours at least one
+    // node, so there are at most n of them), two per round, plus the
+    // max-colour slot
+    int32_t* sizes = ws.take<int32_t>(2 * n + 8);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
-    hipLaunchKernelGGL(k_col_init, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, colours,
-                       wk[0]);
-    GR_LAUNCHED("colour init");
-    int32_t left = (int32_t)n;
-    for (int64_t round = 0; left > 0; ++round) {
-        if (round > n) return set_error(GR_EHIP, "colouring did not converge");
-        int32_t* in = wk[round & 1];
-        int32_t* out = wk[(round + 1) & 1];
-        const unsigned wb = blocks_for((int64_t)left * kWave, kThreads);
-        hipLaunchKernelGGL(k_col_propose, dim3(wb), dim3(kThreads), 0, st, g->row_ptr, g->col,
-                           colours, in, left, tent);
-        GR_LAUNCHED("colour propose");
-        hipLaunchKernelGGL(k_col_resolve, dim3(wb), dim3(kThreads), 0, st, g->row_ptr, g->col,
-                           colours, tent, in, left, seed, ldf, newc);
-        GR_LAUNCHED("colour resolve");
-        GR_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t), st));
-        hipLaunchKernelGGL(k_col_commit, dim3(blocks_for(left, kThreads)), dim3(kThreads), 0, st, in,
-                           left, newc, colours, out, cnt);
-        GR_LAUNCHED("colour commit");
-        int32_t now = 0;
-        GR_HIP(hipMemcpyAsync(&now, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipMemsetAsync(sizes, 0, sizeof(int32_t) * (2 * n + 8), st));
+    hipLaunchKernelGGL(k_col_fill, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, colours);
+    GR_LAUNCHED("colour fill");
+    hipLaunchKernelGGL(k_jp_count, dim3(blocks_for(n * kWave, kThreads)), dim3(kThreads), 0, st,
+                       g->row_ptr, g->col, n, seed, ldf, cnt, small[0], big[0], sizes);
+    GR_LAUNCHED("colour count");
+    int64_t r = 0;
+    for (;;) {
+        for (int b = 0; b < kJpBatch && r < n; ++b, ++r) {
+            hipLaunchKernelGGL(k_jp_round, dim3(kJpBlocks), dim3(kJpThreads), 0, st, g->row_ptr,
+                               g->col, seed, ldf, (const int32_t*)small[r & 1],
+                               (const int32_t*)big[r & 1], small[(r + 1) & 1], big[(r + 1) & 1],
+                               sizes, (int32_t)r, cnt, colours);
+            GR_LAUNCHED("colour round");
+        }
+        int32_t next[2] = {0, 0};
+        GR_HIP(hipMemcpyAsync(next, sizes + 2 * r, sizeof(next), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
-        if (now >= left) return set_error(GR_EHIP, "colouring made no progress");
-        left = now;
+        if (next[0] == 0 && next[1] == 0) break;  // nothing became ready: all coloured
+        if (r >= n) return set_error(GR_EHIP, "colouring did not finish in n rounds");
     }
-    GR_HIP(hipMemsetAsync(cnt + 3, 0xff, sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kThreads), 0, st, colours, n, cnt + 3);
+    int32_t* mxd = sizes + 2 * n + 6;
+    GR_HIP(hipMemsetAsync(mxd, 0xff, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kThreads), 0, st, colours, n, mxd);
     GR_LAUNCHED("max colour");
     int32_t mx = -1;
-    GR_HIP(hipMemcpyAsync(&mx, cnt + 3, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipMemcpyAsync(&mx, mxd, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GR_HIP(hipStreamSynchronize(st));
+    if (mx < 0) return set_error(GR_EHIP, "colouring left nodes uncoloured");
     *n_colours_host = mx + 1;
     ws.used = mark;
     return GR_OK;

@@ -15,6 +15,8 @@ import pytest
 from oracle import oracle as O
 from workloads import graphs as W
 
+from test_gpu_parity import assert_bitwise_symmetric
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
@@ -156,6 +158,7 @@ def test_power_law_full_size_multilevel_and_eigenvalues(power_law):
     ccw = out.coarse.w.cpu().numpy()
     assert np.array_equal(crp, rp) and np.array_equal(ccl, cl)
     assert np.allclose(ccw, cw, rtol=1e-5, atol=0)
+    assert_bitwise_symmetric(crp, ccl, ccw)
 
     say(f"eigenvalues of the reduced graph n={n_c} nnz={cl.size}")
     lam, rep = G.gr_laplacian_eigs(out.coarse, 10)
@@ -237,6 +240,7 @@ def test_grid256_full_size_reduce(grid256):
     ccw = out.coarse.w.cpu().numpy()
     assert np.array_equal(crp, rp) and np.array_equal(ccl, cl)
     assert np.allclose(ccw, cw, rtol=1e-5, atol=0)
+    assert_bitwise_symmetric(crp, ccl, ccw)
     say(f"eigenvalues of the reduced grid n={n_c}")
     lam, rep = G.gr_laplacian_eigs(out.coarse, 10)
     say(f"  {rep}")

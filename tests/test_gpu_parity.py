@@ -231,6 +231,18 @@ def test_galerkin_matches_oracle():
             assert np.array_equal(cg.row_ptr.cpu().numpy(), rp)
             assert np.array_equal(cg.col.cpu().numpy(), cl)
             assert np.allclose(cg.w.cpu().numpy(), w, rtol=1e-5, atol=0)
+            assert_bitwise_symmetric(rp, cl, cg.w.cpu().numpy())
+
+
+def assert_bitwise_symmetric(rp, cl, w):
+    """Both stored directions of every coarse edge carry the same bits."""
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    key = rows * n + cl
+    assert np.all(np.diff(key) > 0)
+    pos = np.searchsorted(key, cl.astype(np.int64) * n + rows)
+    assert np.array_equal(key[pos], cl.astype(np.int64) * n + rows)
+    assert np.array_equal(w.view(np.uint32), w[pos].view(np.uint32))
 
 
 def _reduce_case(g, K, ratio, dtype="f32", ldf=False):
@@ -318,6 +330,7 @@ def test_reduce_end_to_end_multilevel(case):
     assert np.array_equal(out.coarse.row_ptr.cpu().numpy(), rp)
     assert np.array_equal(out.coarse.col.cpu().numpy(), cl)
     assert np.allclose(out.coarse.w.cpu().numpy(), w, rtol=1e-5, atol=0)
+    assert_bitwise_symmetric(rp, cl, out.coarse.w.cpu().numpy())
     agree = partition_agreement(agg, ref.agg)
     print(f"[gpu-case] {case}: nodes whose aggregate equals the oracle's: {agree:.2%}")
     lam_gpu = O.laplacian_eigs(n_c, rp, cl, w, 10)

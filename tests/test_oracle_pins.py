@@ -89,6 +89,47 @@ def test_greedy_colouring_is_valid_and_first_fit(ldf):
             assert set(range(c[v])) <= nb
 
 
+def _priority_keys(g, seed, ldf):
+    deg = g.degrees() if ldf else np.zeros(g.n, np.int64)
+    return [(int(deg[v]), O.splitmix64(seed, v), v) for v in range(g.n)]
+
+
+@pytest.mark.parametrize("ldf", [False, True])
+def test_greedy_colouring_equals_jones_plassmann_rounds(ldf):
+    """The colouring is first fit in decreasing priority.  Pinned two ways:
+    (i) each node's colour is the smallest absent among its higher-priority
+    neighbours' colours; (ii) an independent round-synchronous schedule
+    (Jones-Plassmann: a node is coloured in the round after its last
+    higher-priority neighbour) reproduces it exactly."""
+    for g in zoo() + [G.chung_lu(1500, mean_deg=15, seed=4),
+                      G.knn2d(800, 8, seed=2)]:
+        c, nc = O.colour_greedy(g.n, g.row_ptr, g.col, 91, ldf)
+        key = _priority_keys(g, 91, ldf)
+        nbrs = [g.col[g.row_ptr[v]:g.row_ptr[v + 1]].tolist() for v in range(g.n)]
+        for v in range(g.n):
+            up = {int(c[u]) for u in nbrs[v] if key[u] > key[v]}
+            mex = 0
+            while mex in up:
+                mex += 1
+            assert c[v] == mex
+        jp = [-1] * g.n
+        left = set(range(g.n))
+        rounds = 0
+        while left:
+            ready = [v for v in left
+                     if all(jp[u] >= 0 for u in nbrs[v] if key[u] > key[v])]
+            assert ready
+            for v in ready:
+                used = {jp[u] for u in nbrs[v] if jp[u] >= 0}
+                k = 0
+                while k in used:
+                    k += 1
+                jp[v] = k
+            left -= set(ready)
+            rounds += 1
+        assert np.array_equal(np.array(jp, np.int32), c)
+
+
 def test_colouring_special_cases():
     k6 = G.complete(6)
     c, nc = O.colour_greedy(6, k6.row_ptr, k6.col, 3)
