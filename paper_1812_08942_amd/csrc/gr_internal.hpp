@@ -120,18 +120,30 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
                        Arena& ws, hipStream_t st);
 
 // Colour-major relabel: new row r holds old node perm[r]; rows of colour c
-// are [class_ptr[c], class_ptr[c+1]), with the long rows (degree above the
-// long-row threshold) first: [class_ptr[c], long_end[c]).  Host copies of
-// the boundaries are kept for launch planning.
+// are [class_ptr[c], class_ptr[c+1]), and inside a class the rows come in
+// decreasing degree tiers: tier 0 holds degrees above 2048, tier t in 1..8
+// degrees in (4096 >> (t + 1), 4096 >> t], tier 9 degrees up to 8.  The
+// long rows (degree above 128, tiers 0..4) thus come first:
+// [class_ptr[c], long_end[c]).  Host copies of the boundaries are kept for
+// launch planning.
+constexpr int kNT = 10;
+constexpr int kLongTiers = 5;
+__host__ __device__ inline int degree_tier(int32_t deg) {
+    int t = 0;
+    for (int32_t hi = 2048; t < kNT - 1 && deg <= hi; hi >>= 1) ++t;
+    return t;  // 0: > 2048, 1: (1024, 2048], ..., 9: <= 8
+}
+inline int32_t tier_max_degree(int t) { return t == 0 ? 0x7fffffff : (4096 >> t); }
+
 struct OrderedGraph {
     gr_graph g;          // relabelled CSR (device pointers into the arena)
     int32_t* perm;       // [n] new -> old
     int32_t* iperm;      // [n] old -> new
     int32_t n_colours;
     std::vector<int64_t> class_ptr_h;   // host [C+1]
+    std::vector<int64_t> tier_ptr_h;    // host [C*kNT+1]: row start of (class, tier)
     std::vector<int64_t> long_end_h;    // host [C]
     std::vector<int64_t> class_nnz_h;   // host [C]: stored entries per colour
-    std::vector<int64_t> normal_nnz_h;  // host [C]: entries of the normal rows
     int64_t n_long;      // long rows in all classes
     int32_t* long_rows;  // device [n_long]: their relabelled ids
     double mean_deg;

@@ -13,7 +13,7 @@
 
 namespace gr {
 
-constexpr int kLongRow = 128;     // rows above this degree get a workgroup each
+constexpr int kLongRow = 128;     // rows above this degree get a workgroup each (affinity)
 constexpr int kThreads = 256;
 
 // ------------------------------------------------------------- validation
@@ -85,12 +85,19 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 // Jones-Plassmann rounds: a node is coloured once all its higher-priority
 // neighbours are, so the result does not depend on timing.  Priority:
 // (h(v), v), h(v) = splitmix64 output v of the colour seed, or
-// (deg(v), h(v), v) largest-degree-first.  One pass counts each node's
-// higher-priority neighbours; each round colours the ready nodes (one wave
-// per node) and counts down their lower-priority neighbours, which join the
-// next round's frontier when their count reaches zero.  Every edge is read
-// a constant number of times over all rounds; rounds run in batches with
-// one host synchronisation per batch.
+// (deg(v), h(v), v) largest-degree-first.
+//  * One pass counts each node's higher-priority neighbours (cnt) and marks
+//    every stored entry that points to a lower-priority neighbour.
+//  * When a node takes colour c it sets bit c of the colour masks of its
+//    lower-priority neighbours and counts them down; a neighbour whose count
+//    reaches zero joins the next round's frontier, and its colour is then
+//    the first clear bit of its mask (a scan of its neighbours' colours
+//    only when more than kMaskBits colours are in use around it).
+//  * A round runs on the whole grid (a block per node of degree above
+//    kJpBig, a wave per node of degree above kJpTiny, kJpGroup lanes per
+//    other node), or, while the frontier is small, many rounds run back to
+//    back inside one block, separated by block barriers.
+// Every edge is touched a constant number of times over all rounds.
 struct Prio {
     uint32_t deg;
     uint64_t h;
@@ -121,43 +128,93 @@ __device__ inline uint64_t wave_or(uint64_t x) {
 
 constexpr int kJpThreads = 1024;   // block of a round
 constexpr int kJpWaves = kJpThreads / kWave;
-constexpr int32_t kJpBig = 512;    // degree above which a whole block takes a node
+constexpr int kMaskWords = 8;      // colour mask per node: colours [0, 512)
+constexpr int kMaskBits = 64 * kMaskWords;
+// node kinds by degree: 0 = up to kJpTiny (kJpGroup lanes each), 1 = up to
+// kJpBig (a wave each), 2 = above (a block each); each kind has its own
+// frontier list, sizes[3 r + kind] counting round r's
+constexpr int32_t kJpTiny = 32;
+constexpr int32_t kJpBig = 512;
+constexpr int kJpGroup = 8;
+constexpr int kKinds = 3;
+constexpr uint8_t kDown = 1;       // entry flag: the neighbour has lower priority
+// entry flag bits 1-2: the neighbour's kind
+#ifndef GR_JP_SOLO_COST
+#define GR_JP_SOLO_COST 48
+#endif
+constexpr int kSoloCost = GR_JP_SOLO_COST;  // one block runs a round when
+// tiny / kJpGroup... (in waves) + medium + kJpWaves * big <= kSoloCost
+constexpr int kSoloRounds = 64;    // rounds per single-block launch at most
 
-// frontier lists come in pairs: nodes of degree <= kJpBig (one wave each)
-// and above (one block each); sizes[2 r] and sizes[2 r + 1] count round r's
-__device__ inline void jp_append(const int32_t* rp, int32_t u, int32_t* small, int32_t* big,
-                                 int32_t* sizes2) {
-    if (rp[u + 1] - rp[u] > kJpBig) big[atomicAdd(&sizes2[1], 1)] = u;
-    else small[atomicAdd(&sizes2[0], 1)] = u;
+__host__ __device__ inline int node_kind(int32_t deg) {
+    return deg <= kJpTiny ? 0 : (deg <= kJpBig ? 1 : 2);
 }
 
-// cnt[v] = number of higher-priority neighbours; nodes without any form the
-// first frontier (order of appends is irrelevant to the result)
-__global__ void __launch_bounds__(kThreads) k_jp_count(const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col, int64_t n,
-                                                       uint64_t seed, int ldf,
-                                                       int32_t* __restrict__ cnt,
-                                                       int32_t* __restrict__ small,
-                                                       int32_t* __restrict__ big,
-                                                       int32_t* __restrict__ sizes) {
-    const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+// cnt[v] = number of higher-priority neighbours and the entry flags; nodes
+// without higher-priority neighbours form the first frontier (the order of
+// appends is irrelevant to the result; they are gathered per block so that
+// the global counters see one atomic per block and kind)
+__global__ void __launch_bounds__(kJpThreads) k_jp_count(const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col, int64_t n,
+                                                         uint64_t seed, int ldf,
+                                                         int32_t* __restrict__ cnt,
+                                                         uint8_t* __restrict__ eflag,
+                                                         int32_t* const* lists,
+                                                         int32_t* __restrict__ sizes) {
+    __shared__ int32_t s_cnt[kKinds], s_base[kKinds];
+    const int64_t t = ((int64_t)blockIdx.x * kJpThreads + threadIdx.x) / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    if (t >= n) return;  // whole waves leave together
+    if (threadIdx.x < kKinds) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int kind = 0, slot = -1;
     const int32_t v = (int32_t)t;
-    const Prio pv = prio_of(rp, v, seed, ldf);
-    int32_t c = 0;
-    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave)
-        c += higher(prio_of(rp, col[e], seed, ldf), pv) ? 1 : 0;
+    if (t < n) {
+        const Prio pv = prio_of(rp, v, seed, ldf);
+        int32_t c = 0;
+        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
+            const int32_t u = col[e];
+            const bool up = higher(prio_of(rp, u, seed, ldf), pv);
+            c += up ? 1 : 0;
+            eflag[e] = (uint8_t)((up ? 0 : kDown) | (node_kind(rp[u + 1] - rp[u]) << 1));
+        }
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-    if (lane == 0) {
-        cnt[v] = c;
-        if (c == 0) jp_append(rp, v, small, big, sizes);
+        for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+        if (lane == 0) {
+            cnt[v] = c;
+            if (c == 0) {
+                kind = node_kind(rp[v + 1] - rp[v]);
+                slot = atomicAdd(&s_cnt[kind], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kKinds && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&sizes[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (slot >= 0) lists[kind][s_base[kind] + slot] = v;
+}
+
+// append u to list `kind` of the next round where `want`; every lane of the
+// wave calls this together, and each list counter takes one atomic per wave
+__device__ inline void wave_append(bool want, int kind, int32_t u, int32_t* const* out,
+                                   int32_t* __restrict__ next) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int kd = 0; kd < kKinds; ++kd) {
+        const uint64_t m = __ballot(want && kind == kd);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&next[kd], (int32_t)__popcll(m));
+        base = __shfl(base, leader, kWave);
+        if (want && kind == kd) out[kd][base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = u;
     }
 }
 
 // bits of the colours of neighbours col[e], e = e0 + i*stride (i >= 0,
-// e < e1), that fall in the window [base, base + 256)
+// e < e1), that fall in the window [base, base + 256), or-combined over
+// aligned groups of G lanes
+template <int G>
 __device__ inline void window_bits(const int32_t* __restrict__ col,
                                    const int32_t* __restrict__ colours, int32_t e0, int32_t e1,
                                    int32_t stride, int32_t base, uint64_t used[4]) {
@@ -167,76 +224,222 @@ __device__ inline void window_bits(const int32_t* __restrict__ col,
         if (cj >= base && cj < base + 256) used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
     }
 #pragma unroll
-    for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) {
+            uint32_t lo = __shfl_xor((uint32_t)used[w], off, kWave);
+            uint32_t hi = __shfl_xor((uint32_t)(used[w] >> 32), off, kWave);
+            used[w] |= ((uint64_t)hi << 32) | lo;
+        }
 }
 
-__device__ inline int32_t first_free(const uint64_t used[4], int32_t base) {
+__device__ inline int32_t first_free4(const uint64_t used[4], int32_t base) {
     for (int w = 0; w < 4; ++w)
         if (~used[w]) return base + w * 64 + __ffsll((unsigned long long)~used[w]) - 1;
     return -1;
 }
 
-// one round: colour the frontier of round r (the coloured neighbours of a
-// frontier node are exactly its higher-priority ones) and count down the
-// lower-priority neighbours, appending those that become ready to round
-// r + 1's lists.  Large nodes first, one block each; then small nodes, one
-// wave each; both grid-stride.
-__global__ void __launch_bounds__(kJpThreads) k_jp_round(
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, uint64_t seed, int ldf,
-    const int32_t* __restrict__ in_small, const int32_t* __restrict__ in_big,
-    int32_t* __restrict__ out_small, int32_t* __restrict__ out_big, int32_t* __restrict__ sizes,
-    int32_t r, int32_t* __restrict__ cnt, int32_t* __restrict__ colours) {
+// first clear bit of a node's colour mask (the words were built by atomics:
+// read coherently), or -1 when all kMaskBits are set; lane gl of an aligned
+// group of G >= kMaskWords lanes reads word gl, the group takes the minimum
+template <int G>
+__device__ inline int32_t mask_first_free(uint64_t* m, int gl) {
+    int32_t f = 0x7fffffff;
+    if (gl < kMaskWords) {
+        const uint64_t x = __hip_atomic_load(m + gl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (~x) f = 64 * gl + __ffsll((unsigned long long)~x) - 1;
+    }
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) f = min(f, __shfl_xor(f, off, kWave));
+    return f == 0x7fffffff ? -1 : f;
+}
+
+// a coloured node tells its lower-priority neighbours (entries e0, e0 +
+// stride, ... < e1): mask bit, count down, append the ones that become
+// ready.  Every lane of the wave must call this with the same trip count
+// (trips = steps of kN * stride); lanes of no node pass e0 = e1.
+constexpr int kN = 4;
+__device__ inline void jp_notify(const int32_t* __restrict__ col, const uint8_t* __restrict__ eflag,
+                                 int32_t e0, int32_t e1, int32_t stride, int32_t trips, int32_t c,
+                                 int32_t* __restrict__ cnt, uint64_t* __restrict__ mask,
+                                 int32_t* const* out, int32_t* __restrict__ next) {
+    // four entries per step, so that their atomics are in flight together
+    for (int32_t s = 0; s < trips; ++s) {
+        const int32_t e = e0 + s * kN * stride;
+        uint8_t f[kN];
+        int32_t u[kN], old[kN];
+#pragma unroll
+        for (int k = 0; k < kN; ++k) {
+            const int32_t ek = e + k * stride;
+            const bool ok = ek < e1;
+            f[k] = ok ? eflag[ek] : (uint8_t)0;
+            u[k] = ok ? col[ek] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kN; ++k)
+            if ((f[k] & kDown) && c < kMaskBits)
+                atomicOr((unsigned long long*)&mask[(int64_t)u[k] * kMaskWords + (c >> 6)],
+                         1ull << (c & 63));
+#pragma unroll
+        for (int k = 0; k < kN; ++k) old[k] = (f[k] & kDown) ? atomicSub(&cnt[u[k]], 1) : 0;
+#pragma unroll
+        for (int k = 0; k < kN; ++k) wave_append(old[k] == 1, (f[k] >> 1) & 3, u[k], out, next);
+    }
+}
+
+// colour node v (valid) with an aligned group of G lanes (gl = lane in the
+// group); all lanes of the wave call this together, `trips` being the
+// wave's largest ceil(degree / (kN * G))
+template <int G>
+__device__ inline void jp_group_node(const int32_t* __restrict__ rp,
+                                     const int32_t* __restrict__ col,
+                                     const uint8_t* __restrict__ eflag, bool valid, int32_t v,
+                                     int gl, int32_t* __restrict__ cnt,
+                                     uint64_t* __restrict__ mask, int32_t* __restrict__ colours,
+                                     int32_t* const* out, int32_t* __restrict__ next) {
+    int32_t e0 = 0, e1 = 0, c = 0;
+    if (valid) {
+        e0 = rp[v];
+        e1 = rp[v + 1];
+        c = mask_first_free<G>(mask + (int64_t)v * kMaskWords, gl);
+        for (int32_t base = kMaskBits; c < 0; base += 256) {
+            uint64_t used[4];
+            window_bits<G>(col, colours, e0 + gl, e1, G, base, used);
+            c = first_free4(used, base);
+        }
+        if (gl == 0) colours[v] = c;
+    }
+    int32_t trips = (e1 - e0 + kN * G - 1) / (kN * G);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) trips = max(trips, __shfl_xor(trips, off, kWave));
+    jp_notify(col, eflag, e0 + gl, e1, G, trips, c, cnt, mask, out, next);
+}
+
+// colour the big node v with the whole block (all threads call it)
+__device__ inline void jp_big_node(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                   const uint8_t* __restrict__ eflag, int32_t v,
+                                   int32_t* __restrict__ cnt, uint64_t* __restrict__ mask,
+                                   int32_t* __restrict__ colours, int32_t* const* out,
+                                   int32_t* __restrict__ next, uint64_t (*part)[4],
+                                   int32_t* found) {
+    const int32_t e0 = rp[v], e1 = rp[v + 1];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int32_t c = mask_first_free<kWave>(mask + (int64_t)v * kMaskWords, lane);
+    for (int32_t base = kMaskBits; c < 0; base += 256) {
+        uint64_t used[4];
+        window_bits<kWave>(col, colours, e0 + (int32_t)threadIdx.x, e1, kJpThreads, base, used);
+        if (lane == 0)
+            for (int w = 0; w < 4; ++w) part[wave][w] = used[w];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t all[4] = {0, 0, 0, 0};
+            for (int k = 0; k < kJpWaves; ++k)
+                for (int w = 0; w < 4; ++w) all[w] |= part[k][w];
+            *found = first_free4(all, base);
+        }
+        __syncthreads();
+        c = *found;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) colours[v] = c;
+    const int32_t trips = (e1 - e0 + kN * kJpThreads - 1) / (kN * kJpThreads);
+    jp_notify(col, eflag, e0 + (int32_t)threadIdx.x, e1, kJpThreads, trips, c, cnt, mask, out,
+              next);
+}
+
+struct JpBufs {
+    int32_t* list[2][kKinds];  // frontier lists of even / odd rounds, per kind
+    int32_t* sizes;            // [3 r + kind]: frontier sizes of round r
+    int32_t* state;            // [0] current round, [1] set when a grid round ran
+    int32_t* cnt;
+    uint64_t* mask;
+    uint8_t* eflag;
+    int64_t max_rounds;
+};
+
+// all nodes of round r: big ones a block each, medium ones a wave each,
+// tiny ones kJpGroup lanes each, grid-stride over blk / nblk; every thread
+// of the grid (or of the one block) calls this
+__device__ inline void jp_round(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const JpBufs& jb, int64_t r, const int32_t* nk, int64_t blk,
+                                int64_t nblk, int32_t* __restrict__ colours, uint64_t (*part)[4],
+                                int32_t* found) {
+    int32_t* const* in = jb.list[r & 1];
+    int32_t* const* out = jb.list[(r + 1) & 1];
+    int32_t* next = jb.sizes + kKinds * (r + 1);
+    for (int64_t t = blk; t < nk[2]; t += nblk)
+        jp_big_node(rp, col, jb.eflag, in[2][t], jb.cnt, jb.mask, colours, out, next, part, found);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = blk * kJpWaves + threadIdx.x / kWave, nwaves = nblk * kJpWaves;
+    for (int64_t t = wave; t < nk[1]; t += nwaves)
+        jp_group_node<kWave>(rp, col, jb.eflag, true, in[1][t], lane, jb.cnt, jb.mask, colours, out,
+                             next);
+    constexpr int GPW = kWave / kJpGroup;
+    for (int64_t t0 = wave * GPW; t0 < nk[0]; t0 += nwaves * GPW) {
+        // whole waves stay in the loop together; groups past the end idle
+        const int64_t t = t0 + lane / kJpGroup;
+        const bool valid = t < nk[0];
+        jp_group_node<kJpGroup>(rp, col, jb.eflag, valid, valid ? in[0][t] : 0, lane % kJpGroup,
+                                jb.cnt, jb.mask, colours, out, next);
+    }
+}
+
+// one round on the whole grid, unless the frontier is empty
+__global__ void __launch_bounds__(kJpThreads) k_jp_round(const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         JpBufs jb, int32_t* __restrict__ colours) {
     __shared__ uint64_t part[kJpWaves][4];
     __shared__ int32_t found;
-    const int32_t n_small = sizes[2 * r], n_big = sizes[2 * r + 1];
-    int32_t* next = sizes + 2 * (r + 1);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    for (int32_t t = blockIdx.x; t < n_big; t += gridDim.x) {
-        const int32_t v = in_big[t];
-        const int32_t e0 = rp[v], e1 = rp[v + 1];
-        int32_t c = -1;
-        for (int32_t base = 0; c < 0; base += 256) {
-            uint64_t used[4];
-            window_bits(col, colours, e0 + (int32_t)threadIdx.x, e1, kJpThreads, base, used);
-            if (lane == 0)
-                for (int w = 0; w < 4; ++w) part[wave][w] = used[w];
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint64_t all[4] = {0, 0, 0, 0};
-                for (int k = 0; k < kJpWaves; ++k)
-                    for (int w = 0; w < 4; ++w) all[w] |= part[k][w];
-                found = first_free(all, base);
-            }
-            __syncthreads();
-            c = found;
-            __syncthreads();
+    const int64_t r = jb.state[0];
+    if (r >= jb.max_rounds) return;
+    int32_t nk[kKinds];
+    for (int k = 0; k < kKinds; ++k) nk[k] = jb.sizes[kKinds * r + k];
+    if (nk[0] + nk[1] + nk[2] == 0) return;
+    jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, part, &found);
+    if (blockIdx.x == 0 && threadIdx.x == 0) jb.state[1] = 1;
+}
+
+// one block: first account for a grid round that ran since the last call,
+// then run rounds back to back while the frontier is small
+__global__ void __launch_bounds__(kJpThreads) k_jp_solo(const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        JpBufs jb, int32_t* __restrict__ colours) {
+    __shared__ uint64_t part[kJpWaves][4];
+    __shared__ int32_t found;
+    __shared__ int64_t rs;
+    __shared__ int32_t go, snk[kKinds];
+    if (threadIdx.x == 0) {
+        if (jb.state[1]) {
+            jb.state[0] += 1;
+            jb.state[1] = 0;
         }
-        if (threadIdx.x == 0) colours[v] = c;
-        const Prio pv = prio_of(rp, v, seed, ldf);
-        for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += kJpThreads) {
-            const int32_t u = col[e];
-            if (higher(pv, prio_of(rp, u, seed, ldf)) && atomicSub(&cnt[u], 1) == 1)
-                jp_append(rp, u, out_small, out_big, next);
-        }
+        rs = jb.state[0];
     }
-    const int64_t nwaves = (int64_t)gridDim.x * kJpWaves;
-    for (int64_t t = (int64_t)blockIdx.x * kJpWaves + wave; t < n_small; t += nwaves) {
-        const int32_t v = in_small[t];
-        const int32_t e0 = rp[v], e1 = rp[v + 1];
-        int32_t c = -1;
-        for (int32_t base = 0; c < 0; base += 256) {
-            uint64_t used[4];
-            window_bits(col, colours, e0 + lane, e1, kWave, base, used);
-            c = first_free(used, base);
+    __syncthreads();
+    for (int k = 0; k < kSoloRounds; ++k) {
+        if (threadIdx.x == 0) {
+            const int64_t r = rs;
+            go = 0;
+            if (r < jb.max_rounds) {
+                for (int q = 0; q < kKinds; ++q)
+                    snk[q] = __hip_atomic_load(jb.sizes + kKinds * r + q, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                const int32_t tot = snk[0] + snk[1] + snk[2];
+                const int32_t cost = (snk[0] + kWave / kJpGroup - 1) / (kWave / kJpGroup) +
+                                     snk[1] + kJpWaves * snk[2];
+                go = (tot > 0 && cost <= kSoloCost) ? 1 : 0;
+            }
         }
-        if (lane == 0) colours[v] = c;
-        const Prio pv = prio_of(rp, v, seed, ldf);
-        for (int32_t e = e0 + lane; e < e1; e += kWave) {
-            const int32_t u = col[e];
-            if (higher(pv, prio_of(rp, u, seed, ldf)) && atomicSub(&cnt[u], 1) == 1)
-                jp_append(rp, u, out_small, out_big, next);
+        __syncthreads();
+        if (!go) break;
+        int32_t nk[kKinds] = {snk[0], snk[1], snk[2]};
+        jp_round(rp, col, jb, rs, nk, 0, 1, colours, part, &found);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            rs += 1;
+            jb.state[0] = (int32_t)rs;
         }
+        __syncthreads();
     }
 }
 
@@ -254,45 +457,63 @@ __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out
     if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
 }
 
-constexpr int kJpBatch = 48;    // rounds between host synchronisations
-constexpr int kJpBlocks = 256;  // grid of a round (4096 waves, grid-stride)
+#ifndef GR_JP_BLOCKS
+#define GR_JP_BLOCKS 256
+#endif
+constexpr int kJpBatch = 32;    // (single-block, grid) launch pairs between host checks
+constexpr int kJpBlocks = GR_JP_BLOCKS;  // grid of a round (grid-stride)
 
 int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
                   int32_t* n_colours_host, Arena& ws, hipStream_t st) {
-    const int64_t n = g->n;
+    const int64_t n = g->n, nnz = g->nnz;
     *n_colours_host = 0;
     if (n == 0) return GR_OK;
     size_t mark = ws.used;
-    int32_t* small[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
-    int32_t* big[2] = {ws.take<int32_t>(n), ws.take<int32_t>(n)};
-    int32_t* cnt = ws.take<int32_t>(n);
+    JpBufs jb;
+    for (int h = 0; h < 2; ++h)
+        for (int k = 0; k < kKinds; ++k) jb.list[h][k] = ws.take<int32_t>(n);
+    int32_t** dlists = ws.take<int32_t*>(kKinds);
+    jb.cnt = ws.take<int32_t>(n);
+    jb.mask = ws.take<uint64_t>((size_t)n * kMaskWords);
+    jb.eflag = ws.take<uint8_t>(nnz + 1);
     // frontier sizes of rounds [0, n + 1] (a round colours at least one
-    // node, so there are at most n of them), two per round, plus the
-    // max-colour slot
-    int32_t* sizes = ws.take<int32_t>(2 * n + 8);
+    // node, so there are at most n of them), three per round, then the
+    // round state and the max-colour slot
+    const int64_t nsz = kKinds * (n + 2) + 16;
+    jb.sizes = ws.take<int32_t>(nsz);
+    jb.state = jb.sizes + nsz - 8;
+    jb.max_rounds = n;
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
-    GR_HIP(hipMemsetAsync(sizes, 0, sizeof(int32_t) * (2 * n + 8), st));
+    GR_HIP(hipMemsetAsync(jb.sizes, 0, sizeof(int32_t) * nsz, st));
+    GR_HIP(hipMemsetAsync(jb.mask, 0, sizeof(uint64_t) * (size_t)n * kMaskWords, st));
+    GR_HIP(hipMemcpyAsync(dlists, jb.list[0], sizeof(int32_t*) * kKinds, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_col_fill, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, colours);
     GR_LAUNCHED("colour fill");
-    hipLaunchKernelGGL(k_jp_count, dim3(blocks_for(n * kWave, kThreads)), dim3(kThreads), 0, st,
-                       g->row_ptr, g->col, n, seed, ldf, cnt, small[0], big[0], sizes);
+    hipLaunchKernelGGL(k_jp_count, dim3(blocks_for(n * kWave, kJpThreads)), dim3(kJpThreads), 0, st,
+                       g->row_ptr, g->col, n, seed, ldf, jb.cnt, jb.eflag, (int32_t* const*)dlists,
+                       jb.sizes);
     GR_LAUNCHED("colour count");
-    int64_t r = 0;
-    for (;;) {
-        for (int b = 0; b < kJpBatch && r < n; ++b, ++r) {
+    for (int64_t batch = 0;; ++batch) {
+        for (int b = 0; b < kJpBatch; ++b) {
+            hipLaunchKernelGGL(k_jp_solo, dim3(1), dim3(kJpThreads), 0, st, g->row_ptr, g->col, jb,
+                               colours);
+            GR_LAUNCHED("colour rounds (one block)");
             hipLaunchKernelGGL(k_jp_round, dim3(kJpBlocks), dim3(kJpThreads), 0, st, g->row_ptr,
-                               g->col, seed, ldf, (const int32_t*)small[r & 1],
-                               (const int32_t*)big[r & 1], small[(r + 1) & 1], big[(r + 1) & 1],
-                               sizes, (int32_t)r, cnt, colours);
+                               g->col, jb, colours);
             GR_LAUNCHED("colour round");
         }
-        int32_t next[2] = {0, 0};
-        GR_HIP(hipMemcpyAsync(next, sizes + 2 * r, sizeof(next), hipMemcpyDeviceToHost, st));
+        int32_t stt[2] = {0, 0};
+        GR_HIP(hipMemcpyAsync(stt, jb.state, sizeof(stt), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
-        if (next[0] == 0 && next[1] == 0) break;  // nothing became ready: all coloured
-        if (r >= n) return set_error(GR_EHIP, "colouring did not finish in n rounds");
+        const int64_t r = (int64_t)stt[0] + stt[1];
+        if (r > n) return set_error(GR_EHIP, "colouring did not finish in n rounds");
+        int32_t fr[kKinds] = {0, 0, 0};
+        GR_HIP(hipMemcpyAsync(fr, jb.sizes + kKinds * r, sizeof(fr), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+        if (fr[0] == 0 && fr[1] == 0 && fr[2] == 0) break;  // nothing became ready: all coloured
+        if (batch > n) return set_error(GR_EHIP, "colouring made no progress");
     }
-    int32_t* mxd = sizes + 2 * n + 6;
+    int32_t* mxd = jb.sizes + nsz - 4;
     GR_HIP(hipMemsetAsync(mxd, 0xff, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kThreads), 0, st, colours, n, mxd);
     GR_LAUNCHED("max colour");
@@ -339,16 +560,15 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
 }
 
 // ------------------------------------------------------- colour-major order
-// Rows are relabelled by the key (colour, long?0:1, old id): the rows of one
-// colour become a contiguous range with the long rows (degree > kLongRow)
-// first.  Long rows get a whole workgroup each in the smoothing and affinity
-// kernels, so a hub's latency does not bound a whole colour step.
+// Rows are relabelled by the key (colour, degree tier, old id): the rows of
+// one colour become a contiguous range, in decreasing degree tiers, so that
+// one smoothing launch can give every tier its own lanes-per-row.
 __global__ void k_bucket_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ colours,
                               int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int32_t deg = rp[v + 1] - rp[v];
-    uint64_t b = (uint64_t)colours[v] * 2u + (deg > kLongRow ? 0u : 1u);
+    uint64_t b = (uint64_t)colours[v] * kNT + (uint64_t)degree_tier(deg);
     keys[v] = b;
     vals[v] = (uint32_t)v;
 }
@@ -399,25 +619,16 @@ __global__ void k_bucket_sizes(const int32_t* __restrict__ bfirst, const int32_t
     out[2 * b + 1] = f >= 0 ? (int64_t)(nrp[e] - nrp[f]) : 0;
 }
 
-__global__ void k_long_ids(const int32_t* __restrict__ lrows, int64_t nlong, int32_t* __restrict__ ids) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nlong) ids[i] = lrows[3 * i];
-}
-
-// long rows of the relabelled graph, compacted: their row ids and extents
-__global__ void k_long_rows(const int32_t* __restrict__ nrp, const int32_t* __restrict__ bfirst,
-                            const int32_t* __restrict__ bend, int32_t n_colours,
-                            const int32_t* __restrict__ long_off, int32_t* __restrict__ out) {
+// ids of the long rows, class by class: class c contributes the rows
+// [cls[2c], cls[2c] + cls[2c+1]) at offset off[c]
+__global__ void k_long_rows(const int64_t* __restrict__ cls, const int32_t* __restrict__ off,
+                            int32_t n_colours, int32_t* __restrict__ out) {
     int32_t c = blockIdx.y;
     if (c >= n_colours) return;
-    int32_t f = bfirst[2 * c], e = bend[2 * c];
-    if (f < 0) return;
-    for (int32_t r = f + blockIdx.x * blockDim.x + threadIdx.x; r < e; r += gridDim.x * blockDim.x) {
-        int32_t o = long_off[c] + (r - f);
-        out[3 * o] = r;
-        out[3 * o + 1] = nrp[r];
-        out[3 * o + 2] = nrp[r + 1];
-    }
+    const int64_t first = cls[2 * c], cnt = cls[2 * c + 1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[off[c] + i] = (int32_t)(first + i);
 }
 
 int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours, OrderedGraph* og,
@@ -431,7 +642,7 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
     float* nw = ws.take<float>(nnz);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (relabel)");
     size_t mark = ws.used;
-    const int32_t nb = 2 * n_colours;
+    const int32_t nb = kNT * n_colours;
     uint64_t* k0 = ws.take<uint64_t>(n);
     uint32_t* v0 = ws.take<uint32_t>(n);
     uint64_t* k1 = ws.take<uint64_t>(n);
@@ -473,44 +684,54 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
         GR_HIP(hipStreamSynchronize(st));
     }
     og->class_ptr_h.assign((size_t)n_colours + 1, 0);
+    og->tier_ptr_h.assign((size_t)nb + 1, 0);
     og->long_end_h.assign((size_t)n_colours, 0);
     og->class_nnz_h.assign((size_t)n_colours, 0);
-    og->normal_nnz_h.assign((size_t)n_colours, 0);
+    std::vector<int64_t> cls(2 * (size_t)n_colours + 2, 0);
     std::vector<int32_t> long_off(n_colours + 1, 0);
     int64_t total = 0, nlong = 0;
     for (int c = 0; c < n_colours; ++c) {
         og->class_ptr_h[c] = total;
-        og->long_end_h[c] = total + hs[4 * c];
-        og->class_nnz_h[c] = hs[4 * c + 1] + hs[4 * c + 3];
-        og->normal_nnz_h[c] = hs[4 * c + 3];
+        int64_t nz = 0, lr = 0;
+        for (int t = 0; t < kNT; ++t) {
+            const int b = c * kNT + t;
+            og->tier_ptr_h[b] = total;
+            total += hs[2 * b];
+            nz += hs[2 * b + 1];
+            if (t < kLongTiers) lr += hs[2 * b];
+        }
+        og->class_nnz_h[c] = nz;
+        og->long_end_h[c] = og->class_ptr_h[c] + lr;
+        cls[2 * c] = og->class_ptr_h[c];
+        cls[2 * c + 1] = lr;
         long_off[c] = (int32_t)nlong;
-        nlong += hs[4 * c];
-        total += hs[4 * c] + hs[4 * c + 2];
+        nlong += lr;
     }
     long_off[n_colours] = (int32_t)nlong;
     og->class_ptr_h[n_colours] = total;
+    og->tier_ptr_h[nb] = total;
     if (total != n) return set_error(GR_ECOLOUR, "colouring does not cover every node");
-    // device list of the long rows (relabelled ids), class by class
+    ws.used = mark;
+    // device list of the long rows (relabelled ids), class by class; it
+    // stays at the front of the region released above
     og->n_long = nlong;
     og->long_rows = nullptr;
     if (nlong > 0) {
+        og->long_rows = ws.take<int32_t>(nlong);
+        const size_t keep = ws.used;
         int32_t* loff = ws.take<int32_t>(n_colours + 1);
-        int32_t* lrows = ws.take<int32_t>(3 * nlong);
+        int64_t* dcls = ws.take<int64_t>(2 * (size_t)n_colours + 2);
         if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
         GR_HIP(hipMemcpyAsync(loff, long_off.data(), sizeof(int32_t) * (n_colours + 1),
                               hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_long_rows, dim3(8, n_colours), dim3(kThreads), 0, st, nrp, bfirst, bend,
-                           n_colours, loff, lrows);
+        GR_HIP(hipMemcpyAsync(dcls, cls.data(), sizeof(int64_t) * 2 * n_colours,
+                              hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_long_rows, dim3(8, n_colours), dim3(kThreads), 0, st,
+                           (const int64_t*)dcls, (const int32_t*)loff, n_colours, og->long_rows);
         GR_LAUNCHED("long rows");
-        // keep only the ids, at the front of the persistent region
-        ws.used = mark;
-        og->long_rows = ws.take<int32_t>(nlong);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
-        hipLaunchKernelGGL(k_long_ids, dim3(blocks_for(nlong, kThreads)), dim3(kThreads), 0, st,
-                           (const int32_t*)lrows, nlong, og->long_rows);
-        GR_LAUNCHED("long ids");
-        GR_HIP(hipStreamSynchronize(st));  // lrows lies in memory released below
-        mark = ws.used;
+        // the host vectors and the small tables are released below
+        GR_HIP(hipStreamSynchronize(st));
+        ws.used = keep;
     }
     og->g.n = n;
     og->g.nnz = nnz;
@@ -518,7 +739,6 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
     og->g.col = ncol;
     og->g.w = nw;
     og->mean_deg = n > 0 ? (double)nnz / (double)n : 0.0;
-    ws.used = mark;
     return GR_OK;
 }
 
@@ -619,30 +839,49 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
 
 // ----------------------------------------------------------- GS colour step
 // One Gauss-Seidel colour step (Sec. 3.2.1): every node v of the colour with
-// d_v > 0 becomes sum_j w_vj x_j / d_v.  One launch of kBig-thread blocks per
-// step; block roles:
-//  * blocks [0, n_long): one long row each (degree > kLongRow); P = kBig/Q
-//    neighbour slots, four neighbours per slot per round, partial sums
-//    combined by a fixed shuffle tree and then across waves in LDS;
-//  * the remaining blocks: normal rows, L = Q*P lanes per row, four
-//    neighbours per lane per round so that four gathers are in flight.
+// d_v > 0 becomes sum_j w_vj x_j / d_v.  One launch of kBig-thread blocks
+// per step.  The rows of the colour come in degree tiers; tier t gets L_t
+// lanes per row (a power of two from Q to kBig, about half the tier's
+// largest degree times Q / kU, so that a row takes about two rounds of kU
+// gathers per lane whatever its degree) and its own range of blocks, each
+// block holding kBig / L_t rows.  Lane l of a row owns the 16-byte chunk
+// l % Q of the vector rows and the neighbour slots l / Q, + L/Q, ...; the
+// partial sums are combined by a fixed shuffle tree inside the wave and,
+// for rows wider than a wave, across its waves in LDS.
 constexpr int kU = 4;
 constexpr int kBig = 1024;
 
-template <int Q, int P, int DT>
-__device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                      const float* __restrict__ w, void* __restrict__ X, int32_t K,
-                                      int64_t r_lo, int64_t r_hi, int64_t rblock) {
-    constexpr int L = Q * P;
-    constexpr int RPW = kWave / L;
+struct GsTiers {
+    int32_t nt;                 // tiers present in this colour
+    int32_t lanes[kNT];         // lanes per row
+    int64_t row0[kNT + 1];      // first row of each tier (and the end)
+    int64_t blk0[kNT + 1];      // first block of each tier (and the total)
+};
+
+template <int Q, int DT>
+__global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const float* __restrict__ w,
+                                                  void* __restrict__ X, int32_t K, GsTiers tt) {
     constexpr int E = Chunk<DT>::E;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int l = lane % L;
+    constexpr int NW = kBig / kWave;
+    __shared__ float sacc[NW][Q][E];
+    __shared__ float sd[NW];
+    const int64_t b = blockIdx.x;
+    int t = 0;
+    while (t + 1 < tt.nt && b >= tt.blk0[t + 1]) ++t;
+    const int L = tt.lanes[t];
+    const int P = L / Q;
+    const int tid = threadIdx.x;
+    const int l = tid % L;
     const int p = l / Q, q = l % Q;
-    const int64_t wave = (rblock * kBig + threadIdx.x) / kWave;
-    const int64_t r = r_lo + wave * RPW + lane / L;
-    if (r >= r_hi) return;  // whole row-groups leave together
-    const int32_t e0 = rp[r], e1 = rp[r + 1];
+    const int64_t r = tt.row0[t] + (b - tt.blk0[t]) * (kBig / L) + tid / L;
+    const bool valid = r < tt.row0[t + 1];
+    int32_t e0 = 0, e1 = 0;
+    if (valid) {
+        e0 = rp[r];
+        e1 = rp[r + 1];
+    }
     float acc[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] = 0.0f;
@@ -667,13 +906,40 @@ __device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int3
             d += wt[u];
         }
     }
-#pragma unroll
-    for (int off = Q; off < L; off <<= 1) {
+    // combine the slots of the row inside the wave
+    const int span = L < kWave ? L : kWave;
+    for (int off = Q; off < span; off <<= 1) {
 #pragma unroll
         for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
         d += __shfl_xor(d, off, kWave);
     }
-    if (p == 0 && d > 0.0f) {
+    if (L > kWave) {
+        // rows wider than a wave: the waves of the row meet in LDS
+        const int wid = tid / kWave, lane = tid & (kWave - 1);
+        if (lane < Q) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) sacc[wid][lane][i] = acc[i];
+            if (lane == 0) sd[wid] = d;
+        }
+        __syncthreads();
+        if (l < Q && valid) {
+            const int w0 = (tid - l) / kWave, nw = L / kWave;
+            float y[E];
+            float dd = 0.0f;
+#pragma unroll
+            for (int i = 0; i < E; ++i) y[i] = 0.0f;
+            for (int ww = w0; ww < w0 + nw; ++ww) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) y[i] += sacc[ww][l][i];
+                dd += sd[ww];
+            }
+            if (dd > 0.0f) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) y[i] = y[i] / dd;
+                Chunk<DT>::store(X, r, K, l, y);
+            }
+        }
+    } else if (p == 0 && valid && d > 0.0f) {
         float y[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) y[i] = acc[i] / d;
@@ -681,131 +947,50 @@ __device__ inline void gs_normal_rows(const int32_t* __restrict__ rp, const int3
     }
 }
 
-template <int Q, int DT>
-__device__ inline void gs_long_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                   const float* __restrict__ w, void* __restrict__ X, int32_t K,
-                                   int64_t r) {
-    constexpr int E = Chunk<DT>::E;
-    constexpr int P = kBig / Q;
-    constexpr int NW = kBig / kWave;
-    __shared__ float sacc[NW][Q][E];
-    __shared__ float sd[NW];
-    const int t = threadIdx.x;
-    const int p = t / Q, q = t % Q;
-    const int32_t e0 = rp[r], e1 = rp[r + 1];
-    float acc[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) acc[i] = 0.0f;
-    float d = 0.0f;
-    for (int32_t e = e0 + p; e < e1; e += kU * P) {
-        int32_t j[kU];
-        float wt[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            int32_t eu = e + u * P;
-            bool ok = eu < e1;
-            j[u] = ok ? col[eu] : (int32_t)r;
-            wt[u] = ok ? w[eu] : 0.0f;
-        }
-        float x[kU][E];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) Chunk<DT>::load(X, j[u], K, q, x[u]);
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt[u], x[u][i], acc[i]);
-            d += wt[u];
-        }
-    }
-#pragma unroll
-    for (int off = Q; off < kWave; off <<= 1) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
-        d += __shfl_xor(d, off, kWave);
-    }
-    const int wid = t / kWave, lane = t & (kWave - 1);
-    if (lane < Q) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) sacc[wid][lane][i] = acc[i];
-        if (lane == 0) sd[wid] = d;
-    }
-    __syncthreads();
-    if (t < Q) {
-        float y[E];
-        float dd = 0.0f;
-#pragma unroll
-        for (int i = 0; i < E; ++i) y[i] = 0.0f;
-        for (int ww = 0; ww < NW; ++ww) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) y[i] += sacc[ww][t][i];
-            dd += sd[ww];
-        }
-        if (dd > 0.0f) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) y[i] = y[i] / dd;
-            Chunk<DT>::store(X, r, K, t, y);
-        }
-    }
+// lanes per row of tier t: about half the tier's largest degree times
+// Q / kU (two rounds of kU gathers per lane), a power of two in [Q, kBig]
+static int tier_lanes(int Q, int t) {
+    const int64_t dmax = t == 0 ? 4096 : tier_max_degree(t);
+    const int64_t want = (dmax * Q + 2 * kU - 1) / (2 * kU);
+    int L = Q;
+    while (L < want && L < kBig) L *= 2;
+    return L;
 }
 
-template <int Q, int P, int DT>
-__global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ col,
-                                                  const float* __restrict__ w,
-                                                  void* __restrict__ X, int32_t K, int64_t lo,
-                                                  int64_t n_long, int64_t hi) {
-    const int64_t b = blockIdx.x;
-    if (b < n_long) gs_long_row<Q, DT>(rp, col, w, X, K, lo + b);
-    else gs_normal_rows<Q, P, DT>(rp, col, w, X, K, lo + n_long, hi, b - n_long);
-}
-
-template <int Q, int DT>
-static int launch_gs_step(int P, const OrderedGraph* og, void* X, int K, int c, hipStream_t st) {
-    const int64_t lo = og->class_ptr_h[c], le = og->long_end_h[c], hi = og->class_ptr_h[c + 1];
-    const int64_t nlong = le - lo, rows = hi - le;
-    const int L = Q * P;
-    const int64_t waves = (rows * L + kWave - 1) / kWave;
-    const int64_t rblocks = rows > 0 ? (waves * kWave + kBig - 1) / kBig : 0;
-    const int64_t grid = nlong + rblocks;
-    if (grid == 0) return GR_OK;
-#define GR_GS(PP)                                                                               \
-    case PP:                                                                                   \
-        if constexpr (Q * PP <= kWave)                                                         \
-            hipLaunchKernelGGL((k_gs_step<Q, PP, DT>), dim3((unsigned)grid), dim3(kBig), 0, st,  \
-                               og->g.row_ptr, og->g.col, og->g.w, X, K, lo, nlong, hi);         \
-        break;
-    switch (P) {
-        GR_GS(1) GR_GS(2) GR_GS(4) GR_GS(8) GR_GS(16) GR_GS(32) GR_GS(64)
-        default: return set_error(GR_EINVAL, "bad lane split");
+static GsTiers plan_gs_step(const OrderedGraph* og, int Q, int c) {
+    GsTiers tt{};
+    int64_t blocks = 0;
+    for (int t = 0; t < kNT; ++t) {
+        const int64_t r0 = og->tier_ptr_h[(size_t)c * kNT + t];
+        const int64_t r1 = og->tier_ptr_h[(size_t)c * kNT + t + 1];
+        if (r1 == r0) continue;
+        const int L = tier_lanes(Q, t);
+        const int k = tt.nt++;
+        tt.lanes[k] = L;
+        tt.row0[k] = r0;
+        tt.row0[k + 1] = r1;
+        tt.blk0[k] = blocks;
+        blocks += ((r1 - r0) * L + kBig - 1) / kBig;
+        tt.blk0[k + 1] = blocks;
     }
-#undef GR_GS
-    GR_LAUNCHED("gs step");
-    return GR_OK;
-}
-
-// lanes per row for normal rows: about a quarter of the mean degree (each
-// lane takes four neighbours per round), a power of two, at most a wave
-static int pick_p(int Q, double mean_deg) {
-    int P = 1;
-    while (P * kU < mean_deg && Q * P * 2 <= kWave) P *= 2;
-    return P;
+    return tt;
 }
 
 template <int Q, int DT>
 static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, hipStream_t st) {
     const bool pr = prof::on();
     const int xs = DT == GR_BF16 ? 2 : 4;
-    std::vector<int> Ps(og->n_colours);
-    for (int c = 0; c < og->n_colours; ++c) {
-        int64_t rows = og->class_ptr_h[c + 1] - og->long_end_h[c];
-        Ps[c] = pick_p(Q, rows > 0 ? (double)og->normal_nnz_h[c] / (double)rows : 1.0);
-    }
+    std::vector<GsTiers> plan(og->n_colours);
+    for (int c = 0; c < og->n_colours; ++c) plan[c] = plan_gs_step(og, Q, c);
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < og->n_colours; ++c) {
-            int64_t lo = og->class_ptr_h[c], hi = og->class_ptr_h[c + 1];
-            if (hi == lo) continue;
+            const GsTiers& tt = plan[c];
+            if (tt.nt == 0) continue;
+            const int64_t lo = og->class_ptr_h[c], hi = og->class_ptr_h[c + 1];
             if (pr) prof::begin(st);
-            GR_TRY((launch_gs_step<Q, DT>(Ps[c], og, X, K, c, st)));
+            hipLaunchKernelGGL((k_gs_step<Q, DT>), dim3((unsigned)tt.blk0[tt.nt]), dim3(kBig), 0, st,
+                               og->g.row_ptr, og->g.col, og->g.w, X, K, tt);
+            GR_LAUNCHED("gs step");
             if (pr) {
                 // compulsory bytes of this colour step: its CSR rows, plus one
                 // read and one write of each updated vector row
