@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--random-priority", action="store_true",
                     help="greedy colouring with hashed priorities instead of "
                          "largest-degree-first")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (for "
+                         "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -58,6 +61,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     from paper_1812_08942_amd import graphreduce as G
     from workloads import graphs as W
@@ -162,7 +169,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, dtype),
             "avg_launch_us": avg_us,
             "bytes_per_launch": sm["bytes"] / max(1, sm["launches"]),
             "launches_per_step": sm["launches"] / args.steps,
@@ -202,6 +209,55 @@ def eig_report(G, r, eig_original, dg):
         out["eig_normalised_rel_err"] = float(np.max(
             np.abs(lam / lam[0] - lo / lo[0]) / (lo / lo[0])))
     return out
+
+
+COPY_BYTES = 1 << 30
+
+
+def calibrate_copy():
+    """Three device-to-device copies of exactly 1 GiB: rocprofv3 counters
+    read on these give the scale from counter units to bytes."""
+    import torch
+
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
+
+
+def kernel_source_digest():
+    """Digest of the GS kernel's source file; a traffic figure taken for
+    another version of the kernel is not reported."""
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1812_08942_amd", "csrc", "gr_phase_a.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload, dtype):
+    """HBM bytes per GS colour-step launch from the committed rocprofv3
+    counter summary of this workload, or None when there is none for the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_gs_step_{workload}_{dtype}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(g, wl):
