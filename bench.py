@@ -15,6 +15,9 @@ roofline = the Gauss-Seidel colour-step kernels: compulsory bytes per colour
         over their HIP-event durations, against the 8 TB/s HBM peak.
 cpu_baseline = the FP64 reference oracle (one host thread) on level-0
         smoothing + affinity of the same graph, in the same unit.
+secondary = the same measurement on a second workload (default: the 256^3
+        grid with bfloat16 vectors, whose colour steps are large enough to
+        be bandwidth-bound); --secondary '' skips it.
 """
 from __future__ import annotations
 
@@ -50,6 +53,8 @@ def main():
     ap.add_argument("--random-priority", action="store_true",
                     help="greedy colouring with hashed priorities instead of "
                          "largest-degree-first")
+    ap.add_argument("--secondary", default="grid256",
+                    help="second workload measured the same way ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -67,17 +72,60 @@ def main():
         return
 
     from paper_1812_08942_amd import graphreduce as G
-    from workloads import graphs as W
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     G.load()
-    wl = W.WORKLOADS[args.workload]
-    dtype = args.dtype or wl.dtype
     args.ldf = not args.random_priority
+    res, keep = run_workload(G, args.workload, args.dtype, args.steps,
+                             args.warmup, args.ldf)
+    result = {
+        "metric": "smoothing nnz*K*sweeps/s + affinity edges/s; % HBM peak; "
+                  "eig error vs FP64",
+        "value": res["value"],
+        "unit": "nnz*K*sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "storage": res["storage"],
+        "data": "synthetic",
+    }
+    result.update({k: v for k, v in res.items() if k not in result})
+    g, wl, r, dg = keep
+    if not args.no_eig:
+        result.update(eig_report(G, r, args.eig_original, dg))
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(g, wl)
+    del keep, g, r, dg
+    if args.secondary and args.secondary != args.workload:
+        # the same measurement on a second workload whose colour steps are
+        # large enough to be bandwidth-bound (reported next to the headline)
+        sec, _ = run_workload(G, args.secondary, None, args.steps,
+                              args.warmup, args.ldf)
+        result["secondary"] = {k: sec[k] for k in (
+            "value", "ms_per_step", "storage", "config", "levels",
+            "smooth_only_rate", "affinity_edges_per_s", "phase_ms_per_step",
+            "roofline")}
+    print(json.dumps(result), flush=True)
+
+
+def run_workload(G, key, dtype, steps, warmup, ldf):
+    """Times `steps` full reductions of workload `key` (after `warmup`),
+    then the same steps with the library's event profiler on."""
+    import torch
+
+    from workloads import graphs as W
+
+    wl = W.WORKLOADS[key]
+    dtype = dtype or wl.dtype
     t0 = time.time()
-    g = W.build_graph(args.workload)
+    g = W.build_graph(key)
     log(f"graph {g.name}: n={g.n} nnz={g.nnz} built in {time.time() - t0:.1f}s")
     dev = "cuda:0"
     dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
@@ -94,22 +142,22 @@ def main():
         return G.gr_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed,
                            wl.colour_seed, dtype=code, colours=colours,
                            n_colours=g.n_colours,
-                           largest_degree_first=args.ldf, ws=ws, out=out)
+                           largest_degree_first=ldf, ws=ws, out=out)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         r = step()
         torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup}: levels={r.levels} "
+        log(f"{key} warmup {i + 1}/{warmup}: levels={r.levels} "
             f"n_coarse={r.coarse.n}")
     # headline: K steps with nothing but the steps on the stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         r = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step, levels {r.levels}, "
+    ms = (t1 - t0) * 1e3 / steps
+    log(f"{key} timed {steps} steps: {ms:.3f} ms/step, levels {r.levels}, "
         f"colours {r.level_colours}")
     # breakdown: the same K steps again with the library's HIP-event
     # profiler on (events on the library stream around every phase and
@@ -117,50 +165,35 @@ def main():
     G.gr_profile_start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    ms_prof = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_prof = (time.perf_counter() - t0) * 1e3 / steps
     prof = G.gr_profile_stop()
-    log(f"profiled {args.steps} steps: {ms_prof:.3f} ms/step")
+    log(f"{key} profiled {steps} steps: {ms_prof:.3f} ms/step")
 
     work = sum(nz * wl.K * wl.sweeps for nz in r.level_nnz)
-    value = work / (ms / 1e3)
     sm = prof["smooth"]
     achieved = sm["bytes"] / (sm["ms"] * 1e-3) / 1e9 if sm["ms"] > 0 else 0.0
     avg_us = sm["ms"] * 1e3 / max(1, sm["launches"])
     aff = prof["affinity"]
-    edges = sum(nz // 2 for nz in r.level_nnz) * args.steps
-    phases = {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()}
-    smooth_work_rate = work * args.steps / (sm["ms"] * 1e-3) if sm["ms"] else 0.0
-
-    result = {
-        "metric": "smoothing nnz*K*sweeps/s + affinity edges/s; % HBM peak; "
-                  "eig error vs FP64",
-        "value": value,
-        "unit": "nnz*K*sweeps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    edges = sum(nz // 2 for nz in r.level_nnz) * steps
+    res = {
+        "value": work / (ms / 1e3),
         "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
         "storage": dtype,
-        "data": "synthetic",
-        "config": {"workload": args.workload, "description": wl.description,
+        "config": {"workload": key, "description": wl.description,
                    "n": g.n, "nnz": g.nnz, "K": wl.K, "sweeps": wl.sweeps,
                    "ratio": wl.ratio, "vec_storage": dtype,
                    "colouring": "prescribed" if colours is not None else
-                   ("greedy-ldf" if args.ldf else "greedy"),
+                   ("greedy-ldf" if ldf else "greedy"),
                    "parallelism": "single GPU"},
         "levels": {"n": r.level_n, "nnz": r.level_nnz,
                    "colours": r.level_colours, "n_coarse": r.coarse.n,
                    "nnz_coarse": r.coarse.nnz},
-        "smooth_only_rate": smooth_work_rate,
+        "smooth_only_rate": work * steps / (sm["ms"] * 1e-3) if sm["ms"] else 0.0,
         "affinity_edges_per_s": edges / (aff["ms"] * 1e-3) if aff["ms"] else 0.0,
-        "phase_ms_per_step": phases,
+        "phase_ms_per_step": {k: round(v["ms"] / steps, 4) for k, v in prof.items()},
         "profiled_ms_per_step": ms_prof,
         "roofline": {
             "bound": "hbm",
@@ -169,18 +202,13 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, dtype),
+            "traffic": measured_traffic(key, dtype),
             "avg_launch_us": avg_us,
             "bytes_per_launch": sm["bytes"] / max(1, sm["launches"]),
-            "launches_per_step": sm["launches"] / args.steps,
+            "launches_per_step": sm["launches"] / steps,
         },
     }
-
-    if not args.no_eig:
-        result.update(eig_report(G, r, args.eig_original, dg))
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(g, wl)
-    print(json.dumps(result), flush=True)
+    return res, (g, wl, r, dg)
 
 
 def eig_report(G, r, eig_original, dg):

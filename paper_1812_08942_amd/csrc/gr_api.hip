@@ -187,7 +187,7 @@ int gr_smooth(const gr_graph* g, const int32_t* colours, int32_t n_colours, int3
     char* Xp = A.take<char>(vb);
     if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (smooth)");
     GR_TRY(permute_rows(X, Xp, og.perm, g->n, (size_t)K * (dtype == GR_BF16 ? 2 : 4), 0, st));
-    GR_TRY(smooth_ordered(&og, K, sweeps, dtype, Xp, st));
+    GR_TRY(smooth_ordered(&og, K, sweeps, dtype, Xp, A, st));
     GR_TRY(permute_rows(Xp, X, og.perm, g->n, (size_t)K * (dtype == GR_BF16 ? 2 : 4), 1, st));
     return GR_OK;
 }
@@ -318,7 +318,7 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
         if (pr) prof::begin(st);
         GR_TRY(init_vectors(cur.n, p.K, vseed, p.vec_dtype, og.perm, X, A, st));
         if (pr) prof::end(st, prof::INIT, (double)cur.n * p.K * xs + 4.0 * cur.n, 1);
-        GR_TRY(smooth_ordered(&og, p.K, p.sweeps, p.vec_dtype, X, st));
+        GR_TRY(smooth_ordered(&og, p.K, p.sweeps, p.vec_dtype, X, A, st));
         if (pr) prof::begin(st);
         GR_TRY(affinity(&og.g, p.K, p.vec_dtype, X, og.perm, og.long_rows, og.n_long, nullptr,
                         nullptr, best, dbest, st));

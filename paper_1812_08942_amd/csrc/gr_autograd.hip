@@ -529,7 +529,7 @@ size_t vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t S
 template <int Q, int DT>
 static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vector<int64_t>& seg_ptr,
                     int K, int S, int store, void* states, size_t xbytes, float* xbar, float* H,
-                    float* ge, hipStream_t st) {
+                    float* ge, Arena& ws, hipStream_t st) {
     constexpr int E = Chunk<DT>::E;
     const int C = og->n_colours;
     std::vector<int> Prow(C), Pseg(C);
@@ -546,7 +546,7 @@ static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vecto
     if (store) {
         for (int s = 1; s <= S; ++s) {
             GR_HIP(hipMemcpyAsync(state(s), state(s - 1), xbytes, hipMemcpyDeviceToDevice, st));
-            GR_TRY(smooth_ordered(og, K, 1, DT, state(s), st));
+            GR_TRY(smooth_ordered(og, K, 1, DT, state(s), ws, st));
         }
     }
     for (int s = S; s >= 1; --s) {
@@ -556,9 +556,9 @@ static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vecto
             Xp = state(s - 1);
         } else {
             GR_HIP(hipMemcpyAsync(state(1), state(0), xbytes, hipMemcpyDeviceToDevice, st));
-            GR_TRY(smooth_ordered(og, K, s - 1, DT, state(1), st));
+            GR_TRY(smooth_ordered(og, K, s - 1, DT, state(1), ws, st));
             GR_HIP(hipMemcpyAsync(state(2), state(1), xbytes, hipMemcpyDeviceToDevice, st));
-            GR_TRY(smooth_ordered(og, K, 1, DT, state(2), st));
+            GR_TRY(smooth_ordered(og, K, 1, DT, state(2), ws, st));
             Xs = state(2);
             Xp = state(1);
         }
@@ -650,7 +650,7 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     GR_LAUNCHED("zero");
     const int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
 #define GR_VJ(QQ, DD) \
-    case QQ: GR_TRY((vjp_impl<QQ, DD>(&og, rec, seg_ptr, K, S, store, states, xstride, xbar, H, ge, st))); break;
+    case QQ: GR_TRY((vjp_impl<QQ, DD>(&og, rec, seg_ptr, K, S, store, states, xstride, xbar, H, ge, ws, st))); break;
     if (dtype == GR_BF16) {
         switch (Q) {
             GR_VJ(1, GR_BF16) GR_VJ(2, GR_BF16) GR_VJ(4, GR_BF16) GR_VJ(8, GR_BF16)

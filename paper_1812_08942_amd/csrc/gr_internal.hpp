@@ -159,7 +159,7 @@ int permute_rows(const void* src, void* dst, const int32_t* perm, int64_t n, siz
 int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32_t* ids,
                  void* X, Arena& ws, hipStream_t st);
 int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dtype,
-                   void* X, hipStream_t st);
+                   void* X, Arena& ws, hipStream_t st);
 // a (affinity) and dist (algebraic distance d = 1 - a) per entry are
 // optional; best = argmin (d, id) per row, dbest its distance.  Rows of
 // degree above the long-row threshold are listed in long_rows (n_long of

@@ -96,8 +96,37 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 //  * A round runs on the whole grid (a block per node of degree above
 //    kJpBig, a wave per node of degree above kJpTiny, kJpGroup lanes per
 //    other node), or, while the frontier is small, many rounds run back to
-//    back inside one block, separated by block barriers.
+//    back in a cooperative launch of a few blocks, separated by device-wide
+//    barriers.
 // Every edge is touched a constant number of times over all rounds.
+// Device-wide barrier for a cooperatively launched grid: the block's writes
+// are released to the device, a monotonic counter collects the blocks, and
+// the wait is bounded: past kSpinLimit polls (far beyond any colour step) the
+// block raises the abort flag and every block leaves at its next barrier.
+constexpr unsigned kSpinLimit = 1u << 22;
+__device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abort_flag) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(counter, 1u);
+        unsigned spins = 0;
+        ok = 1;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit ||
+                __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicExch(abort_flag, 1);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
 struct Prio {
     uint32_t deg;
     uint64_t h;
@@ -140,11 +169,13 @@ constexpr int kKinds = 3;
 constexpr uint8_t kDown = 1;       // entry flag: the neighbour has lower priority
 // entry flag bits 1-2: the neighbour's kind
 #ifndef GR_JP_SOLO_COST
-#define GR_JP_SOLO_COST 48
+#define GR_JP_SOLO_COST 32
 #endif
-constexpr int kSoloCost = GR_JP_SOLO_COST;  // one block runs a round when
-// tiny / kJpGroup... (in waves) + medium + kJpWaves * big <= kSoloCost
-constexpr int kSoloRounds = 64;    // rounds per single-block launch at most
+// the few-block kernel runs a round when its cost in waves, tiny / (nodes
+// per wave) + medium + kJpWaves * big, is at most kSoloCost per block
+constexpr int kSoloCost = GR_JP_SOLO_COST;
+constexpr int kSoloRounds = 256;   // rounds per few-block launch at most
+constexpr int kJpMultiBlocks = 32; // blocks of the few-block kernel
 
 __host__ __device__ inline int node_kind(int32_t deg) {
     return deg <= kJpTiny ? 0 : (deg <= kJpBig ? 1 : 2);
@@ -316,12 +347,14 @@ __device__ inline void jp_group_node(const int32_t* __restrict__ rp,
 }
 
 // colour the big node v with the whole block (all threads call it)
+// piece f of `pieces` (a contiguous share of the node's entries to notify;
+// every piece computes the same colour, piece 0 stores it)
 __device__ inline void jp_big_node(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                   const uint8_t* __restrict__ eflag, int32_t v,
-                                   int32_t* __restrict__ cnt, uint64_t* __restrict__ mask,
-                                   int32_t* __restrict__ colours, int32_t* const* out,
-                                   int32_t* __restrict__ next, uint64_t (*part)[4],
-                                   int32_t* found) {
+                                   const uint8_t* __restrict__ eflag, int32_t v, int f,
+                                   int pieces, int32_t* __restrict__ cnt,
+                                   uint64_t* __restrict__ mask, int32_t* __restrict__ colours,
+                                   int32_t* const* out, int32_t* __restrict__ next,
+                                   uint64_t (*part)[4], int32_t* found) {
     const int32_t e0 = rp[v], e1 = rp[v + 1];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     int32_t c = mask_first_free<kWave>(mask + (int64_t)v * kMaskWords, lane);
@@ -341,9 +374,11 @@ __device__ inline void jp_big_node(const int32_t* __restrict__ rp, const int32_t
         c = *found;
         __syncthreads();
     }
-    if (threadIdx.x == 0) colours[v] = c;
-    const int32_t trips = (e1 - e0 + kN * kJpThreads - 1) / (kN * kJpThreads);
-    jp_notify(col, eflag, e0 + (int32_t)threadIdx.x, e1, kJpThreads, trips, c, cnt, mask, out,
+    if (threadIdx.x == 0 && f == 0) colours[v] = c;
+    const int32_t len = (e1 - e0 + pieces - 1) / pieces;
+    const int32_t p1 = min(e1, e0 + (f + 1) * len), p0 = min(p1, e0 + f * len);
+    const int32_t trips = (p1 - p0 + kN * kJpThreads - 1) / (kN * kJpThreads);
+    jp_notify(col, eflag, p0 + (int32_t)threadIdx.x, p1, kJpThreads, trips, c, cnt, mask, out,
               next);
 }
 
@@ -367,8 +402,11 @@ __device__ inline void jp_round(const int32_t* __restrict__ rp, const int32_t* _
     int32_t* const* in = jb.list[r & 1];
     int32_t* const* out = jb.list[(r + 1) & 1];
     int32_t* next = jb.sizes + kKinds * (r + 1);
-    for (int64_t t = blk; t < nk[2]; t += nblk)
-        jp_big_node(rp, col, jb.eflag, in[2][t], jb.cnt, jb.mask, colours, out, next, part, found);
+    // big nodes: when they are few, several blocks share each node's entries
+    const int pieces = nk[2] > 0 ? (int)max<int64_t>(1, min<int64_t>(8, nblk / nk[2])) : 1;
+    for (int64_t t = blk; t < (int64_t)nk[2] * pieces; t += nblk)
+        jp_big_node(rp, col, jb.eflag, in[2][t / pieces], (int)(t % pieces), pieces, jb.cnt,
+                    jb.mask, colours, out, next, part, found);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = blk * kJpWaves + threadIdx.x / kWave, nwaves = nblk * kJpWaves;
     for (int64_t t = wave; t < nk[1]; t += nwaves)
@@ -399,26 +437,27 @@ __global__ void __launch_bounds__(kJpThreads) k_jp_round(const int32_t* __restri
     if (blockIdx.x == 0 && threadIdx.x == 0) jb.state[1] = 1;
 }
 
-// one block: first account for a grid round that ran since the last call,
-// then run rounds back to back while the frontier is small
-__global__ void __launch_bounds__(kJpThreads) k_jp_solo(const int32_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ col,
-                                                        JpBufs jb, int32_t* __restrict__ colours) {
+// a few blocks (cooperative launch): first account for a grid round that
+// ran since the last call, then run rounds back to back, separated by
+// device-wide barriers, while the frontier fits them; the wide grid kernel
+// takes the large rounds
+__global__ void __launch_bounds__(kJpThreads) k_jp_multi(const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         JpBufs jb, int32_t* __restrict__ colours,
+                                                         unsigned* counter, int* abort_flag) {
     __shared__ uint64_t part[kJpWaves][4];
     __shared__ int32_t found;
-    __shared__ int64_t rs;
     __shared__ int32_t go, snk[kKinds];
-    if (threadIdx.x == 0) {
-        if (jb.state[1]) {
-            jb.state[0] += 1;
-            jb.state[1] = 0;
-        }
-        rs = jb.state[0];
+    int64_t r = (int64_t)jb.state[0] + jb.state[1];
+    unsigned epoch = 1;
+    // every block has read the state before block 0 rewrites it
+    if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        jb.state[0] = (int32_t)r;
+        jb.state[1] = 0;
     }
-    __syncthreads();
     for (int k = 0; k < kSoloRounds; ++k) {
         if (threadIdx.x == 0) {
-            const int64_t r = rs;
             go = 0;
             if (r < jb.max_rounds) {
                 for (int q = 0; q < kKinds; ++q)
@@ -427,20 +466,18 @@ __global__ void __launch_bounds__(kJpThreads) k_jp_solo(const int32_t* __restric
                 const int32_t tot = snk[0] + snk[1] + snk[2];
                 const int32_t cost = (snk[0] + kWave / kJpGroup - 1) / (kWave / kJpGroup) +
                                      snk[1] + kJpWaves * snk[2];
-                go = (tot > 0 && cost <= kSoloCost) ? 1 : 0;
+                go = (tot > 0 && cost <= kSoloCost * (int32_t)gridDim.x) ? 1 : 0;
             }
         }
         __syncthreads();
-        if (!go) break;
+        if (!go) break;  // the same decision in every block: same sizes after the barrier
         int32_t nk[kKinds] = {snk[0], snk[1], snk[2]};
-        jp_round(rp, col, jb, rs, nk, 0, 1, colours, part, &found);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            rs += 1;
-            jb.state[0] = (int32_t)rs;
-        }
-        __syncthreads();
+        jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, part, &found);
+        ++epoch;
+        if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
+        ++r;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) jb.state[0] = (int32_t)r;
 }
 
 __global__ void k_col_fill(int64_t n, int32_t* __restrict__ colours) {
@@ -483,7 +520,12 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
     jb.sizes = ws.take<int32_t>(nsz);
     jb.state = jb.sizes + nsz - 8;
     jb.max_rounds = n;
+    unsigned* sync = ws.take<unsigned>(4);
+    int* abort_flag = (int*)(sync + 1);
+    const int32_t* rp = g->row_ptr;
+    const int32_t* cl = g->col;
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
+    GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned) * 4, st));
     GR_HIP(hipMemsetAsync(jb.sizes, 0, sizeof(int32_t) * nsz, st));
     GR_HIP(hipMemsetAsync(jb.mask, 0, sizeof(uint64_t) * (size_t)n * kMaskWords, st));
     GR_HIP(hipMemcpyAsync(dlists, jb.list[0], sizeof(int32_t*) * kKinds, hipMemcpyHostToDevice, st));
@@ -495,16 +537,20 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
     GR_LAUNCHED("colour count");
     for (int64_t batch = 0;; ++batch) {
         for (int b = 0; b < kJpBatch; ++b) {
-            hipLaunchKernelGGL(k_jp_solo, dim3(1), dim3(kJpThreads), 0, st, g->row_ptr, g->col, jb,
-                               colours);
-            GR_LAUNCHED("colour rounds (one block)");
+            GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned), st));
+            void* args[] = {(void*)&rp, (void*)&cl, (void*)&jb, (void*)&colours, (void*)&sync,
+                            (void*)&abort_flag};
+            GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_multi, dim3(kJpMultiBlocks),
+                                              dim3(kJpThreads), args, 0, st));
             hipLaunchKernelGGL(k_jp_round, dim3(kJpBlocks), dim3(kJpThreads), 0, st, g->row_ptr,
                                g->col, jb, colours);
             GR_LAUNCHED("colour round");
         }
-        int32_t stt[2] = {0, 0};
+        int32_t stt[2] = {0, 0}, hflag = 0;
         GR_HIP(hipMemcpyAsync(stt, jb.state, sizeof(stt), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipMemcpyAsync(&hflag, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
+        if (hflag) return set_error(GR_EHIP, "colouring barrier timed out");
         const int64_t r = (int64_t)stt[0] + stt[1];
         if (r > n) return set_error(GR_EHIP, "colouring did not finish in n rounds");
         int32_t fr[kKinds] = {0, 0, 0};
@@ -851,23 +897,26 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
 constexpr int kU = 4;
 constexpr int kBig = 1024;
 
+// Rows of degree above 2048 (tier 0) are split: kSplit blocks each take a
+// contiguous 1/kSplit of the row's entries and write a partial sum (K values
+// and the weight sum) to `part`; a second pass adds the kSplit partials of
+// each such row in order and stores the row.
+constexpr int kSplit = 8;
+
 struct GsTiers {
     int32_t nt;                 // tiers present in this colour
+    int32_t split;              // tier index 0 is the split tier 0
     int32_t lanes[kNT];         // lanes per row
     int64_t row0[kNT + 1];      // first row of each tier (and the end)
     int64_t blk0[kNT + 1];      // first block of each tier (and the total)
 };
 
 template <int Q, int DT>
-__global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ col,
-                                                  const float* __restrict__ w,
-                                                  void* __restrict__ X, int32_t K, GsTiers tt) {
+__device__ inline void gs_block(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const float* __restrict__ w, void* __restrict__ X, int32_t K,
+                                const GsTiers& tt, int64_t b, float* __restrict__ part,
+                                float (*sacc)[Q][Chunk<DT>::E], float* sd) {
     constexpr int E = Chunk<DT>::E;
-    constexpr int NW = kBig / kWave;
-    __shared__ float sacc[NW][Q][E];
-    __shared__ float sd[NW];
-    const int64_t b = blockIdx.x;
     int t = 0;
     while (t + 1 < tt.nt && b >= tt.blk0[t + 1]) ++t;
     const int L = tt.lanes[t];
@@ -875,12 +924,25 @@ __global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp
     const int tid = threadIdx.x;
     const int l = tid % L;
     const int p = l / Q, q = l % Q;
-    const int64_t r = tt.row0[t] + (b - tt.blk0[t]) * (kBig / L) + tid / L;
+    const bool split = tt.split && t == 0;  // block-uniform
+    int64_t r, slot = 0;
+    if (split) {
+        r = tt.row0[0] + (b - tt.blk0[0]) / kSplit;
+        slot = b - tt.blk0[0];  // (row in the tier) * kSplit + piece
+    } else {
+        r = tt.row0[t] + (b - tt.blk0[t]) * (kBig / L) + tid / L;
+    }
     const bool valid = r < tt.row0[t + 1];
     int32_t e0 = 0, e1 = 0;
     if (valid) {
         e0 = rp[r];
         e1 = rp[r + 1];
+        if (split) {
+            const int32_t f = (int32_t)(slot % kSplit);
+            const int32_t len = (e1 - e0 + kSplit - 1) / kSplit;
+            e1 = min(e1, e0 + (f + 1) * len);
+            e0 = min(e1, e0 + f * len);
+        }
     }
     float acc[E];
 #pragma unroll
@@ -933,18 +995,104 @@ __global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp
                 for (int i = 0; i < E; ++i) y[i] += sacc[ww][l][i];
                 dd += sd[ww];
             }
-            if (dd > 0.0f) {
+            if (split) {
+                float* pp = part + slot * (int64_t)(K + 1);
+#pragma unroll
+                for (int i = 0; i < E; ++i) pp[l * E + i] = y[i];
+                if (l == 0) pp[K] = dd;
+            } else if (dd > 0.0f) {
 #pragma unroll
                 for (int i = 0; i < E; ++i) y[i] = y[i] / dd;
                 Chunk<DT>::store(X, r, K, l, y);
             }
         }
+        __syncthreads();  // the LDS slots are reused by the block's next rows
     } else if (p == 0 && valid && d > 0.0f) {
         float y[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) y[i] = acc[i] / d;
         Chunk<DT>::store(X, r, K, q, y);
     }
+}
+
+template <int Q, int DT>
+__global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const float* __restrict__ w,
+                                                  void* __restrict__ X, int32_t K, GsTiers tt,
+                                                  float* __restrict__ part) {
+    __shared__ float sacc[kBig / kWave][Q][Chunk<DT>::E];
+    __shared__ float sd[kBig / kWave];
+    gs_block<Q, DT>(rp, col, w, X, K, tt, blockIdx.x, part, sacc, sd);
+}
+
+// second pass of the split rows: one group of Q lanes per row adds the
+// row's kSplit partials in order; rows i = first .. first + n - 1 of the
+// split tier, taken from global group index g0 with stride gstride
+template <int Q, int DT>
+__device__ inline void gs_split_rows(void* __restrict__ X, int32_t K, int64_t row0, int64_t nrows,
+                                     const float* __restrict__ part, int64_t g0, int64_t gstride) {
+    constexpr int E = Chunk<DT>::E;
+    const int q = threadIdx.x % Q;
+    for (int64_t i = g0; i < nrows; i += gstride) {
+        float y[E];
+        float dd = 0.0f;
+#pragma unroll
+        for (int k = 0; k < E; ++k) y[k] = 0.0f;
+        for (int f = 0; f < kSplit; ++f) {
+            const float* pp = part + (i * kSplit + f) * (int64_t)(K + 1);
+#pragma unroll
+            for (int k = 0; k < E; ++k) y[k] += pp[q * E + k];
+            dd += pp[K];
+        }
+        if (dd > 0.0f) {
+#pragma unroll
+            for (int k = 0; k < E; ++k) y[k] = y[k] / dd;
+            Chunk<DT>::store(X, row0 + i, K, q, y);
+        }
+    }
+}
+
+template <int Q, int DT>
+__global__ void k_gs_split(void* __restrict__ X, int32_t K, int64_t row0, int64_t nrows,
+                           const float* __restrict__ part) {
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / Q;
+    gs_split_rows<Q, DT>(X, K, row0, nrows, part, g, ((int64_t)gridDim.x * blockDim.x) / Q);
+}
+
+// All sweeps of a level whose colour steps are small, in one cooperative
+// launch of a few blocks: the blocks share each step's work (the plan's
+// blocks, grid-stride) and meet at a device-wide barrier between steps,
+// instead of paying a kernel launch per step.
+template <int Q, int DT>
+__global__ void __launch_bounds__(kBig) k_gs_persistent(const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ col,
+                                                        const float* __restrict__ w,
+                                                        void* __restrict__ X, int32_t K,
+                                                        const GsTiers* __restrict__ plans,
+                                                        int32_t n_colours, int32_t sweeps,
+                                                        float* __restrict__ part,
+                                                        unsigned* counter, int* abort_flag) {
+    __shared__ float sacc[kBig / kWave][Q][Chunk<DT>::E];
+    __shared__ float sd[kBig / kWave];
+    unsigned epoch = 0;
+    for (int s = 0; s < sweeps; ++s)
+        for (int c = 0; c < n_colours; ++c) {
+            const GsTiers& tt = plans[c];
+            if (tt.nt == 0) continue;
+            const int64_t nb = tt.blk0[tt.nt];
+            for (int64_t b = blockIdx.x; b < nb; b += gridDim.x)
+                gs_block<Q, DT>(rp, col, w, X, K, tt, b, part, sacc, sd);
+            ++epoch;
+            if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
+            if (tt.split) {
+                gs_split_rows<Q, DT>(X, K, tt.row0[0], tt.row0[1] - tt.row0[0], part,
+                                     ((int64_t)blockIdx.x * kBig + threadIdx.x) / Q,
+                                     ((int64_t)gridDim.x * kBig) / Q);
+                ++epoch;
+                if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
+            }
+        }
 }
 
 // lanes per row of tier t: about half the tier's largest degree times
@@ -970,27 +1118,86 @@ static GsTiers plan_gs_step(const OrderedGraph* og, int Q, int c) {
         tt.row0[k] = r0;
         tt.row0[k + 1] = r1;
         tt.blk0[k] = blocks;
-        blocks += ((r1 - r0) * L + kBig - 1) / kBig;
+        if (t == 0 && L == kBig) {
+            tt.split = 1;  // k == 0 here: tier 0 comes first
+            blocks += (r1 - r0) * kSplit;
+        } else {
+            blocks += ((r1 - r0) * L + kBig - 1) / kBig;
+        }
         tt.blk0[k + 1] = blocks;
     }
     return tt;
 }
 
+constexpr int kPersistBlocks = 32;       // blocks of a persistent smoothing launch
+constexpr int64_t kPersistMaxStep = 96;  // largest step (plan blocks) it takes
+
 template <int Q, int DT>
-static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, hipStream_t st) {
+static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& ws,
+                    hipStream_t st) {
     const bool pr = prof::on();
     const int xs = DT == GR_BF16 ? 2 : 4;
-    std::vector<GsTiers> plan(og->n_colours);
-    for (int c = 0; c < og->n_colours; ++c) plan[c] = plan_gs_step(og, Q, c);
+    const int C = og->n_colours;
+    std::vector<GsTiers> plan(C);
+    int64_t biggest = 0;
+    int steps = 0;
+    double sweep_bytes = 0.0;
+    for (int c = 0; c < C; ++c) {
+        plan[c] = plan_gs_step(og, Q, c);
+        if (plan[c].nt == 0) continue;
+        ++steps;
+        biggest = std::max<int64_t>(biggest, plan[c].blk0[plan[c].nt]);
+        const double rows = (double)(og->class_ptr_h[c + 1] - og->class_ptr_h[c]);
+        sweep_bytes += 4.0 * (rows + 1) + 8.0 * (double)og->class_nnz_h[c] + 2.0 * rows * K * xs;
+    }
+    if (steps == 0) return GR_OK;
+    int64_t split_rows = 0;
+    for (int c = 0; c < C; ++c)
+        if (plan[c].split) split_rows = std::max<int64_t>(split_rows, plan[c].row0[1] - plan[c].row0[0]);
+    const size_t mark = ws.used;
+    float* part = ws.take<float>((size_t)std::max<int64_t>(split_rows, 1) * kSplit * (K + 1));
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (smoothing partials)");
+    if (biggest <= kPersistMaxStep && steps * sweeps >= 8) {
+        // every step is small: one cooperative launch for all sweeps
+        GsTiers* dplan = ws.take<GsTiers>(C);
+        unsigned* sync = ws.take<unsigned>(4);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (smoothing plan)");
+        int* abort_flag = (int*)(sync + 1);
+        GR_HIP(hipMemcpyAsync(dplan, plan.data(), sizeof(GsTiers) * C, hipMemcpyHostToDevice, st));
+        GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned) * 4, st));
+        const int32_t* rp = og->g.row_ptr;
+        const int32_t* cl = og->g.col;
+        const float* wt = og->g.w;
+        const GsTiers* cp = dplan;
+        int32_t nc = C, sw = sweeps;
+        void* args[] = {(void*)&rp, (void*)&cl, (void*)&wt, (void*)&X, (void*)&K, (void*)&cp,
+                        (void*)&nc, (void*)&sw, (void*)&part, (void*)&sync, (void*)&abort_flag};
+        if (pr) prof::begin(st);
+        GR_HIP(hipLaunchCooperativeKernel((const void*)k_gs_persistent<Q, DT>, dim3(kPersistBlocks),
+                                          dim3(kBig), args, 0, st));
+        if (pr) prof::end(st, prof::SMOOTH, sweep_bytes * sweeps, (int64_t)steps * sweeps);
+        int hflag = 0;
+        GR_HIP(hipMemcpyAsync(&hflag, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));  // also keeps `plan` alive for the copy
+        if (hflag) return set_error(GR_EHIP, "smoothing barrier timed out");
+        ws.used = mark;
+        return GR_OK;
+    }
     for (int s = 0; s < sweeps; ++s)
-        for (int c = 0; c < og->n_colours; ++c) {
+        for (int c = 0; c < C; ++c) {
             const GsTiers& tt = plan[c];
             if (tt.nt == 0) continue;
             const int64_t lo = og->class_ptr_h[c], hi = og->class_ptr_h[c + 1];
             if (pr) prof::begin(st);
             hipLaunchKernelGGL((k_gs_step<Q, DT>), dim3((unsigned)tt.blk0[tt.nt]), dim3(kBig), 0, st,
-                               og->g.row_ptr, og->g.col, og->g.w, X, K, tt);
+                               og->g.row_ptr, og->g.col, og->g.w, X, K, tt, part);
             GR_LAUNCHED("gs step");
+            if (tt.split) {
+                const int64_t nr = tt.row0[1] - tt.row0[0];
+                hipLaunchKernelGGL((k_gs_split<Q, DT>), dim3(blocks_for(nr * Q, 256)), dim3(256), 0,
+                                   st, X, K, tt.row0[0], nr, (const float*)part);
+                GR_LAUNCHED("gs split rows");
+            }
             if (pr) {
                 // compulsory bytes of this colour step: its CSR rows, plus one
                 // read and one write of each updated vector row
@@ -1000,28 +1207,29 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, hipStrea
                 prof::end(st, prof::SMOOTH, bytes, 1);
             }
         }
+    ws.used = mark;
     return GR_OK;
 }
 
 int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dtype, void* X,
-                   hipStream_t st) {
+                   Arena& ws, hipStream_t st) {
     if (og->g.n == 0 || sweeps == 0) return GR_OK;
     int bytes = K * (dtype == GR_BF16 ? 2 : 4);
     int Q = bytes / 16;
     if (dtype == GR_BF16) {
         switch (Q) {
-            case 1: return smooth_q<1, GR_BF16>(og, K, sweeps, X, st);
-            case 2: return smooth_q<2, GR_BF16>(og, K, sweeps, X, st);
-            case 4: return smooth_q<4, GR_BF16>(og, K, sweeps, X, st);
-            case 8: return smooth_q<8, GR_BF16>(og, K, sweeps, X, st);
+            case 1: return smooth_q<1, GR_BF16>(og, K, sweeps, X, ws, st);
+            case 2: return smooth_q<2, GR_BF16>(og, K, sweeps, X, ws, st);
+            case 4: return smooth_q<4, GR_BF16>(og, K, sweeps, X, ws, st);
+            case 8: return smooth_q<8, GR_BF16>(og, K, sweeps, X, ws, st);
         }
     } else {
         switch (Q) {
-            case 1: return smooth_q<1, GR_F32>(og, K, sweeps, X, st);
-            case 2: return smooth_q<2, GR_F32>(og, K, sweeps, X, st);
-            case 4: return smooth_q<4, GR_F32>(og, K, sweeps, X, st);
-            case 8: return smooth_q<8, GR_F32>(og, K, sweeps, X, st);
-            case 16: return smooth_q<16, GR_F32>(og, K, sweeps, X, st);
+            case 1: return smooth_q<1, GR_F32>(og, K, sweeps, X, ws, st);
+            case 2: return smooth_q<2, GR_F32>(og, K, sweeps, X, ws, st);
+            case 4: return smooth_q<4, GR_F32>(og, K, sweeps, X, ws, st);
+            case 8: return smooth_q<8, GR_F32>(og, K, sweeps, X, ws, st);
+            case 16: return smooth_q<16, GR_F32>(og, K, sweeps, X, ws, st);
         }
     }
     return set_error(GR_EUNSUP, "unsupported K=%d for this dtype", K);

@@ -125,7 +125,11 @@ def test_greedy_colouring_bit_exact(ldf):
 def test_smoothing_matches_oracle(dtype):
     dev = _dev()
     G = _G()
-    for name, g in small_graphs().items():
+    graphs = dict(small_graphs())
+    # hubs of degree above 2048: rows split across blocks
+    graphs["chunglu_hubs_10000"] = W.chung_lu(10000, mean_deg=700.0, seed=7)
+    assert graphs["chunglu_hubs_10000"].degrees().max() > 2048
+    for name, g in graphs.items():
         for K in ((8, 16) if dtype == "f32" else (8, 32)):
             say(f"smooth {name} K={K} {dtype}")
             c, nc = _colour(g)
