@@ -87,12 +87,15 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 // (h(v), v), h(v) = splitmix64 output v of the colour seed, or
 // (deg(v), h(v), v) largest-degree-first.
 //  * One pass counts each node's higher-priority neighbours (cnt) and marks
-//    every stored entry that points to a lower-priority neighbour.
-//  * When a node takes colour c it sets bit c of the colour masks of its
-//    lower-priority neighbours and counts them down; a neighbour whose count
-//    reaches zero joins the next round's frontier, and its colour is then
-//    the first clear bit of its mask (a scan of its neighbours' colours
-//    only when more than kMaskBits colours are in use around it).
+//    every stored entry that points to a lower-priority neighbour (a thread
+//    per node of degree up to kCountLane, a wave per other node).
+//  * When a node takes colour c it counts its lower-priority neighbours
+//    down; a neighbour whose count reaches zero joins the next round's
+//    frontier.  A node's colour is the first colour absent among its
+//    neighbours (the coloured ones are exactly the higher-priority ones):
+//    a scan of their colours, except for nodes of degree above kJpBig,
+//    whose higher-priority neighbours also set bit c of a per-node colour
+//    mask, so that a hub reads its colour from the mask.
 //  * A round runs on the whole grid (a block per node of degree above
 //    kJpBig, a wave per node of degree above kJpTiny, kJpGroup lanes per
 //    other node), or, while the frontier is small, many rounds run back to
@@ -169,60 +172,19 @@ constexpr int kKinds = 3;
 constexpr uint8_t kDown = 1;       // entry flag: the neighbour has lower priority
 // entry flag bits 1-2: the neighbour's kind
 #ifndef GR_JP_SOLO_COST
-#define GR_JP_SOLO_COST 32
+#define GR_JP_SOLO_COST 128
 #endif
 // the few-block kernel runs a round when its cost in waves, tiny / (nodes
 // per wave) + medium + kJpWaves * big, is at most kSoloCost per block
 constexpr int kSoloCost = GR_JP_SOLO_COST;
 constexpr int kSoloRounds = 256;   // rounds per few-block launch at most
-constexpr int kJpMultiBlocks = 32; // blocks of the few-block kernel
+#ifndef GR_JP_MULTI_BLOCKS
+#define GR_JP_MULTI_BLOCKS 32
+#endif
+constexpr int kJpMultiBlocks = GR_JP_MULTI_BLOCKS;  // blocks of the few-block kernel
 
 __host__ __device__ inline int node_kind(int32_t deg) {
     return deg <= kJpTiny ? 0 : (deg <= kJpBig ? 1 : 2);
-}
-
-// cnt[v] = number of higher-priority neighbours and the entry flags; nodes
-// without higher-priority neighbours form the first frontier (the order of
-// appends is irrelevant to the result; they are gathered per block so that
-// the global counters see one atomic per block and kind)
-__global__ void __launch_bounds__(kJpThreads) k_jp_count(const int32_t* __restrict__ rp,
-                                                         const int32_t* __restrict__ col, int64_t n,
-                                                         uint64_t seed, int ldf,
-                                                         int32_t* __restrict__ cnt,
-                                                         uint8_t* __restrict__ eflag,
-                                                         int32_t* const* lists,
-                                                         int32_t* __restrict__ sizes) {
-    __shared__ int32_t s_cnt[kKinds], s_base[kKinds];
-    const int64_t t = ((int64_t)blockIdx.x * kJpThreads + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (threadIdx.x < kKinds) s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    int kind = 0, slot = -1;
-    const int32_t v = (int32_t)t;
-    if (t < n) {
-        const Prio pv = prio_of(rp, v, seed, ldf);
-        int32_t c = 0;
-        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
-            const int32_t u = col[e];
-            const bool up = higher(prio_of(rp, u, seed, ldf), pv);
-            c += up ? 1 : 0;
-            eflag[e] = (uint8_t)((up ? 0 : kDown) | (node_kind(rp[u + 1] - rp[u]) << 1));
-        }
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-        if (lane == 0) {
-            cnt[v] = c;
-            if (c == 0) {
-                kind = node_kind(rp[v + 1] - rp[v]);
-                slot = atomicAdd(&s_cnt[kind], 1);
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < kKinds && s_cnt[threadIdx.x] > 0)
-        s_base[threadIdx.x] = atomicAdd(&sizes[threadIdx.x], s_cnt[threadIdx.x]);
-    __syncthreads();
-    if (slot >= 0) lists[kind][s_base[kind] + slot] = v;
 }
 
 // append u to list `kind` of the next round where `want`; every lane of the
@@ -239,6 +201,83 @@ __device__ inline void wave_append(bool want, int kind, int32_t u, int32_t* cons
         if (lane == leader) base = atomicAdd(&next[kd], (int32_t)__popcll(m));
         base = __shfl(base, leader, kWave);
         if (want && kind == kd) out[kd][base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = u;
+    }
+}
+
+constexpr int32_t kCountLane = 64;  // the count pass takes nodes up to this degree per thread
+
+// count pass, nodes of degree <= kCountLane: one thread per node; larger
+// nodes are listed (biglist, its size in bigcnt) for k_jp_count_wide.  Nodes
+// without higher-priority neighbours form the first frontier (the order of
+// appends is irrelevant to the result).
+__global__ void __launch_bounds__(kThreads) k_jp_count(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col, int64_t n,
+                                                       uint64_t seed, int ldf,
+                                                       int32_t* __restrict__ cnt,
+                                                       uint8_t* __restrict__ eflag,
+                                                       int32_t* const* lists,
+                                                       int32_t* __restrict__ sizes,
+                                                       int32_t* __restrict__ biglist,
+                                                       int32_t* __restrict__ bigcnt) {
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t t0 = t - (threadIdx.x & (kWave - 1));
+    if (t0 >= n) return;  // whole waves leave together
+    const bool in = t < n;
+    const int32_t v = (int32_t)(in ? t : 0);
+    const int32_t e0 = in ? rp[v] : 0, e1 = in ? rp[v + 1] : 0;
+    const bool wide = in && e1 - e0 > kCountLane;
+    int32_t c = 0;
+    if (in && !wide) {
+        const Prio pv = prio_of(rp, v, seed, ldf);
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t u = col[e];
+            const bool up = higher(prio_of(rp, u, seed, ldf), pv);
+            c += up ? 1 : 0;
+            eflag[e] = (uint8_t)((up ? 0 : kDown) | (node_kind(rp[u + 1] - rp[u]) << 1));
+        }
+        cnt[v] = c;
+    }
+    wave_append(in && !wide && c == 0, node_kind(e1 - e0), v, lists, sizes);
+    // the wide nodes: a list of their own (one atomic per wave)
+    const uint64_t m = __ballot(wide);
+    if (m) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(bigcnt, (int32_t)__popcll(m));
+        base = __shfl(base, leader, kWave);
+        if (wide) biglist[base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = v;
+    }
+}
+
+// count pass, the listed wide nodes: one wave per node, grid-stride; nodes
+// of degree above kJpBig also get their colour-mask slot
+__global__ void __launch_bounds__(kThreads) k_jp_count_wide(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, uint64_t seed, int ldf,
+    const int32_t* __restrict__ biglist, const int32_t* __restrict__ bigcnt,
+    int32_t* __restrict__ cnt, uint8_t* __restrict__ eflag, int32_t* const* lists,
+    int32_t* __restrict__ sizes, int32_t* __restrict__ mslot, int32_t* __restrict__ nslots) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kThreads / kWave);
+    const int32_t nbig = *bigcnt;
+    for (int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave; t < nbig; t += nw) {
+        const int32_t v = biglist[t];
+        const Prio pv = prio_of(rp, v, seed, ldf);
+        int32_t c = 0;
+        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
+            const int32_t u = col[e];
+            const bool up = higher(prio_of(rp, u, seed, ldf), pv);
+            c += up ? 1 : 0;
+            eflag[e] = (uint8_t)((up ? 0 : kDown) | (node_kind(rp[u + 1] - rp[u]) << 1));
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+        if (lane == 0) {
+            cnt[v] = c;
+            const int k = node_kind(rp[v + 1] - rp[v]);
+            if (k == 2) mslot[v] = atomicAdd(nslots, 1);
+            if (c == 0) lists[k][atomicAdd(&sizes[k], 1)] = v;
+        }
     }
 }
 
@@ -285,15 +324,26 @@ __device__ inline int32_t mask_first_free(uint64_t* m, int gl) {
     return f == 0x7fffffff ? -1 : f;
 }
 
+// LDS of a block's append aggregation
+struct JpShared {
+    uint64_t part[kJpWaves][4];
+    int32_t found;
+    int32_t cnt[kKinds];
+    int32_t base[kKinds];
+};
+
 // a coloured node tells its lower-priority neighbours (entries e0, e0 +
-// stride, ... < e1): mask bit, count down, append the ones that become
-// ready.  Every lane of the wave must call this with the same trip count
-// (trips = steps of kN * stride); lanes of no node pass e0 = e1.
+// stride, ... < e1): mask bit (hubs only), count down, and the neighbours
+// that become ready are appended to the next round's lists.  Every thread
+// of the block calls this with the same trip count (steps of kN * stride;
+// threads of no node pass e0 = e1); the appends of a step are gathered in
+// LDS so that each list counter takes one atomic per block and step.
 constexpr int kN = 4;
 __device__ inline void jp_notify(const int32_t* __restrict__ col, const uint8_t* __restrict__ eflag,
                                  int32_t e0, int32_t e1, int32_t stride, int32_t trips, int32_t c,
                                  int32_t* __restrict__ cnt, uint64_t* __restrict__ mask,
-                                 int32_t* const* out, int32_t* __restrict__ next) {
+                                 const int32_t* __restrict__ mslot, int32_t* const* out,
+                                 int32_t* __restrict__ next, JpShared& sh) {
     // four entries per step, so that their atomics are in flight together
     for (int32_t s = 0; s < trips; ++s) {
         const int32_t e = e0 + s * kN * stride;
@@ -308,42 +358,69 @@ __device__ inline void jp_notify(const int32_t* __restrict__ col, const uint8_t*
         }
 #pragma unroll
         for (int k = 0; k < kN; ++k)
-            if ((f[k] & kDown) && c < kMaskBits)
-                atomicOr((unsigned long long*)&mask[(int64_t)u[k] * kMaskWords + (c >> 6)],
+            if ((f[k] & kDown) && ((f[k] >> 1) & 3) == 2 && c < kMaskBits)
+                atomicOr((unsigned long long*)&mask[(int64_t)mslot[u[k]] * kMaskWords + (c >> 6)],
                          1ull << (c & 63));
 #pragma unroll
         for (int k = 0; k < kN; ++k) old[k] = (f[k] & kDown) ? atomicSub(&cnt[u[k]], 1) : 0;
+        // block-level append: slots in LDS, one global reservation per kind
+        if (threadIdx.x < kKinds) sh.cnt[threadIdx.x] = 0;
+        __syncthreads();
+        int32_t slot[kN];
 #pragma unroll
-        for (int k = 0; k < kN; ++k) wave_append(old[k] == 1, (f[k] >> 1) & 3, u[k], out, next);
+        for (int k = 0; k < kN; ++k)
+            slot[k] = old[k] == 1 ? atomicAdd(&sh.cnt[(f[k] >> 1) & 3], 1) : -1;
+        __syncthreads();
+        if (threadIdx.x < kKinds && sh.cnt[threadIdx.x] > 0)
+            sh.base[threadIdx.x] = atomicAdd(&next[threadIdx.x], sh.cnt[threadIdx.x]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kN; ++k)
+            if (slot[k] >= 0) {
+                const int kd = (f[k] >> 1) & 3;
+                out[kd][sh.base[kd] + slot[k]] = u[k];
+            }
     }
 }
 
+// block-wide maximum (every thread calls it)
+__device__ inline int32_t block_max(int32_t x, JpShared& sh) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) x = max(x, __shfl_xor(x, off, kWave));
+    __syncthreads();
+    if (threadIdx.x == 0) sh.found = 0;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&sh.found, x);
+    __syncthreads();
+    const int32_t m = sh.found;
+    __syncthreads();
+    return m;
+}
+
 // colour node v (valid) with an aligned group of G lanes (gl = lane in the
-// group); all lanes of the wave call this together, `trips` being the
-// wave's largest ceil(degree / (kN * G))
+// group); every thread of the block calls this together
 template <int G>
 __device__ inline void jp_group_node(const int32_t* __restrict__ rp,
                                      const int32_t* __restrict__ col,
                                      const uint8_t* __restrict__ eflag, bool valid, int32_t v,
                                      int gl, int32_t* __restrict__ cnt,
-                                     uint64_t* __restrict__ mask, int32_t* __restrict__ colours,
-                                     int32_t* const* out, int32_t* __restrict__ next) {
+                                     uint64_t* __restrict__ mask, const int32_t* __restrict__ mslot,
+                                     int32_t* __restrict__ colours, int32_t* const* out,
+                                     int32_t* __restrict__ next, JpShared& sh) {
     int32_t e0 = 0, e1 = 0, c = 0;
     if (valid) {
         e0 = rp[v];
         e1 = rp[v + 1];
-        c = mask_first_free<G>(mask + (int64_t)v * kMaskWords, gl);
-        for (int32_t base = kMaskBits; c < 0; base += 256) {
+        c = -1;
+        for (int32_t base = 0; c < 0; base += 256) {
             uint64_t used[4];
             window_bits<G>(col, colours, e0 + gl, e1, G, base, used);
             c = first_free4(used, base);
         }
         if (gl == 0) colours[v] = c;
     }
-    int32_t trips = (e1 - e0 + kN * G - 1) / (kN * G);
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) trips = max(trips, __shfl_xor(trips, off, kWave));
-    jp_notify(col, eflag, e0 + gl, e1, G, trips, c, cnt, mask, out, next);
+    const int32_t trips = block_max((e1 - e0 + kN * G - 1) / (kN * G), sh);
+    jp_notify(col, eflag, e0 + gl, e1, G, trips, c, cnt, mask, mslot, out, next, sh);
 }
 
 // colour the big node v with the whole block (all threads call it)
@@ -352,12 +429,14 @@ __device__ inline void jp_group_node(const int32_t* __restrict__ rp,
 __device__ inline void jp_big_node(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                    const uint8_t* __restrict__ eflag, int32_t v, int f,
                                    int pieces, int32_t* __restrict__ cnt,
-                                   uint64_t* __restrict__ mask, int32_t* __restrict__ colours,
-                                   int32_t* const* out, int32_t* __restrict__ next,
-                                   uint64_t (*part)[4], int32_t* found) {
+                                   uint64_t* __restrict__ mask, const int32_t* __restrict__ mslot,
+                                   int32_t* __restrict__ colours, int32_t* const* out,
+                                   int32_t* __restrict__ next, JpShared& sh) {
+    uint64_t (*part)[4] = sh.part;
+    int32_t* found = &sh.found;
     const int32_t e0 = rp[v], e1 = rp[v + 1];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    int32_t c = mask_first_free<kWave>(mask + (int64_t)v * kMaskWords, lane);
+    int32_t c = mask_first_free<kWave>(mask + (int64_t)mslot[v] * kMaskWords, lane);
     for (int32_t base = kMaskBits; c < 0; base += 256) {
         uint64_t used[4];
         window_bits<kWave>(col, colours, e0 + (int32_t)threadIdx.x, e1, kJpThreads, base, used);
@@ -378,8 +457,9 @@ __device__ inline void jp_big_node(const int32_t* __restrict__ rp, const int32_t
     const int32_t len = (e1 - e0 + pieces - 1) / pieces;
     const int32_t p1 = min(e1, e0 + (f + 1) * len), p0 = min(p1, e0 + f * len);
     const int32_t trips = (p1 - p0 + kN * kJpThreads - 1) / (kN * kJpThreads);
-    jp_notify(col, eflag, p0 + (int32_t)threadIdx.x, p1, kJpThreads, trips, c, cnt, mask, out,
-              next);
+    __syncthreads();  // `found` is reused below
+    jp_notify(col, eflag, p0 + (int32_t)threadIdx.x, p1, kJpThreads, trips, c, cnt, mask, mslot,
+              out, next, sh);
 }
 
 struct JpBufs {
@@ -387,7 +467,8 @@ struct JpBufs {
     int32_t* sizes;            // [3 r + kind]: frontier sizes of round r
     int32_t* state;            // [0] current round, [1] set when a grid round ran
     int32_t* cnt;
-    uint64_t* mask;
+    uint64_t* mask;   // colour masks of the nodes of degree above kJpBig
+    int32_t* mslot;   // their slot in `mask`
     uint8_t* eflag;
     int64_t max_rounds;
 };
@@ -397,8 +478,7 @@ struct JpBufs {
 // of the grid (or of the one block) calls this
 __device__ inline void jp_round(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                 const JpBufs& jb, int64_t r, const int32_t* nk, int64_t blk,
-                                int64_t nblk, int32_t* __restrict__ colours, uint64_t (*part)[4],
-                                int32_t* found) {
+                                int64_t nblk, int32_t* __restrict__ colours, JpShared& sh) {
     int32_t* const* in = jb.list[r & 1];
     int32_t* const* out = jb.list[(r + 1) & 1];
     int32_t* next = jb.sizes + kKinds * (r + 1);
@@ -406,19 +486,22 @@ __device__ inline void jp_round(const int32_t* __restrict__ rp, const int32_t* _
     const int pieces = nk[2] > 0 ? (int)max<int64_t>(1, min<int64_t>(8, nblk / nk[2])) : 1;
     for (int64_t t = blk; t < (int64_t)nk[2] * pieces; t += nblk)
         jp_big_node(rp, col, jb.eflag, in[2][t / pieces], (int)(t % pieces), pieces, jb.cnt,
-                    jb.mask, colours, out, next, part, found);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = blk * kJpWaves + threadIdx.x / kWave, nwaves = nblk * kJpWaves;
-    for (int64_t t = wave; t < nk[1]; t += nwaves)
-        jp_group_node<kWave>(rp, col, jb.eflag, true, in[1][t], lane, jb.cnt, jb.mask, colours, out,
-                             next);
-    constexpr int GPW = kWave / kJpGroup;
-    for (int64_t t0 = wave * GPW; t0 < nk[0]; t0 += nwaves * GPW) {
-        // whole waves stay in the loop together; groups past the end idle
-        const int64_t t = t0 + lane / kJpGroup;
+                    jb.mask, jb.mslot, colours, out, next, sh);
+    // medium nodes: a wave each; tiny nodes: kJpGroup lanes each; the loops
+    // step a whole block at a time so that the block appends together
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int64_t t0 = blk * kJpWaves; t0 < nk[1]; t0 += nblk * kJpWaves) {
+        const int64_t t = t0 + wave;
+        const bool valid = t < nk[1];
+        jp_group_node<kWave>(rp, col, jb.eflag, valid, valid ? in[1][t] : 0, lane, jb.cnt, jb.mask,
+                             jb.mslot, colours, out, next, sh);
+    }
+    constexpr int GPB = kJpThreads / kJpGroup;
+    for (int64_t t0 = blk * GPB; t0 < nk[0]; t0 += nblk * GPB) {
+        const int64_t t = t0 + threadIdx.x / kJpGroup;
         const bool valid = t < nk[0];
         jp_group_node<kJpGroup>(rp, col, jb.eflag, valid, valid ? in[0][t] : 0, lane % kJpGroup,
-                                jb.cnt, jb.mask, colours, out, next);
+                                jb.cnt, jb.mask, jb.mslot, colours, out, next, sh);
     }
 }
 
@@ -426,14 +509,13 @@ __device__ inline void jp_round(const int32_t* __restrict__ rp, const int32_t* _
 __global__ void __launch_bounds__(kJpThreads) k_jp_round(const int32_t* __restrict__ rp,
                                                          const int32_t* __restrict__ col,
                                                          JpBufs jb, int32_t* __restrict__ colours) {
-    __shared__ uint64_t part[kJpWaves][4];
-    __shared__ int32_t found;
+    __shared__ JpShared sh;
     const int64_t r = jb.state[0];
     if (r >= jb.max_rounds) return;
     int32_t nk[kKinds];
     for (int k = 0; k < kKinds; ++k) nk[k] = jb.sizes[kKinds * r + k];
     if (nk[0] + nk[1] + nk[2] == 0) return;
-    jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, part, &found);
+    jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, sh);
     if (blockIdx.x == 0 && threadIdx.x == 0) jb.state[1] = 1;
 }
 
@@ -445,13 +527,15 @@ __global__ void __launch_bounds__(kJpThreads) k_jp_multi(const int32_t* __restri
                                                          const int32_t* __restrict__ col,
                                                          JpBufs jb, int32_t* __restrict__ colours,
                                                          unsigned* counter, int* abort_flag) {
-    __shared__ uint64_t part[kJpWaves][4];
-    __shared__ int32_t found;
+    __shared__ JpShared sh;
     __shared__ int32_t go, snk[kKinds];
     int64_t r = (int64_t)jb.state[0] + jb.state[1];
+    // the barrier counter keeps counting across launches: counter[1] holds
+    // the value it had when the previous launch ended
+    const unsigned base = counter[1];
     unsigned epoch = 1;
     // every block has read the state before block 0 rewrites it
-    if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
+    if (!grid_barrier(counter, base + gridDim.x * epoch, abort_flag)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         jb.state[0] = (int32_t)r;
         jb.state[1] = 0;
@@ -472,12 +556,15 @@ __global__ void __launch_bounds__(kJpThreads) k_jp_multi(const int32_t* __restri
         __syncthreads();
         if (!go) break;  // the same decision in every block: same sizes after the barrier
         int32_t nk[kKinds] = {snk[0], snk[1], snk[2]};
-        jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, part, &found);
+        jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, sh);
         ++epoch;
-        if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
+        if (!grid_barrier(counter, base + gridDim.x * epoch, abort_flag)) return;
         ++r;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) jb.state[0] = (int32_t)r;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        jb.state[0] = (int32_t)r;
+        counter[1] = base + gridDim.x * epoch;
+    }
 }
 
 __global__ void k_col_fill(int64_t n, int32_t* __restrict__ colours) {
@@ -511,7 +598,11 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
         for (int k = 0; k < kKinds; ++k) jb.list[h][k] = ws.take<int32_t>(n);
     int32_t** dlists = ws.take<int32_t*>(kKinds);
     jb.cnt = ws.take<int32_t>(n);
-    jb.mask = ws.take<uint64_t>((size_t)n * kMaskWords);
+    // a node of degree above kJpBig holds more than kJpBig entries
+    const int64_t nmask = nnz / (kJpBig + 1) + 1;
+    jb.mask = ws.take<uint64_t>((size_t)nmask * kMaskWords);
+    jb.mslot = ws.take<int32_t>(n);
+    int32_t* biglist = ws.take<int32_t>(n);
     jb.eflag = ws.take<uint8_t>(nnz + 1);
     // frontier sizes of rounds [0, n + 1] (a round colours at least one
     // node, so there are at most n of them), three per round, then the
@@ -520,24 +611,29 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
     jb.sizes = ws.take<int32_t>(nsz);
     jb.state = jb.sizes + nsz - 8;
     jb.max_rounds = n;
-    unsigned* sync = ws.take<unsigned>(4);
-    int* abort_flag = (int*)(sync + 1);
+    unsigned* sync = ws.take<unsigned>(4);  // barrier counter, its base, abort flag
+    int* abort_flag = (int*)(sync + 2);
     const int32_t* rp = g->row_ptr;
     const int32_t* cl = g->col;
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
     GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned) * 4, st));
     GR_HIP(hipMemsetAsync(jb.sizes, 0, sizeof(int32_t) * nsz, st));
-    GR_HIP(hipMemsetAsync(jb.mask, 0, sizeof(uint64_t) * (size_t)n * kMaskWords, st));
+    GR_HIP(hipMemsetAsync(jb.mask, 0, sizeof(uint64_t) * (size_t)nmask * kMaskWords, st));
     GR_HIP(hipMemcpyAsync(dlists, jb.list[0], sizeof(int32_t*) * kKinds, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_col_fill, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, colours);
     GR_LAUNCHED("colour fill");
-    hipLaunchKernelGGL(k_jp_count, dim3(blocks_for(n * kWave, kJpThreads)), dim3(kJpThreads), 0, st,
-                       g->row_ptr, g->col, n, seed, ldf, jb.cnt, jb.eflag, (int32_t* const*)dlists,
-                       jb.sizes);
+    int32_t* bigcnt = (int32_t*)(sync + 3);
+    int32_t* nslots = jb.state + 2;
+    hipLaunchKernelGGL(k_jp_count, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, g->row_ptr,
+                       g->col, n, seed, ldf, jb.cnt, jb.eflag, (int32_t* const*)dlists, jb.sizes,
+                       biglist, bigcnt);
     GR_LAUNCHED("colour count");
+    hipLaunchKernelGGL(k_jp_count_wide, dim3(1024), dim3(kThreads), 0, st, g->row_ptr, g->col, seed,
+                       ldf, (const int32_t*)biglist, (const int32_t*)bigcnt, jb.cnt, jb.eflag,
+                       (int32_t* const*)dlists, jb.sizes, jb.mslot, nslots);
+    GR_LAUNCHED("colour count (wide rows)");
     for (int64_t batch = 0;; ++batch) {
         for (int b = 0; b < kJpBatch; ++b) {
-            GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned), st));
             void* args[] = {(void*)&rp, (void*)&cl, (void*)&jb, (void*)&colours, (void*)&sync,
                             (void*)&abort_flag};
             GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_multi, dim3(kJpMultiBlocks),
@@ -638,17 +734,18 @@ __global__ void k_perm_degrees(const int32_t* __restrict__ rp, const uint32_t* _
     deg[r] = rp[v + 1] - rp[v];
 }
 
-// one wave per new row: copy the old row's entries with relabelled columns
+// G lanes per new row (G a power of two sized to the mean degree): copy the
+// old row's entries with relabelled columns
 __global__ void k_perm_entries(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                const float* __restrict__ w, const uint32_t* __restrict__ perm,
                                const int32_t* __restrict__ iperm, const int32_t* __restrict__ nrp,
-                               int64_t n, int32_t* __restrict__ ncol, float* __restrict__ nw) {
-    int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    int lane = threadIdx.x & (kWave - 1);
+                               int64_t n, int G, int32_t* __restrict__ ncol, float* __restrict__ nw) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int l = threadIdx.x % G;
     if (r >= n) return;
     int32_t v = (int32_t)perm[r];
     int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[r];
-    for (int32_t e = e0 + lane; e < e1; e += kWave) {
+    for (int32_t e = e0 + l; e < e1; e += G) {
         ncol[o + (e - e0)] = iperm[col[e]];
         nw[o + (e - e0)] = w[e];
     }
@@ -715,9 +812,11 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
     }
     GR_TRY(scan_exclusive_i32(deg, nrp, n, nrp + n, ws, st));
     if (n > 0) {
-        hipLaunchKernelGGL(k_perm_entries, dim3(blocks_for(n * kWave, kThreads)), dim3(kThreads), 0,
+        int G = 4;
+        while (G < kWave && G * 2 <= nnz / n) G *= 2;  // about half the mean degree
+        hipLaunchKernelGGL(k_perm_entries, dim3(blocks_for(n * G, kThreads)), dim3(kThreads), 0,
                            st, g->row_ptr, g->col, g->w, (const uint32_t*)og->perm, og->iperm, nrp,
-                           n, ncol, nw);
+                           n, G, ncol, nw);
         GR_LAUNCHED("perm entries");
     }
     // bucket sizes (rows, entries) on the host
