@@ -1228,8 +1228,14 @@ static GsTiers plan_gs_step(const OrderedGraph* og, int Q, int c) {
     return tt;
 }
 
-constexpr int kPersistBlocks = 32;       // blocks of a persistent smoothing launch
-constexpr int64_t kPersistMaxStep = 96;  // largest step (plan blocks) it takes
+#ifndef GR_GS_PERSIST_BLOCKS
+#define GR_GS_PERSIST_BLOCKS 32
+#endif
+#ifndef GR_GS_PERSIST_MAX
+#define GR_GS_PERSIST_MAX 96
+#endif
+constexpr int kPersistBlocks = GR_GS_PERSIST_BLOCKS;  // blocks of a persistent smoothing launch
+constexpr int64_t kPersistMaxStep = GR_GS_PERSIST_MAX;  // largest step (plan blocks) it takes
 
 template <int Q, int DT>
 static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& ws,
