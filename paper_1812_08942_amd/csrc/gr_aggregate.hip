@@ -305,8 +305,9 @@ __global__ void __launch_bounds__(kT) k_seg_tile(const uint32_t* __restrict__ va
 }
 
 // pass 2: one thread per run adds the run's pieces in tile order; the run's
-// key (I << jbits | J, I < J) and sum go to ukey / uw, and its mirrored key
-// (J << jbits | I) with the run index to mkey / midx for the second sort
+// key (I << jbits | J, I < J) and sum go to ukey / uw, and its column J with
+// the run index to mkey / midx: the runs are ordered by I, so a stable sort
+// by J alone orders the mirrored entries (J, I) by row and column
 __global__ void k_seg_runs(const uint64_t* __restrict__ keys, const int32_t* __restrict__ start,
                            const float* __restrict__ piece, int64_t runs, int64_t m, int jbits,
                            uint64_t* __restrict__ ukey, float* __restrict__ uw,
@@ -324,19 +325,19 @@ __global__ void k_seg_runs(const uint64_t* __restrict__ keys, const int32_t* __r
     const uint64_t mask = (1ull << jbits) - 1;
     ukey[r] = k;
     uw[r] = acc;
-    mkey[r] = ((k & mask) << jbits) | (k >> jbits);
+    mkey[r] = k & mask;
     midx[r] = (uint32_t)r;
 }
 
 // first and one-past-last position of every row in a key array sorted by
-// row (row = key >> jbits)
-__global__ void k_row_bounds(const uint64_t* __restrict__ keys, int64_t cnt, int jbits,
+// row (row = key >> shift)
+__global__ void k_row_bounds(const uint64_t* __restrict__ keys, int64_t cnt, int shift,
                              int32_t* __restrict__ rfirst, int32_t* __restrict__ rend) {
     int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= cnt) return;
-    uint64_t I = keys[r] >> jbits;
-    if (r == 0 || (keys[r - 1] >> jbits) != I) rfirst[I] = (int32_t)r;
-    if (r == cnt - 1 || (keys[r + 1] >> jbits) != I) rend[I] = (int32_t)(r + 1);
+    uint64_t I = keys[r] >> shift;
+    if (r == 0 || (keys[r - 1] >> shift) != I) rfirst[I] = (int32_t)r;
+    if (r == cnt - 1 || (keys[r + 1] >> shift) != I) rend[I] = (int32_t)(r + 1);
 }
 
 // coarse row I = [lower part: mirrored entries (I, J < I)] ++ [upper part:
@@ -365,17 +366,17 @@ __global__ void k_place_upper(const uint64_t* __restrict__ ukey, const float* __
 }
 
 __global__ void k_place_lower(const uint64_t* __restrict__ mkey, const uint32_t* __restrict__ midx,
-                              const float* __restrict__ uw, int64_t runs, int jbits,
-                              const int32_t* __restrict__ c_row_ptr,
+                              const uint64_t* __restrict__ ukey, const float* __restrict__ uw,
+                              int64_t runs, int jbits, const int32_t* __restrict__ c_row_ptr,
                               const int32_t* __restrict__ lfirst, int32_t* __restrict__ c_col,
                               float* __restrict__ c_w) {
     int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (t >= runs) return;
-    const uint64_t k = mkey[t];
-    const int64_t J = (int64_t)(k >> jbits);
+    const int64_t J = (int64_t)mkey[t];
+    const uint32_t r = midx[t];
     const int64_t p = (int64_t)c_row_ptr[J] + (t - lfirst[J]);
-    c_col[p] = (int32_t)(k & ((1ull << jbits) - 1));
-    c_w[p] = uw[midx[t]];
+    c_col[p] = (int32_t)(ukey[r] >> jbits);
+    c_w[p] = uw[r];
 }
 
 int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_ptr,
@@ -445,11 +446,11 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         hipLaunchKernelGGL(k_seg_runs, dim3(nbr), dim3(kT), 0, st, k1, start, piece, (int64_t)runs,
                            (int64_t)m, jbits, ukey, uw, mk0, mi0);
         GR_LAUNCHED("segment runs");
-        GR_TRY(radix_sort_pairs(mk0, mi0, mk1, mi1, runs, 2 * jbits, ws, st));
+        GR_TRY(radix_sort_pairs(mk0, mi0, mk1, mi1, runs, jbits, ws, st));
         hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, ukey, (int64_t)runs, jbits,
                            ufirst, uend);
         GR_LAUNCHED("upper row bounds");
-        hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, mk1, (int64_t)runs, jbits,
+        hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, mk1, (int64_t)runs, 0,
                            lfirst, lend);
         GR_LAUNCHED("lower row bounds");
         if (n_c > 0) {
@@ -461,8 +462,9 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         hipLaunchKernelGGL(k_place_upper, dim3(nbr), dim3(kT), 0, st, ukey, uw, (int64_t)runs, jbits,
                            c_row_ptr, ufirst, lfirst, lend, c_col, c_w);
         GR_LAUNCHED("place upper");
-        hipLaunchKernelGGL(k_place_lower, dim3(nbr), dim3(kT), 0, st, mk1, mi1, uw, (int64_t)runs,
-                           jbits, c_row_ptr, lfirst, c_col, c_w);
+        hipLaunchKernelGGL(k_place_lower, dim3(nbr), dim3(kT), 0, st, mk1, mi1,
+                           (const uint64_t*)ukey, uw, (int64_t)runs, jbits, c_row_ptr, lfirst, c_col,
+                           c_w);
         GR_LAUNCHED("place lower");
     } else {
         GR_TRY(fill_i32(c_row_ptr, 0, n_c + 1, st));

@@ -212,8 +212,11 @@ int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tota
 }
 
 // ----------------------------------------------------------- radix sort
+#ifndef GR_SORT_ITERS
+#define GR_SORT_ITERS 8
+#endif
 constexpr int kSortThreads = 256;
-constexpr int kSortIters = 8;
+constexpr int kSortIters = GR_SORT_ITERS;
 constexpr int kSortTile = kSortThreads * kSortIters;
 constexpr int kRadix = 256;
 
