@@ -15,6 +15,8 @@ roofline = the Gauss-Seidel colour-step kernels: compulsory bytes per colour
         over their HIP-event durations, against the 8 TB/s HBM peak.
 cpu_baseline = the FP64 reference oracle (one host thread) on level-0
         smoothing + affinity of the same graph, in the same unit.
+bf16 = the headline workload again with bfloat16 vector storage, with its
+        reduced graph's eigenvalues against the float32 run's.
 secondary = the same measurement on a second workload (default: the 256^3
         grid with bfloat16 vectors, whose colour steps are large enough to
         be bandwidth-bound); --secondary '' skips it.
@@ -53,6 +55,8 @@ def main():
     ap.add_argument("--random-priority", action="store_true",
                     help="greedy colouring with hashed priorities instead of "
                          "largest-degree-first")
+    ap.add_argument("--no-bf16-compare", action="store_true",
+                    help="skip the bfloat16-storage run of the headline workload")
     ap.add_argument("--secondary", default="grid256",
                     help="second workload measured the same way ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -100,9 +104,23 @@ def main():
     g, wl, r, dg = keep
     if not args.no_eig:
         result.update(eig_report(G, r, args.eig_original, dg))
+    if (not args.no_bf16_compare and res["storage"] == "f32" and wl.K % 8 == 0):
+        # the same workload with bfloat16 vector storage (FP32 arithmetic)
+        lam32 = np.array(result["eig_reduced"]) if "eig_reduced" in result else None
+        del r
+        b16, keep16 = run_workload(G, args.workload, "bf16", args.steps, args.warmup,
+                                   args.ldf, g=g)
+        entry = {k: b16[k] for k in ("value", "ms_per_step", "levels", "phase_ms_per_step",
+                                     "smooth_only_rate", "roofline")}
+        if lam32 is not None:
+            lam16, _ = G.gr_laplacian_eigs(keep16[2].coarse, 10)
+            entry["eig_reduced"] = [float(x) for x in lam16]
+            entry["eig_rel_diff_vs_f32"] = float(np.max(np.abs(lam16 - lam32) / lam32))
+        result["bf16"] = entry
+        del keep16
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(g, wl)
-    del keep, g, r, dg
+    del keep, g, dg
     if args.secondary and args.secondary != args.workload:
         # the same measurement on a second workload whose colour steps are
         # large enough to be bandwidth-bound (reported next to the headline)
@@ -115,7 +133,7 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def run_workload(G, key, dtype, steps, warmup, ldf):
+def run_workload(G, key, dtype, steps, warmup, ldf, g=None):
     """Times `steps` full reductions of workload `key` (after `warmup`),
     then the same steps with the library's event profiler on."""
     import torch
@@ -124,9 +142,10 @@ def run_workload(G, key, dtype, steps, warmup, ldf):
 
     wl = W.WORKLOADS[key]
     dtype = dtype or wl.dtype
-    t0 = time.time()
-    g = W.build_graph(key)
-    log(f"graph {g.name}: n={g.n} nnz={g.nnz} built in {time.time() - t0:.1f}s")
+    if g is None:
+        t0 = time.time()
+        g = W.build_graph(key)
+        log(f"graph {g.name}: n={g.n} nnz={g.nnz} built in {time.time() - t0:.1f}s")
     dev = "cuda:0"
     dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
     colours = torch.from_numpy(g.colours).to(dev) if g.colours is not None else None
