@@ -587,8 +587,8 @@ __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out
 constexpr int kJpBatch = 32;    // (single-block, grid) launch pairs between host checks
 constexpr int kJpBlocks = GR_JP_BLOCKS;  // grid of a round (grid-stride)
 
-int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
-                  int32_t* n_colours_host, Arena& ws, hipStream_t st) {
+static int colour_rounds(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
+                         int32_t* n_colours_host, Arena& ws, hipStream_t st) {
     const int64_t n = g->n, nnz = g->nnz;
     *n_colours_host = 0;
     if (n == 0) return GR_OK;
@@ -666,6 +666,326 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
     *n_colours_host = mx + 1;
     ws.used = mark;
     return GR_OK;
+}
+
+// ------------------------------------------------ colouring as a dataflow
+// The same greedy colouring without rounds.  The nodes are sorted once into
+// decreasing priority (position = rank); every node lists the ranks of its
+// higher-priority neighbours (`uplist`, from the node's row offset on).  A
+// cooperative launch holds as many waves as the device keeps resident; wave
+// w takes the positions w, w + W, w + 2W, ... in order, waits until each
+// listed neighbour has a colour (device-coherent polling loads), takes the
+// first colour absent among them and publishes it with a device-coherent
+// store.  A wave's positions come in priority order and a node waits only on
+// earlier positions, so the earliest uncoloured position is always at the
+// head of some wave with all its inputs published: no deadlock while all
+// waves are resident, which the cooperative launch guarantees.  The colour
+// values are the only data passed between waves, so relaxed device-scope
+// atomics suffice.  Every wait is bounded: past kFlowSpinLimit polls a lane
+// raises the abort flag, and every waiting lane leaves at its next check.
+constexpr int kFlowThreads = 256;
+constexpr int kFlowWaves = kFlowThreads / kWave;
+constexpr int kFlowU = 4;                      // listed neighbours in flight per lane
+constexpr unsigned kFlowSpinLimit = 1u << 21;  // polls of one neighbour at most
+#ifndef GR_FLOW_BLOCKS_PER_CU
+#define GR_FLOW_BLOCKS_PER_CU 4
+#endif
+
+__device__ inline int32_t ld_dev(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_dev(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_max_degree(const int32_t* __restrict__ rp, int64_t n, int32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t m = 0;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) m = max(m, rp[i + 1] - rp[i]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
+}
+
+// bits of the largest degree (at least 1)
+__device__ inline int degree_bits(int32_t maxdeg) {
+    return maxdeg > 0 ? 32 - __clz(maxdeg) : 1;
+}
+
+// Sort keys whose ascending order is decreasing priority.  mode 0: h(v)
+// alone (a bijection of v, so no ties); mode 1 (largest degree first): the
+// degree in the top bd bits, the top 64 - bd bits of h(v) below it (ties of
+// the truncated key are detected after the sort).
+__global__ void k_prio_keys(const int32_t* __restrict__ rp, int64_t n, uint64_t seed, int mode,
+                            const int32_t* __restrict__ maxdeg, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    uint64_t k = splitmix64(seed, (uint64_t)v);
+    if (mode) {
+        const int bd = degree_bits(*maxdeg);
+        k = ((uint64_t)(rp[v + 1] - rp[v]) << (64 - bd)) | (k >> bd);
+    }
+    keys[v] = ~k;
+    vals[v] = (uint32_t)v;
+}
+
+// second key of the exact largest-degree-first order: decreasing degree
+// (a stable sort on it after a sort on h alone)
+__global__ void k_degree_keys(const int32_t* __restrict__ rp, const uint32_t* __restrict__ order,
+                              int64_t n, uint64_t* __restrict__ keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = order[i];
+    keys[i] = ~(uint64_t)(uint32_t)(rp[v + 1] - rp[v]);
+}
+
+__global__ void k_adjacent_ties(const uint64_t* __restrict__ keys, int64_t n, int32_t* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + 1 < n && keys[i] == keys[i + 1]) atomicOr(flag, 1);
+}
+
+__global__ void k_rank_of(const uint32_t* __restrict__ order, int64_t n, int32_t* __restrict__ rank) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rank[order[i]] = (int32_t)i;
+}
+
+// up-lists, nodes of degree <= kCountLane: a thread per position; wider
+// nodes are listed for k_flow_count_wide
+__global__ void __launch_bounds__(kThreads) k_flow_count(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const uint32_t* __restrict__ order, const int32_t* __restrict__ rank, int64_t n,
+    int32_t* __restrict__ uplist, int32_t* __restrict__ pstart, int32_t* __restrict__ pcnt,
+    int32_t* __restrict__ wide, int32_t* __restrict__ nwide) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i - (threadIdx.x & (kWave - 1)) >= n) return;  // whole waves leave together
+    const bool in = i < n;
+    const int32_t v = in ? (int32_t)order[i] : 0;
+    const int32_t e0 = in ? rp[v] : 0, e1 = in ? rp[v + 1] : 0;
+    const bool wd = in && e1 - e0 > kCountLane;
+    if (in && !wd) {
+        int32_t k = 0;
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t r = rank[col[e]];
+            if (r < i) uplist[e0 + k++] = r;
+        }
+        pstart[i] = e0;
+        pcnt[i] = k;
+    }
+    const uint64_t m = __ballot(wd);
+    if (m) {
+        const int lane = threadIdx.x & (kWave - 1);
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(nwide, (int32_t)__popcll(m));
+        base = __shfl(base, leader, kWave);
+        if (wd) wide[base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = (int32_t)i;
+    }
+}
+
+// up-lists of the listed wide nodes: a wave per node, grid-stride
+__global__ void __launch_bounds__(kThreads) k_flow_count_wide(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+    const uint32_t* __restrict__ order, const int32_t* __restrict__ rank,
+    const int32_t* __restrict__ wide, const int32_t* __restrict__ nwide,
+    int32_t* __restrict__ uplist, int32_t* __restrict__ pstart, int32_t* __restrict__ pcnt) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * (kThreads / kWave);
+    const int32_t total = *nwide;
+    for (int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave; t < total; t += nw) {
+        const int32_t i = wide[t];
+        const int32_t v = (int32_t)order[i];
+        const int32_t e0 = rp[v], e1 = rp[v + 1];
+        int32_t k = 0;
+        for (int32_t b = e0; b < e1; b += kWave) {
+            const int32_t e = b + lane;
+            const int32_t r = e < e1 ? rank[col[e]] : 0x7fffffff;
+            const bool up = r < i;
+            const uint64_t m = __ballot(up);
+            if (up) uplist[e0 + k + (int32_t)__popcll(m & ((1ull << lane) - 1))] = r;
+            k += (int32_t)__popcll(m);
+        }
+        if (lane == 0) {
+            pstart[i] = e0;
+            pcnt[i] = k;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restrict__ pstart,
+                                                          const int32_t* __restrict__ pcnt,
+                                                          const int32_t* __restrict__ uplist,
+                                                          int64_t n, int32_t* cpos,
+                                                          int32_t* abort_flag) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * kFlowWaves;
+    for (int64_t i = (int64_t)blockIdx.x * kFlowWaves + threadIdx.x / kWave; i < n; i += nw) {
+        const int32_t s = pstart[i], m = pcnt[i];
+        uint64_t used[4] = {0, 0, 0, 0};
+        int stop = 0;
+        for (int32_t b = lane; b < m && !stop; b += kWave * kFlowU) {
+            int32_t u[kFlowU], c[kFlowU];
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k) {
+                const int32_t e = b + k * kWave;
+                u[k] = e < m ? uplist[s + e] : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k) c[k] = u[k] >= 0 ? ld_dev(cpos + u[k]) : -2;
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k) {
+                unsigned spins = 0;
+                while (c[k] == -1 && !stop) {
+                    __builtin_amdgcn_s_sleep(2);
+                    c[k] = ld_dev(cpos + u[k]);
+                    ++spins;
+                    if (spins >= kFlowSpinLimit) {
+                        atomicExch(abort_flag, 1);
+                        stop = 1;
+                    } else if ((spins & 255u) == 0 && ld_dev(abort_flag)) {
+                        stop = 1;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k)
+                if (c[k] >= 0 && c[k] < 256) used[c[k] >> 6] |= 1ull << (c[k] & 63);
+        }
+        if (__ballot(stop)) return;  // the whole wave leaves
+#pragma unroll
+        for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
+        int32_t c = first_free4(used, 0);
+        // colours 0..255 all taken: later windows (every listed neighbour
+        // is coloured by now); colour <= m ends the search
+        for (int32_t base = 256; c < 0; base += 256) {
+            uint64_t wu[4] = {0, 0, 0, 0};
+            for (int32_t e = lane; e < m; e += kWave) {
+                const int32_t cj = ld_dev(cpos + uplist[s + e]);
+                if (cj >= base && cj < base + 256) wu[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
+            }
+#pragma unroll
+            for (int w = 0; w < 4; ++w) wu[w] = wave_or(wu[w]);
+            c = first_free4(wu, base);
+        }
+        if (lane == 0) st_dev(cpos + i, c);
+    }
+}
+
+__global__ void k_flow_scatter(const uint32_t* __restrict__ order, const int32_t* __restrict__ cpos,
+                               int64_t n, int32_t* __restrict__ colours, int32_t* mx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t m = -1;
+    if (i < n) {
+        m = cpos[i];
+        colours[order[i]] = m;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(mx, m);
+}
+
+static int flow_blocks(int64_t n) {
+    int dev = 0, cus = 0, per_cu = 0;
+    GR_HIP(hipGetDevice(&dev));
+    GR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_jp_flow,
+                                                        kFlowThreads, 0));
+    per_cu = std::min(per_cu, GR_FLOW_BLOCKS_PER_CU);
+    if (per_cu < 1 || cus < 1) return set_error(GR_EHIP, "colouring kernel does not fit a CU");
+    const int64_t want = (n + kFlowWaves - 1) / kFlowWaves;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, want));
+}
+
+static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
+                       int32_t* n_colours_host, Arena& ws, hipStream_t st) {
+    const int64_t n = g->n, nnz = g->nnz;
+    *n_colours_host = 0;
+    if (n == 0) return GR_OK;
+    const size_t mark = ws.used;
+    uint64_t* ka = ws.take<uint64_t>(n);
+    uint64_t* kb = ws.take<uint64_t>(n);
+    uint32_t* va = ws.take<uint32_t>(n);
+    uint32_t* order = ws.take<uint32_t>(n);
+    int32_t* rank = ws.take<int32_t>(n);
+    int32_t* pstart = ws.take<int32_t>(n);
+    int32_t* pcnt = ws.take<int32_t>(n);
+    int32_t* cpos = ws.take<int32_t>(n);
+    int32_t* wide = ws.take<int32_t>(n);
+    int32_t* uplist = ws.take<int32_t>(nnz + 1);
+    // [0] largest degree, [1] tie flag, [2] wide count, [3] abort flag, [4] largest colour
+    int32_t* small = ws.take<int32_t>(8);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
+    const int nblk = flow_blocks(n);
+    if (nblk < 0) return nblk;
+    const unsigned nb = blocks_for(n, kThreads);
+    for (int exact = 0; exact < 2; ++exact) {
+        GR_HIP(hipMemsetAsync(small, 0, sizeof(int32_t) * 8, st));
+        GR_HIP(hipMemsetAsync(small + 4, 0xff, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_max_degree, dim3(256), dim3(kThreads), 0, st, g->row_ptr, n, small);
+        GR_LAUNCHED("colour max degree");
+        // the priority order
+        hipLaunchKernelGGL(k_prio_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, n, seed,
+                           (ldf && !exact) ? 1 : 0, (const int32_t*)small, ka, va);
+        GR_LAUNCHED("colour keys");
+        GR_TRY(radix_sort_pairs(ka, va, kb, order, n, 64, ws, st));
+        if (ldf && !exact) {
+            hipLaunchKernelGGL(k_adjacent_ties, dim3(nb), dim3(kThreads), 0, st, (const uint64_t*)kb,
+                               n, small + 1);
+            GR_LAUNCHED("colour key ties");
+        } else if (ldf) {
+            hipLaunchKernelGGL(k_degree_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr,
+                               (const uint32_t*)order, n, ka);
+            GR_LAUNCHED("colour degree keys");
+            GR_HIP(hipMemcpyAsync(va, order, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+            GR_TRY(radix_sort_pairs(ka, va, kb, order, n, 32, ws, st));
+        }
+        hipLaunchKernelGGL(k_rank_of, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)order, n,
+                           rank);
+        GR_LAUNCHED("colour ranks");
+        // the higher-priority neighbours of every position
+        hipLaunchKernelGGL(k_flow_count, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, g->col,
+                           (const uint32_t*)order, (const int32_t*)rank, n, uplist, pstart, pcnt,
+                           wide, small + 2);
+        GR_LAUNCHED("colour up-lists");
+        hipLaunchKernelGGL(k_flow_count_wide, dim3(1024), dim3(kThreads), 0, st, g->row_ptr,
+                           g->col, (const uint32_t*)order, (const int32_t*)rank,
+                           (const int32_t*)wide, (const int32_t*)(small + 2), uplist, pstart,
+                           pcnt);
+        GR_LAUNCHED("colour up-lists (wide rows)");
+        hipLaunchKernelGGL(k_col_fill, dim3(nb), dim3(kThreads), 0, st, n, cpos);
+        GR_LAUNCHED("colour fill");
+        const int32_t* ps = pstart;
+        const int32_t* pc = pcnt;
+        const int32_t* ul = uplist;
+        int32_t* abort_flag = small + 3;
+        int64_t nn = n;
+        void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&nn, (void*)&cpos,
+                        (void*)&abort_flag};
+        GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
+                                          args, 0, st));
+        hipLaunchKernelGGL(k_flow_scatter, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)order,
+                           (const int32_t*)cpos, n, colours, small + 4);
+        GR_LAUNCHED("colour scatter");
+        int32_t hs[8];
+        GR_HIP(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+        if (hs[3]) return set_error(GR_EHIP, "colouring wait timed out");
+        if (ldf && !exact && hs[1]) continue;  // truncated keys tied: again with the exact order
+        if (hs[4] < 0) return set_error(GR_EHIP, "colouring left nodes uncoloured");
+        *n_colours_host = hs[4] + 1;
+        break;
+    }
+    ws.used = mark;
+    return GR_OK;
+}
+
+int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
+                  int32_t* n_colours_host, Arena& ws, hipStream_t st) {
+#ifdef GR_COLOUR_ROUNDS
+    return colour_rounds(g, seed, ldf, colours, n_colours_host, ws, st);
+#else
+    return colour_flow(g, seed, ldf, colours, n_colours_host, ws, st);
+#endif
 }
 
 __global__ void k_check_colouring(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
