@@ -673,13 +673,17 @@ static int colour_rounds(const gr_graph* g, uint64_t seed, int ldf, int32_t* col
 // decreasing priority (position = rank); every node lists the ranks of its
 // higher-priority neighbours (`uplist`, from the node's row offset on).  A
 // cooperative launch holds as many waves as the device keeps resident; wave
-// w takes the positions w, w + W, w + 2W, ... in order, waits until each
-// listed neighbour has a colour (device-coherent polling loads), takes the
-// first colour absent among them and publishes it with a device-coherent
-// store.  A wave's positions come in priority order and a node waits only on
-// earlier positions, so the earliest uncoloured position is always at the
-// head of some wave with all its inputs published: no deadlock while all
-// waves are resident, which the cooperative launch guarantees.  The colour
+// w takes the batches of kFlowBatch consecutive positions w, w + W, ... in
+// order.  A position waits until each listed neighbour has a colour
+// (device-coherent polling loads), takes the first colour absent among them
+// and publishes it with a device-coherent store.  A batch whose positions
+// all have few listed neighbours is coloured together, kFlowG lanes per
+// position, each group publishing as soon as its own inputs are there;
+// otherwise the whole wave takes the batch's positions one after another.
+// A node waits only on earlier positions, so the earliest uncoloured
+// position is always in a batch at the head of some wave, with all its
+// inputs published: no deadlock while all waves are resident, which the
+// cooperative launch guarantees.  The colour
 // values are the only data passed between waves, so relaxed device-scope
 // atomics suffice.  Every wait is bounded: past kFlowSpinLimit polls a lane
 // raises the abort flag, and every waiting lane leaves at its next check.
@@ -687,6 +691,9 @@ constexpr int kFlowThreads = 256;
 constexpr int kFlowWaves = kFlowThreads / kWave;
 constexpr int kFlowU = 4;                      // listed neighbours in flight per lane
 constexpr unsigned kFlowSpinLimit = 1u << 21;  // polls of one neighbour at most
+constexpr int kFlowG = 8;                      // lanes per position of a narrow batch
+constexpr int kFlowBatch = kWave / kFlowG;     // positions of a batch
+constexpr int32_t kFlowNarrow = 64;            // listed neighbours per position of a narrow batch
 #ifndef GR_FLOW_BLOCKS_PER_CU
 #define GR_FLOW_BLOCKS_PER_CU 4
 #endif
@@ -812,62 +819,176 @@ __global__ void __launch_bounds__(kThreads) k_flow_count_wide(
     }
 }
 
+// one position with the whole wave; false when the wave must leave (abort)
+__device__ inline bool flow_wide(const int32_t* __restrict__ uplist, int32_t s, int32_t m,
+                                 int64_t i, int32_t* cpos, int32_t* abort_flag) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t used[4] = {0, 0, 0, 0};
+    int stop = 0;
+    for (int32_t b = lane; b < m && !stop; b += kWave * kFlowU) {
+        int32_t u[kFlowU], c[kFlowU];
+#pragma unroll
+        for (int k = 0; k < kFlowU; ++k) {
+            const int32_t e = b + k * kWave;
+            u[k] = e < m ? uplist[s + e] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kFlowU; ++k) c[k] = u[k] >= 0 ? ld_dev(cpos + u[k]) : -2;
+#pragma unroll
+        for (int k = 0; k < kFlowU; ++k) {
+            unsigned spins = 0;
+            while (c[k] == -1 && !stop) {
+                __builtin_amdgcn_s_sleep(2);
+                c[k] = ld_dev(cpos + u[k]);
+                ++spins;
+                if (spins >= kFlowSpinLimit) {
+                    atomicExch(abort_flag, 1);
+                    stop = 1;
+                } else if ((spins & 255u) == 0 && ld_dev(abort_flag)) {
+                    stop = 1;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kFlowU; ++k)
+            if (c[k] >= 0 && c[k] < 256) used[c[k] >> 6] |= 1ull << (c[k] & 63);
+    }
+    if (__ballot(stop)) return false;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
+    int32_t c = first_free4(used, 0);
+    // colours 0..255 all taken: later windows (every listed neighbour is
+    // coloured by now); colour <= m ends the search
+    for (int32_t base = 256; c < 0; base += 256) {
+        uint64_t wu[4] = {0, 0, 0, 0};
+        for (int32_t e = lane; e < m; e += kWave) {
+            const int32_t cj = ld_dev(cpos + uplist[s + e]);
+            if (cj >= base && cj < base + 256) wu[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) wu[w] = wave_or(wu[w]);
+        c = first_free4(wu, base);
+    }
+    if (lane == 0) st_dev(cpos + i, c);
+    return true;
+}
+
+// or over the aligned group of kFlowG lanes (every lane of the wave calls it)
+__device__ inline uint64_t group_or(uint64_t x) {
+#pragma unroll
+    for (int off = 1; off < kFlowG; off <<= 1) {
+        uint32_t lo = __shfl_xor((uint32_t)x, off, kWave);
+        uint32_t hi = __shfl_xor((uint32_t)(x >> 32), off, kWave);
+        x |= ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// kFlowBatch positions together, kFlowG lanes each, every position with at
+// most kFlowNarrow listed neighbours (so at most kFlowNarrow / kFlowG per lane,
+// all loaded at once, and a colour <= kFlowNarrow < 128).  The loop is
+// wave-uniform: a group publishes as soon as its own neighbours are all
+// coloured, whatever the other groups of the wave still wait for.
+__device__ inline bool flow_narrow(const int32_t* __restrict__ uplist, int32_t s, int32_t m,
+                                   int64_t i, bool valid, int32_t* cpos, int32_t* abort_flag) {
+    constexpr int U = kFlowNarrow / kFlowG;
+    const int gl = threadIdx.x & (kFlowG - 1);
+    int32_t u[U];
+    uint32_t pend = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int32_t e = gl + k * kFlowG;
+        u[k] = e < m ? uplist[s + e] : 0;
+        if (e < m) pend |= 1u << k;
+    }
+    uint64_t used0 = 0, used1 = 0;
+    bool pub = !valid;
+    for (unsigned it = 0;; ++it) {
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if ((pend >> k) & 1u) {
+                const int32_t c = ld_dev(cpos + u[k]);
+                if (c >= 0) {
+                    if (c < 64) used0 |= 1ull << c;
+                    else used1 |= 1ull << (c - 64);
+                    pend &= ~(1u << k);
+                }
+            }
+        const bool waiting = group_or(pend != 0 ? 1ull : 0ull) != 0;
+        const uint64_t a0 = group_or(used0), a1 = group_or(used1);
+        if (!pub && !waiting) {
+            const int32_t c = ~a0 ? __ffsll((unsigned long long)~a0) - 1
+                                  : 64 + __ffsll((unsigned long long)~a1) - 1;
+            if (gl == 0) st_dev(cpos + i, c);
+            pub = true;
+        }
+        if (__ballot(!pub) == 0) return true;
+        __builtin_amdgcn_s_sleep(2);
+        if (it >= kFlowSpinLimit) {
+            if ((threadIdx.x & (kWave - 1)) == 0) atomicExch(abort_flag, 1);
+            return false;
+        }
+        if ((it & 255u) == 255u && ld_dev(abort_flag)) return false;
+    }
+}
+
+// batches of the dataflow: aligned groups of kFlowBatch positions; a group
+// whose positions all have at most kFlowNarrow listed neighbours is one
+// (narrow) batch, any other group gives a batch per position.  A batch is
+// coded as its first position, with kNarrowBatch set for a narrow one.
+constexpr uint32_t kNarrowBatch = 0x80000000u;
+
+__device__ inline bool flow_group_narrow(const int32_t* __restrict__ pcnt, int64_t i0, int c) {
+    bool narrow = true;
+    for (int j = 0; j < c; ++j) narrow = narrow && pcnt[i0 + j] <= kFlowNarrow;
+    return narrow;
+}
+
+__global__ void k_flow_group_sizes(const int32_t* __restrict__ pcnt, int64_t n,
+                                   int32_t* __restrict__ nbat) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = k * kFlowBatch;
+    if (i0 >= n) return;
+    const int c = (int)(n - i0 < kFlowBatch ? n - i0 : kFlowBatch);
+    nbat[k] = flow_group_narrow(pcnt, i0, c) ? 1 : c;
+}
+
+__global__ void k_flow_batches(const int32_t* __restrict__ pcnt, int64_t n,
+                               const int32_t* __restrict__ boff, uint32_t* __restrict__ batches) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i0 = k * kFlowBatch;
+    if (i0 >= n) return;
+    const int c = (int)(n - i0 < kFlowBatch ? n - i0 : kFlowBatch);
+    const int32_t b = boff[k];
+    if (flow_group_narrow(pcnt, i0, c)) {
+        batches[b] = (uint32_t)i0 | kNarrowBatch;
+    } else {
+        for (int j = 0; j < c; ++j) batches[b + j] = (uint32_t)(i0 + j);
+    }
+}
+
 __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restrict__ pstart,
                                                           const int32_t* __restrict__ pcnt,
                                                           const int32_t* __restrict__ uplist,
+                                                          const uint32_t* __restrict__ batches,
+                                                          const int32_t* __restrict__ nbatches,
                                                           int64_t n, int32_t* cpos,
                                                           int32_t* abort_flag) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * kFlowWaves;
-    for (int64_t i = (int64_t)blockIdx.x * kFlowWaves + threadIdx.x / kWave; i < n; i += nw) {
-        const int32_t s = pstart[i], m = pcnt[i];
-        uint64_t used[4] = {0, 0, 0, 0};
-        int stop = 0;
-        for (int32_t b = lane; b < m && !stop; b += kWave * kFlowU) {
-            int32_t u[kFlowU], c[kFlowU];
-#pragma unroll
-            for (int k = 0; k < kFlowU; ++k) {
-                const int32_t e = b + k * kWave;
-                u[k] = e < m ? uplist[s + e] : -1;
-            }
-#pragma unroll
-            for (int k = 0; k < kFlowU; ++k) c[k] = u[k] >= 0 ? ld_dev(cpos + u[k]) : -2;
-#pragma unroll
-            for (int k = 0; k < kFlowU; ++k) {
-                unsigned spins = 0;
-                while (c[k] == -1 && !stop) {
-                    __builtin_amdgcn_s_sleep(2);
-                    c[k] = ld_dev(cpos + u[k]);
-                    ++spins;
-                    if (spins >= kFlowSpinLimit) {
-                        atomicExch(abort_flag, 1);
-                        stop = 1;
-                    } else if ((spins & 255u) == 0 && ld_dev(abort_flag)) {
-                        stop = 1;
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kFlowU; ++k)
-                if (c[k] >= 0 && c[k] < 256) used[c[k] >> 6] |= 1ull << (c[k] & 63);
+    const int32_t nbt = *nbatches;
+    for (int64_t bt = (int64_t)blockIdx.x * kFlowWaves + threadIdx.x / kWave; bt < nbt;
+         bt += nw) {
+        const uint32_t code = batches[bt];
+        if (code & kNarrowBatch) {
+            const int64_t ig = (int64_t)(code & ~kNarrowBatch) + lane / kFlowG;
+            const bool valid = ig < n;
+            const int32_t s = valid ? pstart[ig] : 0, m = valid ? pcnt[ig] : 0;
+            if (!flow_narrow(uplist, s, m, ig, valid, cpos, abort_flag)) return;
+        } else {
+            const int64_t i = code;
+            if (!flow_wide(uplist, pstart[i], pcnt[i], i, cpos, abort_flag)) return;
         }
-        if (__ballot(stop)) return;  // the whole wave leaves
-#pragma unroll
-        for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
-        int32_t c = first_free4(used, 0);
-        // colours 0..255 all taken: later windows (every listed neighbour
-        // is coloured by now); colour <= m ends the search
-        for (int32_t base = 256; c < 0; base += 256) {
-            uint64_t wu[4] = {0, 0, 0, 0};
-            for (int32_t e = lane; e < m; e += kWave) {
-                const int32_t cj = ld_dev(cpos + uplist[s + e]);
-                if (cj >= base && cj < base + 256) wu[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
-            }
-#pragma unroll
-            for (int w = 0; w < 4; ++w) wu[w] = wave_or(wu[w]);
-            c = first_free4(wu, base);
-        }
-        if (lane == 0) st_dev(cpos + i, c);
     }
 }
 
@@ -912,7 +1033,11 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     int32_t* cpos = ws.take<int32_t>(n);
     int32_t* wide = ws.take<int32_t>(n);
     int32_t* uplist = ws.take<int32_t>(nnz + 1);
-    // [0] largest degree, [1] tie flag, [2] wide count, [3] abort flag, [4] largest colour
+    const int64_t ngroups = (n + kFlowBatch - 1) / kFlowBatch;
+    int32_t* nbat = ws.take<int32_t>(ngroups);
+    int32_t* boff = ws.take<int32_t>(ngroups);
+    // [0] largest degree, [1] tie flag, [2] wide count, [3] abort flag,
+    // [4] largest colour, [5] batches
     int32_t* small = ws.take<int32_t>(8);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
     const int nblk = flow_blocks(n);
@@ -952,15 +1077,27 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
                            (const int32_t*)wide, (const int32_t*)(small + 2), uplist, pstart,
                            pcnt);
         GR_LAUNCHED("colour up-lists (wide rows)");
+        // the batches (the wide list is free again: it holds them)
+        const unsigned ngb = blocks_for(ngroups, kThreads);
+        hipLaunchKernelGGL(k_flow_group_sizes, dim3(ngb), dim3(kThreads), 0, st,
+                           (const int32_t*)pcnt, n, nbat);
+        GR_LAUNCHED("colour batch sizes");
+        GR_TRY(scan_exclusive_i32(nbat, boff, ngroups, small + 5, ws, st));
+        uint32_t* batches = (uint32_t*)wide;
+        hipLaunchKernelGGL(k_flow_batches, dim3(ngb), dim3(kThreads), 0, st, (const int32_t*)pcnt,
+                           n, (const int32_t*)boff, batches);
+        GR_LAUNCHED("colour batches");
         hipLaunchKernelGGL(k_col_fill, dim3(nb), dim3(kThreads), 0, st, n, cpos);
         GR_LAUNCHED("colour fill");
         const int32_t* ps = pstart;
         const int32_t* pc = pcnt;
         const int32_t* ul = uplist;
+        const uint32_t* bl = batches;
+        const int32_t* nbt = small + 5;
         int32_t* abort_flag = small + 3;
         int64_t nn = n;
-        void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&nn, (void*)&cpos,
-                        (void*)&abort_flag};
+        void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&bl, (void*)&nbt, (void*)&nn,
+                        (void*)&cpos, (void*)&abort_flag};
         GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
                                           args, 0, st));
         hipLaunchKernelGGL(k_flow_scatter, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)order,
