@@ -50,10 +50,8 @@ static size_t plan_bytes(int64_t n, int64_t nnz, int32_t K, int32_t dtype) {
                         + 2 * (4 * N + 8 * M)                  // coarse ping-pong
                         + 4 * N;                               // long-row ids
     size_t relabel = 36 * N + 8 * 1024 + sort_scratch(N);
-    // colouring: sort keys and values, ranks, up-lists (the round-based
-    // variant needs at most 96 N + M)
+    // colouring: sort keys and values, ranks, positions, batches, up-lists
     size_t colour = 46 * N + 4 * M + sort_scratch(N) + 8192;
-    if (96 * N + M + 8192 > colour) colour = 96 * N + M + 8192;
     size_t agg = 24 * N + 44 * N + sort_scratch(N);
     size_t gal = 8 * M + 4 * N + 36 * M + sort_scratch(M);
     size_t temp = relabel;

@@ -80,28 +80,12 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 }
 
 // -------------------------------------------------------------- colouring
-// Sequential greedy colouring in decreasing priority (every node takes the
-// smallest colour absent among its higher-priority neighbours), computed in
-// Jones-Plassmann rounds: a node is coloured once all its higher-priority
-// neighbours are, so the result does not depend on timing.  Priority:
-// (h(v), v), h(v) = splitmix64 output v of the colour seed, or
+// The Gauss-Seidel smoothing of Sec. 3.2.1 runs in a multicolour order; the
+// colouring is sequential greedy in decreasing priority: every node takes
+// the smallest colour absent among its higher-priority neighbours.
+// Priority: (h(v), v), h(v) = splitmix64 output v of the colour seed, or
 // (deg(v), h(v), v) largest-degree-first.
-//  * One pass counts each node's higher-priority neighbours (cnt) and marks
-//    every stored entry that points to a lower-priority neighbour (a thread
-//    per node of degree up to kCountLane, a wave per other node).
-//  * When a node takes colour c it counts its lower-priority neighbours
-//    down; a neighbour whose count reaches zero joins the next round's
-//    frontier.  A node's colour is the first colour absent among its
-//    neighbours (the coloured ones are exactly the higher-priority ones):
-//    a scan of their colours, except for nodes of degree above kJpBig,
-//    whose higher-priority neighbours also set bit c of a per-node colour
-//    mask, so that a hub reads its colour from the mask.
-//  * A round runs on the whole grid (a block per node of degree above
-//    kJpBig, a wave per node of degree above kJpTiny, kJpGroup lanes per
-//    other node), or, while the frontier is small, many rounds run back to
-//    back in a cooperative launch of a few blocks, separated by device-wide
-//    barriers.
-// Every edge is touched a constant number of times over all rounds.
+
 // Device-wide barrier for a cooperatively launched grid: the block's writes
 // are released to the device, a monotonic counter collects the blocks, and
 // the wait is bounded: past kSpinLimit polls (far beyond any colour step) the
@@ -130,24 +114,6 @@ __device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abo
     return ok != 0;
 }
 
-struct Prio {
-    uint32_t deg;
-    uint64_t h;
-    int32_t v;
-};
-__device__ inline Prio prio_of(const int32_t* rp, int32_t v, uint64_t seed, int ldf) {
-    Prio p;
-    p.deg = ldf ? (uint32_t)(rp[v + 1] - rp[v]) : 0u;
-    p.h = splitmix64(seed, (uint64_t)v);
-    p.v = v;
-    return p;
-}
-__device__ inline bool higher(const Prio& a, const Prio& b) {
-    if (a.deg != b.deg) return a.deg > b.deg;
-    if (a.h != b.h) return a.h > b.h;
-    return a.v > b.v;
-}
-
 __device__ inline uint64_t wave_or(uint64_t x) {
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -158,150 +124,7 @@ __device__ inline uint64_t wave_or(uint64_t x) {
     return x;
 }
 
-constexpr int kJpThreads = 1024;   // block of a round
-constexpr int kJpWaves = kJpThreads / kWave;
-constexpr int kMaskWords = 8;      // colour mask per node: colours [0, 512)
-constexpr int kMaskBits = 64 * kMaskWords;
-// node kinds by degree: 0 = up to kJpTiny (kJpGroup lanes each), 1 = up to
-// kJpBig (a wave each), 2 = above (a block each); each kind has its own
-// frontier list, sizes[3 r + kind] counting round r's
-constexpr int32_t kJpTiny = 32;
-constexpr int32_t kJpBig = 512;
-constexpr int kJpGroup = 8;
-constexpr int kKinds = 3;
-constexpr uint8_t kDown = 1;       // entry flag: the neighbour has lower priority
-// entry flag bits 1-2: the neighbour's kind
-#ifndef GR_JP_SOLO_COST
-#define GR_JP_SOLO_COST 128
-#endif
-// the few-block kernel runs a round when its cost in waves, tiny / (nodes
-// per wave) + medium + kJpWaves * big, is at most kSoloCost per block
-constexpr int kSoloCost = GR_JP_SOLO_COST;
-constexpr int kSoloRounds = 256;   // rounds per few-block launch at most
-#ifndef GR_JP_MULTI_BLOCKS
-#define GR_JP_MULTI_BLOCKS 32
-#endif
-constexpr int kJpMultiBlocks = GR_JP_MULTI_BLOCKS;  // blocks of the few-block kernel
-
-__host__ __device__ inline int node_kind(int32_t deg) {
-    return deg <= kJpTiny ? 0 : (deg <= kJpBig ? 1 : 2);
-}
-
-// append u to list `kind` of the next round where `want`; every lane of the
-// wave calls this together, and each list counter takes one atomic per wave
-__device__ inline void wave_append(bool want, int kind, int32_t u, int32_t* const* out,
-                                   int32_t* __restrict__ next) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int kd = 0; kd < kKinds; ++kd) {
-        const uint64_t m = __ballot(want && kind == kd);
-        if (m == 0) continue;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&next[kd], (int32_t)__popcll(m));
-        base = __shfl(base, leader, kWave);
-        if (want && kind == kd) out[kd][base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = u;
-    }
-}
-
-constexpr int32_t kCountLane = 64;  // the count pass takes nodes up to this degree per thread
-
-// count pass, nodes of degree <= kCountLane: one thread per node; larger
-// nodes are listed (biglist, its size in bigcnt) for k_jp_count_wide.  Nodes
-// without higher-priority neighbours form the first frontier (the order of
-// appends is irrelevant to the result).
-__global__ void __launch_bounds__(kThreads) k_jp_count(const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ col, int64_t n,
-                                                       uint64_t seed, int ldf,
-                                                       int32_t* __restrict__ cnt,
-                                                       uint8_t* __restrict__ eflag,
-                                                       int32_t* const* lists,
-                                                       int32_t* __restrict__ sizes,
-                                                       int32_t* __restrict__ biglist,
-                                                       int32_t* __restrict__ bigcnt) {
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t t0 = t - (threadIdx.x & (kWave - 1));
-    if (t0 >= n) return;  // whole waves leave together
-    const bool in = t < n;
-    const int32_t v = (int32_t)(in ? t : 0);
-    const int32_t e0 = in ? rp[v] : 0, e1 = in ? rp[v + 1] : 0;
-    const bool wide = in && e1 - e0 > kCountLane;
-    int32_t c = 0;
-    if (in && !wide) {
-        const Prio pv = prio_of(rp, v, seed, ldf);
-        for (int32_t e = e0; e < e1; ++e) {
-            const int32_t u = col[e];
-            const bool up = higher(prio_of(rp, u, seed, ldf), pv);
-            c += up ? 1 : 0;
-            eflag[e] = (uint8_t)((up ? 0 : kDown) | (node_kind(rp[u + 1] - rp[u]) << 1));
-        }
-        cnt[v] = c;
-    }
-    wave_append(in && !wide && c == 0, node_kind(e1 - e0), v, lists, sizes);
-    // the wide nodes: a list of their own (one atomic per wave)
-    const uint64_t m = __ballot(wide);
-    if (m) {
-        const int lane = threadIdx.x & (kWave - 1);
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(bigcnt, (int32_t)__popcll(m));
-        base = __shfl(base, leader, kWave);
-        if (wide) biglist[base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = v;
-    }
-}
-
-// count pass, the listed wide nodes: one wave per node, grid-stride; nodes
-// of degree above kJpBig also get their colour-mask slot
-__global__ void __launch_bounds__(kThreads) k_jp_count_wide(
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, uint64_t seed, int ldf,
-    const int32_t* __restrict__ biglist, const int32_t* __restrict__ bigcnt,
-    int32_t* __restrict__ cnt, uint8_t* __restrict__ eflag, int32_t* const* lists,
-    int32_t* __restrict__ sizes, int32_t* __restrict__ mslot, int32_t* __restrict__ nslots) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nw = (int64_t)gridDim.x * (kThreads / kWave);
-    const int32_t nbig = *bigcnt;
-    for (int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave; t < nbig; t += nw) {
-        const int32_t v = biglist[t];
-        const Prio pv = prio_of(rp, v, seed, ldf);
-        int32_t c = 0;
-        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
-            const int32_t u = col[e];
-            const bool up = higher(prio_of(rp, u, seed, ldf), pv);
-            c += up ? 1 : 0;
-            eflag[e] = (uint8_t)((up ? 0 : kDown) | (node_kind(rp[u + 1] - rp[u]) << 1));
-        }
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-        if (lane == 0) {
-            cnt[v] = c;
-            const int k = node_kind(rp[v + 1] - rp[v]);
-            if (k == 2) mslot[v] = atomicAdd(nslots, 1);
-            if (c == 0) lists[k][atomicAdd(&sizes[k], 1)] = v;
-        }
-    }
-}
-
-// bits of the colours of neighbours col[e], e = e0 + i*stride (i >= 0,
-// e < e1), that fall in the window [base, base + 256), or-combined over
-// aligned groups of G lanes
-template <int G>
-__device__ inline void window_bits(const int32_t* __restrict__ col,
-                                   const int32_t* __restrict__ colours, int32_t e0, int32_t e1,
-                                   int32_t stride, int32_t base, uint64_t used[4]) {
-    used[0] = used[1] = used[2] = used[3] = 0;
-    for (int32_t e = e0; e < e1; e += stride) {
-        int32_t cj = colours[col[e]];
-        if (cj >= base && cj < base + 256) used[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
-    }
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-#pragma unroll
-        for (int off = 1; off < G; off <<= 1) {
-            uint32_t lo = __shfl_xor((uint32_t)used[w], off, kWave);
-            uint32_t hi = __shfl_xor((uint32_t)(used[w] >> 32), off, kWave);
-            used[w] |= ((uint64_t)hi << 32) | lo;
-        }
-}
+constexpr int32_t kCountLane = 64;  // the up-list pass takes nodes up to this degree per thread
 
 __device__ inline int32_t first_free4(const uint64_t used[4], int32_t base) {
     for (int w = 0; w < 4; ++w)
@@ -309,367 +132,13 @@ __device__ inline int32_t first_free4(const uint64_t used[4], int32_t base) {
     return -1;
 }
 
-// first clear bit of a node's colour mask (the words were built by atomics:
-// read coherently), or -1 when all kMaskBits are set; lane gl of an aligned
-// group of G >= kMaskWords lanes reads word gl, the group takes the minimum
-template <int G>
-__device__ inline int32_t mask_first_free(uint64_t* m, int gl) {
-    int32_t f = 0x7fffffff;
-    if (gl < kMaskWords) {
-        const uint64_t x = __hip_atomic_load(m + gl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (~x) f = 64 * gl + __ffsll((unsigned long long)~x) - 1;
-    }
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) f = min(f, __shfl_xor(f, off, kWave));
-    return f == 0x7fffffff ? -1 : f;
-}
-
-// LDS of a block's append aggregation
-struct JpShared {
-    uint64_t part[kJpWaves][4];
-    int32_t found;
-    int32_t cnt[kKinds];
-    int32_t base[kKinds];
-};
-
-// a coloured node tells its lower-priority neighbours (entries e0, e0 +
-// stride, ... < e1): mask bit (hubs only), count down, and the neighbours
-// that become ready are appended to the next round's lists.  Every thread
-// of the block calls this with the same trip count (steps of kN * stride;
-// threads of no node pass e0 = e1); the appends of a step are gathered in
-// LDS so that each list counter takes one atomic per block and step.
-constexpr int kN = 4;
-__device__ inline void jp_notify(const int32_t* __restrict__ col, const uint8_t* __restrict__ eflag,
-                                 int32_t e0, int32_t e1, int32_t stride, int32_t trips, int32_t c,
-                                 int32_t* __restrict__ cnt, uint64_t* __restrict__ mask,
-                                 const int32_t* __restrict__ mslot, int32_t* const* out,
-                                 int32_t* __restrict__ next, JpShared& sh) {
-    // four entries per step, so that their atomics are in flight together
-    for (int32_t s = 0; s < trips; ++s) {
-        const int32_t e = e0 + s * kN * stride;
-        uint8_t f[kN];
-        int32_t u[kN], old[kN];
-#pragma unroll
-        for (int k = 0; k < kN; ++k) {
-            const int32_t ek = e + k * stride;
-            const bool ok = ek < e1;
-            f[k] = ok ? eflag[ek] : (uint8_t)0;
-            u[k] = ok ? col[ek] : 0;
-        }
-#pragma unroll
-        for (int k = 0; k < kN; ++k)
-            if ((f[k] & kDown) && ((f[k] >> 1) & 3) == 2 && c < kMaskBits)
-                atomicOr((unsigned long long*)&mask[(int64_t)mslot[u[k]] * kMaskWords + (c >> 6)],
-                         1ull << (c & 63));
-#pragma unroll
-        for (int k = 0; k < kN; ++k) old[k] = (f[k] & kDown) ? atomicSub(&cnt[u[k]], 1) : 0;
-        // block-level append: slots in LDS, one global reservation per kind
-        if (threadIdx.x < kKinds) sh.cnt[threadIdx.x] = 0;
-        __syncthreads();
-        int32_t slot[kN];
-#pragma unroll
-        for (int k = 0; k < kN; ++k)
-            slot[k] = old[k] == 1 ? atomicAdd(&sh.cnt[(f[k] >> 1) & 3], 1) : -1;
-        __syncthreads();
-        if (threadIdx.x < kKinds && sh.cnt[threadIdx.x] > 0)
-            sh.base[threadIdx.x] = atomicAdd(&next[threadIdx.x], sh.cnt[threadIdx.x]);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kN; ++k)
-            if (slot[k] >= 0) {
-                const int kd = (f[k] >> 1) & 3;
-                out[kd][sh.base[kd] + slot[k]] = u[k];
-            }
-    }
-}
-
-// block-wide maximum (every thread calls it)
-__device__ inline int32_t block_max(int32_t x, JpShared& sh) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) x = max(x, __shfl_xor(x, off, kWave));
-    __syncthreads();
-    if (threadIdx.x == 0) sh.found = 0;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&sh.found, x);
-    __syncthreads();
-    const int32_t m = sh.found;
-    __syncthreads();
-    return m;
-}
-
-// colour node v (valid) with an aligned group of G lanes (gl = lane in the
-// group); every thread of the block calls this together
-template <int G>
-__device__ inline void jp_group_node(const int32_t* __restrict__ rp,
-                                     const int32_t* __restrict__ col,
-                                     const uint8_t* __restrict__ eflag, bool valid, int32_t v,
-                                     int gl, int32_t* __restrict__ cnt,
-                                     uint64_t* __restrict__ mask, const int32_t* __restrict__ mslot,
-                                     int32_t* __restrict__ colours, int32_t* const* out,
-                                     int32_t* __restrict__ next, JpShared& sh) {
-    int32_t e0 = 0, e1 = 0, c = 0;
-    if (valid) {
-        e0 = rp[v];
-        e1 = rp[v + 1];
-        c = -1;
-        for (int32_t base = 0; c < 0; base += 256) {
-            uint64_t used[4];
-            window_bits<G>(col, colours, e0 + gl, e1, G, base, used);
-            c = first_free4(used, base);
-        }
-        if (gl == 0) colours[v] = c;
-    }
-    const int32_t trips = block_max((e1 - e0 + kN * G - 1) / (kN * G), sh);
-    jp_notify(col, eflag, e0 + gl, e1, G, trips, c, cnt, mask, mslot, out, next, sh);
-}
-
-// colour the big node v with the whole block (all threads call it)
-// piece f of `pieces` (a contiguous share of the node's entries to notify;
-// every piece computes the same colour, piece 0 stores it)
-__device__ inline void jp_big_node(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                   const uint8_t* __restrict__ eflag, int32_t v, int f,
-                                   int pieces, int32_t* __restrict__ cnt,
-                                   uint64_t* __restrict__ mask, const int32_t* __restrict__ mslot,
-                                   int32_t* __restrict__ colours, int32_t* const* out,
-                                   int32_t* __restrict__ next, JpShared& sh) {
-    uint64_t (*part)[4] = sh.part;
-    int32_t* found = &sh.found;
-    const int32_t e0 = rp[v], e1 = rp[v + 1];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    int32_t c = mask_first_free<kWave>(mask + (int64_t)mslot[v] * kMaskWords, lane);
-    for (int32_t base = kMaskBits; c < 0; base += 256) {
-        uint64_t used[4];
-        window_bits<kWave>(col, colours, e0 + (int32_t)threadIdx.x, e1, kJpThreads, base, used);
-        if (lane == 0)
-            for (int w = 0; w < 4; ++w) part[wave][w] = used[w];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t all[4] = {0, 0, 0, 0};
-            for (int k = 0; k < kJpWaves; ++k)
-                for (int w = 0; w < 4; ++w) all[w] |= part[k][w];
-            *found = first_free4(all, base);
-        }
-        __syncthreads();
-        c = *found;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && f == 0) colours[v] = c;
-    const int32_t len = (e1 - e0 + pieces - 1) / pieces;
-    const int32_t p1 = min(e1, e0 + (f + 1) * len), p0 = min(p1, e0 + f * len);
-    const int32_t trips = (p1 - p0 + kN * kJpThreads - 1) / (kN * kJpThreads);
-    __syncthreads();  // `found` is reused below
-    jp_notify(col, eflag, p0 + (int32_t)threadIdx.x, p1, kJpThreads, trips, c, cnt, mask, mslot,
-              out, next, sh);
-}
-
-struct JpBufs {
-    int32_t* list[2][kKinds];  // frontier lists of even / odd rounds, per kind
-    int32_t* sizes;            // [3 r + kind]: frontier sizes of round r
-    int32_t* state;            // [0] current round, [1] set when a grid round ran
-    int32_t* cnt;
-    uint64_t* mask;   // colour masks of the nodes of degree above kJpBig
-    int32_t* mslot;   // their slot in `mask`
-    uint8_t* eflag;
-    int64_t max_rounds;
-};
-
-// all nodes of round r: big ones a block each, medium ones a wave each,
-// tiny ones kJpGroup lanes each, grid-stride over blk / nblk; every thread
-// of the grid (or of the one block) calls this
-__device__ inline void jp_round(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                const JpBufs& jb, int64_t r, const int32_t* nk, int64_t blk,
-                                int64_t nblk, int32_t* __restrict__ colours, JpShared& sh) {
-    int32_t* const* in = jb.list[r & 1];
-    int32_t* const* out = jb.list[(r + 1) & 1];
-    int32_t* next = jb.sizes + kKinds * (r + 1);
-    // big nodes: when they are few, several blocks share each node's entries
-    const int pieces = nk[2] > 0 ? (int)max<int64_t>(1, min<int64_t>(8, nblk / nk[2])) : 1;
-    for (int64_t t = blk; t < (int64_t)nk[2] * pieces; t += nblk)
-        jp_big_node(rp, col, jb.eflag, in[2][t / pieces], (int)(t % pieces), pieces, jb.cnt,
-                    jb.mask, jb.mslot, colours, out, next, sh);
-    // medium nodes: a wave each; tiny nodes: kJpGroup lanes each; the loops
-    // step a whole block at a time so that the block appends together
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (int64_t t0 = blk * kJpWaves; t0 < nk[1]; t0 += nblk * kJpWaves) {
-        const int64_t t = t0 + wave;
-        const bool valid = t < nk[1];
-        jp_group_node<kWave>(rp, col, jb.eflag, valid, valid ? in[1][t] : 0, lane, jb.cnt, jb.mask,
-                             jb.mslot, colours, out, next, sh);
-    }
-    constexpr int GPB = kJpThreads / kJpGroup;
-    for (int64_t t0 = blk * GPB; t0 < nk[0]; t0 += nblk * GPB) {
-        const int64_t t = t0 + threadIdx.x / kJpGroup;
-        const bool valid = t < nk[0];
-        jp_group_node<kJpGroup>(rp, col, jb.eflag, valid, valid ? in[0][t] : 0, lane % kJpGroup,
-                                jb.cnt, jb.mask, jb.mslot, colours, out, next, sh);
-    }
-}
-
-// one round on the whole grid, unless the frontier is empty
-__global__ void __launch_bounds__(kJpThreads) k_jp_round(const int32_t* __restrict__ rp,
-                                                         const int32_t* __restrict__ col,
-                                                         JpBufs jb, int32_t* __restrict__ colours) {
-    __shared__ JpShared sh;
-    const int64_t r = jb.state[0];
-    if (r >= jb.max_rounds) return;
-    int32_t nk[kKinds];
-    for (int k = 0; k < kKinds; ++k) nk[k] = jb.sizes[kKinds * r + k];
-    if (nk[0] + nk[1] + nk[2] == 0) return;
-    jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) jb.state[1] = 1;
-}
-
-// a few blocks (cooperative launch): first account for a grid round that
-// ran since the last call, then run rounds back to back, separated by
-// device-wide barriers, while the frontier fits them; the wide grid kernel
-// takes the large rounds
-__global__ void __launch_bounds__(kJpThreads) k_jp_multi(const int32_t* __restrict__ rp,
-                                                         const int32_t* __restrict__ col,
-                                                         JpBufs jb, int32_t* __restrict__ colours,
-                                                         unsigned* counter, int* abort_flag) {
-    __shared__ JpShared sh;
-    __shared__ int32_t go, snk[kKinds];
-    int64_t r = (int64_t)jb.state[0] + jb.state[1];
-    // the barrier counter keeps counting across launches: counter[1] holds
-    // the value it had when the previous launch ended
-    const unsigned base = counter[1];
-    unsigned epoch = 1;
-    // every block has read the state before block 0 rewrites it
-    if (!grid_barrier(counter, base + gridDim.x * epoch, abort_flag)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        jb.state[0] = (int32_t)r;
-        jb.state[1] = 0;
-    }
-    for (int k = 0; k < kSoloRounds; ++k) {
-        if (threadIdx.x == 0) {
-            go = 0;
-            if (r < jb.max_rounds) {
-                for (int q = 0; q < kKinds; ++q)
-                    snk[q] = __hip_atomic_load(jb.sizes + kKinds * r + q, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                const int32_t tot = snk[0] + snk[1] + snk[2];
-                const int32_t cost = (snk[0] + kWave / kJpGroup - 1) / (kWave / kJpGroup) +
-                                     snk[1] + kJpWaves * snk[2];
-                go = (tot > 0 && cost <= kSoloCost * (int32_t)gridDim.x) ? 1 : 0;
-            }
-        }
-        __syncthreads();
-        if (!go) break;  // the same decision in every block: same sizes after the barrier
-        int32_t nk[kKinds] = {snk[0], snk[1], snk[2]};
-        jp_round(rp, col, jb, r, nk, blockIdx.x, gridDim.x, colours, sh);
-        ++epoch;
-        if (!grid_barrier(counter, base + gridDim.x * epoch, abort_flag)) return;
-        ++r;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        jb.state[0] = (int32_t)r;
-        counter[1] = base + gridDim.x * epoch;
-    }
-}
-
 __global__ void k_col_fill(int64_t n, int32_t* __restrict__ colours) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) colours[v] = -1;
 }
 
-__global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int32_t* out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t m = -1;
-    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) m = max(m, x[i]);
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, m);
-}
-
-#ifndef GR_JP_BLOCKS
-#define GR_JP_BLOCKS 256
-#endif
-constexpr int kJpBatch = 32;    // (single-block, grid) launch pairs between host checks
-constexpr int kJpBlocks = GR_JP_BLOCKS;  // grid of a round (grid-stride)
-
-static int colour_rounds(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
-                         int32_t* n_colours_host, Arena& ws, hipStream_t st) {
-    const int64_t n = g->n, nnz = g->nnz;
-    *n_colours_host = 0;
-    if (n == 0) return GR_OK;
-    size_t mark = ws.used;
-    JpBufs jb;
-    for (int h = 0; h < 2; ++h)
-        for (int k = 0; k < kKinds; ++k) jb.list[h][k] = ws.take<int32_t>(n);
-    int32_t** dlists = ws.take<int32_t*>(kKinds);
-    jb.cnt = ws.take<int32_t>(n);
-    // a node of degree above kJpBig holds more than kJpBig entries
-    const int64_t nmask = nnz / (kJpBig + 1) + 1;
-    jb.mask = ws.take<uint64_t>((size_t)nmask * kMaskWords);
-    jb.mslot = ws.take<int32_t>(n);
-    int32_t* biglist = ws.take<int32_t>(n);
-    jb.eflag = ws.take<uint8_t>(nnz + 1);
-    // frontier sizes of rounds [0, n + 1] (a round colours at least one
-    // node, so there are at most n of them), three per round, then the
-    // round state and the max-colour slot
-    const int64_t nsz = kKinds * (n + 2) + 16;
-    jb.sizes = ws.take<int32_t>(nsz);
-    jb.state = jb.sizes + nsz - 8;
-    jb.max_rounds = n;
-    unsigned* sync = ws.take<unsigned>(4);  // barrier counter, its base, abort flag
-    int* abort_flag = (int*)(sync + 2);
-    const int32_t* rp = g->row_ptr;
-    const int32_t* cl = g->col;
-    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
-    GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned) * 4, st));
-    GR_HIP(hipMemsetAsync(jb.sizes, 0, sizeof(int32_t) * nsz, st));
-    GR_HIP(hipMemsetAsync(jb.mask, 0, sizeof(uint64_t) * (size_t)nmask * kMaskWords, st));
-    GR_HIP(hipMemcpyAsync(dlists, jb.list[0], sizeof(int32_t*) * kKinds, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_col_fill, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, colours);
-    GR_LAUNCHED("colour fill");
-    int32_t* bigcnt = (int32_t*)(sync + 3);
-    int32_t* nslots = jb.state + 2;
-    hipLaunchKernelGGL(k_jp_count, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, g->row_ptr,
-                       g->col, n, seed, ldf, jb.cnt, jb.eflag, (int32_t* const*)dlists, jb.sizes,
-                       biglist, bigcnt);
-    GR_LAUNCHED("colour count");
-    hipLaunchKernelGGL(k_jp_count_wide, dim3(1024), dim3(kThreads), 0, st, g->row_ptr, g->col, seed,
-                       ldf, (const int32_t*)biglist, (const int32_t*)bigcnt, jb.cnt, jb.eflag,
-                       (int32_t* const*)dlists, jb.sizes, jb.mslot, nslots);
-    GR_LAUNCHED("colour count (wide rows)");
-    for (int64_t batch = 0;; ++batch) {
-        for (int b = 0; b < kJpBatch; ++b) {
-            void* args[] = {(void*)&rp, (void*)&cl, (void*)&jb, (void*)&colours, (void*)&sync,
-                            (void*)&abort_flag};
-            GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_multi, dim3(kJpMultiBlocks),
-                                              dim3(kJpThreads), args, 0, st));
-            hipLaunchKernelGGL(k_jp_round, dim3(kJpBlocks), dim3(kJpThreads), 0, st, g->row_ptr,
-                               g->col, jb, colours);
-            GR_LAUNCHED("colour round");
-        }
-        int32_t stt[2] = {0, 0}, hflag = 0;
-        GR_HIP(hipMemcpyAsync(stt, jb.state, sizeof(stt), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipMemcpyAsync(&hflag, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));
-        if (hflag) return set_error(GR_EHIP, "colouring barrier timed out");
-        const int64_t r = (int64_t)stt[0] + stt[1];
-        if (r > n) return set_error(GR_EHIP, "colouring did not finish in n rounds");
-        int32_t fr[kKinds] = {0, 0, 0};
-        GR_HIP(hipMemcpyAsync(fr, jb.sizes + kKinds * r, sizeof(fr), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));
-        if (fr[0] == 0 && fr[1] == 0 && fr[2] == 0) break;  // nothing became ready: all coloured
-        if (batch > n) return set_error(GR_EHIP, "colouring made no progress");
-    }
-    int32_t* mxd = jb.sizes + nsz - 4;
-    GR_HIP(hipMemsetAsync(mxd, 0xff, sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_max_i32, dim3(256), dim3(kThreads), 0, st, colours, n, mxd);
-    GR_LAUNCHED("max colour");
-    int32_t mx = -1;
-    GR_HIP(hipMemcpyAsync(&mx, mxd, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    GR_HIP(hipStreamSynchronize(st));
-    if (mx < 0) return set_error(GR_EHIP, "colouring left nodes uncoloured");
-    *n_colours_host = mx + 1;
-    ws.used = mark;
-    return GR_OK;
-}
-
 // ------------------------------------------------ colouring as a dataflow
-// The same greedy colouring without rounds.  The nodes are sorted once into
+// The greedy colouring computed without rounds.  The nodes are sorted once into
 // decreasing priority (position = rank); every node lists the ranks of its
 // higher-priority neighbours (`uplist`, from the node's row offset on).  A
 // cooperative launch holds as many waves as the device keeps resident; wave
@@ -1118,11 +587,7 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
 
 int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
                   int32_t* n_colours_host, Arena& ws, hipStream_t st) {
-#ifdef GR_COLOUR_ROUNDS
-    return colour_rounds(g, seed, ldf, colours, n_colours_host, ws, st);
-#else
     return colour_flow(g, seed, ldf, colours, n_colours_host, ws, st);
-#endif
 }
 
 __global__ void k_check_colouring(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
