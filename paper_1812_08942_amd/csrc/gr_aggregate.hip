@@ -202,32 +202,47 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
 // stored entries (v, j) with agg(v) < agg(j) (each fine edge between two
 // aggregates exactly once) enter the sort, and every summed (I, J) is then
 // written to both (I, J) and (J, I), so both directions carry equal bits.
-// flag[e] = 1 for such entries; 8 lanes per row.
-__global__ void k_rap_flags(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            const int32_t* __restrict__ agg, int64_t n, int32_t* __restrict__ flag) {
-    int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
-    int l = threadIdx.x & 7;
-    if (v >= n) return;
-    int32_t I = agg[v];
-    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) flag[e] = agg[col[e]] > I;
+
+// 8 lanes per fine row: the number of the row's kept entries
+__global__ void k_rap_count(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ agg, int64_t n, int32_t* __restrict__ cnt) {
+    const int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
+    const int l = threadIdx.x & 7;
+    if (v >= n) return;  // the 8 lanes of a row leave together
+    const int32_t I = agg[v];
+    int32_t c = 0;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) c += agg[col[e]] > I ? 1 : 0;
+    c += __shfl_xor(c, 1, kWave);
+    c += __shfl_xor(c, 2, kWave);
+    c += __shfl_xor(c, 4, kWave);
+    if (l == 0) cnt[v] = c;
 }
 
+// the kept pairs of each fine row, in entry order, from the row's offset on
+// (so the tuples come in (fine row, entry) order, as a scan of per-entry
+// flags would place them)
 __global__ void k_rap_scatter(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                               const float* __restrict__ w, const int32_t* __restrict__ agg,
-                              const int32_t* __restrict__ pos, int64_t n, int jbits,
+                              const int32_t* __restrict__ roff, int64_t n, int jbits,
                               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
-    int l = threadIdx.x & 7;
+    const int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
+    const int l = threadIdx.x & 7;
+    const int grp = (threadIdx.x & (kWave - 1)) >> 3;
     if (v >= n) return;
-    uint64_t I = (uint64_t)agg[v];
-    int32_t e1 = rp[v + 1];
-    for (int32_t e = rp[v] + l; e < e1; e += 8) {
-        int32_t J = agg[col[e]];
-        if ((uint64_t)J > I) {
-            int32_t s = pos[e];
-            keys[s] = (I << jbits) | (uint64_t)J;
+    const int32_t I = agg[v];
+    const int32_t e1 = rp[v + 1];
+    int64_t out = roff[v];
+    for (int32_t e0 = rp[v]; e0 < e1; e0 += 8) {  // the same trip count for the row's lanes
+        const int32_t e = e0 + l;
+        const int32_t J = e < e1 ? agg[col[e]] : -1;
+        const bool keep = J > I;
+        const uint32_t bits = (uint32_t)(__ballot(keep) >> (8 * grp)) & 0xffu;
+        if (keep) {
+            const int64_t s = out + __popc(bits & ((1u << l) - 1u));
+            keys[s] = ((uint64_t)I << jbits) | (uint64_t)J;
             vals[s] = __float_as_uint(w[e]);
         }
+        out += __popc(bits);
     }
 }
 
@@ -384,8 +399,8 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     const int64_t n = g->n, nnz = g->nnz;
     *nnz_coarse = 0;
     size_t mark = ws.used;
-    int32_t* flag = ws.take<int32_t>(nnz + 1);
-    int32_t* pos = ws.take<int32_t>(nnz + 1);
+    int32_t* rcnt = ws.take<int32_t>(n + 1);
+    int32_t* roff = ws.take<int32_t>(n + 1);
     int32_t* small = ws.take<int32_t>(4);
     int32_t* row_cnt = ws.take<int32_t>(n_c + 1);
     int32_t* ufirst = ws.take<int32_t>(n_c + 1);
@@ -396,9 +411,9 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     int32_t m = 0;
     if (nnz > 0) {
         const unsigned rb = blocks_for(n * 8, kT);
-        hipLaunchKernelGGL(k_rap_flags, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, flag);
-        GR_LAUNCHED("rap flags");
-        GR_TRY(scan_exclusive_i32(flag, pos, nnz, small, ws, st));
+        hipLaunchKernelGGL(k_rap_count, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt);
+        GR_LAUNCHED("rap count");
+        GR_TRY(scan_exclusive_i32(rcnt, roff, n, small, ws, st));
         GR_HIP(hipMemcpyAsync(&m, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
     }
@@ -420,7 +435,7 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin sort)");
         const unsigned rb = blocks_for(n * 8, kT);
         hipLaunchKernelGGL(k_rap_scatter, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, g->w, agg,
-                           pos, n, jbits, k0, v0);
+                           (const int32_t*)roff, n, jbits, k0, v0);
         GR_LAUNCHED("rap scatter");
         GR_TRY(radix_sort_pairs(k0, v0, k1, v1, m, 2 * jbits, ws, st));
         const unsigned mb = blocks_for(m, kT);

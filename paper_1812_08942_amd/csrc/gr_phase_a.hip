@@ -920,8 +920,9 @@ constexpr int kBig = 1024;
 
 // Rows of degree above 2048 (tier 0) are split: kSplit blocks each take a
 // contiguous 1/kSplit of the row's entries and write a partial sum (K values
-// and the weight sum) to `part`; a second pass adds the kSplit partials of
-// each such row in order and stores the row.
+// and the weight sum) to `part`, release it to the device and count itself
+// in the row's counter; the block that arrives last adds the kSplit partials
+// in piece order, stores the row and clears the counter for the next use.
 constexpr int kSplit = 8;
 
 struct GsTiers {
@@ -936,7 +937,8 @@ template <int Q, int DT>
 __device__ inline void gs_block(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                 const float* __restrict__ w, void* __restrict__ X, int32_t K,
                                 const GsTiers& tt, int64_t b, float* __restrict__ part,
-                                float (*sacc)[Q][Chunk<DT>::E], float* sd) {
+                                int32_t* __restrict__ splitcnt, float (*sacc)[Q][Chunk<DT>::E],
+                                float* sd) {
     constexpr int E = Chunk<DT>::E;
     int t = 0;
     while (t + 1 < tt.nt && b >= tt.blk0[t + 1]) ++t;
@@ -1027,6 +1029,47 @@ __device__ inline void gs_block(const int32_t* __restrict__ rp, const int32_t* _
                 Chunk<DT>::store(X, r, K, l, y);
             }
         }
+        if (split && tid < kWave) {
+            // wave 0 wrote the partial: release it, count the piece; the
+            // last piece of the row combines all of them
+            const int64_t row = slot / kSplit;
+            __threadfence();
+            int last = 0;
+            if (tid == 0) last = atomicAdd(splitcnt + row, 1) == kSplit - 1;
+            last = __shfl(last, 0, kWave);
+            if (last) {
+                __threadfence();
+                // lane (f0, q) adds partials f0, f0 + F, ... of chunk q; a
+                // fixed xor tree over f0 combines them
+                constexpr int F = kWave / Q < kSplit ? kWave / Q : kSplit;
+                const int f0 = tid / Q, qq = tid % Q;
+                float y[E];
+                float dd = 0.0f;
+#pragma unroll
+                for (int i = 0; i < E; ++i) y[i] = 0.0f;
+                if (f0 < F) {
+#pragma unroll
+                    for (int j = 0; j < kSplit / F; ++j) {
+                        const float* pp = part + (row * kSplit + f0 + j * F) * (int64_t)(K + 1);
+#pragma unroll
+                        for (int i = 0; i < E; ++i) y[i] += pp[qq * E + i];
+                        dd += pp[K];
+                    }
+                }
+#pragma unroll
+                for (int off = Q; off < Q * F; off <<= 1) {
+#pragma unroll
+                    for (int i = 0; i < E; ++i) y[i] += __shfl_xor(y[i], off, kWave);
+                    dd += __shfl_xor(dd, off, kWave);
+                }
+                if (f0 == 0 && dd > 0.0f) {
+#pragma unroll
+                    for (int i = 0; i < E; ++i) y[i] = y[i] / dd;
+                    Chunk<DT>::store(X, r, K, qq, y);
+                }
+                if (tid == 0) splitcnt[row] = 0;
+            }
+        }
         __syncthreads();  // the LDS slots are reused by the block's next rows
     } else if (p == 0 && valid && d > 0.0f) {
         float y[E];
@@ -1041,44 +1084,11 @@ __global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp
                                                   const int32_t* __restrict__ col,
                                                   const float* __restrict__ w,
                                                   void* __restrict__ X, int32_t K, GsTiers tt,
-                                                  float* __restrict__ part) {
+                                                  float* __restrict__ part,
+                                                  int32_t* __restrict__ splitcnt) {
     __shared__ float sacc[kBig / kWave][Q][Chunk<DT>::E];
     __shared__ float sd[kBig / kWave];
-    gs_block<Q, DT>(rp, col, w, X, K, tt, blockIdx.x, part, sacc, sd);
-}
-
-// second pass of the split rows: one group of Q lanes per row adds the
-// row's kSplit partials in order; rows i = first .. first + n - 1 of the
-// split tier, taken from global group index g0 with stride gstride
-template <int Q, int DT>
-__device__ inline void gs_split_rows(void* __restrict__ X, int32_t K, int64_t row0, int64_t nrows,
-                                     const float* __restrict__ part, int64_t g0, int64_t gstride) {
-    constexpr int E = Chunk<DT>::E;
-    const int q = threadIdx.x % Q;
-    for (int64_t i = g0; i < nrows; i += gstride) {
-        float y[E];
-        float dd = 0.0f;
-#pragma unroll
-        for (int k = 0; k < E; ++k) y[k] = 0.0f;
-        for (int f = 0; f < kSplit; ++f) {
-            const float* pp = part + (i * kSplit + f) * (int64_t)(K + 1);
-#pragma unroll
-            for (int k = 0; k < E; ++k) y[k] += pp[q * E + k];
-            dd += pp[K];
-        }
-        if (dd > 0.0f) {
-#pragma unroll
-            for (int k = 0; k < E; ++k) y[k] = y[k] / dd;
-            Chunk<DT>::store(X, row0 + i, K, q, y);
-        }
-    }
-}
-
-template <int Q, int DT>
-__global__ void k_gs_split(void* __restrict__ X, int32_t K, int64_t row0, int64_t nrows,
-                           const float* __restrict__ part) {
-    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / Q;
-    gs_split_rows<Q, DT>(X, K, row0, nrows, part, g, ((int64_t)gridDim.x * blockDim.x) / Q);
+    gs_block<Q, DT>(rp, col, w, X, K, tt, blockIdx.x, part, splitcnt, sacc, sd);
 }
 
 // All sweeps of a level whose colour steps are small, in one cooperative
@@ -1093,6 +1103,7 @@ __global__ void __launch_bounds__(kBig) k_gs_persistent(const int32_t* __restric
                                                         const GsTiers* __restrict__ plans,
                                                         int32_t n_colours, int32_t sweeps,
                                                         float* __restrict__ part,
+                                                        int32_t* __restrict__ splitcnt,
                                                         unsigned* counter, int* abort_flag) {
     __shared__ float sacc[kBig / kWave][Q][Chunk<DT>::E];
     __shared__ float sd[kBig / kWave];
@@ -1103,16 +1114,9 @@ __global__ void __launch_bounds__(kBig) k_gs_persistent(const int32_t* __restric
             if (tt.nt == 0) continue;
             const int64_t nb = tt.blk0[tt.nt];
             for (int64_t b = blockIdx.x; b < nb; b += gridDim.x)
-                gs_block<Q, DT>(rp, col, w, X, K, tt, b, part, sacc, sd);
+                gs_block<Q, DT>(rp, col, w, X, K, tt, b, part, splitcnt, sacc, sd);
             ++epoch;
             if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
-            if (tt.split) {
-                gs_split_rows<Q, DT>(X, K, tt.row0[0], tt.row0[1] - tt.row0[0], part,
-                                     ((int64_t)blockIdx.x * kBig + threadIdx.x) / Q,
-                                     ((int64_t)gridDim.x * kBig) / Q);
-                ++epoch;
-                if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
-            }
         }
 }
 
@@ -1183,7 +1187,9 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& w
         if (plan[c].split) split_rows = std::max<int64_t>(split_rows, plan[c].row0[1] - plan[c].row0[0]);
     const size_t mark = ws.used;
     float* part = ws.take<float>((size_t)std::max<int64_t>(split_rows, 1) * kSplit * (K + 1));
+    int32_t* splitcnt = ws.take<int32_t>((size_t)std::max<int64_t>(split_rows, 1));
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (smoothing partials)");
+    if (split_rows > 0) GR_TRY(fill_i32(splitcnt, 0, split_rows, st));
     if (biggest <= kPersistMaxStep && steps * sweeps >= 8) {
         // every step is small: one cooperative launch for all sweeps
         GsTiers* dplan = ws.take<GsTiers>(C);
@@ -1198,7 +1204,8 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& w
         const GsTiers* cp = dplan;
         int32_t nc = C, sw = sweeps;
         void* args[] = {(void*)&rp, (void*)&cl, (void*)&wt, (void*)&X, (void*)&K, (void*)&cp,
-                        (void*)&nc, (void*)&sw, (void*)&part, (void*)&sync, (void*)&abort_flag};
+                        (void*)&nc, (void*)&sw, (void*)&part, (void*)&splitcnt, (void*)&sync,
+                        (void*)&abort_flag};
         if (pr) prof::begin(st);
         GR_HIP(hipLaunchCooperativeKernel((const void*)k_gs_persistent<Q, DT>, dim3(kPersistBlocks),
                                           dim3(kBig), args, 0, st));
@@ -1217,14 +1224,8 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& w
             const int64_t lo = og->class_ptr_h[c], hi = og->class_ptr_h[c + 1];
             if (pr) prof::begin(st);
             hipLaunchKernelGGL((k_gs_step<Q, DT>), dim3((unsigned)tt.blk0[tt.nt]), dim3(kBig), 0, st,
-                               og->g.row_ptr, og->g.col, og->g.w, X, K, tt, part);
+                               og->g.row_ptr, og->g.col, og->g.w, X, K, tt, part, splitcnt);
             GR_LAUNCHED("gs step");
-            if (tt.split) {
-                const int64_t nr = tt.row0[1] - tt.row0[0];
-                hipLaunchKernelGGL((k_gs_split<Q, DT>), dim3(blocks_for(nr * Q, 256)), dim3(256), 0,
-                                   st, X, K, tt.row0[0], nr, (const float*)part);
-                GR_LAUNCHED("gs split rows");
-            }
             if (pr) {
                 // compulsory bytes of this colour step: its CSR rows, plus one
                 // read and one write of each updated vector row

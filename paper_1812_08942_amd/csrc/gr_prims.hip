@@ -237,47 +237,70 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// One pass of the stable LSD sort on digit (key >> shift) & 0xff.  The block
+// first ranks its tile in LDS (digit-major, original order inside a digit:
+// ballots give the rank inside a wave, per-wave counts the order of the
+// waves, a running count the order of the rounds), then writes the tile out
+// digit by digit, so that the elements of one digit leave as a contiguous
+// run (coalesced stores) at the digit's global offset for this tile.
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, const int32_t* __restrict__ offs,
-    int nblocks) {
+    uint32_t* __restrict__ vout, int64_t n, int shift, const int32_t* __restrict__ hist,
+    const int32_t* __restrict__ offs, int nblocks) {
     constexpr int kW = kSortThreads / kWave;
-    __shared__ int32_t base[kRadix];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ int32_t gbase[kRadix];
+    __shared__ int32_t lbase[kRadix];
     __shared__ int32_t run[kRadix];
+    __shared__ int32_t wsum[kW];
     __shared__ int32_t wcnt[kW][kRadix];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
-    base[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    gbase[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    // exclusive scan of the tile's digit counts: the digits' local offsets
+    const int32_t c = hist[(int64_t)tid * nblocks + blockIdx.x];
+    int32_t x = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wsum[wid] = x;
     run[tid] = 0;
 #pragma unroll
     for (int w = 0; w < kW; ++w) wcnt[w][tid] = 0;
     __syncthreads();
+    int32_t pre_w = 0;
+    for (int w = 0; w < wid; ++w) pre_w += wsum[w];
+    lbase[tid] = pre_w + x - c;
+    __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    int64_t tbase = (int64_t)blockIdx.x * kSortTile;
+    const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
     for (int it = 0; it < kSortIters; ++it) {
-        int64_t i = tbase + it * kSortThreads + tid;
-        bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0ull;
-        uint32_t val = valid ? vin[i] : 0u;
-        int d = valid ? (int)((key >> shift) & 0xff) : 0;
+        const int64_t i = tbase + it * kSortThreads + tid;
+        const bool valid = i < n;
+        const uint64_t key = valid ? kin[i] : 0ull;
+        const uint32_t val = valid ? vin[i] : 0u;
+        const int d = valid ? (int)((key >> shift) & 0xff) : 0;
         // lanes of this wave holding the same digit (and validity)
         uint64_t peers = __ballot(valid);
         if (!valid) peers = ~peers;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bb = __ballot((d >> b) & 1);
+            const uint64_t bb = __ballot((d >> b) & 1);
             peers &= ((d >> b) & 1) ? bb : ~bb;
         }
-        int rank = __popcll(peers & lt);
+        const int rank = __popcll(peers & lt);
         if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
         __syncthreads();
         if (valid) {
             int pre = 0;
             for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
-            int pos = base[d] + run[d] + pre + rank;
-            kout[pos] = key;
-            vout[pos] = val;
+            const int lpos = lbase[d] + run[d] + pre + rank;
+            skey[lpos] = key;
+            sval[lpos] = val;
         }
         __syncthreads();
         int add = 0;
@@ -288,6 +311,14 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
         }
         run[tid] += add;
         __syncthreads();
+    }
+    const int cnt = (int)(n - tbase < kSortTile ? n - tbase : kSortTile);
+    for (int j = tid; j < cnt; j += kSortThreads) {
+        const uint64_t key = skey[j];
+        const int d = (int)((key >> shift) & 0xff);
+        const int64_t pos = (int64_t)gbase[d] + (j - lbase[d]);
+        kout[pos] = key;
+        vout[pos] = sval[j];
     }
 }
 
@@ -315,7 +346,7 @@ int radix_sort_pairs(uint64_t* keys_in, uint32_t* vals_in, uint64_t* keys_out, u
         GR_LAUNCHED("radix hist");
         GR_TRY(scan_exclusive_i32(hist, offs, (int64_t)kRadix * nb, nullptr, ws, st));
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, st, ks, vs, kd, vd, n,
-                           shift, offs, (int)nb);
+                           shift, (const int32_t*)hist, (const int32_t*)offs, (int)nb);
         GR_LAUNCHED("radix scatter");
         uint64_t* tk = ks; ks = kd; kd = tk;
         uint32_t* tv = vs; vs = vd; vd = tv;
