@@ -208,7 +208,7 @@ __global__ void k_rap_count(const int32_t* __restrict__ rp, const int32_t* __res
                             const int32_t* __restrict__ agg, int64_t n, int32_t* __restrict__ cnt) {
     const int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
     const int l = threadIdx.x & 7;
-    if (v >= n) return;  // the 8 lanes of a row leave together
+    if (v >= n || rp[v + 1] - rp[v] > kLongRow) return;  // the 8 lanes of a row leave together
     const int32_t I = agg[v];
     int32_t c = 0;
     for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) c += agg[col[e]] > I ? 1 : 0;
@@ -228,7 +228,7 @@ __global__ void k_rap_scatter(const int32_t* __restrict__ rp, const int32_t* __r
     const int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
     const int l = threadIdx.x & 7;
     const int grp = (threadIdx.x & (kWave - 1)) >> 3;
-    if (v >= n) return;
+    if (v >= n || rp[v + 1] - rp[v] > kLongRow) return;
     const int32_t I = agg[v];
     const int32_t e1 = rp[v + 1];
     int64_t out = roff[v];
@@ -243,6 +243,64 @@ __global__ void k_rap_scatter(const int32_t* __restrict__ rp, const int32_t* __r
             vals[s] = __float_as_uint(w[e]);
         }
         out += __popc(bits);
+    }
+}
+
+// the same two passes for the listed rows of degree above kLongRow, a
+// workgroup each (a hub would serialise 8 lanes)
+__global__ void __launch_bounds__(kT) k_rap_count_long(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ agg,
+                                                       const int32_t* __restrict__ long_rows,
+                                                       int32_t* __restrict__ cnt) {
+    __shared__ int32_t wc[kT / kWave];
+    const int32_t v = long_rows[blockIdx.x];
+    const int32_t I = agg[v];
+    int32_t c = 0;
+    for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += kT) c += agg[col[e]] > I ? 1 : 0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) wc[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kT / kWave; ++w) t += wc[w];
+        cnt[v] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_rap_scatter_long(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const float* __restrict__ w,
+    const int32_t* __restrict__ agg, const int32_t* __restrict__ roff,
+    const int32_t* __restrict__ long_rows, int jbits, uint64_t* __restrict__ keys,
+    uint32_t* __restrict__ vals) {
+    __shared__ int32_t wc[kT / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int32_t v = long_rows[blockIdx.x];
+    const int32_t I = agg[v];
+    const int32_t e1 = rp[v + 1];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    int64_t out = roff[v];
+    for (int32_t e0 = rp[v]; e0 < e1; e0 += kT) {  // the same trip count for the whole block
+        const int32_t e = e0 + tid;
+        const int32_t J = e < e1 ? agg[col[e]] : -1;
+        const bool keep = J > I;
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) wc[wid] = __popcll(m);
+        __syncthreads();
+        int32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < kT / kWave; ++ww) {
+            pre += ww < wid ? wc[ww] : 0;
+            tot += wc[ww];
+        }
+        if (keep) {
+            const int64_t s = out + pre + __popcll(m & lt);
+            keys[s] = ((uint64_t)I << jbits) | (uint64_t)J;
+            vals[s] = __float_as_uint(w[e]);
+        }
+        out += tot;
+        __syncthreads();
     }
 }
 
@@ -395,7 +453,8 @@ __global__ void k_place_lower(const uint64_t* __restrict__ mkey, const uint32_t*
 }
 
 int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_ptr,
-             int32_t* c_col, float* c_w, int64_t* nnz_coarse, Arena& ws, hipStream_t st) {
+             int32_t* c_col, float* c_w, int64_t* nnz_coarse, const int32_t* long_rows,
+             int64_t n_long, Arena& ws, hipStream_t st) {
     const int64_t n = g->n, nnz = g->nnz;
     *nnz_coarse = 0;
     size_t mark = ws.used;
@@ -413,6 +472,11 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         const unsigned rb = blocks_for(n * 8, kT);
         hipLaunchKernelGGL(k_rap_count, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt);
         GR_LAUNCHED("rap count");
+        if (n_long > 0) {
+            hipLaunchKernelGGL(k_rap_count_long, dim3((unsigned)n_long), dim3(kT), 0, st, g->row_ptr,
+                               g->col, agg, long_rows, rcnt);
+            GR_LAUNCHED("rap count (long rows)");
+        }
         GR_TRY(scan_exclusive_i32(rcnt, roff, n, small, ws, st));
         GR_HIP(hipMemcpyAsync(&m, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
@@ -437,6 +501,12 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         hipLaunchKernelGGL(k_rap_scatter, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, g->w, agg,
                            (const int32_t*)roff, n, jbits, k0, v0);
         GR_LAUNCHED("rap scatter");
+        if (n_long > 0) {
+            hipLaunchKernelGGL(k_rap_scatter_long, dim3((unsigned)n_long), dim3(kT), 0, st,
+                               g->row_ptr, g->col, g->w, agg, (const int32_t*)roff, long_rows,
+                               jbits, k0, v0);
+            GR_LAUNCHED("rap scatter (long rows)");
+        }
         GR_TRY(radix_sort_pairs(k0, v0, k1, v1, m, 2 * jbits, ws, st));
         const unsigned mb = blocks_for(m, kT);
         hipLaunchKernelGGL(k_run_heads, dim3(mb), dim3(kT), 0, st, k1, (int64_t)m, head);

@@ -241,7 +241,11 @@ int gr_galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t
     if (!c_row_ptr || !ws || (g->n > 0 && !agg) || (g->nnz > 0 && (!c_col || !c_w)))
         return set_error(GR_EINVAL, "NULL argument");
     Arena A(ws, ws_bytes);
-    return galerkin(g, agg, n_coarse, c_row_ptr, c_col, c_w, nnz_coarse, A, S(stream));
+    int32_t* long_rows = nullptr;
+    int64_t n_long = 0;
+    GR_TRY(find_long_rows(g, &long_rows, &n_long, A, S(stream)));
+    return galerkin(g, agg, n_coarse, c_row_ptr, c_col, c_w, nnz_coarse, long_rows, n_long, A,
+                    S(stream));
 }
 
 int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws, size_t ws_bytes,
@@ -343,7 +347,7 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
         int64_t nnzc = 0;
         if (pr) prof::begin(st);
         GR_TRY(galerkin(&og.g, aggp, ncoarse, gbuf_rp[which], gbuf_col[which], gbuf_w[which], &nnzc,
-                        A, st));
+                        og.long_rows, og.n_long, A, st));
         if (pr) prof::end(st, prof::GALERKIN, 0.0, 1);
         next.nnz = nnzc;
         hipLaunchKernelGGL(k_compose, dim3(blocks_for(n0, 256)), dim3(256), 0, st, aggl, n0,

@@ -13,6 +13,9 @@
 namespace gr {
 
 constexpr int kWave = 64;
+// rows above this degree are listed (long_rows) and get a workgroup each
+// in the per-row kernels that would otherwise serialise on them
+constexpr int kLongRow = 128;
 
 // ------------------------------------------------------------------ errors
 int set_error(int code, const char* fmt, ...);
@@ -175,7 +178,8 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
               int64_t target, int32_t* agg, int64_t* n_coarse, int64_t* n_forest,
               Arena& ws, hipStream_t st);
 int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c_row_ptr,
-             int32_t* c_col, float* c_w, int64_t* nnz_coarse, Arena& ws, hipStream_t st);
+             int32_t* c_col, float* c_w, int64_t* nnz_coarse, const int32_t* long_rows,
+             int64_t n_long, Arena& ws, hipStream_t st);
 
 // ------------------------------------------------------ edge derivatives
 int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t* n_edges,

@@ -13,7 +13,6 @@
 
 namespace gr {
 
-constexpr int kLongRow = 128;     // rows above this degree get a workgroup each (affinity)
 constexpr int kThreads = 256;
 
 // ------------------------------------------------------------- validation
