@@ -123,8 +123,6 @@ __device__ inline uint64_t wave_or(uint64_t x) {
     return x;
 }
 
-constexpr int32_t kCountLane = 64;  // the up-list pass takes nodes up to this degree per thread
-
 __device__ inline int32_t first_free4(const uint64_t used[4], int32_t base) {
     for (int w = 0; w < 4; ++w)
         if (~used[w]) return base + w * 64 + __ffsll((unsigned long long)~used[w]) - 1;
@@ -225,36 +223,46 @@ __global__ void k_rank_of(const uint32_t* __restrict__ order, int64_t n, int32_t
     if (i < n) rank[order[i]] = (int32_t)i;
 }
 
-// up-lists, nodes of degree <= kCountLane: a thread per position; wider
-// nodes are listed for k_flow_count_wide
+// up-lists of the nodes of degree <= kLongRow: 8 lanes per node, in node
+// order (coalesced rows); the order inside a list is irrelevant to the
+// colour.  Wider nodes are listed (by position) for k_flow_count_wide.
 __global__ void __launch_bounds__(kThreads) k_flow_count(
     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-    const uint32_t* __restrict__ order, const int32_t* __restrict__ rank, int64_t n,
-    int32_t* __restrict__ uplist, int32_t* __restrict__ pstart, int32_t* __restrict__ pcnt,
-    int32_t* __restrict__ wide, int32_t* __restrict__ nwide) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i - (threadIdx.x & (kWave - 1)) >= n) return;  // whole waves leave together
-    const bool in = i < n;
-    const int32_t v = in ? (int32_t)order[i] : 0;
+    const int32_t* __restrict__ rank, int64_t n, int32_t* __restrict__ uplist,
+    int32_t* __restrict__ pstart, int32_t* __restrict__ pcnt, int32_t* __restrict__ wide,
+    int32_t* __restrict__ nwide) {
+    const int64_t v = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 3;
+    const int l = threadIdx.x & 7;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int grp = lane >> 3;
+    if (v - (lane >> 3) >= n) return;  // whole waves leave together
+    const bool in = v < n;
     const int32_t e0 = in ? rp[v] : 0, e1 = in ? rp[v + 1] : 0;
-    const bool wd = in && e1 - e0 > kCountLane;
-    if (in && !wd) {
-        int32_t k = 0;
-        for (int32_t e = e0; e < e1; ++e) {
-            const int32_t r = rank[col[e]];
-            if (r < i) uplist[e0 + k++] = r;
-        }
+    const int32_t i = in ? rank[v] : 0;
+    const bool wd = in && e1 - e0 > kLongRow;
+    int32_t k = 0;
+    const int32_t end = wd ? e0 : e1;  // wide rows: no trips here
+    for (int32_t b = e0; b < end; b += 8) {  // the same trip count for the node's lanes
+        const int32_t e = b + l;
+        const int32_t r = e < end ? rank[col[e]] : 0x7fffffff;
+        const bool up = r < i;
+        const uint32_t bits = (uint32_t)(__ballot(up) >> (8 * grp)) & 0xffu;
+        if (up) uplist[e0 + k + __popc(bits & ((1u << l) - 1u))] = r;
+        k += __popc(bits);
+    }
+    if (in && !wd && l == 0) {
         pstart[i] = e0;
         pcnt[i] = k;
     }
-    const uint64_t m = __ballot(wd);
+    // the wide nodes: one append per wave (lane 0 of each group votes)
+    const bool app = wd && l == 0;
+    const uint64_t m = __ballot(app);
     if (m) {
-        const int lane = threadIdx.x & (kWave - 1);
         const int leader = __ffsll((unsigned long long)m) - 1;
         int32_t base = 0;
         if (lane == leader) base = atomicAdd(nwide, (int32_t)__popcll(m));
         base = __shfl(base, leader, kWave);
-        if (wd) wide[base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = (int32_t)i;
+        if (app) wide[base + (int32_t)__popcll(m & ((1ull << lane) - 1))] = i;
     }
 }
 
@@ -460,13 +468,14 @@ __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restr
     }
 }
 
-__global__ void k_flow_scatter(const uint32_t* __restrict__ order, const int32_t* __restrict__ cpos,
+// colours in node order (a gather through the ranks) and the largest one
+__global__ void k_flow_colours(const int32_t* __restrict__ rank, const int32_t* __restrict__ cpos,
                                int64_t n, int32_t* __restrict__ colours, int32_t* mx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t m = -1;
-    if (i < n) {
-        m = cpos[i];
-        colours[order[i]] = m;
+    if (v < n) {
+        m = cpos[rank[v]];
+        colours[v] = m;
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
@@ -536,9 +545,9 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
                            rank);
         GR_LAUNCHED("colour ranks");
         // the higher-priority neighbours of every position
-        hipLaunchKernelGGL(k_flow_count, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, g->col,
-                           (const uint32_t*)order, (const int32_t*)rank, n, uplist, pstart, pcnt,
-                           wide, small + 2);
+        hipLaunchKernelGGL(k_flow_count, dim3(blocks_for(n * 8, kThreads)), dim3(kThreads), 0, st,
+                           g->row_ptr, g->col, (const int32_t*)rank, n, uplist, pstart, pcnt, wide,
+                           small + 2);
         GR_LAUNCHED("colour up-lists");
         hipLaunchKernelGGL(k_flow_count_wide, dim3(1024), dim3(kThreads), 0, st, g->row_ptr,
                            g->col, (const uint32_t*)order, (const int32_t*)rank,
@@ -568,9 +577,9 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
                         (void*)&cpos, (void*)&abort_flag};
         GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
                                           args, 0, st));
-        hipLaunchKernelGGL(k_flow_scatter, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)order,
+        hipLaunchKernelGGL(k_flow_colours, dim3(nb), dim3(kThreads), 0, st, (const int32_t*)rank,
                            (const int32_t*)cpos, n, colours, small + 4);
-        GR_LAUNCHED("colour scatter");
+        GR_LAUNCHED("colour gather");
         int32_t hs[8];
         GR_HIP(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
