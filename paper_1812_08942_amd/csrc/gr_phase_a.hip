@@ -85,34 +85,6 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
 // Priority: (h(v), v), h(v) = splitmix64 output v of the colour seed, or
 // (deg(v), h(v), v) largest-degree-first.
 
-// Device-wide barrier for a cooperatively launched grid: the block's writes
-// are released to the device, a monotonic counter collects the blocks, and
-// the wait is bounded: past kSpinLimit polls (far beyond any colour step) the
-// block raises the abort flag and every block leaves at its next barrier.
-constexpr unsigned kSpinLimit = 1u << 22;
-__device__ inline bool grid_barrier(unsigned* counter, unsigned target, int* abort_flag) {
-    __shared__ int ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(counter, 1u);
-        unsigned spins = 0;
-        ok = 1;
-        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit ||
-                __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                atomicExch(abort_flag, 1);
-                ok = 0;
-                break;
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
-    return ok != 0;
-}
-
 __device__ inline uint64_t wave_or(uint64_t x) {
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -1099,35 +1071,6 @@ __global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp
     gs_block<Q, DT>(rp, col, w, X, K, tt, blockIdx.x, part, splitcnt, sacc, sd);
 }
 
-// All sweeps of a level whose colour steps are small, in one cooperative
-// launch of a few blocks: the blocks share each step's work (the plan's
-// blocks, grid-stride) and meet at a device-wide barrier between steps,
-// instead of paying a kernel launch per step.
-template <int Q, int DT>
-__global__ void __launch_bounds__(kBig) k_gs_persistent(const int32_t* __restrict__ rp,
-                                                        const int32_t* __restrict__ col,
-                                                        const float* __restrict__ w,
-                                                        void* __restrict__ X, int32_t K,
-                                                        const GsTiers* __restrict__ plans,
-                                                        int32_t n_colours, int32_t sweeps,
-                                                        float* __restrict__ part,
-                                                        int32_t* __restrict__ splitcnt,
-                                                        unsigned* counter, int* abort_flag) {
-    __shared__ float sacc[kBig / kWave][Q][Chunk<DT>::E];
-    __shared__ float sd[kBig / kWave];
-    unsigned epoch = 0;
-    for (int s = 0; s < sweeps; ++s)
-        for (int c = 0; c < n_colours; ++c) {
-            const GsTiers& tt = plans[c];
-            if (tt.nt == 0) continue;
-            const int64_t nb = tt.blk0[tt.nt];
-            for (int64_t b = blockIdx.x; b < nb; b += gridDim.x)
-                gs_block<Q, DT>(rp, col, w, X, K, tt, b, part, splitcnt, sacc, sd);
-            ++epoch;
-            if (!grid_barrier(counter, gridDim.x * epoch, abort_flag)) return;
-        }
-}
-
 // lanes per row of tier t: about half the tier's largest degree times
 // Q / kU (two rounds of kU gathers per lane), a power of two in [Q, kBig]
 static int tier_lanes(int Q, int t) {
@@ -1162,15 +1105,6 @@ static GsTiers plan_gs_step(const OrderedGraph* og, int Q, int c) {
     return tt;
 }
 
-#ifndef GR_GS_PERSIST_BLOCKS
-#define GR_GS_PERSIST_BLOCKS 32
-#endif
-#ifndef GR_GS_PERSIST_MAX
-#define GR_GS_PERSIST_MAX 96
-#endif
-constexpr int kPersistBlocks = GR_GS_PERSIST_BLOCKS;  // blocks of a persistent smoothing launch
-constexpr int64_t kPersistMaxStep = GR_GS_PERSIST_MAX;  // largest step (plan blocks) it takes
-
 template <int Q, int DT>
 static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& ws,
                     hipStream_t st) {
@@ -1178,14 +1112,14 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& w
     const int xs = DT == GR_BF16 ? 2 : 4;
     const int C = og->n_colours;
     std::vector<GsTiers> plan(C);
-    int64_t biggest = 0;
     int steps = 0;
-    double sweep_bytes = 0.0;
+    double sweep_bytes = 0.0;  // compulsory bytes of one sweep (see below)
     for (int c = 0; c < C; ++c) {
         plan[c] = plan_gs_step(og, Q, c);
         if (plan[c].nt == 0) continue;
         ++steps;
-        biggest = std::max<int64_t>(biggest, plan[c].blk0[plan[c].nt]);
+        // a colour step's CSR rows, plus one read and one write of each
+        // updated vector row
         const double rows = (double)(og->class_ptr_h[c + 1] - og->class_ptr_h[c]);
         sweep_bytes += 4.0 * (rows + 1) + 8.0 * (double)og->class_nnz_h[c] + 2.0 * rows * K * xs;
     }
@@ -1198,51 +1132,18 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& w
     int32_t* splitcnt = ws.take<int32_t>((size_t)std::max<int64_t>(split_rows, 1));
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (smoothing partials)");
     if (split_rows > 0) GR_TRY(fill_i32(splitcnt, 0, split_rows, st));
-    if (biggest <= kPersistMaxStep && steps * sweeps >= 8) {
-        // every step is small: one cooperative launch for all sweeps
-        GsTiers* dplan = ws.take<GsTiers>(C);
-        unsigned* sync = ws.take<unsigned>(4);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (smoothing plan)");
-        int* abort_flag = (int*)(sync + 1);
-        GR_HIP(hipMemcpyAsync(dplan, plan.data(), sizeof(GsTiers) * C, hipMemcpyHostToDevice, st));
-        GR_HIP(hipMemsetAsync(sync, 0, sizeof(unsigned) * 4, st));
-        const int32_t* rp = og->g.row_ptr;
-        const int32_t* cl = og->g.col;
-        const float* wt = og->g.w;
-        const GsTiers* cp = dplan;
-        int32_t nc = C, sw = sweeps;
-        void* args[] = {(void*)&rp, (void*)&cl, (void*)&wt, (void*)&X, (void*)&K, (void*)&cp,
-                        (void*)&nc, (void*)&sw, (void*)&part, (void*)&splitcnt, (void*)&sync,
-                        (void*)&abort_flag};
-        if (pr) prof::begin(st);
-        GR_HIP(hipLaunchCooperativeKernel((const void*)k_gs_persistent<Q, DT>, dim3(kPersistBlocks),
-                                          dim3(kBig), args, 0, st));
-        if (pr) prof::end(st, prof::SMOOTH, sweep_bytes * sweeps, (int64_t)steps * sweeps);
-        int hflag = 0;
-        GR_HIP(hipMemcpyAsync(&hflag, abort_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));  // also keeps `plan` alive for the copy
-        if (hflag) return set_error(GR_EHIP, "smoothing barrier timed out");
-        ws.used = mark;
-        return GR_OK;
-    }
+    // the profiler brackets all steps of the level at once (events between
+    // the launches would stall the launch queue)
+    if (pr) prof::begin(st);
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < C; ++c) {
             const GsTiers& tt = plan[c];
             if (tt.nt == 0) continue;
-            const int64_t lo = og->class_ptr_h[c], hi = og->class_ptr_h[c + 1];
-            if (pr) prof::begin(st);
             hipLaunchKernelGGL((k_gs_step<Q, DT>), dim3((unsigned)tt.blk0[tt.nt]), dim3(kBig), 0, st,
                                og->g.row_ptr, og->g.col, og->g.w, X, K, tt, part, splitcnt);
             GR_LAUNCHED("gs step");
-            if (pr) {
-                // compulsory bytes of this colour step: its CSR rows, plus one
-                // read and one write of each updated vector row
-                double rows = (double)(hi - lo);
-                double bytes = 4.0 * (rows + 1) + 8.0 * (double)og->class_nnz_h[c] +
-                               2.0 * rows * K * xs;
-                prof::end(st, prof::SMOOTH, bytes, 1);
-            }
         }
+    if (pr) prof::end(st, prof::SMOOTH, sweep_bytes * sweeps, (int64_t)steps * sweeps);
     ws.used = mark;
     return GR_OK;
 }
