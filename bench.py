@@ -276,14 +276,24 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
 
 
+GS_SECTION = "// ----------------------------------------------------------- GS colour step"
+
+
 def kernel_source_digest():
-    """Digest of the GS kernel's source file; a traffic figure taken for
-    another version of the kernel is not reported."""
+    """Digest of the GS kernel's source: its section of gr_phase_a.hip (to
+    the end of the file) and the shared device helpers.  A traffic figure
+    taken for another version of the kernel is not reported."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_1812_08942_amd", "csrc", "gr_phase_a.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    csrc = os.path.join(ROOT, "paper_1812_08942_amd", "csrc")
+    with open(os.path.join(csrc, "gr_phase_a.hip"), "rb") as f:
+        text = f.read()
+    at = text.find(GS_SECTION.encode())
+    if at < 0:
+        raise RuntimeError("GS section marker not found in gr_phase_a.hip")
+    with open(os.path.join(csrc, "gr_device.hpp"), "rb") as f:
+        helpers = f.read()
+    return hashlib.sha256(text[at:] + helpers).hexdigest()
 
 
 def measured_traffic(workload, dtype):

@@ -109,14 +109,39 @@ def test_init_vectors_match_oracle():
             assert np.max(np.abs(X - want)) <= 2.0**-8 * np.max(np.abs(ref))
 
 
+def colouring_graphs():
+    """The small graphs plus two that reach the colouring's wide paths: a
+    complete graph (every node waits on all earlier ones; colours above 255
+    need the later colour windows) and a power-law graph with hubs above
+    degree 2048."""
+    gs = dict(small_graphs())
+    gs["complete_300"] = W.complete(300)
+    gs["chunglu_hubs_10000"] = W.chung_lu(10000, mean_deg=700.0, seed=7)
+    return gs
+
+
 @pytest.mark.parametrize("ldf", [False, True])
 def test_greedy_colouring_bit_exact(ldf):
     dev = _dev()
     G = _G()
-    for name, g in small_graphs().items():
+    for name, g in colouring_graphs().items():
         say(f"colour {name} ldf={ldf}")
         c, nc = G.gr_colour_greedy(dgraph(g, dev), 777, ldf)
         rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 777, ldf)
+        assert nc == rnc
+        assert np.array_equal(c.cpu().numpy(), rc)
+
+
+def test_greedy_colouring_exact_order_path(monkeypatch):
+    """Largest-degree-first colouring through the exact two-key priority
+    order (normally taken only when truncated sort keys tie)."""
+    dev = _dev()
+    G = _G()
+    monkeypatch.setenv("GR_COLOUR_EXACT_ORDER", "1")
+    for name, g in colouring_graphs().items():
+        say(f"colour (exact order) {name}")
+        c, nc = G.gr_colour_greedy(dgraph(g, dev), 4242, True)
+        rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 4242, True)
         assert nc == rnc
         assert np.array_equal(c.cpu().numpy(), rc)
 
