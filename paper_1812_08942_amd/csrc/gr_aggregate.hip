@@ -72,21 +72,30 @@ __global__ void k_parent(const int32_t* __restrict__ best, const int32_t* __rest
     par[v] = p;
 }
 
+// one pointer-jumping round; `changed` (when given) is raised by one lane
+// per wave that moved a pointer (a benign same-value race)
 __global__ void k_jump(const int32_t* __restrict__ pa, int64_t n, int32_t* __restrict__ pb,
                        int32_t* __restrict__ changed) {
-    int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (v >= n) return;
-    int32_t p = pa[v];
-    int32_t q = pa[p];
-    pb[v] = q;
-    if (q != p) *changed = 1;  // benign same-value race
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    bool ch = false;
+    if (v < n) {
+        const int32_t p = pa[v];
+        const int32_t q = pa[p];
+        pb[v] = q;
+        ch = q != p;
+    }
+    if (changed && __ballot(ch) && (threadIdx.x & (kWave - 1)) == 0) *changed = 1;
 }
 
 __global__ void k_min_member(const int32_t* __restrict__ root, const int32_t* __restrict__ ids,
                              int64_t n, int32_t* __restrict__ minid) {
     int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (v >= n) return;
-    atomicMin(&minid[root[v]], idof(ids, (int32_t)v));
+    // read first: once a small id has arrived, the larger ones of a big
+    // aggregate skip the atomic (same-address atomics serialise); a stale
+    // read only costs an atomic that changes nothing
+    const int32_t r = root[v], id = idof(ids, (int32_t)v);
+    if (id < minid[r]) atomicMin(&minid[r], id);
 }
 
 __global__ void k_leader_flags(const int32_t* __restrict__ root, const int32_t* __restrict__ ids,
@@ -165,16 +174,23 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
     }
     hipLaunchKernelGGL(k_parent, dim3(gb), dim3(kT), 0, st, best, ids, acc, n, pa);
     GR_LAUNCHED("parent");
-    // pointer jumping to the roots; the depth halves each round
-    for (int round = 0;; ++round) {
+    // pointer jumping to the roots; the depth halves each round.  Rounds go
+    // in batches of kJumpBatch with one host check: only the batch's last
+    // round reports, and a round that moves nothing means every later one
+    // moves nothing too (extra rounds on converged pointers are no-ops)
+    constexpr int kJumpBatch = 4;
+    for (int round = 0;; round += kJumpBatch) {
         if (round > 64) return set_error(GR_EHIP, "pointer jumping did not converge");
         GR_HIP(hipMemsetAsync(small, 0, sizeof(int32_t), st));
-        hipLaunchKernelGGL(k_jump, dim3(gb), dim3(kT), 0, st, pa, n, pb, small);
-        GR_LAUNCHED("jump");
+        for (int b = 0; b < kJumpBatch; ++b) {
+            hipLaunchKernelGGL(k_jump, dim3(gb), dim3(kT), 0, st, pa, n, pb,
+                               b == kJumpBatch - 1 ? small : (int32_t*)nullptr);
+            GR_LAUNCHED("jump");
+            int32_t* t = pa; pa = pb; pb = t;
+        }
         int32_t ch = 0;
         GR_HIP(hipMemcpyAsync(&ch, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
-        int32_t* t = pa; pa = pb; pb = t;
         if (!ch) break;
     }
     int32_t* root = pa;

@@ -440,18 +440,29 @@ __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restr
     }
 }
 
-// colours in node order (a gather through the ranks) and the largest one
-__global__ void k_flow_colours(const int32_t* __restrict__ rank, const int32_t* __restrict__ cpos,
-                               int64_t n, int32_t* __restrict__ colours, int32_t* mx) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// colours in node order (a gather through the ranks) and the largest one:
+// grid-stride, one atomic per block (same-address atomics serialise)
+constexpr int kGatherBlocks = 1024;
+__global__ void __launch_bounds__(kThreads) k_flow_colours(const int32_t* __restrict__ rank,
+                                                           const int32_t* __restrict__ cpos,
+                                                           int64_t n, int32_t* __restrict__ colours,
+                                                           int32_t* mx) {
+    __shared__ int32_t wm[kThreads / kWave];
     int32_t m = -1;
-    if (v < n) {
-        m = cpos[rank[v]];
-        colours[v] = m;
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * kThreads) {
+        const int32_t c = cpos[rank[v]];
+        colours[v] = c;
+        m = max(m, c);
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(mx, m);
+    if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / kWave; ++w) m = max(m, wm[w]);
+        atomicMax(mx, m);
+    }
 }
 
 static int flow_blocks(int64_t n) {
@@ -553,8 +564,9 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
                         (void*)&cpos, (void*)&abort_flag};
         GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
                                           args, 0, st));
-        hipLaunchKernelGGL(k_flow_colours, dim3(nb), dim3(kThreads), 0, st, (const int32_t*)rank,
-                           (const int32_t*)cpos, n, colours, small + 4);
+        hipLaunchKernelGGL(k_flow_colours, dim3(std::min<unsigned>(nb, kGatherBlocks)),
+                           dim3(kThreads), 0, st, (const int32_t*)rank, (const int32_t*)cpos, n,
+                           colours, small + 4);
         GR_LAUNCHED("colour gather");
         int32_t hs[8];
         GR_HIP(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, st));
