@@ -652,17 +652,17 @@ __global__ void k_perm_degrees(const int32_t* __restrict__ rp, const uint32_t* _
     deg[r] = rp[v + 1] - rp[v];
 }
 
-// G lanes per new row (G a power of two sized to the mean degree): copy the
-// old row's entries with relabelled columns
+// G lanes per old row (G a power of two sized to the mean degree), in old
+// order so that the old CSR streams in: copy the row's entries, columns
+// relabelled, to its new row (each new row is written contiguously)
 __global__ void k_perm_entries(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               const float* __restrict__ w, const uint32_t* __restrict__ perm,
-                               const int32_t* __restrict__ iperm, const int32_t* __restrict__ nrp,
-                               int64_t n, int G, int32_t* __restrict__ ncol, float* __restrict__ nw) {
-    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+                               const float* __restrict__ w, const int32_t* __restrict__ iperm,
+                               const int32_t* __restrict__ nrp, int64_t n, int G,
+                               int32_t* __restrict__ ncol, float* __restrict__ nw) {
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int l = threadIdx.x % G;
-    if (r >= n) return;
-    int32_t v = (int32_t)perm[r];
-    int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[r];
+    if (v >= n) return;
+    const int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[iperm[v]];
     for (int32_t e = e0 + l; e < e1; e += G) {
         ncol[o + (e - e0)] = iperm[col[e]];
         nw[o + (e - e0)] = w[e];
@@ -733,8 +733,7 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
         int G = 4;
         while (G < kWave && G * 2 <= nnz / n) G *= 2;  // about half the mean degree
         hipLaunchKernelGGL(k_perm_entries, dim3(blocks_for(n * G, kThreads)), dim3(kThreads), 0,
-                           st, g->row_ptr, g->col, g->w, (const uint32_t*)og->perm, og->iperm, nrp,
-                           n, G, ncol, nw);
+                           st, g->row_ptr, g->col, g->w, og->iperm, nrp, n, G, ncol, nw);
         GR_LAUNCHED("perm entries");
     }
     // bucket sizes (rows, entries) on the host
