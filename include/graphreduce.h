@@ -107,7 +107,7 @@ typedef struct gr_result {
 #define GR_PHASE_COLOUR 0
 #define GR_PHASE_RELABEL 1
 #define GR_PHASE_INIT 2
-#define GR_PHASE_SMOOTH 3    /* one record per Gauss-Seidel colour step */
+#define GR_PHASE_SMOOTH 3    /* one record per level: its Gauss-Seidel steps */
 #define GR_PHASE_AFFINITY 4
 #define GR_PHASE_AGGREGATE 5
 #define GR_PHASE_GALERKIN 6
@@ -155,8 +155,9 @@ int gr_reduce(const gr_graph* g, const gr_params* p, gr_result* res, void* ws,
 /*
  * gr_profile_start / gr_profile_stop — measurement aid.  After start, calls
  * made on this thread record HIP events on their stream around each phase
- * of gr_reduce (and each Gauss-Seidel colour step of gr_reduce/gr_smooth),
- * with the compulsory bytes each one moves.  stop synchronises on the
+ * of gr_reduce (the Gauss-Seidel colour steps of a level, in gr_reduce and
+ * gr_smooth, as one bracket with their count), with the compulsory bytes
+ * each one moves.  stop synchronises on the
  * recorded events, fills *out (HOST) and turns recording off.
  */
 int gr_profile_start(void);
@@ -173,14 +174,14 @@ int gr_validate(const gr_graph* g, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * gr_colour_greedy — greedy colouring (the multicolour order that makes
- * Gauss-Seidel on L x = 0 reproducible, Sec. 3.2.1), built in synchronous
- * rounds from a snapshot: every uncoloured node proposes the smallest colour
- * absent from its coloured neighbours and keeps it unless an uncoloured
- * neighbour of higher priority proposes the same colour; kept proposals are
- * committed together.  Priority is (h(v), v), h(v) = splitmix64 output v of
- * `seed` — or (deg(v), h(v), v) when `largest_degree_first`.  Output:
- * colours int32[n] (device), *n_colours (HOST).  Synchronises once per
- * round.
+ * Gauss-Seidel on L x = 0 reproducible, Sec. 3.2.1): the result of visiting
+ * the nodes in decreasing priority and giving each the smallest colour
+ * absent among its already coloured (higher-priority) neighbours.  Priority
+ * is (h(v), v), h(v) = splitmix64 output v of `seed` — or (deg(v), h(v), v)
+ * when `largest_degree_first`.  The device computes it without rounds: the
+ * nodes are sorted by priority and each waits for its higher-priority
+ * neighbours' colours (a bounded wait; GR_EHIP if it ever runs out).
+ * Output: colours int32[n] (device), *n_colours (HOST).  Synchronises.
  */
 int gr_colour_greedy(const gr_graph* g, uint64_t seed, int32_t largest_degree_first,
                      int32_t* colours, int32_t* n_colours, void* ws, size_t ws_bytes,
