@@ -133,7 +133,10 @@ constexpr int kFlowG = 8;                      // lanes per position of a narrow
 constexpr int kFlowBatch = kWave / kFlowG;     // positions of a batch
 constexpr int32_t kFlowNarrow = 64;            // listed neighbours per position of a narrow batch
 #ifndef GR_FLOW_BLOCKS_PER_CU
-#define GR_FLOW_BLOCKS_PER_CU 4
+#define GR_FLOW_BLOCKS_PER_CU 2
+#endif
+#ifndef GR_FLOW_SLEEP
+#define GR_FLOW_SLEEP 2  // s_sleep units (64 cycles) between polls
 #endif
 
 __device__ inline int32_t ld_dev(const int32_t* p) {
@@ -286,7 +289,7 @@ __device__ inline bool flow_wide(const int32_t* __restrict__ uplist, int32_t s, 
         for (int k = 0; k < kFlowU; ++k) {
             unsigned spins = 0;
             while (c[k] == -1 && !stop) {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(GR_FLOW_SLEEP);
                 c[k] = ld_dev(cpos + u[k]);
                 ++spins;
                 if (spins >= kFlowSpinLimit) {
@@ -371,7 +374,7 @@ __device__ inline bool flow_narrow(const int32_t* __restrict__ uplist, int32_t s
             pub = true;
         }
         if (__ballot(!pub) == 0) return true;
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(GR_FLOW_SLEEP);
         if (it >= kFlowSpinLimit) {
             if ((threadIdx.x & (kWave - 1)) == 0) atomicExch(abort_flag, 1);
             return false;
