@@ -65,7 +65,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU "
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU "
               f"path (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 

@@ -265,11 +265,12 @@ void or_affinity(int64_t n, const int32_t *row_ptr, const int32_t *col,
     }
 }
 
-/* Strongest neighbour: "nodes with large affinity or small algebraic
- * distance should be aggregated together" (Sec. 3.2.2).  best(v) minimises
- * (d_vj, j) over the neighbours of v, i.e. the smallest algebraic distance
- * (largest affinity) with ties to the smaller index; -1 without neighbours.
- * The rule that picks the partner is this build's reading. */
+/* Strongest neighbour (Sec. 3.2.2: aggregation joins node pairs of high
+ * affinity, i.e. of small algebraic distance).  best(v) minimises (d_vj, j)
+ * over the neighbours of v, i.e. the smallest algebraic distance (largest
+ * affinity) with ties to the smaller index; -1 without neighbours.  The
+ * paper gives the criterion, not the rule that picks the partner: this rule
+ * is a reading of it. */
 void or_best(int64_t n, const int32_t *row_ptr, const int32_t *col,
              const double *d, int32_t *best)
 {
