@@ -932,7 +932,12 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
 // partial sums are combined by a fixed shuffle tree inside the wave and,
 // for rows wider than a wave, across its waves in LDS.
 constexpr int kU = 4;
-constexpr int kBig = 1024;
+// threads of a smoothing block (measured: 512 beats 1024 by 0.5 ms per
+// reduction on the power-law graph; 256 loses 1.1 ms)
+#ifndef GR_GS_BLOCK
+#define GR_GS_BLOCK 512
+#endif
+constexpr int kBig = GR_GS_BLOCK;
 
 // Rows of degree above 2048 (tier 0) are split: kSplit blocks each take a
 // contiguous 1/kSplit of the row's entries and write a partial sum (K values
