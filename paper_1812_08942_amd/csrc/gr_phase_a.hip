@@ -123,7 +123,7 @@ __global__ void k_col_fill(int64_t n, int32_t* __restrict__ colours) {
 // inputs published: no deadlock while all waves are resident, which the
 // cooperative launch guarantees.  The colour
 // values are the only data passed between waves, so relaxed device-scope
-// atomics suffice.  Every wait is bounded: past kFlowSpinLimit polls a lane
+// atomics suffice.  Every wait is bounded: past spin_limit polls a lane
 // raises the abort flag, and every waiting lane leaves at its next check.
 constexpr int kFlowThreads = 256;
 constexpr int kFlowWaves = kFlowThreads / kWave;
@@ -272,7 +272,8 @@ __global__ void __launch_bounds__(kThreads) k_flow_count_wide(
 
 // one position with the whole wave; false when the wave must leave (abort)
 __device__ inline bool flow_wide(const int32_t* __restrict__ uplist, int32_t s, int32_t m,
-                                 int64_t i, int32_t* cpos, int32_t* abort_flag) {
+                                 int64_t i, int32_t* cpos, int32_t* abort_flag,
+                                 unsigned spin_limit) {
     const int lane = threadIdx.x & (kWave - 1);
     uint64_t used[4] = {0, 0, 0, 0};
     int stop = 0;
@@ -292,7 +293,7 @@ __device__ inline bool flow_wide(const int32_t* __restrict__ uplist, int32_t s, 
                 __builtin_amdgcn_s_sleep(GR_FLOW_SLEEP);
                 c[k] = ld_dev(cpos + u[k]);
                 ++spins;
-                if (spins >= kFlowSpinLimit) {
+                if (spins >= spin_limit) {
                     atomicExch(abort_flag, 1);
                     stop = 1;
                 } else if ((spins & 255u) == 0 && ld_dev(abort_flag)) {
@@ -341,7 +342,8 @@ __device__ inline uint64_t group_or(uint64_t x) {
 // wave-uniform: a group publishes as soon as its own neighbours are all
 // coloured, whatever the other groups of the wave still wait for.
 __device__ inline bool flow_narrow(const int32_t* __restrict__ uplist, int32_t s, int32_t m,
-                                   int64_t i, bool valid, int32_t* cpos, int32_t* abort_flag) {
+                                   int64_t i, bool valid, int32_t* cpos, int32_t* abort_flag,
+                                   unsigned spin_limit) {
     constexpr int U = kFlowNarrow / kFlowG;
     const int gl = threadIdx.x & (kFlowG - 1);
     int32_t u[U];
@@ -375,7 +377,7 @@ __device__ inline bool flow_narrow(const int32_t* __restrict__ uplist, int32_t s
         }
         if (__ballot(!pub) == 0) return true;
         __builtin_amdgcn_s_sleep(GR_FLOW_SLEEP);
-        if (it >= kFlowSpinLimit) {
+        if (it >= spin_limit) {
             if ((threadIdx.x & (kWave - 1)) == 0) atomicExch(abort_flag, 1);
             return false;
         }
@@ -424,7 +426,8 @@ __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restr
                                                           const uint32_t* __restrict__ batches,
                                                           const int32_t* __restrict__ nbatches,
                                                           int64_t n, int32_t* cpos,
-                                                          int32_t* abort_flag) {
+                                                          int32_t* abort_flag,
+                                                          unsigned spin_limit) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * kFlowWaves;
     const int32_t nbt = *nbatches;
@@ -435,10 +438,10 @@ __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restr
             const int64_t ig = (int64_t)(code & ~kNarrowBatch) + lane / kFlowG;
             const bool valid = ig < n;
             const int32_t s = valid ? pstart[ig] : 0, m = valid ? pcnt[ig] : 0;
-            if (!flow_narrow(uplist, s, m, ig, valid, cpos, abort_flag)) return;
+            if (!flow_narrow(uplist, s, m, ig, valid, cpos, abort_flag, spin_limit)) return;
         } else {
             const int64_t i = code;
-            if (!flow_wide(uplist, pstart[i], pcnt[i], i, cpos, abort_flag)) return;
+            if (!flow_wide(uplist, pstart[i], pcnt[i], i, cpos, abort_flag, spin_limit)) return;
         }
     }
 }
@@ -510,6 +513,13 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     // (the path that ties of truncated keys take; tests use it)
     const char* force = getenv("GR_COLOUR_EXACT_ORDER");
     const int first = (ldf && force && force[0] == '1') ? 1 : 0;
+    // GR_COLOUR_SPIN_LIMIT=k shortens every wait to k polls (tests of the
+    // timed-out path: every wave then leaves early and the call fails)
+    unsigned spin_limit = kFlowSpinLimit;
+    if (const char* sl = getenv("GR_COLOUR_SPIN_LIMIT")) {
+        const long v = atol(sl);
+        if (v > 0 && v < (long)kFlowSpinLimit) spin_limit = (unsigned)v;
+    }
     for (int exact = first; exact < 2; ++exact) {
         GR_HIP(hipMemsetAsync(small, 0, sizeof(int32_t) * 8, st));
         GR_HIP(hipMemsetAsync(small + 4, 0xff, sizeof(int32_t), st));
@@ -564,7 +574,7 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         int32_t* abort_flag = small + 3;
         int64_t nn = n;
         void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&bl, (void*)&nbt, (void*)&nn,
-                        (void*)&cpos, (void*)&abort_flag};
+                        (void*)&cpos, (void*)&abort_flag, (void*)&spin_limit};
         GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
                                           args, 0, st));
         hipLaunchKernelGGL(k_flow_colours, dim3(std::min<unsigned>(nb, kGatherBlocks)),

@@ -146,6 +146,27 @@ def test_greedy_colouring_exact_order_path(monkeypatch):
         assert np.array_equal(c.cpu().numpy(), rc)
 
 
+def test_colouring_wait_limit_fails_cleanly(monkeypatch):
+    """A colouring whose waits run out reports the failure and leaves the
+    device usable: GR_COLOUR_SPIN_LIMIT=1 cuts every wait to one poll (on a
+    complete graph every node waits for the earlier ones), then the same
+    call without it colours as the oracle does."""
+    dev = _dev()
+    G = _G()
+    g = W.complete(300)
+    monkeypatch.setenv("GR_COLOUR_SPIN_LIMIT", "1")
+    say("colour complete_300 with one poll per wait")
+    with pytest.raises(G.GraphReduceError) as err:
+        G.gr_colour_greedy(dgraph(g, dev), 5, True)
+    assert "timed out" in str(err.value)
+    monkeypatch.delenv("GR_COLOUR_SPIN_LIMIT")
+    say("colour complete_300 again")
+    c, nc = G.gr_colour_greedy(dgraph(g, dev), 5, True)
+    rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 5, True)
+    assert nc == rnc
+    assert np.array_equal(c.cpu().numpy(), rc)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_smoothing_matches_oracle(dtype):
     dev = _dev()
