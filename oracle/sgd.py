@@ -28,7 +28,7 @@ Iteration k (the algorithm's steps in order):
   * stop when (lambda_n^(k-1) - lambda_n^(k)) / lambda_n^(k) < eps, or after
     K_max iterations.
 Readings for values the paper leaves open: Delta = Delta_bar^(1/K_max)
-(Alg. 1, line 1), eta_max = eta_scale * mean(w_P) / max|s^(1)| with
+(Alg. 1's initialisation), eta_max = eta_scale * mean(w_P) / max|s^(1)| with
 eta_scale = 0.1, h_0 from the test-vector generator (one column, centred).
 """
 from __future__ import annotations
@@ -89,8 +89,8 @@ def sgd_scale(n, g_eu, g_ev, g_w, p_eu, p_ev, w_P, params: SgdParams):
     Lg = _lap(n, g_eu, g_ev, np.asarray(g_w, np.float64))
     d_G = np.diag(Lg).copy()
     h0 = O.init_vectors(n, 1, params.seed, centre=True)[:, 0]
-    delta = params.delta_bar ** (1.0 / params.k_max)      # Alg. 1, line 1
-    dw = np.zeros_like(w)                                 # line 2
+    delta = params.delta_bar ** (1.0 / params.k_max)      # cap factor (Alg. 1 set-up)
+    dw = np.zeros_like(w)                                 # momentum starts at zero
     d_P = np.bincount(p_eu, w, n) + np.bincount(p_ev, w, n)
     lam1 = float(np.min(d_G / d_P))
     lam_n_hist, lam_1_hist = [], [lam1]
@@ -99,30 +99,30 @@ def sgd_scale(n, g_eu, g_ev, g_w, p_eu, p_ev, w_P, params: SgdParams):
     k = 0
     while k < params.k_max:
         Lp = _lap(n, p_eu, p_ev, w)
-        h = power_vector(Lg, Lp, h0, params.t)            # line 4
+        h = power_vector(Lg, Lp, h0, params.t)            # t power iterations
         lam_n = float(h @ Lg @ h)                         # h^T L_P h = 1
         if lam_n0 is None:
             lam_n0 = lam_n
-        elif (lam_n_hist[-1] - lam_n) / lam_n < params.eps:  # line 3
+        elif (lam_n_hist[-1] - lam_n) / lam_n < params.eps:  # stopping test
             lam_n_hist.append(lam_n)
             break
         lam_n_hist.append(lam_n)
-        s = -lam_n * (h[p_eu] - h[p_ev]) ** 2             # line 6
+        s = -lam_n * (h[p_eu] - h[p_ev]) ** 2             # edge sensitivities
         if eta_max is None:
             eta_max = params.eta_scale * float(np.mean(w0)) / float(np.max(np.abs(s)))
             eta = eta_max
-        dw = params.alpha * dw - eta * s                  # line 7
-        prop = np.maximum(dw, 0.0)                        # lines 8-13 (parallel)
+        dw = params.alpha * dw - eta * s                  # momentum step
+        prop = np.maximum(dw, 0.0)                        # endpoint caps (parallel reading)
         S = np.bincount(p_eu, prop, n) + np.bincount(p_ev, prop, n)
         cap = d_G / (lam1 * delta) - d_P
         safe = np.where(S > 0, S, 1.0)
         fac = np.where(S > 0, cap / safe, np.inf)
         lim = np.where(prop > 0, np.minimum(fac[p_eu], fac[p_ev]) * np.where(prop > 0, prop, 1.0), 0.0)
         dw = np.maximum(0.0, np.minimum(dw, lim))
-        w = w + dw                                        # lines 15-17
+        w = w + dw                                        # weights, then degrees
         d_P = np.bincount(p_eu, w, n) + np.bincount(p_ev, w, n)
-        eta = (lam_n / lam_n0) * eta_max                  # line 19
-        lam1 = float(np.min(d_G / d_P))                   # line 21
+        eta = (lam_n / lam_n0) * eta_max                  # step-size schedule
+        lam1 = float(np.min(d_G / d_P))                   # lambda_1 from the degrees
         lam_1_hist.append(lam1)
         k += 1
     return SgdResult(w, lam_n_hist, lam_1_hist, k)
