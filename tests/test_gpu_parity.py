@@ -417,6 +417,36 @@ def test_reduce_end_to_end_multilevel(case, dtype):
         assert np.array_equal(agg, ref.agg)
 
 
+@pytest.mark.parametrize("case", ["star_30000", "chunglu_hubs_10000"])
+def test_reduce_hub_graphs(case):
+    """Graphs whose hubs reach every wide path (split smoothing rows, a
+    workgroup per long affinity and Galerkin row, wide colouring positions,
+    one giant aggregate): the reduction is a valid aggregation, and its
+    coarse graph is exactly the Galerkin product of its own map, stored
+    with bitwise-symmetric weights."""
+    dev = _dev()
+    G = _G()
+    if case == "star_30000":
+        n = 30000
+        rng = np.random.default_rng(3)
+        g = W.csr_from_edges(n, np.zeros(n - 1, np.int64), np.arange(1, n),
+                             rng.uniform(0.5, 2.0, n - 1))
+    else:
+        g = W.chung_lu(10000, mean_deg=700.0, seed=7)
+    for ldf in (False, True):
+        say(f"reduce {case} ldf={ldf}")
+        out = G.gr_reduce(dgraph(g, dev), 16, 5, 20.0, 31, 41, largest_degree_first=ldf)
+        agg = out.agg.cpu().numpy()
+        n_c = out.coarse.n
+        assert n_c >= O.target_size(g.n, 20.0)
+        check_valid_aggregation(g, agg, n_c)
+        rp, cl, w = O.galerkin(g.n, g.row_ptr, g.col, g.w.astype(np.float64), agg, n_c)
+        assert np.array_equal(out.coarse.row_ptr.cpu().numpy(), rp)
+        assert np.array_equal(out.coarse.col.cpu().numpy(), cl)
+        assert np.allclose(out.coarse.w.cpu().numpy(), w, rtol=1e-5, atol=0)
+        assert_bitwise_symmetric(rp, cl, out.coarse.w.cpu().numpy())
+
+
 def test_reduce_is_deterministic():
     dev = _dev()
     G = _G()
