@@ -57,6 +57,9 @@ def main():
                          "largest-degree-first")
     ap.add_argument("--no-bf16-compare", action="store_true",
                     help="skip the bfloat16-storage run of the headline workload")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the differentiable pieces (GS "
+                         "backward, Rayleigh-quotient gradients, Alg. 1)")
     ap.add_argument("--secondary", default="grid256",
                     help="second workload measured the same way ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -104,6 +107,8 @@ def main():
     g, wl, r, dg = keep
     if not args.no_eig:
         result.update(eig_report(G, r, args.eig_original, dg))
+    if not args.no_extras:
+        result["extras"] = extras_report(G, wl, dg, r, args.ldf)
     if (not args.no_bf16_compare and res["storage"] == "f32" and wl.K % 8 == 0):
         # the same workload with bfloat16 vector storage (FP32 arithmetic)
         lam32 = np.array(result["eig_reduced"]) if "eig_reduced" in result else None
@@ -255,6 +260,91 @@ def eig_report(G, r, eig_original, dg):
         out["eig_original_normalised"] = [float(x / lo[0]) for x in lo]
         out["eig_normalised_rel_err"] = float(np.max(
             np.abs(lam / lam[0] - lo / lo[0]) / (lo / lo[0])))
+    return out
+
+
+def _timed(fn, reps):
+    """Mean wall time (ms) of `reps` calls after one warm-up, device idle at
+    both ends."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3, out
+
+
+def extras_report(G, wl, dg, r, ldf):
+    """Timings of the differentiable pieces on the headline workload:
+    * the Gauss-Seidel backward pass (vector-Jacobian product, recomputing
+      the sweeps) on the full graph, K and sweeps of the workload;
+    * Rayleigh quotients of 10 vectors and their edge gradients on the
+      reduced graph (random FP64 vectors and edge weights: timing only);
+    * Alg. 1 edge scaling of a spanning sparsifier P of the reduced graph G
+      (maximum spanning forest plus the heaviest 10% of the other edges).
+    A failure is reported in place of the figures."""
+    import torch
+
+    from workloads import graphs as W
+
+    out = {}
+    try:
+        K, S = wl.K, wl.sweeps
+        el = G.gr_edge_list(dg)
+        colours, nc = G.gr_colour_greedy(dg, 1, ldf)
+        X0 = G.gr_init_vectors(dg.n, K, 2, "f32", device=dg.row_ptr.device)
+        gen = torch.Generator(device=dg.row_ptr.device).manual_seed(3)
+        cot = torch.randn(dg.n, K, generator=gen, device=dg.row_ptr.device)
+        ms, _ = _timed(lambda: G.gr_smooth_vjp(dg, el, colours, nc, X0, cot, S, False), 3)
+        out["gs_vjp"] = {"ms": ms, "n": dg.n, "nnz": dg.nnz, "K": K, "sweeps": S,
+                         "colours": int(nc), "mode": "recompute",
+                         "nnz_K_sweeps_per_s": dg.nnz * K * S / (ms * 1e-3)}
+        log(f"GS backward: {ms:.2f} ms")
+        del el, X0, cot
+    except Exception as e:  # keep the headline figures
+        out["gs_vjp"] = {"error": repr(e)}
+    try:
+        cg = r.coarse
+        elr = G.gr_edge_list(cg)
+        dev = cg.row_ptr.device
+        gen = torch.Generator(device=dev).manual_seed(4)
+        wE = torch.rand(elr.E, generator=gen, device=dev, dtype=torch.float64) + 0.5
+        U = torch.randn(cg.n, 10, generator=gen, device=dev, dtype=torch.float64)
+        gR = torch.ones(10, dtype=torch.float64, device=dev)
+
+        def rq():
+            R, den = G.gr_rq_forward(elr, wE, U)
+            return G.gr_rq_backward(elr, U, R, den, gR)
+
+        ms, _ = _timed(rq, 5)
+        out["rq_forward_backward"] = {"ms": ms, "n": cg.n, "edges": elr.E, "vectors": 10}
+        log(f"Rayleigh quotients + gradients: {ms:.3f} ms")
+        # Alg. 1 on a spanning sparsifier of the reduced graph
+        w_entries = cg.w.to(torch.float64)
+        w_edge = torch.zeros(elr.E, dtype=torch.float64, device=dev)
+        w_edge[elr.edge_of_entry.long()] = w_entries
+        eu, ev, we = (elr.eu.cpu().numpy(), elr.ev.cpu().numpy(), w_edge.cpu().numpy())
+        keep = W.spanning_sparsifier(cg.n, eu, ev, we, 0.1)
+        pg = W.csr_from_edges(cg.n, eu[keep], ev[keep], we[keep])
+        dP = G.DeviceGraph.from_numpy(pg.row_ptr, pg.col, pg.w, dev)
+        pel = G.gr_edge_list(dP)
+        wP = torch.from_numpy(we[keep].copy()).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = G.gr_sgd_scale(cg, dP, pel, wP, k_max=20)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out["sgd_scale"] = {"ms": ms, "n": cg.n, "edges_G": elr.E, "edges_P": int(keep.size),
+                            "iterations": rep["iterations"],
+                            "lambda_n_first_last": [rep["lambda_n"][0], rep["lambda_n"][-1]],
+                            "cg_iterations_max": rep["cg_iterations_max"]}
+        log(f"Alg. 1: {ms:.1f} ms, {rep['iterations']} iterations")
+    except Exception as e:
+        out.setdefault("rq_forward_backward", {"error": repr(e)})
+        out["sgd_scale"] = {"error": repr(e)}
     return out
 
 

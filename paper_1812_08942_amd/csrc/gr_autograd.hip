@@ -14,19 +14,22 @@ constexpr int kA = 256;
 // Undirected edge e = (p, q), p < q, is numbered by the position of the upper
 // entry (p, q) among all upper entries in CSR order; both stored entries map
 // to it.
+// a wave per row for both kernels: hub rows would serialise one thread
 __global__ void k_upper_counts(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                int64_t n, int32_t* __restrict__ flag) {
-    int64_t v = (int64_t)blockIdx.x * kA + threadIdx.x;
+    const int64_t v = ((int64_t)blockIdx.x * kA + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (v >= n) return;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) flag[e] = col[e] > v ? 1 : 0;
+    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) flag[e] = col[e] > v ? 1 : 0;
 }
 
 __global__ void k_edge_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                             const int32_t* __restrict__ pos, int64_t n, int32_t* __restrict__ eu,
                             int32_t* __restrict__ ev, int32_t* __restrict__ eoe) {
-    int64_t v = (int64_t)blockIdx.x * kA + threadIdx.x;
+    const int64_t v = ((int64_t)blockIdx.x * kA + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (v >= n) return;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
         int32_t j = col[e];
         if (j > v) {
             int32_t k = pos[e];
@@ -55,7 +58,7 @@ int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t
     int32_t* flag = ws.take<int32_t>(g->nnz);
     int32_t* pos = ws.take<int32_t>(g->nnz + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (edge list)");
-    const unsigned nb = blocks_for(g->n, kA);
+    const unsigned nb = blocks_for(g->n * kWave, kA);
     hipLaunchKernelGGL(k_upper_counts, dim3(nb), dim3(kA), 0, st, g->row_ptr, g->col, g->n, flag);
     GR_LAUNCHED("upper counts");
     GR_TRY(scan_exclusive_i32(flag, pos, g->nnz, pos + g->nnz, ws, st));
@@ -298,37 +301,62 @@ __device__ inline int32_t class_of(const int32_t* __restrict__ cp, int32_t C, in
     return lo;
 }
 
-// segments: maximal runs of one colour inside a column-sorted row
-__global__ void k_seg_count(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+// Segments: the maximal runs of one colour inside a column-sorted row. A row
+// of colour-contiguous columns holds at most one run per colour, and the runs
+// tile the entries in CSR order, so a run ends where the next one starts.
+// A wave per row marks the first entry of every run.
+__global__ void k_seg_heads(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                             int64_t n, const int32_t* __restrict__ cp, int32_t C,
-                            int32_t* __restrict__ cnt) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                            int32_t* __restrict__ head) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (r >= n) return;
-    int32_t prev = -1;
-    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
-        int32_t c = class_of(cp, C, col[e]);
-        if (c != prev) atomicAdd(&cnt[c], 1);
-        prev = c;
+    const int32_t e0 = rp[r], e1 = rp[r + 1];
+    for (int32_t e = e0 + lane; e < e1; e += kWave) {
+        const int32_t c = class_of(cp, C, col[e]);
+        head[e] = (e == e0 || col[e - 1] < cp[c]) ? 1 : 0;
     }
 }
 
-__global__ void k_seg_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+// the run starting at entry e goes to slot hpos[e], keyed by its colour
+__global__ void k_seg_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                            int64_t n, const int32_t* __restrict__ cp, int32_t C,
-                           int32_t* __restrict__ cursor, int32_t* __restrict__ rec) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                           const int32_t* __restrict__ head, const int32_t* __restrict__ hpos,
+                           uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                           int32_t* __restrict__ hrow, int32_t* __restrict__ hstart) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (r >= n) return;
-    const int32_t e1 = rp[r + 1];
-    int32_t e = rp[r];
-    while (e < e1) {
-        int32_t c = class_of(cp, C, col[e]);
-        int32_t f = e + 1;
-        while (f < e1 && col[f] < cp[c + 1]) ++f;
-        int32_t slot = atomicAdd(&cursor[c], 1);
-        rec[3 * slot] = (int32_t)r;
-        rec[3 * slot + 1] = e;
-        rec[3 * slot + 2] = f;
-        e = f;
+    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) {
+        if (!head[e]) continue;
+        const int32_t s = hpos[e];
+        key[s] = (uint64_t)class_of(cp, C, col[e]);
+        val[s] = (uint32_t)s;
+        hrow[s] = (int32_t)r;
+        hstart[s] = e;
     }
+}
+
+// record k = the k-th run in (colour, entry) order: (row, first, end)
+__global__ void k_seg_records(const uint32_t* __restrict__ order, int64_t nh, int64_t nnz,
+                              const int32_t* __restrict__ hrow, const int32_t* __restrict__ hstart,
+                              int32_t* __restrict__ rec) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nh) return;
+    const uint32_t s = order[k];
+    rec[3 * k] = hrow[s];
+    rec[3 * k + 1] = hstart[s];
+    rec[3 * k + 2] = (int64_t)s + 1 < nh ? hstart[s + 1] : (int32_t)nnz;
+}
+
+// segp[c] = first record of colour c (colour-sorted keys); k runs over [0, nh]
+__global__ void k_seg_bounds(const uint64_t* __restrict__ skey, int64_t nh, int32_t C,
+                             int32_t* __restrict__ segp) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nh) return;
+    const int32_t lo = k == 0 ? -1 : (int32_t)skey[k - 1];
+    const int32_t hi = k == nh ? C : (int32_t)skey[k];
+    for (int32_t c = lo + 1; c <= hi; ++c) segp[c] = (int32_t)k;
 }
 
 template <int E>
@@ -350,11 +378,11 @@ __device__ inline void store_f32(float* __restrict__ A, int64_t row, int K, int 
 template <int Q, int P, int DT>
 __global__ void __launch_bounds__(256) k_vjp_rows(const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
-                                                  const float* __restrict__ w,
                                                   const void* __restrict__ Xs,
-                                                  const void* __restrict__ Xp, int32_t K, int64_t lo,
-                                                  int64_t hi, float* __restrict__ xbar,
-                                                  float* __restrict__ H, float* __restrict__ ge) {
+                                                  const void* __restrict__ Xp, int32_t K, int64_t clo,
+                                                  int64_t lo, int64_t hi, const float* __restrict__ dw,
+                                                  float* __restrict__ xbar, float* __restrict__ H,
+                                                  float* __restrict__ ge) {
     constexpr int L = Q * P;
     constexpr int RPW = kWave / L;
     constexpr int E = Chunk<DT>::E;
@@ -365,10 +393,7 @@ __global__ void __launch_bounds__(256) k_vjp_rows(const int32_t* __restrict__ rp
     const int64_t r = lo + wave * RPW + lane / L;
     if (r >= hi) return;
     const int32_t e0 = rp[r], e1 = rp[r + 1];
-    float d = 0.0f;
-    for (int32_t e = e0 + p; e < e1; e += P) d += w[e];
-#pragma unroll
-    for (int off = Q; off < L; off <<= 1) d += __shfl_xor(d, off, kWave);
+    const float d = dw[r];
     if (!(d > 0.0f)) return;  // no equation: the step leaves this row alone
     float g[E], xi[E];
     load_f32<E>(xbar, r, K, q, g);
@@ -379,7 +404,7 @@ __global__ void __launch_bounds__(256) k_vjp_rows(const int32_t* __restrict__ rp
         bool ok = e < e1;
         int32_t j = ok ? col[e] : (int32_t)r;
         float xj[E];
-        Chunk<DT>::load(j < lo ? Xs : Xp, j, K, q, xj);
+        Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj);
         float s = 0.0f;
 #pragma unroll
         for (int i = 0; i < E; ++i) s = __fmaf_rn(g[i], xj[i] - xi[i], s);
@@ -396,6 +421,72 @@ __global__ void __launch_bounds__(256) k_vjp_rows(const int32_t* __restrict__ rp
         store_f32<E>(H, r, K, q, h);
         store_f32<E>(xbar, r, K, q, z);
     }
+}
+
+// The rows of degree above kLongRow (the colour's first rows: its degree
+// tiers come in decreasing order) take two launches, so that a hub row is
+// spread over many workgroups: the first sets H_i = xbar_i / d_i and clears
+// xbar_i, then every entry of those rows, Q lanes each, adds
+// H_i . (x_j - x_i) to its gradient.  Weights are positive, so d_i > 0.
+template <int Q, int DT>
+__global__ void k_vjp_long_rows(const float* __restrict__ dw, int32_t K, int64_t lo, int64_t hi,
+                                float* __restrict__ xbar, float* __restrict__ H) {
+    constexpr int E = Chunk<DT>::E;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = lo + t / Q;
+    const int q = (int)(t % Q);
+    if (r >= hi) return;
+    const float d = dw[r];
+    float h[E], z[E];
+    load_f32<E>(xbar, r, K, q, h);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        h[i] = h[i] / d;
+        z[i] = 0.0f;
+    }
+    store_f32<E>(H, r, K, q, h);
+    store_f32<E>(xbar, r, K, q, z);
+}
+
+// entries [rp[lo], rp[hi]) of the long rows [lo, hi)
+template <int Q, int DT>
+__global__ void __launch_bounds__(256) k_vjp_long_edges(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const void* __restrict__ Xs,
+    const void* __restrict__ Xp, int32_t K, int64_t clo, int64_t lo, int64_t hi, int64_t ebeg,
+    int64_t eend, const float* __restrict__ H, float* __restrict__ ge) {
+    constexpr int E = Chunk<DT>::E;
+    const int q = threadIdx.x % Q;
+    const int64_t e = ebeg + ((int64_t)blockIdx.x * 256 + threadIdx.x) / Q;
+    if (e >= eend) return;
+    int64_t a = lo, b = hi - 1;  // the row holding e: last r with rp[r] <= e
+    while (a < b) {
+        const int64_t m = (a + b + 1) >> 1;
+        if (rp[m] <= e) a = m; else b = m - 1;
+    }
+    const int64_t r = a;
+    const int32_t j = col[e];
+    float h[E], xi[E], xj[E];
+    load_f32<E>(H, r, K, q, h);
+    Chunk<DT>::load(Xs, r, K, q, xi);
+    Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj);
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < E; ++i) s = __fmaf_rn(h[i], xj[i] - xi[i], s);
+    s = qsum<Q>(s);
+    if (q == 0) ge[e] += s;
+}
+
+// d_i = sum_j w_ij, a wave per row; constant over the sweeps
+__global__ void k_row_weight(const int32_t* __restrict__ rp, const float* __restrict__ w, int64_t n,
+                             float* __restrict__ dw) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (r >= n) return;
+    float d = 0.0f;
+    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) d += w[e];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) d += __shfl_xor(d, off, kWave);
+    if (lane == 0) dw[r] = d;
 }
 
 // one row-group per segment (row j, entries [a, b) whose columns have colour c)
@@ -472,7 +563,8 @@ static int pick_p_vjp(int Q, double mean_deg) {
 
 template <int Q, int DT>
 static int vjp_launch_rows(int P, const gr_graph* g, const void* Xs, const void* Xp, int K,
-                           int64_t lo, int64_t hi, float* xbar, float* H, float* ge, hipStream_t st) {
+                           int64_t clo, int64_t lo, int64_t hi, const float* dw, float* xbar,
+                           float* H, float* ge, hipStream_t st) {
     if (hi <= lo) return GR_OK;
     const int64_t waves = ((hi - lo) * Q * P + kWave - 1) / kWave;
     dim3 grid(blocks_for(waves * kWave, 256));
@@ -480,7 +572,7 @@ static int vjp_launch_rows(int P, const gr_graph* g, const void* Xs, const void*
     case PP:                                                                                    \
         if constexpr (Q * PP <= kWave)                                                          \
             hipLaunchKernelGGL((k_vjp_rows<Q, PP, DT>), grid, dim3(256), 0, st, g->row_ptr, g->col, \
-                               g->w, Xs, Xp, K, lo, hi, xbar, H, ge);                            \
+                               Xs, Xp, K, clo, lo, hi, dw, xbar, H, ge);                         \
         break;
     switch (P) {
         GR_VR(1) GR_VR(2) GR_VR(4) GR_VR(8) GR_VR(16) GR_VR(32) GR_VR(64)
@@ -522,14 +614,15 @@ size_t vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t S
                + 4 * M                    // per-entry gradients
                + 8 * (M / 2 + 1)          // edge slots
                + (size_t)(store ? S + 1 : 3) * xb + 2 * fb  // states, xbar, H
-               + 40 * M + 64 * N;         // sort / relabel temporaries
+               + 4 * N                    // weighted degrees
+               + 48 * M + 64 * N;         // sort / relabel / segment temporaries
     return b + b / 16 + (16u << 20);
 }
 
 template <int Q, int DT>
 static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vector<int64_t>& seg_ptr,
-                    int K, int S, int store, void* states, size_t xbytes, float* xbar, float* H,
-                    float* ge, Arena& ws, hipStream_t st) {
+                    int K, int S, int store, void* states, size_t xbytes, const float* dw, float* xbar,
+                    float* H, float* ge, Arena& ws, hipStream_t st) {
     constexpr int E = Chunk<DT>::E;
     const int C = og->n_colours;
     std::vector<int> Prow(C), Pseg(C);
@@ -563,8 +656,21 @@ static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vecto
             Xp = state(1);
         }
         for (int c = C - 1; c >= 0; --c) {
-            GR_TRY((vjp_launch_rows<Q, DT>(Prow[c], &og->g, Xs, Xp, K, og->class_ptr_h[c],
-                                           og->class_ptr_h[c + 1], xbar, H, ge, st)));
+            const int64_t clo = og->class_ptr_h[c], chi = og->class_ptr_h[c + 1];
+            const int64_t mid = og->tier_ptr_h[(size_t)c * kNT + kLongTiers];  // end of long rows
+            if (mid > clo) {
+                hipLaunchKernelGGL((k_vjp_long_rows<Q, DT>), dim3(blocks_for((mid - clo) * Q, 256)),
+                                   dim3(256), 0, st, dw, K, clo, mid, xbar, H);
+                GR_LAUNCHED("vjp long rows");
+                const int64_t ebeg = og->class_e_h[c], eend = ebeg + og->long_nnz_h[c];
+                hipLaunchKernelGGL((k_vjp_long_edges<Q, DT>),
+                                   dim3(blocks_for((eend - ebeg) * Q, 256)), dim3(256), 0, st,
+                                   og->g.row_ptr, og->g.col, Xs, Xp, K, clo, clo, mid, ebeg, eend,
+                                   (const float*)H, ge);
+                GR_LAUNCHED("vjp long edges");
+            }
+            GR_TRY((vjp_launch_rows<Q, DT>(Prow[c], &og->g, Xs, Xp, K, clo, mid, chi, dw, xbar, H,
+                                           ge, st)));
             GR_TRY((vjp_launch_segs<Q, E>(Pseg[c], rec + 3 * seg_ptr[c], seg_ptr[c + 1] - seg_ptr[c],
                                           &og->g, H, K, xbar, st)));
         }
@@ -608,38 +714,59 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     }
     og.g.col = col_s;
     og.g.w = w_s;
-    // colour segments of every row
+    // colour segments of every row, grouped by colour
     std::vector<int32_t> cp32(C + 1);
     for (int c = 0; c <= C; ++c) cp32[c] = (int32_t)og.class_ptr_h[c];
     int32_t* cp = ws.take<int32_t>(C + 1);
-    int32_t* cnt = ws.take<int32_t>(C + 1);
+    int32_t* segp = ws.take<int32_t>(C + 1);
     int32_t* rec = ws.take<int32_t>(3 * (nnz + 1));
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp segments)");
-    GR_HIP(hipMemcpy(cp, cp32.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice));
-    GR_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (C + 1), st));
+    GR_HIP(hipMemcpyAsync(cp, cp32.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, st));
     std::vector<int64_t> seg_ptr(C + 1, 0);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_seg_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, og.g.row_ptr,
-                           og.g.col, n, (const int32_t*)cp, C, cnt);
-        GR_LAUNCHED("segment count");
-        std::vector<int32_t> hc(C);
-        GR_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * C, hipMemcpyDeviceToHost, st));
+    if (nnz > 0) {
+        size_t mark = ws.used;
+        int32_t* head = ws.take<int32_t>(nnz);
+        int32_t* hpos = ws.take<int32_t>(nnz + 1);
+        uint64_t* k0 = ws.take<uint64_t>(nnz);
+        uint32_t* v0 = ws.take<uint32_t>(nnz);
+        uint64_t* k1 = ws.take<uint64_t>(nnz);
+        uint32_t* v1 = ws.take<uint32_t>(nnz);
+        int32_t* hrow = ws.take<int32_t>(nnz);
+        int32_t* hstart = ws.take<int32_t>(nnz);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp segments)");
+        const unsigned wb = blocks_for(n * kWave, 256);
+        hipLaunchKernelGGL(k_seg_heads, dim3(wb), dim3(256), 0, st, og.g.row_ptr, og.g.col, n,
+                           (const int32_t*)cp, C, head);
+        GR_LAUNCHED("segment heads");
+        GR_TRY(scan_exclusive_i32(head, hpos, nnz, hpos + nnz, ws, st));
+        int32_t nh32 = 0;
+        GR_HIP(hipMemcpyAsync(&nh32, hpos + nnz, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
-        std::vector<int32_t> cur(C + 1);
-        for (int c = 0; c < C; ++c) {
-            seg_ptr[c + 1] = seg_ptr[c] + hc[c];
-            cur[c] = (int32_t)seg_ptr[c];
-        }
-        GR_HIP(hipMemcpy(cnt, cur.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(k_seg_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, og.g.row_ptr,
-                           og.g.col, n, (const int32_t*)cp, C, cnt, rec);
-        GR_LAUNCHED("segment fill");
+        const int64_t nh = nh32;
+        hipLaunchKernelGGL(k_seg_keys, dim3(wb), dim3(256), 0, st, og.g.row_ptr, og.g.col, n,
+                           (const int32_t*)cp, C, (const int32_t*)head, (const int32_t*)hpos, k0, v0,
+                           hrow, hstart);
+        GR_LAUNCHED("segment keys");
+        GR_TRY(radix_sort_pairs(k0, v0, k1, v1, nh, bits_for(C), ws, st));
+        hipLaunchKernelGGL(k_seg_records, dim3(blocks_for(nh, 256)), dim3(256), 0, st,
+                           (const uint32_t*)v1, nh, nnz, (const int32_t*)hrow,
+                           (const int32_t*)hstart, rec);
+        GR_LAUNCHED("segment records");
+        hipLaunchKernelGGL(k_seg_bounds, dim3(blocks_for(nh + 1, 256)), dim3(256), 0, st,
+                           (const uint64_t*)k1, nh, C, segp);
+        GR_LAUNCHED("segment bounds");
+        std::vector<int32_t> hs(C + 1);
+        GR_HIP(hipMemcpyAsync(hs.data(), segp, sizeof(int32_t) * (C + 1), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+        for (int c = 0; c <= C; ++c) seg_ptr[c] = hs[c];
+        ws.used = mark;
     }
     // states, adjoints, per-entry gradients
     const size_t xbytes = (size_t)n * K * (dtype == GR_BF16 ? 2 : 4);
     void* states = ws.take<char>((size_t)(store ? S + 1 : 3) * ((xbytes + 255) & ~size_t(255)));
     float* xbar = ws.take<float>((size_t)n * K + 4);
     float* H = ws.take<float>((size_t)n * K + 4);
+    float* dw = ws.take<float>(n + 1);
     float* ge = ws.take<float>(nnz + 1);
     int32_t* slots = ws.take<int32_t>(2 * (E + 1));
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp states)");
@@ -648,9 +775,14 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     GR_TRY(permute_rows(Gc, xbar, og.perm, n, (size_t)K * 4, 0, st));
     hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(nnz + 1, 256)), dim3(256), 0, st, ge, nnz + 1);
     GR_LAUNCHED("zero");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_row_weight, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
+                           og.g.row_ptr, og.g.w, n, dw);
+        GR_LAUNCHED("row weights");
+    }
     const int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
 #define GR_VJ(QQ, DD) \
-    case QQ: GR_TRY((vjp_impl<QQ, DD>(&og, rec, seg_ptr, K, S, store, states, xstride, xbar, H, ge, ws, st))); break;
+    case QQ: GR_TRY((vjp_impl<QQ, DD>(&og, rec, seg_ptr, K, S, store, states, xstride, dw, xbar, H, ge, ws, st))); break;
     if (dtype == GR_BF16) {
         switch (Q) {
             GR_VJ(1, GR_BF16) GR_VJ(2, GR_BF16) GR_VJ(4, GR_BF16) GR_VJ(8, GR_BF16)

@@ -147,6 +147,8 @@ struct OrderedGraph {
     std::vector<int64_t> tier_ptr_h;    // host [C*kNT+1]: row start of (class, tier)
     std::vector<int64_t> long_end_h;    // host [C]
     std::vector<int64_t> class_nnz_h;   // host [C]: stored entries per colour
+    std::vector<int64_t> class_e_h;     // host [C+1]: first entry of each colour
+    std::vector<int64_t> long_nnz_h;    // host [C]: entries of the colour's long rows
     int64_t n_long;      // long rows in all classes
     int32_t* long_rows;  // device [n_long]: their relabelled ids
     double mean_deg;

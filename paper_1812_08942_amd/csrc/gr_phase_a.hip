@@ -599,16 +599,18 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
     return colour_flow(g, seed, ldf, colours, n_colours_host, ws, st);
 }
 
+// a wave per row
 __global__ void k_check_colouring(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                   const int32_t* __restrict__ colours, int64_t n, int32_t nc,
                                   int32_t* bad) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (v >= n) return;
-    int32_t c = colours[v];
+    const int32_t c = colours[v];
     int f = 0;
     if (c < 0 || c >= nc) f = 1;
     else
-        for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave)
             if (colours[col[e]] == c) { f = 2; break; }
     if (f) atomicOr(bad, f);
 }
@@ -620,7 +622,7 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
     int32_t* bad = ws.take<int32_t>(1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small");
     GR_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_check_colouring, dim3(blocks_for(g->n, kThreads)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(k_check_colouring, dim3(blocks_for(g->n * kWave, kThreads)), dim3(kThreads), 0, st,
                        g->row_ptr, g->col, colours, g->n, n_colours, bad);
     GR_LAUNCHED("check colouring");
     int32_t hb = 0;
@@ -762,20 +764,27 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
     og->tier_ptr_h.assign((size_t)nb + 1, 0);
     og->long_end_h.assign((size_t)n_colours, 0);
     og->class_nnz_h.assign((size_t)n_colours, 0);
+    og->class_e_h.assign((size_t)n_colours + 1, 0);
+    og->long_nnz_h.assign((size_t)n_colours, 0);
     std::vector<int64_t> cls(2 * (size_t)n_colours + 2, 0);
     std::vector<int32_t> long_off(n_colours + 1, 0);
     int64_t total = 0, nlong = 0;
     for (int c = 0; c < n_colours; ++c) {
         og->class_ptr_h[c] = total;
-        int64_t nz = 0, lr = 0;
+        int64_t nz = 0, lr = 0, lz = 0;
         for (int t = 0; t < kNT; ++t) {
             const int b = c * kNT + t;
             og->tier_ptr_h[b] = total;
             total += hs[2 * b];
             nz += hs[2 * b + 1];
-            if (t < kLongTiers) lr += hs[2 * b];
+            if (t < kLongTiers) {
+                lr += hs[2 * b];
+                lz += hs[2 * b + 1];
+            }
         }
         og->class_nnz_h[c] = nz;
+        og->class_e_h[c + 1] = og->class_e_h[c] + nz;
+        og->long_nnz_h[c] = lz;
         og->long_end_h[c] = og->class_ptr_h[c] + lr;
         cls[2 * c] = og->class_ptr_h[c];
         cls[2 * c + 1] = lr;

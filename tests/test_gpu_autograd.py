@@ -158,12 +158,25 @@ def _vjp_case(g, K, dtype, store, seed=0):
     return gw.cpu().numpy(), gX.cpu().numpy(), rgw, rgX, (dg, el, cd, nc, X0d, Gc)
 
 
+def _wheel(n):
+    """A hub joined to every node of a cycle on n - 1 nodes (a plain star
+    would be degenerate: one sweep copies the hub into every leaf, and the
+    weight gradient is exactly zero)."""
+    v = np.arange(1, n)
+    u = np.concatenate([np.zeros(n - 1, np.int64), v])
+    t = np.concatenate([v, np.roll(v, -1)])
+    w = np.random.default_rng(4).uniform(0.5, 2.0, u.size).astype(np.float32)
+    return W.csr_from_edges(n, u, t, w, f"wheel{n}")
+
+
 def vjp_graphs():
     return {"er_30": W.random_weighted(30, 0.2, seed=3),
             "grid8_lognormal": W.grid2d(8, 8, "lognormal", 5),
             "knn_600": W.knn2d(600, 10, seed=6),
             "chunglu_3000": W.chung_lu(3000, mean_deg=40.0, seed=2),
-            "grid3d_6": W.grid3d(6, seed=1)}
+            "grid3d_6": W.grid3d(6, seed=1),
+            # one row of 2999 entries, spread over many workgroups
+            "wheel_3000": _wheel(3000)}
 
 
 @pytest.mark.parametrize("store", [True, False])
