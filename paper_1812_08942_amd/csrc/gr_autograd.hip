@@ -245,15 +245,26 @@ int rq_backward(int64_t E, const int32_t* eu, const int32_t* ev, const double* U
 // A colour step maps row i of colour c (d_i > 0) to x_i' = sum_j w_ij x_j / d_i
 // and leaves the other rows.  Its partial derivatives are
 // dx_i'/dw_ij = (x_j - x_i') / d_i and dx_i'/dx_j = w_ij / d_i, and x_i' does
-// not depend on the old x_i.  Undoing the steps in reverse order (sweeps
-// S..1, colours C-1..0), with g = the adjoint of x_i':
-//   wbar_ij += g . (x_j - x_i') / d_i          (kernel k_vjp_rows)
-//   xbar_j  += (w_ij / d_i) g  for j in N(i)   (kernel k_vjp_segs, gather form:
-//              each row j adds over its neighbours of colour c)
-//   xbar_i   = 0.
-// The state seen by step (s, c) is, in the colour-major order, rows of
-// colour < c from X_s and rows of colour >= c from X_{s-1}; so the sweep
-// boundary states X_0..X_S (stored, or recomputed from X_0) suffice.
+// not depend on the old x_i.  The steps are undone in reverse order (sweeps
+// S..1, colours C-1..0) in pull form.  Let g_i be the adjoint of the value
+// x_i^s that step (s, c) gives row i, and h_i = g_i / d_i.  That value is
+// read by the steps of sweep s with a larger colour and by the steps of
+// sweep s+1 with a smaller one, so
+//   g_i = [s = S] G_i + sum_{j in N(i)} w_ij h_j,
+// with h_j from sweep s when colour(j) > c and from sweep s+1 when
+// colour(j) < c.  One array H holds exactly that: in reverse order, step
+// (s, c) runs after the larger colours of sweep s have rewritten their rows
+// and before the smaller colours of sweep s replace their sweep-(s+1)
+// values (H starts at zero: there is no sweep S+1).  Then
+//   wbar_ij += h_i . (x_j - x_i')   for j in N(i),
+// and, once sweep 1 is undone, x_j^0 has been read only by the sweep-1 steps
+// of smaller colours:  gX0_j = sum_{i in N(j), colour(i) < colour(j)} w_ij h_i
+// (a row without neighbours keeps G_j).  The state seen by step (s, c) is, in
+// the colour-major order, rows of colour < c from X_s and rows of colour
+// >= c from X_{s-1}; so the sweep-boundary states X_0..X_S (stored, or
+// recomputed from X_0) suffice.  No value is accumulated by atomics and no
+// array is written by two steps of one launch (a colour class has no inner
+// edges).
 namespace gr {
 
 __global__ void k_perm_payload(const int32_t* __restrict__ rp, const uint32_t* __restrict__ perm,
@@ -265,98 +276,6 @@ __global__ void k_perm_payload(const int32_t* __restrict__ rp, const uint32_t* _
     int32_t v = (int32_t)perm[r];
     int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[r];
     for (int32_t e = e0 + lane; e < e1; e += kWave) out[o + (e - e0)] = in[e];
-}
-
-// keys (row, column) of the relabelled entries, to order each row by column
-__global__ void k_row_col_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               int64_t n, int cb, uint64_t* __restrict__ keys,
-                               uint32_t* __restrict__ vals) {
-    int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    int lane = threadIdx.x & (kWave - 1);
-    if (r >= n) return;
-    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) {
-        keys[e] = ((uint64_t)r << cb) | (uint64_t)col[e];
-        vals[e] = (uint32_t)e;
-    }
-}
-
-__global__ void k_gather3(const uint32_t* __restrict__ order, int64_t m,
-                          const int32_t* __restrict__ a, const float* __restrict__ b,
-                          const int32_t* __restrict__ c, int32_t* __restrict__ a2,
-                          float* __restrict__ b2, int32_t* __restrict__ c2) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    uint32_t o = order[i];
-    a2[i] = a[o];
-    b2[i] = b[o];
-    c2[i] = c[o];
-}
-
-__device__ inline int32_t class_of(const int32_t* __restrict__ cp, int32_t C, int32_t j) {
-    int32_t lo = 0, hi = C - 1;  // last c with cp[c] <= j
-    while (lo < hi) {
-        int32_t mid = (lo + hi + 1) >> 1;
-        if (cp[mid] <= j) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Segments: the maximal runs of one colour inside a column-sorted row. A row
-// of colour-contiguous columns holds at most one run per colour, and the runs
-// tile the entries in CSR order, so a run ends where the next one starts.
-// A wave per row marks the first entry of every run.
-__global__ void k_seg_heads(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            int64_t n, const int32_t* __restrict__ cp, int32_t C,
-                            int32_t* __restrict__ head) {
-    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (r >= n) return;
-    const int32_t e0 = rp[r], e1 = rp[r + 1];
-    for (int32_t e = e0 + lane; e < e1; e += kWave) {
-        const int32_t c = class_of(cp, C, col[e]);
-        head[e] = (e == e0 || col[e - 1] < cp[c]) ? 1 : 0;
-    }
-}
-
-// the run starting at entry e goes to slot hpos[e], keyed by its colour
-__global__ void k_seg_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           int64_t n, const int32_t* __restrict__ cp, int32_t C,
-                           const int32_t* __restrict__ head, const int32_t* __restrict__ hpos,
-                           uint64_t* __restrict__ key, uint32_t* __restrict__ val,
-                           int32_t* __restrict__ hrow, int32_t* __restrict__ hstart) {
-    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (r >= n) return;
-    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) {
-        if (!head[e]) continue;
-        const int32_t s = hpos[e];
-        key[s] = (uint64_t)class_of(cp, C, col[e]);
-        val[s] = (uint32_t)s;
-        hrow[s] = (int32_t)r;
-        hstart[s] = e;
-    }
-}
-
-// record k = the k-th run in (colour, entry) order: (row, first, end)
-__global__ void k_seg_records(const uint32_t* __restrict__ order, int64_t nh, int64_t nnz,
-                              const int32_t* __restrict__ hrow, const int32_t* __restrict__ hstart,
-                              int32_t* __restrict__ rec) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nh) return;
-    const uint32_t s = order[k];
-    rec[3 * k] = hrow[s];
-    rec[3 * k + 1] = hstart[s];
-    rec[3 * k + 2] = (int64_t)s + 1 < nh ? hstart[s + 1] : (int32_t)nnz;
-}
-
-// segp[c] = first record of colour c (colour-sorted keys); k runs over [0, nh]
-__global__ void k_seg_bounds(const uint64_t* __restrict__ skey, int64_t nh, int32_t C,
-                             int32_t* __restrict__ segp) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > nh) return;
-    const int32_t lo = k == 0 ? -1 : (int32_t)skey[k - 1];
-    const int32_t hi = k == nh ? C : (int32_t)skey[k];
-    for (int32_t c = lo + 1; c <= hi; ++c) segp[c] = (int32_t)k;
 }
 
 template <int E>
@@ -374,15 +293,28 @@ __device__ inline void store_f32(float* __restrict__ A, int64_t row, int K, int 
         *reinterpret_cast<float4*>(A + row * K + q * E + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
 }
 
-// rows [lo, hi) of colour c; L = Q*P lanes per row
-template <int Q, int P, int DT>
-__global__ void __launch_bounds__(256) k_vjp_rows(const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ col,
-                                                  const void* __restrict__ Xs,
-                                                  const void* __restrict__ Xp, int32_t K, int64_t clo,
-                                                  int64_t lo, int64_t hi, const float* __restrict__ dw,
-                                                  float* __restrict__ xbar, float* __restrict__ H,
-                                                  float* __restrict__ ge) {
+// d_i = sum_j w_ij, a wave per row; constant over the sweeps
+__global__ void k_row_weight(const int32_t* __restrict__ rp, const float* __restrict__ w, int64_t n,
+                             float* __restrict__ dw) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (r >= n) return;
+    float d = 0.0f;
+    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) d += w[e];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) d += __shfl_xor(d, off, kWave);
+    if (lane == 0) dw[r] = d;
+}
+
+// Rows [lo, hi) of colour c with degree <= kLongRow, L = Q*P lanes per row.
+// FINAL = 0: the reverse step (G = the cotangent in the last sweep, else
+// null).  FINAL = 1: gX0 of those rows into out.
+template <int Q, int P, int DT, int FINAL>
+__global__ void __launch_bounds__(256) k_vjp_rows(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const float* __restrict__ w,
+    const void* __restrict__ Xs, const void* __restrict__ Xp, int32_t K, int64_t clo, int64_t lo,
+    int64_t hi, const float* __restrict__ dw, const float* __restrict__ G, float* __restrict__ H,
+    float* __restrict__ ge, float* __restrict__ out) {
     constexpr int L = Q * P;
     constexpr int RPW = kWave / L;
     constexpr int E = Chunk<DT>::E;
@@ -394,61 +326,170 @@ __global__ void __launch_bounds__(256) k_vjp_rows(const int32_t* __restrict__ rp
     if (r >= hi) return;
     const int32_t e0 = rp[r], e1 = rp[r + 1];
     const float d = dw[r];
-    if (!(d > 0.0f)) return;  // no equation: the step leaves this row alone
-    float g[E], xi[E];
-    load_f32<E>(xbar, r, K, q, g);
-    Chunk<DT>::load(Xs, r, K, q, xi);
-    const int32_t trips = (e1 - e0 + P - 1) / P;
-    for (int32_t t = 0; t < trips; ++t) {
-        int32_t e = e0 + p + t * P;
-        bool ok = e < e1;
-        int32_t j = ok ? col[e] : (int32_t)r;
-        float xj[E];
-        Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj);
-        float s = 0.0f;
-#pragma unroll
-        for (int i = 0; i < E; ++i) s = __fmaf_rn(g[i], xj[i] - xi[i], s);
-        s = qsum<Q>(s);
-        if (ok && q == 0) ge[e] += s / d;
-    }
-    if (p == 0) {
-        float h[E], z[E];
-#pragma unroll
-        for (int i = 0; i < E; ++i) {
-            h[i] = g[i] / d;
-            z[i] = 0.0f;
+    if (!(d > 0.0f)) {  // no neighbours: no step changes this row
+        if (FINAL && p == 0) {
+            float gi[E];
+            load_f32<E>(G, r, K, q, gi);
+            store_f32<E>(out, r, K, q, gi);
         }
-        store_f32<E>(H, r, K, q, h);
-        store_f32<E>(xbar, r, K, q, z);
+        return;
+    }
+    float acc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc[i] = 0.0f;
+    for (int32_t e = e0 + p; e < e1; e += P) {
+        const int32_t j = col[e];
+        if (FINAL && j >= clo) continue;
+        float hj[E];
+        load_f32<E>(H, j, K, q, hj);
+        const float wt = w[e];
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt, hj[i], acc[i]);
+    }
+#pragma unroll
+    for (int off = Q; off < L; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
+    if constexpr (FINAL) {
+        if (p == 0) store_f32<E>(out, r, K, q, acc);
+    } else {
+        if (G) {
+            float gi[E];
+            load_f32<E>(G, r, K, q, gi);
+#pragma unroll
+            for (int i = 0; i < E; ++i) acc[i] += gi[i];
+        }
+        float h[E], xi[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) h[i] = acc[i] / d;
+        if (p == 0) store_f32<E>(H, r, K, q, h);
+        Chunk<DT>::load(Xs, r, K, q, xi);
+        const int32_t trips = (e1 - e0 + P - 1) / P;
+        for (int32_t t = 0; t < trips; ++t) {
+            const int32_t e = e0 + p + t * P;
+            const bool ok = e < e1;
+            const int32_t j = ok ? col[e] : (int32_t)r;
+            float xj[E];
+            Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj);
+            float s = 0.0f;
+#pragma unroll
+            for (int i = 0; i < E; ++i) s = __fmaf_rn(h[i], xj[i] - xi[i], s);
+            s = qsum<Q>(s);
+            if (ok && q == 0) ge[e] += s;
+        }
     }
 }
 
 // The rows of degree above kLongRow (the colour's first rows: its degree
-// tiers come in decreasing order) take two launches, so that a hub row is
-// spread over many workgroups: the first sets H_i = xbar_i / d_i and clears
-// xbar_i, then every entry of those rows, Q lanes each, adds
-// H_i . (x_j - x_i) to its gradient.  Weights are positive, so d_i > 0.
-template <int Q, int DT>
-__global__ void k_vjp_long_rows(const float* __restrict__ dw, int32_t K, int64_t lo, int64_t hi,
-                                float* __restrict__ xbar, float* __restrict__ H) {
+// tiers come in decreasing order) are cut into pieces of kPiece entries, so
+// that a hub row is spread over many workgroups.  Three launches: the
+// partial sums of w_ij h_j of every piece; per row, g_i from its pieces in
+// order and h_i = g_i / d_i into H; then every entry of those rows, Q lanes
+// each, adds h_i . (x_j - x_i) to its gradient.  Weights are positive, so
+// d_i > 0 on these rows.
+constexpr int kPiece = 256;
+
+__global__ void k_piece_counts(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ cnt) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t deg = rp[r + 1] - rp[r];
+    cnt[r] = deg > kLongRow ? (deg + kPiece - 1) / kPiece : 0;
+}
+
+__global__ void k_gather_i32(const int32_t* __restrict__ src, const int64_t* __restrict__ idx,
+                             int64_t m, int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) out[i] = src[idx[i]];
+}
+
+// pieces [pbeg, pbeg + gridDim.x) of the long rows [lo, hi); FINAL: only
+// neighbours j < clo count
+template <int Q, int DT, int FINAL>
+__global__ void __launch_bounds__(256) k_vjp_pieces(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const float* __restrict__ w,
+    const float* __restrict__ H, int32_t K, const int32_t* __restrict__ ppos, int64_t lo,
+    int64_t hi, int64_t pbeg, int64_t clo, float* __restrict__ part) {
+    constexpr int P = 256 / Q;
+    constexpr int NW = 256 / kWave;
+    constexpr int E = Chunk<DT>::E;
+    __shared__ float red[NW * Q * E];
+    const int tid = threadIdx.x;
+    const int p = tid / Q, q = tid % Q;
+    const int64_t k = pbeg + blockIdx.x;
+    int64_t a = lo, b = hi - 1;  // the row of piece k: last r with ppos[r] <= k
+    while (a < b) {
+        const int64_t m = (a + b + 1) >> 1;
+        if (ppos[m] <= k) a = m; else b = m - 1;
+    }
+    const int64_t r = a;
+    const int32_t e0 = rp[r] + (int32_t)(k - ppos[r]) * kPiece;
+    const int32_t e1 = min(e0 + kPiece, rp[r + 1]);
+    float acc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) acc[i] = 0.0f;
+    for (int32_t e = e0 + p; e < e1; e += P) {
+        const int32_t j = col[e];
+        if (FINAL && j >= clo) continue;
+        float hj[E];
+        load_f32<E>(H, j, K, q, hj);
+        const float wt = w[e];
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt, hj[i], acc[i]);
+    }
+#pragma unroll
+    for (int off = Q; off < kWave; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
+    if ((tid & (kWave - 1)) < Q)
+#pragma unroll
+        for (int i = 0; i < E; ++i) red[(tid / kWave) * Q * E + q * E + i] = acc[i];
+    __syncthreads();
+    if (tid < Q) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[i] = red[q * E + i];
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww)
+#pragma unroll
+            for (int i = 0; i < E; ++i) acc[i] += red[ww * Q * E + q * E + i];
+        store_f32<E>(part, k, K, q, acc);
+    }
+}
+
+// a thread per (row, chunk) of the long rows [lo, hi): FINAL = 0: h_i into
+// H (G as in k_vjp_rows); FINAL = 1: gX0_i into out
+template <int Q, int DT, int FINAL>
+__global__ void k_vjp_long_rows(const int32_t* __restrict__ ppos, const float* __restrict__ dw,
+                                const float* __restrict__ G, const float* __restrict__ part,
+                                int32_t K, int64_t lo, int64_t hi, float* __restrict__ out) {
     constexpr int E = Chunk<DT>::E;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t r = lo + t / Q;
     const int q = (int)(t % Q);
     if (r >= hi) return;
-    const float d = dw[r];
-    float h[E], z[E];
-    load_f32<E>(xbar, r, K, q, h);
+    float g[E];
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        h[i] = h[i] / d;
-        z[i] = 0.0f;
+    for (int i = 0; i < E; ++i) g[i] = 0.0f;
+    for (int32_t k = ppos[r]; k < ppos[r + 1]; ++k) {
+        float v[E];
+        load_f32<E>(part, k, K, q, v);
+#pragma unroll
+        for (int i = 0; i < E; ++i) g[i] += v[i];
     }
-    store_f32<E>(H, r, K, q, h);
-    store_f32<E>(xbar, r, K, q, z);
+    if constexpr (!FINAL) {
+        if (G) {
+            float gi[E];
+            load_f32<E>(G, r, K, q, gi);
+#pragma unroll
+            for (int i = 0; i < E; ++i) g[i] += gi[i];
+        }
+        const float d = dw[r];
+#pragma unroll
+        for (int i = 0; i < E; ++i) g[i] = g[i] / d;
+    }
+    store_f32<E>(out, r, K, q, g);
 }
 
-// entries [rp[lo], rp[hi]) of the long rows [lo, hi)
+// entries [ebeg, eend) = those of the long rows [lo, hi)
 template <int Q, int DT>
 __global__ void __launch_bounds__(256) k_vjp_long_edges(
     const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const void* __restrict__ Xs,
@@ -474,58 +515,6 @@ __global__ void __launch_bounds__(256) k_vjp_long_edges(
     for (int i = 0; i < E; ++i) s = __fmaf_rn(h[i], xj[i] - xi[i], s);
     s = qsum<Q>(s);
     if (q == 0) ge[e] += s;
-}
-
-// d_i = sum_j w_ij, a wave per row; constant over the sweeps
-__global__ void k_row_weight(const int32_t* __restrict__ rp, const float* __restrict__ w, int64_t n,
-                             float* __restrict__ dw) {
-    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (r >= n) return;
-    float d = 0.0f;
-    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) d += w[e];
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) d += __shfl_xor(d, off, kWave);
-    if (lane == 0) dw[r] = d;
-}
-
-// one row-group per segment (row j, entries [a, b) whose columns have colour c)
-template <int Q, int P, int E>
-__global__ void __launch_bounds__(256) k_vjp_segs(const int32_t* __restrict__ rec, int64_t nrec,
-                                                  const int32_t* __restrict__ col,
-                                                  const float* __restrict__ w,
-                                                  const float* __restrict__ H, int32_t K,
-                                                  float* __restrict__ xbar) {
-    constexpr int L = Q * P;
-    constexpr int RPW = kWave / L;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int l = lane % L;
-    const int p = l / Q, q = l % Q;
-    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kWave;
-    const int64_t k = wave * RPW + lane / L;
-    if (k >= nrec) return;
-    const int32_t row = rec[3 * k], a = rec[3 * k + 1], b = rec[3 * k + 2];
-    float acc[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) acc[i] = 0.0f;
-    for (int32_t e = a + p; e < b; e += P) {
-        float h[E];
-        load_f32<E>(H, col[e], K, q, h);
-        const float wt = w[e];
-#pragma unroll
-        for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt, h[i], acc[i]);
-    }
-#pragma unroll
-    for (int off = Q; off < L; off <<= 1)
-#pragma unroll
-        for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
-    if (p == 0) {
-        float x[E];
-        load_f32<E>(xbar, row, K, q, x);
-#pragma unroll
-        for (int i = 0; i < E; ++i) x[i] += acc[i];
-        store_f32<E>(xbar, row, K, q, x);
-    }
 }
 
 // the two relabelled entries of each undirected edge: slot 0 = the entry
@@ -561,20 +550,50 @@ static int pick_p_vjp(int Q, double mean_deg) {
     return P;
 }
 
-template <int Q, int DT>
-static int vjp_launch_rows(int P, const gr_graph* g, const void* Xs, const void* Xp, int K,
-                           int64_t clo, int64_t lo, int64_t hi, const float* dw, float* xbar,
-                           float* H, float* ge, hipStream_t st) {
-    if (hi <= lo) return GR_OK;
-    const int64_t waves = ((hi - lo) * Q * P + kWave - 1) / kWave;
+// What the launches of one colour need, fixed for the whole call.
+struct VjpPlan {
+    const OrderedGraph* og;
+    const float* dw;
+    const int32_t* ppos;
+    std::vector<int64_t> pbeg, pend;  // the pieces of each colour's long rows
+    std::vector<int> P;               // lanes per row (x Q) for its short rows
+    float* part;
+};
+
+template <int Q, int DT, int FINAL>
+static int vjp_colour(const VjpPlan& pl, int c, const void* Xs, const void* Xp, int K,
+                      const float* G, float* H, float* ge, float* out, hipStream_t st) {
+    const OrderedGraph* og = pl.og;
+    const gr_graph* g = &og->g;
+    const int64_t clo = og->class_ptr_h[c], chi = og->class_ptr_h[c + 1];
+    const int64_t mid = og->long_end_h[c];
+    if (mid > clo && pl.pend[c] > pl.pbeg[c]) {
+        hipLaunchKernelGGL((k_vjp_pieces<Q, DT, FINAL>), dim3((unsigned)(pl.pend[c] - pl.pbeg[c])),
+                           dim3(256), 0, st, g->row_ptr, g->col, g->w, (const float*)H, K, pl.ppos,
+                           clo, mid, pl.pbeg[c], clo, pl.part);
+        GR_LAUNCHED("vjp pieces");
+        hipLaunchKernelGGL((k_vjp_long_rows<Q, DT, FINAL>), dim3(blocks_for((mid - clo) * Q, 256)),
+                           dim3(256), 0, st, pl.ppos, pl.dw, G, (const float*)pl.part, K, clo, mid,
+                           FINAL ? out : H);
+        GR_LAUNCHED("vjp long rows");
+        if constexpr (!FINAL) {
+            const int64_t ebeg = og->class_e_h[c], eend = ebeg + og->long_nnz_h[c];
+            hipLaunchKernelGGL((k_vjp_long_edges<Q, DT>), dim3(blocks_for((eend - ebeg) * Q, 256)),
+                               dim3(256), 0, st, g->row_ptr, g->col, Xs, Xp, K, clo, clo, mid, ebeg,
+                               eend, (const float*)H, ge);
+            GR_LAUNCHED("vjp long edges");
+        }
+    }
+    if (chi <= mid) return GR_OK;
+    const int64_t waves = ((chi - mid) * Q * pl.P[c] + kWave - 1) / kWave;
     dim3 grid(blocks_for(waves * kWave, 256));
-#define GR_VR(PP)                                                                                \
-    case PP:                                                                                    \
-        if constexpr (Q * PP <= kWave)                                                          \
-            hipLaunchKernelGGL((k_vjp_rows<Q, PP, DT>), grid, dim3(256), 0, st, g->row_ptr, g->col, \
-                               Xs, Xp, K, clo, lo, hi, dw, xbar, H, ge);                         \
+#define GR_VR(PP)                                                                                   \
+    case PP:                                                                                       \
+        if constexpr (Q * PP <= kWave)                                                             \
+            hipLaunchKernelGGL((k_vjp_rows<Q, PP, DT, FINAL>), grid, dim3(256), 0, st, g->row_ptr,  \
+                               g->col, g->w, Xs, Xp, K, clo, mid, chi, pl.dw, G, H, ge, out);      \
         break;
-    switch (P) {
+    switch (pl.P[c]) {
         GR_VR(1) GR_VR(2) GR_VR(4) GR_VR(8) GR_VR(16) GR_VR(32) GR_VR(64)
         default: return set_error(GR_EINVAL, "bad lane split");
     }
@@ -583,55 +602,27 @@ static int vjp_launch_rows(int P, const gr_graph* g, const void* Xs, const void*
     return GR_OK;
 }
 
-template <int Q, int E>
-static int vjp_launch_segs(int P, const int32_t* rec, int64_t nrec, const gr_graph* g,
-                           const float* H, int K, float* xbar, hipStream_t st) {
-    if (nrec <= 0) return GR_OK;
-    const int64_t waves = (nrec * Q * P + kWave - 1) / kWave;
-    dim3 grid(blocks_for(waves * kWave, 256));
-#define GR_VS(PP)                                                                                 \
-    case PP:                                                                                     \
-        if constexpr (Q * PP <= kWave)                                                           \
-            hipLaunchKernelGGL((k_vjp_segs<Q, PP, E>), grid, dim3(256), 0, st, rec, nrec, g->col,  \
-                               g->w, H, K, xbar);                                                 \
-        break;
-    switch (P) {
-        GR_VS(1) GR_VS(2) GR_VS(4) GR_VS(8) GR_VS(16) GR_VS(32) GR_VS(64)
-        default: return set_error(GR_EINVAL, "bad lane split");
-    }
-#undef GR_VS
-    GR_LAUNCHED("vjp segments");
-    return GR_OK;
-}
-
 size_t vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t S, int32_t store) {
     const size_t N = (size_t)n + 1, M = (size_t)nnz + 1;
     const size_t xb = N * (size_t)K * (dtype == GR_BF16 ? 2 : 4) + 256;
     const size_t fb = N * (size_t)K * 4 + 256;
+    const size_t pieces = M / kPiece + M / kLongRow + 1;
     size_t b = 4 * N * 3 + 8 * M          // relabelled graph
-               + 12 * M                   // column-sorted col / w / eoe
-               + 12 * M                   // segment records
+               + 4 * M                    // relabelled edge ids
                + 4 * M                    // per-entry gradients
                + 8 * (M / 2 + 1)          // edge slots
-               + (size_t)(store ? S + 1 : 3) * xb + 2 * fb  // states, xbar, H
-               + 4 * N                    // weighted degrees
-               + 48 * M + 64 * N;         // sort / relabel / segment temporaries
+               + (size_t)(store ? S + 1 : 3) * xb + 3 * fb  // states, G, H, gX0
+               + 12 * N                   // weighted degrees, piece offsets and counts
+               + pieces * (size_t)K * 4   // piece sums
+               + 48 * M + 64 * N;         // sort / relabel temporaries
     return b + b / 16 + (16u << 20);
 }
 
 template <int Q, int DT>
-static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vector<int64_t>& seg_ptr,
-                    int K, int S, int store, void* states, size_t xbytes, const float* dw, float* xbar,
-                    float* H, float* ge, Arena& ws, hipStream_t st) {
-    constexpr int E = Chunk<DT>::E;
+static int vjp_impl(const VjpPlan& pl, int K, int S, int store, void* states, size_t xbytes,
+                    const float* Gp, float* H, float* ge, float* gx, Arena& ws, hipStream_t st) {
+    const OrderedGraph* og = pl.og;
     const int C = og->n_colours;
-    std::vector<int> Prow(C), Pseg(C);
-    for (int c = 0; c < C; ++c) {
-        int64_t rows = og->class_ptr_h[c + 1] - og->class_ptr_h[c];
-        Prow[c] = pick_p_vjp(Q, rows > 0 ? (double)og->class_nnz_h[c] / (double)rows : 1.0);
-        int64_t ns = seg_ptr[c + 1] - seg_ptr[c];
-        Pseg[c] = pick_p_vjp(Q, ns > 0 ? (double)og->class_nnz_h[c] / (double)ns : 1.0);
-    }
     char* base = (char*)states;
     auto state = [&](int s) { return (void*)(base + (size_t)s * xbytes); };
     // states: store mode keeps X_0..X_S; recompute mode keeps X_0 in slot 0
@@ -655,26 +646,13 @@ static int vjp_impl(const OrderedGraph* og, const int32_t* rec, const std::vecto
             Xs = state(2);
             Xp = state(1);
         }
-        for (int c = C - 1; c >= 0; --c) {
-            const int64_t clo = og->class_ptr_h[c], chi = og->class_ptr_h[c + 1];
-            const int64_t mid = og->tier_ptr_h[(size_t)c * kNT + kLongTiers];  // end of long rows
-            if (mid > clo) {
-                hipLaunchKernelGGL((k_vjp_long_rows<Q, DT>), dim3(blocks_for((mid - clo) * Q, 256)),
-                                   dim3(256), 0, st, dw, K, clo, mid, xbar, H);
-                GR_LAUNCHED("vjp long rows");
-                const int64_t ebeg = og->class_e_h[c], eend = ebeg + og->long_nnz_h[c];
-                hipLaunchKernelGGL((k_vjp_long_edges<Q, DT>),
-                                   dim3(blocks_for((eend - ebeg) * Q, 256)), dim3(256), 0, st,
-                                   og->g.row_ptr, og->g.col, Xs, Xp, K, clo, clo, mid, ebeg, eend,
-                                   (const float*)H, ge);
-                GR_LAUNCHED("vjp long edges");
-            }
-            GR_TRY((vjp_launch_rows<Q, DT>(Prow[c], &og->g, Xs, Xp, K, clo, mid, chi, dw, xbar, H,
-                                           ge, st)));
-            GR_TRY((vjp_launch_segs<Q, E>(Pseg[c], rec + 3 * seg_ptr[c], seg_ptr[c + 1] - seg_ptr[c],
-                                          &og->g, H, K, xbar, st)));
-        }
+        const float* G = s == S ? Gp : nullptr;
+        for (int c = C - 1; c >= 0; --c)
+            GR_TRY((vjp_colour<Q, DT, 0>(pl, c, Xs, Xp, K, G, H, ge, nullptr, st)));
     }
+    if (S >= 1)
+        for (int c = 0; c < C; ++c)
+            GR_TRY((vjp_colour<Q, DT, 1>(pl, c, nullptr, nullptr, K, Gp, H, nullptr, gx, st)));
     return GR_OK;
 }
 
@@ -685,104 +663,80 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     GR_TRY(validate_colouring(g, colours, C, ws, st));
     OrderedGraph og;
     GR_TRY(order_by_colour(g, colours, C, &og, ws, st));
-    // per-entry edge ids in the relabelled order, then each row by column
+    // edge ids of the relabelled entries, weighted degrees, long-row pieces
     int32_t* eoe_r = ws.take<int32_t>(nnz + 1);
-    int32_t* col_s = ws.take<int32_t>(nnz + 1);
-    float* w_s = ws.take<float>(nnz + 1);
-    int32_t* eoe_s = ws.take<int32_t>(nnz + 1);
+    float* dw = ws.take<float>(n + 1);
+    int32_t* ppos = ws.take<int32_t>(n + 1);
+    int32_t* pbounds = ws.take<int32_t>(2 * (size_t)C + 1);
+    int64_t* pidx = ws.take<int64_t>(2 * (size_t)C + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp)");
     if (nnz > 0) {
-        size_t mark = ws.used;
-        uint64_t* k0 = ws.take<uint64_t>(nnz);
-        uint32_t* v0 = ws.take<uint32_t>(nnz);
-        uint64_t* k1 = ws.take<uint64_t>(nnz);
-        uint32_t* v1 = ws.take<uint32_t>(nnz);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp sort)");
-        const unsigned wb = blocks_for(n * kWave, 256);
-        hipLaunchKernelGGL(k_perm_payload, dim3(wb), dim3(256), 0, st, g->row_ptr,
-                           (const uint32_t*)og.perm, og.g.row_ptr, n, eoe, eoe_r);
+        hipLaunchKernelGGL(k_perm_payload, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
+                           g->row_ptr, (const uint32_t*)og.perm, og.g.row_ptr, n, eoe, eoe_r);
         GR_LAUNCHED("perm payload");
-        const int cb = bits_for(n);
-        hipLaunchKernelGGL(k_row_col_keys, dim3(wb), dim3(256), 0, st, og.g.row_ptr, og.g.col, n, cb,
-                           k0, v0);
-        GR_LAUNCHED("row col keys");
-        GR_TRY(radix_sort_pairs(k0, v0, k1, v1, nnz, 2 * cb, ws, st));
-        hipLaunchKernelGGL(k_gather3, dim3(blocks_for(nnz, 256)), dim3(256), 0, st, (const uint32_t*)v1,
-                           nnz, og.g.col, og.g.w, (const int32_t*)eoe_r, col_s, w_s, eoe_s);
-        GR_LAUNCHED("gather sorted rows");
-        ws.used = mark;
     }
-    og.g.col = col_s;
-    og.g.w = w_s;
-    // colour segments of every row, grouped by colour
-    std::vector<int32_t> cp32(C + 1);
-    for (int c = 0; c <= C; ++c) cp32[c] = (int32_t)og.class_ptr_h[c];
-    int32_t* cp = ws.take<int32_t>(C + 1);
-    int32_t* segp = ws.take<int32_t>(C + 1);
-    int32_t* rec = ws.take<int32_t>(3 * (nnz + 1));
-    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp segments)");
-    GR_HIP(hipMemcpyAsync(cp, cp32.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, st));
-    std::vector<int64_t> seg_ptr(C + 1, 0);
-    if (nnz > 0) {
+    hipLaunchKernelGGL(k_row_weight, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st, og.g.row_ptr,
+                       og.g.w, n, dw);
+    GR_LAUNCHED("row weights");
+    {
         size_t mark = ws.used;
-        int32_t* head = ws.take<int32_t>(nnz);
-        int32_t* hpos = ws.take<int32_t>(nnz + 1);
-        uint64_t* k0 = ws.take<uint64_t>(nnz);
-        uint32_t* v0 = ws.take<uint32_t>(nnz);
-        uint64_t* k1 = ws.take<uint64_t>(nnz);
-        uint32_t* v1 = ws.take<uint32_t>(nnz);
-        int32_t* hrow = ws.take<int32_t>(nnz);
-        int32_t* hstart = ws.take<int32_t>(nnz);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp segments)");
-        const unsigned wb = blocks_for(n * kWave, 256);
-        hipLaunchKernelGGL(k_seg_heads, dim3(wb), dim3(256), 0, st, og.g.row_ptr, og.g.col, n,
-                           (const int32_t*)cp, C, head);
-        GR_LAUNCHED("segment heads");
-        GR_TRY(scan_exclusive_i32(head, hpos, nnz, hpos + nnz, ws, st));
-        int32_t nh32 = 0;
-        GR_HIP(hipMemcpyAsync(&nh32, hpos + nnz, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));
-        const int64_t nh = nh32;
-        hipLaunchKernelGGL(k_seg_keys, dim3(wb), dim3(256), 0, st, og.g.row_ptr, og.g.col, n,
-                           (const int32_t*)cp, C, (const int32_t*)head, (const int32_t*)hpos, k0, v0,
-                           hrow, hstart);
-        GR_LAUNCHED("segment keys");
-        GR_TRY(radix_sort_pairs(k0, v0, k1, v1, nh, bits_for(C), ws, st));
-        hipLaunchKernelGGL(k_seg_records, dim3(blocks_for(nh, 256)), dim3(256), 0, st,
-                           (const uint32_t*)v1, nh, nnz, (const int32_t*)hrow,
-                           (const int32_t*)hstart, rec);
-        GR_LAUNCHED("segment records");
-        hipLaunchKernelGGL(k_seg_bounds, dim3(blocks_for(nh + 1, 256)), dim3(256), 0, st,
-                           (const uint64_t*)k1, nh, C, segp);
-        GR_LAUNCHED("segment bounds");
-        std::vector<int32_t> hs(C + 1);
-        GR_HIP(hipMemcpyAsync(hs.data(), segp, sizeof(int32_t) * (C + 1), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));
-        for (int c = 0; c <= C; ++c) seg_ptr[c] = hs[c];
+        int32_t* cnt = ws.take<int32_t>(n);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp pieces)");
+        hipLaunchKernelGGL(k_piece_counts, dim3(blocks_for(n, 256)), dim3(256), 0, st, og.g.row_ptr,
+                           n, cnt);
+        GR_LAUNCHED("piece counts");
+        GR_TRY(scan_exclusive_i32(cnt, ppos, n, ppos + n, ws, st));
         ws.used = mark;
     }
-    // states, adjoints, per-entry gradients
+    // piece ranges of every colour's long rows [class start, long end), and the total
+    std::vector<int64_t> hidx(2 * (size_t)C + 1);
+    for (int c = 0; c < C; ++c) {
+        hidx[2 * c] = og.class_ptr_h[c];
+        hidx[2 * c + 1] = og.long_end_h[c];
+    }
+    hidx[2 * C] = n;
+    std::vector<int32_t> hpb(2 * (size_t)C + 1);
+    GR_HIP(hipMemcpyAsync(pidx, hidx.data(), sizeof(int64_t) * hidx.size(), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_i32, dim3(blocks_for(2 * C + 1, 256)), dim3(256), 0, st,
+                       (const int32_t*)ppos, (const int64_t*)pidx, (int64_t)(2 * C + 1), pbounds);
+    GR_LAUNCHED("piece bounds");
+    GR_HIP(hipMemcpyAsync(hpb.data(), pbounds, sizeof(int32_t) * hpb.size(), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    const int64_t n_pieces = hpb[2 * C];
+    VjpPlan pl;
+    pl.og = &og;
+    pl.dw = dw;
+    pl.ppos = ppos;
+    pl.pbeg.resize(C);
+    pl.pend.resize(C);
+    pl.P.resize(C);
+    const int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
+    for (int c = 0; c < C; ++c) {
+        pl.pbeg[c] = hpb[2 * c];
+        pl.pend[c] = hpb[2 * c + 1];
+        const int64_t rows = og.class_ptr_h[c + 1] - og.long_end_h[c];
+        const int64_t nz = og.class_nnz_h[c] - og.long_nnz_h[c];
+        pl.P[c] = pick_p_vjp(Q, rows > 0 ? (double)nz / (double)rows : 1.0);
+    }
+    pl.part = ws.take<float>((size_t)(n_pieces + 1) * K);
+    // states, cotangent, H, gX0 (relabelled), per-entry gradients
     const size_t xbytes = (size_t)n * K * (dtype == GR_BF16 ? 2 : 4);
-    void* states = ws.take<char>((size_t)(store ? S + 1 : 3) * ((xbytes + 255) & ~size_t(255)));
-    float* xbar = ws.take<float>((size_t)n * K + 4);
+    const size_t xstride = (xbytes + 255) & ~size_t(255);
+    void* states = ws.take<char>((size_t)(store ? S + 1 : 3) * xstride);
+    float* Gp = ws.take<float>((size_t)n * K + 4);
     float* H = ws.take<float>((size_t)n * K + 4);
-    float* dw = ws.take<float>(n + 1);
+    float* gx = ws.take<float>((size_t)n * K + 4);
     float* ge = ws.take<float>(nnz + 1);
     int32_t* slots = ws.take<int32_t>(2 * (E + 1));
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp states)");
-    const size_t xstride = (xbytes + 255) & ~size_t(255);
     GR_TRY(permute_rows(X0, states, og.perm, n, (size_t)K * (dtype == GR_BF16 ? 2 : 4), 0, st));
-    GR_TRY(permute_rows(Gc, xbar, og.perm, n, (size_t)K * 4, 0, st));
+    GR_TRY(permute_rows(Gc, Gp, og.perm, n, (size_t)K * 4, 0, st));
+    hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(n * K, 256)), dim3(256), 0, st, H, (int64_t)n * K);
+    GR_LAUNCHED("zero");
     hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(nnz + 1, 256)), dim3(256), 0, st, ge, nnz + 1);
     GR_LAUNCHED("zero");
-    if (n > 0) {
-        hipLaunchKernelGGL(k_row_weight, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
-                           og.g.row_ptr, og.g.w, n, dw);
-        GR_LAUNCHED("row weights");
-    }
-    const int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
 #define GR_VJ(QQ, DD) \
-    case QQ: GR_TRY((vjp_impl<QQ, DD>(&og, rec, seg_ptr, K, S, store, states, xstride, dw, xbar, H, ge, ws, st))); break;
+    case QQ: GR_TRY((vjp_impl<QQ, DD>(pl, K, S, store, states, xstride, Gp, H, ge, gx, ws, st))); break;
     if (dtype == GR_BF16) {
         switch (Q) {
             GR_VJ(1, GR_BF16) GR_VJ(2, GR_BF16) GR_VJ(4, GR_BF16) GR_VJ(8, GR_BF16)
@@ -795,12 +749,13 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
         }
     }
 #undef GR_VJ
-    GR_TRY(permute_rows(xbar, gX0, og.perm, n, (size_t)K * 4, 1, st));
+    // no sweep: X_S = X0 and the cotangent passes through
+    GR_TRY(permute_rows(S >= 1 ? gx : Gp, gX0, og.perm, n, (size_t)K * 4, 1, st));
     if (E > 0) {
         GR_TRY(fill_i32(slots, 0, 2 * E, st));  // unmatched slots read entry 0, never garbage
         GR_TRY(reset_bad_edge_flag(st));
         hipLaunchKernelGGL(k_edge_slots, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
-                           og.g.row_ptr, og.g.col, (const int32_t*)eoe_s, og.perm, n, E, slots);
+                           og.g.row_ptr, og.g.col, (const int32_t*)eoe_r, og.perm, n, E, slots);
         GR_LAUNCHED("edge slots");
         GR_TRY(check_bad_edge_flag(st));
         hipLaunchKernelGGL(k_edge_grad, dim3(blocks_for(E, 256)), dim3(256), 0, st,
