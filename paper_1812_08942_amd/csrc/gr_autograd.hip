@@ -382,11 +382,10 @@ __global__ void __launch_bounds__(256) k_vjp_rows(
 
 // The rows of degree above kLongRow (the colour's first rows: its degree
 // tiers come in decreasing order) are cut into pieces of kPiece entries, so
-// that a hub row is spread over many workgroups.  Three launches: the
-// partial sums of w_ij h_j of every piece; per row, g_i from its pieces in
-// order and h_i = g_i / d_i into H; then every entry of those rows, Q lanes
-// each, adds h_i . (x_j - x_i) to its gradient.  Weights are positive, so
-// d_i > 0 on these rows.
+// that a hub row is spread over many workgroups.  Two launches: the partial
+// sums of w_ij h_j of every piece, then a workgroup per piece that forms
+// h_i = g_i / d_i and applies it to the piece's entries.  Weights are
+// positive, so d_i > 0 on these rows.
 constexpr int kPiece = 256;
 
 __global__ void k_piece_counts(const int32_t* __restrict__ rp, int64_t n, int32_t* __restrict__ cnt) {
@@ -400,6 +399,17 @@ __global__ void k_gather_i32(const int32_t* __restrict__ src, const int64_t* __r
                              int64_t m, int32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) out[i] = src[idx[i]];
+}
+
+// the row of piece k among the long rows [lo, hi): last r with ppos[r] <= k
+__device__ inline int64_t piece_row(const int32_t* __restrict__ ppos, int64_t lo, int64_t hi,
+                                    int64_t k) {
+    int64_t a = lo, b = hi - 1;
+    while (a < b) {
+        const int64_t m = (a + b + 1) >> 1;
+        if (ppos[m] <= k) a = m; else b = m - 1;
+    }
+    return a;
 }
 
 // pieces [pbeg, pbeg + gridDim.x) of the long rows [lo, hi); FINAL: only
@@ -416,12 +426,7 @@ __global__ void __launch_bounds__(256) k_vjp_pieces(
     const int tid = threadIdx.x;
     const int p = tid / Q, q = tid % Q;
     const int64_t k = pbeg + blockIdx.x;
-    int64_t a = lo, b = hi - 1;  // the row of piece k: last r with ppos[r] <= k
-    while (a < b) {
-        const int64_t m = (a + b + 1) >> 1;
-        if (ppos[m] <= k) a = m; else b = m - 1;
-    }
-    const int64_t r = a;
+    const int64_t r = piece_row(ppos, lo, hi, k);
     const int32_t e0 = rp[r] + (int32_t)(k - ppos[r]) * kPiece;
     const int32_t e1 = min(e0 + kPiece, rp[r + 1]);
     float acc[E];
@@ -455,12 +460,67 @@ __global__ void __launch_bounds__(256) k_vjp_pieces(
     }
 }
 
-// a thread per (row, chunk) of the long rows [lo, hi): FINAL = 0: h_i into
-// H (G as in k_vjp_rows); FINAL = 1: gX0_i into out
-template <int Q, int DT, int FINAL>
-__global__ void k_vjp_long_rows(const int32_t* __restrict__ ppos, const float* __restrict__ dw,
-                                const float* __restrict__ G, const float* __restrict__ part,
-                                int32_t K, int64_t lo, int64_t hi, float* __restrict__ out) {
+// a workgroup per piece: h_i of its row from the row's pieces in order (plus
+// G_i in the last sweep) over d_i, stored into H by the row's first piece;
+// then every entry of the piece, Q lanes each, adds h_i . (x_j - x_i) to its
+// gradient
+template <int Q, int DT>
+__global__ void __launch_bounds__(256) k_vjp_long_apply(
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const void* __restrict__ Xs,
+    const void* __restrict__ Xp, int32_t K, int64_t clo, const int32_t* __restrict__ ppos,
+    int64_t lo, int64_t hi, int64_t pbeg, const float* __restrict__ dw,
+    const float* __restrict__ G, const float* __restrict__ part, float* __restrict__ H,
+    float* __restrict__ ge) {
+    constexpr int P = 256 / Q;
+    constexpr int E = Chunk<DT>::E;
+    const int tid = threadIdx.x;
+    const int p = tid / Q, q = tid % Q;
+    const int64_t k = pbeg + blockIdx.x;
+    const int64_t r = piece_row(ppos, lo, hi, k);
+    const int32_t k0 = ppos[r], k1 = ppos[r + 1];
+    float h[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) h[i] = 0.0f;
+    for (int32_t kk = k0; kk < k1; ++kk) {
+        float v[E];
+        load_f32<E>(part, kk, K, q, v);
+#pragma unroll
+        for (int i = 0; i < E; ++i) h[i] += v[i];
+    }
+    if (G) {
+        float gi[E];
+        load_f32<E>(G, r, K, q, gi);
+#pragma unroll
+        for (int i = 0; i < E; ++i) h[i] += gi[i];
+    }
+    const float d = dw[r];
+#pragma unroll
+    for (int i = 0; i < E; ++i) h[i] = h[i] / d;
+    if (k == k0 && p == 0) store_f32<E>(H, r, K, q, h);
+    float xi[E];
+    Chunk<DT>::load(Xs, r, K, q, xi);
+    const int32_t e0 = rp[r] + (int32_t)(k - k0) * kPiece;
+    const int32_t e1 = min(e0 + kPiece, rp[r + 1]);
+#pragma unroll
+    for (int t = 0; t < kPiece / P; ++t) {
+        const int32_t e = e0 + p + t * P;
+        const bool ok = e < e1;
+        const int32_t j = ok ? col[e] : (int32_t)r;
+        float xj[E];
+        Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj);
+        float s = 0.0f;
+#pragma unroll
+        for (int i = 0; i < E; ++i) s = __fmaf_rn(h[i], xj[i] - xi[i], s);
+        s = qsum<Q>(s);
+        if (ok && q == 0) ge[e] += s;
+    }
+}
+
+// after the last reverse step: gX0_i of the long rows [lo, hi) from their
+// pieces in order, a thread per (row, chunk)
+template <int Q, int DT>
+__global__ void k_vjp_long_final(const int32_t* __restrict__ ppos, const float* __restrict__ part,
+                                 int32_t K, int64_t lo, int64_t hi, float* __restrict__ out) {
     constexpr int E = Chunk<DT>::E;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t r = lo + t / Q;
@@ -475,46 +535,7 @@ __global__ void k_vjp_long_rows(const int32_t* __restrict__ ppos, const float* _
 #pragma unroll
         for (int i = 0; i < E; ++i) g[i] += v[i];
     }
-    if constexpr (!FINAL) {
-        if (G) {
-            float gi[E];
-            load_f32<E>(G, r, K, q, gi);
-#pragma unroll
-            for (int i = 0; i < E; ++i) g[i] += gi[i];
-        }
-        const float d = dw[r];
-#pragma unroll
-        for (int i = 0; i < E; ++i) g[i] = g[i] / d;
-    }
     store_f32<E>(out, r, K, q, g);
-}
-
-// entries [ebeg, eend) = those of the long rows [lo, hi)
-template <int Q, int DT>
-__global__ void __launch_bounds__(256) k_vjp_long_edges(
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ col, const void* __restrict__ Xs,
-    const void* __restrict__ Xp, int32_t K, int64_t clo, int64_t lo, int64_t hi, int64_t ebeg,
-    int64_t eend, const float* __restrict__ H, float* __restrict__ ge) {
-    constexpr int E = Chunk<DT>::E;
-    const int q = threadIdx.x % Q;
-    const int64_t e = ebeg + ((int64_t)blockIdx.x * 256 + threadIdx.x) / Q;
-    if (e >= eend) return;
-    int64_t a = lo, b = hi - 1;  // the row holding e: last r with rp[r] <= e
-    while (a < b) {
-        const int64_t m = (a + b + 1) >> 1;
-        if (rp[m] <= e) a = m; else b = m - 1;
-    }
-    const int64_t r = a;
-    const int32_t j = col[e];
-    float h[E], xi[E], xj[E];
-    load_f32<E>(H, r, K, q, h);
-    Chunk<DT>::load(Xs, r, K, q, xi);
-    Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj);
-    float s = 0.0f;
-#pragma unroll
-    for (int i = 0; i < E; ++i) s = __fmaf_rn(h[i], xj[i] - xi[i], s);
-    s = qsum<Q>(s);
-    if (q == 0) ge[e] += s;
 }
 
 // the two relabelled entries of each undirected edge: slot 0 = the entry
@@ -572,16 +593,15 @@ static int vjp_colour(const VjpPlan& pl, int c, const void* Xs, const void* Xp, 
                            dim3(256), 0, st, g->row_ptr, g->col, g->w, (const float*)H, K, pl.ppos,
                            clo, mid, pl.pbeg[c], clo, pl.part);
         GR_LAUNCHED("vjp pieces");
-        hipLaunchKernelGGL((k_vjp_long_rows<Q, DT, FINAL>), dim3(blocks_for((mid - clo) * Q, 256)),
-                           dim3(256), 0, st, pl.ppos, pl.dw, G, (const float*)pl.part, K, clo, mid,
-                           FINAL ? out : H);
-        GR_LAUNCHED("vjp long rows");
-        if constexpr (!FINAL) {
-            const int64_t ebeg = og->class_e_h[c], eend = ebeg + og->long_nnz_h[c];
-            hipLaunchKernelGGL((k_vjp_long_edges<Q, DT>), dim3(blocks_for((eend - ebeg) * Q, 256)),
-                               dim3(256), 0, st, g->row_ptr, g->col, Xs, Xp, K, clo, clo, mid, ebeg,
-                               eend, (const float*)H, ge);
-            GR_LAUNCHED("vjp long edges");
+        if constexpr (FINAL) {
+            hipLaunchKernelGGL((k_vjp_long_final<Q, DT>), dim3(blocks_for((mid - clo) * Q, 256)),
+                               dim3(256), 0, st, pl.ppos, (const float*)pl.part, K, clo, mid, out);
+            GR_LAUNCHED("vjp long final");
+        } else {
+            hipLaunchKernelGGL((k_vjp_long_apply<Q, DT>), dim3((unsigned)(pl.pend[c] - pl.pbeg[c])),
+                               dim3(256), 0, st, g->row_ptr, g->col, Xs, Xp, K, clo, pl.ppos, clo,
+                               mid, pl.pbeg[c], pl.dw, G, (const float*)pl.part, H, ge);
+            GR_LAUNCHED("vjp long apply");
         }
     }
     if (chi <= mid) return GR_OK;
