@@ -279,8 +279,9 @@ def _timed(fn, reps):
 
 def extras_report(G, wl, dg, r, ldf):
     """Timings of the differentiable pieces on the headline workload:
-    * the Gauss-Seidel backward pass (vector-Jacobian product, recomputing
-      the sweeps) on the full graph, K and sweeps of the workload;
+    * the Gauss-Seidel backward pass (vector-Jacobian product) on the full
+      graph, K and sweeps of the workload, with the sweep states stored and
+      with them recomputed from X0;
     * Rayleigh quotients of 10 vectors and their edge gradients on the
       reduced graph (random FP64 vectors and edge weights: timing only);
     * Alg. 1 edge scaling of a spanning sparsifier P of the reduced graph G
@@ -298,11 +299,11 @@ def extras_report(G, wl, dg, r, ldf):
         X0 = G.gr_init_vectors(dg.n, K, 2, "f32", device=dg.row_ptr.device)
         gen = torch.Generator(device=dg.row_ptr.device).manual_seed(3)
         cot = torch.randn(dg.n, K, generator=gen, device=dg.row_ptr.device)
-        ms, _ = _timed(lambda: G.gr_smooth_vjp(dg, el, colours, nc, X0, cot, S, False), 3)
-        out["gs_vjp"] = {"ms": ms, "n": dg.n, "nnz": dg.nnz, "K": K, "sweeps": S,
-                         "colours": int(nc), "mode": "recompute",
-                         "nnz_K_sweeps_per_s": dg.nnz * K * S / (ms * 1e-3)}
-        log(f"GS backward: {ms:.2f} ms")
+        out["gs_vjp"] = {"n": dg.n, "nnz": dg.nnz, "K": K, "sweeps": S, "colours": int(nc)}
+        for mode, store in (("stored_states", True), ("recomputed_states", False)):
+            ms, _ = _timed(lambda: G.gr_smooth_vjp(dg, el, colours, nc, X0, cot, S, store), 3)
+            out["gs_vjp"][mode] = {"ms": ms, "nnz_K_sweeps_per_s": dg.nnz * K * S / (ms * 1e-3)}
+            log(f"GS backward ({mode}): {ms:.2f} ms")
         del el, X0, cot
     except Exception as e:  # keep the headline figures
         out["gs_vjp"] = {"error": repr(e)}

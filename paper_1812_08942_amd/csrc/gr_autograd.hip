@@ -10,26 +10,37 @@ namespace gr {
 
 constexpr int kA = 256;
 
+// lanes per row for the row-walking kernels below: a power of two up to a
+// wave, about half the mean degree (hub rows loop)
+inline int lanes_per_row(int64_t n, int64_t nnz) {
+    int G = 4;
+    while (G < kWave && n > 0 && G * 2 <= nnz / n) G *= 2;
+    return G;
+}
+
 // ------------------------------------------------------------- edge list
 // Undirected edge e = (p, q), p < q, is numbered by the position of the upper
 // entry (p, q) among all upper entries in CSR order; both stored entries map
 // to it.
-// a wave per row for both kernels: hub rows would serialise one thread
+// G lanes per row for both kernels (one thread would serialise a hub row)
 __global__ void k_upper_counts(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               int64_t n, int32_t* __restrict__ flag) {
-    const int64_t v = ((int64_t)blockIdx.x * kA + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
+                               int64_t n, int G, int32_t* __restrict__ flag) {
+    const int64_t t = (int64_t)blockIdx.x * kA + threadIdx.x;
+    const int64_t v = t / G;
+    const int lane = (int)(t % G);
     if (v >= n) return;
-    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) flag[e] = col[e] > v ? 1 : 0;
+    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += G) flag[e] = col[e] > v ? 1 : 0;
 }
 
 __global__ void k_edge_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            const int32_t* __restrict__ pos, int64_t n, int32_t* __restrict__ eu,
-                            int32_t* __restrict__ ev, int32_t* __restrict__ eoe) {
-    const int64_t v = ((int64_t)blockIdx.x * kA + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
+                            const int32_t* __restrict__ pos, int64_t n, int G,
+                            int32_t* __restrict__ eu, int32_t* __restrict__ ev,
+                            int32_t* __restrict__ eoe) {
+    const int64_t t = (int64_t)blockIdx.x * kA + threadIdx.x;
+    const int64_t v = t / G;
+    const int lane = (int)(t % G);
     if (v >= n) return;
-    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
+    for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += G) {
         int32_t j = col[e];
         if (j > v) {
             int32_t k = pos[e];
@@ -58,12 +69,13 @@ int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t
     int32_t* flag = ws.take<int32_t>(g->nnz);
     int32_t* pos = ws.take<int32_t>(g->nnz + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (edge list)");
-    const unsigned nb = blocks_for(g->n * kWave, kA);
-    hipLaunchKernelGGL(k_upper_counts, dim3(nb), dim3(kA), 0, st, g->row_ptr, g->col, g->n, flag);
+    const int G = lanes_per_row(g->n, g->nnz);
+    const unsigned nb = blocks_for(g->n * G, kA);
+    hipLaunchKernelGGL(k_upper_counts, dim3(nb), dim3(kA), 0, st, g->row_ptr, g->col, g->n, G, flag);
     GR_LAUNCHED("upper counts");
     GR_TRY(scan_exclusive_i32(flag, pos, g->nnz, pos + g->nnz, ws, st));
-    hipLaunchKernelGGL(k_edge_fill, dim3(nb), dim3(kA), 0, st, g->row_ptr, g->col, pos, g->n, eu, ev,
-                       eoe);
+    hipLaunchKernelGGL(k_edge_fill, dim3(nb), dim3(kA), 0, st, g->row_ptr, g->col, pos, g->n, G, eu,
+                       ev, eoe);
     GR_LAUNCHED("edge fill");
     int32_t E = 0;
     GR_HIP(hipMemcpyAsync(&E, pos + g->nnz, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -268,14 +280,15 @@ int rq_backward(int64_t E, const int32_t* eu, const int32_t* ev, const double* U
 namespace gr {
 
 __global__ void k_perm_payload(const int32_t* __restrict__ rp, const uint32_t* __restrict__ perm,
-                               const int32_t* __restrict__ nrp, int64_t n,
+                               const int32_t* __restrict__ nrp, int64_t n, int G,
                                const int32_t* __restrict__ in, int32_t* __restrict__ out) {
-    int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t / G;
+    const int lane = (int)(t % G);
     if (r >= n) return;
     int32_t v = (int32_t)perm[r];
     int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[r];
-    for (int32_t e = e0 + lane; e < e1; e += kWave) out[o + (e - e0)] = in[e];
+    for (int32_t e = e0 + lane; e < e1; e += G) out[o + (e - e0)] = in[e];
 }
 
 template <int E>
@@ -293,16 +306,16 @@ __device__ inline void store_f32(float* __restrict__ A, int64_t row, int K, int 
         *reinterpret_cast<float4*>(A + row * K + q * E + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
 }
 
-// d_i = sum_j w_ij, a wave per row; constant over the sweeps
+// d_i = sum_j w_ij, G lanes per row; constant over the sweeps
 __global__ void k_row_weight(const int32_t* __restrict__ rp, const float* __restrict__ w, int64_t n,
-                             float* __restrict__ dw) {
-    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (r >= n) return;
+                             int G, float* __restrict__ dw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t / G;
+    const int lane = (int)(t % G);
+    if (r >= n) return;  // G divides the wave: a row's lanes leave together
     float d = 0.0f;
-    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) d += w[e];
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) d += __shfl_xor(d, off, kWave);
+    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += G) d += w[e];
+    for (int off = 1; off < G; off <<= 1) d += __shfl_xor(d, off, kWave);
     if (lane == 0) dw[r] = d;
 }
 
@@ -542,12 +555,13 @@ __global__ void k_vjp_long_final(const int32_t* __restrict__ ppos, const float* 
 // whose original row is the smaller endpoint
 __global__ void k_edge_slots(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                              const int32_t* __restrict__ eoe, const int32_t* __restrict__ perm,
-                             int64_t n, int64_t E, int32_t* __restrict__ slots) {
-    int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    int lane = threadIdx.x & (kWave - 1);
+                             int64_t n, int64_t E, int G, int32_t* __restrict__ slots) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = t / G;
+    const int lane = (int)(t % G);
     if (r >= n) return;
     const int32_t orow = perm[r];
-    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += kWave) {
+    for (int32_t e = rp[r] + lane; e < rp[r + 1]; e += G) {
         int32_t k = eoe[e];
         if (k >= 0 && k < E) slots[2 * k + (orow < perm[col[e]] ? 0 : 1)] = e;
         else g_bad_edge_id = 1;
@@ -684,6 +698,7 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     OrderedGraph og;
     GR_TRY(order_by_colour(g, colours, C, &og, ws, st));
     // edge ids of the relabelled entries, weighted degrees, long-row pieces
+    const int G = lanes_per_row(n, nnz);
     int32_t* eoe_r = ws.take<int32_t>(nnz + 1);
     float* dw = ws.take<float>(n + 1);
     int32_t* ppos = ws.take<int32_t>(n + 1);
@@ -691,12 +706,12 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     int64_t* pidx = ws.take<int64_t>(2 * (size_t)C + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (vjp)");
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_perm_payload, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
-                           g->row_ptr, (const uint32_t*)og.perm, og.g.row_ptr, n, eoe, eoe_r);
+        hipLaunchKernelGGL(k_perm_payload, dim3(blocks_for(n * G, 256)), dim3(256), 0, st,
+                           g->row_ptr, (const uint32_t*)og.perm, og.g.row_ptr, n, G, eoe, eoe_r);
         GR_LAUNCHED("perm payload");
     }
-    hipLaunchKernelGGL(k_row_weight, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st, og.g.row_ptr,
-                       og.g.w, n, dw);
+    hipLaunchKernelGGL(k_row_weight, dim3(blocks_for(n * G, 256)), dim3(256), 0, st, og.g.row_ptr,
+                       og.g.w, n, G, dw);
     GR_LAUNCHED("row weights");
     {
         size_t mark = ws.used;
@@ -774,8 +789,8 @@ int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* 
     if (E > 0) {
         GR_TRY(fill_i32(slots, 0, 2 * E, st));  // unmatched slots read entry 0, never garbage
         GR_TRY(reset_bad_edge_flag(st));
-        hipLaunchKernelGGL(k_edge_slots, dim3(blocks_for(n * kWave, 256)), dim3(256), 0, st,
-                           og.g.row_ptr, og.g.col, (const int32_t*)eoe_r, og.perm, n, E, slots);
+        hipLaunchKernelGGL(k_edge_slots, dim3(blocks_for(n * G, 256)), dim3(256), 0, st,
+                           og.g.row_ptr, og.g.col, (const int32_t*)eoe_r, og.perm, n, E, G, slots);
         GR_LAUNCHED("edge slots");
         GR_TRY(check_bad_edge_flag(st));
         hipLaunchKernelGGL(k_edge_grad, dim3(blocks_for(E, 256)), dim3(256), 0, st,

@@ -599,18 +599,19 @@ int colour_greedy(const gr_graph* g, uint64_t seed, int ldf, int32_t* colours,
     return colour_flow(g, seed, ldf, colours, n_colours_host, ws, st);
 }
 
-// a wave per row
+// G lanes per row (a power of two up to a wave, from the mean degree)
 __global__ void k_check_colouring(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                   const int32_t* __restrict__ colours, int64_t n, int32_t nc,
-                                  int32_t* bad) {
-    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
+                                  int G, int32_t* bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = t / G;
+    const int lane = (int)(t % G);
     if (v >= n) return;
     const int32_t c = colours[v];
     int f = 0;
     if (c < 0 || c >= nc) f = 1;
     else
-        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += kWave)
+        for (int32_t e = rp[v] + lane; e < rp[v + 1]; e += G)
             if (colours[col[e]] == c) { f = 2; break; }
     if (f) atomicOr(bad, f);
 }
@@ -622,8 +623,10 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
     int32_t* bad = ws.take<int32_t>(1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small");
     GR_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_check_colouring, dim3(blocks_for(g->n * kWave, kThreads)), dim3(kThreads), 0, st,
-                       g->row_ptr, g->col, colours, g->n, n_colours, bad);
+    int G = 4;
+    while (G < kWave && G * 2 <= g->nnz / g->n) G *= 2;  // about half the mean degree
+    hipLaunchKernelGGL(k_check_colouring, dim3(blocks_for(g->n * G, kThreads)), dim3(kThreads), 0, st,
+                       g->row_ptr, g->col, colours, g->n, n_colours, G, bad);
     GR_LAUNCHED("check colouring");
     int32_t hb = 0;
     GR_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
