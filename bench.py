@@ -129,12 +129,15 @@ def main():
     if args.secondary and args.secondary != args.workload:
         # the same measurement on a second workload whose colour steps are
         # large enough to be bandwidth-bound (reported next to the headline)
-        sec, _ = run_workload(G, args.secondary, None, args.steps,
-                              args.warmup, args.ldf)
+        sec, keep2 = run_workload(G, args.secondary, None, args.steps,
+                                  args.warmup, args.ldf)
         result["secondary"] = {k: sec[k] for k in (
             "value", "ms_per_step", "storage", "config", "levels",
             "smooth_only_rate", "affinity_edges_per_s", "phase_ms_per_step",
             "roofline")}
+        if not args.no_extras:
+            result["secondary"]["extras"] = secondary_extras(G, keep2)
+        del keep2
     print(json.dumps(result), flush=True)
 
 
@@ -277,6 +280,24 @@ def _timed(fn, reps):
     return (time.perf_counter() - t0) / reps * 1e3, out
 
 
+def vjp_report(G, dg, el, colours, nc, K, S, dtype):
+    """Wall time of the GS backward (A8) with stored and with recomputed
+    sweep states: random X0 of `dtype` and float32 cotangent."""
+    import torch
+
+    dev = dg.row_ptr.device
+    X0 = G.gr_init_vectors(dg.n, K, 2, dtype, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(3)
+    cot = torch.randn(dg.n, K, generator=gen, device=dev)
+    out = {"n": dg.n, "nnz": dg.nnz, "K": K, "sweeps": S, "colours": int(nc),
+           "states": dtype}
+    for mode, store in (("stored_states", True), ("recomputed_states", False)):
+        ms, _ = _timed(lambda: G.gr_smooth_vjp(dg, el, colours, nc, X0, cot, S, store), 3)
+        out[mode] = {"ms": ms, "nnz_K_sweeps_per_s": dg.nnz * K * S / (ms * 1e-3)}
+        log(f"GS backward ({mode}, {dtype} states): {ms:.2f} ms")
+    return out
+
+
 def extras_report(G, wl, dg, r, ldf):
     """Timings of the differentiable pieces on the headline workload:
     * the Gauss-Seidel backward pass (vector-Jacobian product) on the full
@@ -296,15 +317,8 @@ def extras_report(G, wl, dg, r, ldf):
         K, S = wl.K, wl.sweeps
         el = G.gr_edge_list(dg)
         colours, nc = G.gr_colour_greedy(dg, 1, ldf)
-        X0 = G.gr_init_vectors(dg.n, K, 2, "f32", device=dg.row_ptr.device)
-        gen = torch.Generator(device=dg.row_ptr.device).manual_seed(3)
-        cot = torch.randn(dg.n, K, generator=gen, device=dg.row_ptr.device)
-        out["gs_vjp"] = {"n": dg.n, "nnz": dg.nnz, "K": K, "sweeps": S, "colours": int(nc)}
-        for mode, store in (("stored_states", True), ("recomputed_states", False)):
-            ms, _ = _timed(lambda: G.gr_smooth_vjp(dg, el, colours, nc, X0, cot, S, store), 3)
-            out["gs_vjp"][mode] = {"ms": ms, "nnz_K_sweeps_per_s": dg.nnz * K * S / (ms * 1e-3)}
-            log(f"GS backward ({mode}): {ms:.2f} ms")
-        del el, X0, cot
+        out["gs_vjp"] = vjp_report(G, dg, el, colours, nc, K, S, "f32")
+        del el
     except Exception as e:  # keep the headline figures
         out["gs_vjp"] = {"error": repr(e)}
     try:
@@ -347,6 +361,25 @@ def extras_report(G, wl, dg, r, ldf):
         out.setdefault("rq_forward_backward", {"error": repr(e)})
         out["sgd_scale"] = {"error": repr(e)}
     return out
+
+
+def secondary_extras(G, keep):
+    """The GS backward on the second workload, in its own configuration
+    (vector storage type, K, sweeps; its colouring when it prescribes one)."""
+    import torch
+
+    g, wl, r, dg = keep
+    del r
+    try:
+        el = G.gr_edge_list(dg)
+        if g.colours is not None:
+            colours = torch.from_numpy(g.colours).to(dg.row_ptr.device)
+            nc = g.n_colours
+        else:
+            colours, nc = G.gr_colour_greedy(dg, 1, True)
+        return {"gs_vjp": vjp_report(G, dg, el, colours, nc, wl.K, wl.sweeps, wl.dtype)}
+    except Exception as e:  # keep the other figures
+        return {"gs_vjp": {"error": repr(e)}}
 
 
 COPY_BYTES = 1 << 30

@@ -246,3 +246,71 @@ def test_grid256_full_size_reduce(grid256):
     say(f"  {rep}")
     ref = O.laplacian_eigs(n_c, crp, ccl, ccw, 10)
     assert np.allclose(lam, ref, rtol=1e-9, atol=0), (lam, ref)
+
+
+@pytest.mark.timeout(600)
+def test_grid256_full_size_smooth_vjp(grid256):
+    """The GS backward in the benchmark's 256^3 configuration (K = 32,
+    parity colouring, 5 sweeps, recomputed states), through properties that
+    hold at any size:
+    * gX0 is the adjoint of the linear float32 smoothing S:
+      <G, S(dX)> = <gX0, dX> for a random dX;
+    * gw (float32 states) is the gradient of F(w) = <G, S_w(X0)>: along a
+      random +-1 direction of relative edge-weight changes, a central
+      difference of F from the float32 forward agrees with <gw, w * delta>;
+    * with bfloat16 states (rounding taken as the identity in the reverse
+      pass) gw stays within 5e-2 of the float32-state gradient, and stored
+      and recomputed states give the same bits."""
+    g, wl = grid256
+    dev, G = _dev(), _G()
+    K, S = wl.K, wl.sweeps
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    el = G.gr_edge_list(dg)
+    colours = torch.from_numpy(g.colours).to(dev)
+    nc = g.n_colours
+    gen = torch.Generator(device=dev).manual_seed(21)
+    X0 = G.gr_init_vectors(g.n, K, 5, "bf16", dev)
+    X0f = X0.float().contiguous()
+    Gc = torch.randn(g.n, K, generator=gen, device=dev)
+
+    say(f"full-size vjp {g.name} K={K} sweeps={S} f32 states, recompute")
+    gw, gX = G.gr_smooth_vjp(dg, el, colours, nc, X0f, Gc, S, False)
+    assert bool(torch.isfinite(gw).all()) and bool(torch.isfinite(gX).all())
+
+    say("adjoint identity of gX0")
+    dX = torch.randn(g.n, K, generator=gen, device=dev)
+    Y = dX.clone()
+    G.gr_smooth(dg, colours, nc, Y, S)
+    lhs = float((Gc.double() * Y.double()).sum())
+    rhs = float((gX.double() * dX.double()).sum())
+    del Y, dX
+    print(f"[gpu-case] <G, S dX> = {lhs:.6e}, <gX0, dX> = {rhs:.6e}")
+    assert abs(lhs - rhs) <= 1e-4 * (abs(lhs) + abs(rhs))
+
+    say("directional derivative of the edge weights")
+    wE = torch.empty(el.E, dtype=torch.float32, device=dev)
+    wE[el.edge_of_entry.long()] = dg.w
+    delta = torch.randint(0, 2, (el.E,), generator=gen, device=dev).float() * 2 - 1
+    eps = 1e-2
+
+    def F(sign):
+        w = G.gr_expand_edge_weights(el, (wE * (1 + sign * eps * delta)).contiguous())
+        Y = X0f.clone()
+        G.gr_smooth(G.DeviceGraph(dg.row_ptr, dg.col, w), colours, nc, Y, S)
+        return float((Gc.double() * Y.double()).sum())
+
+    fd = (F(1.0) - F(-1.0)) / (2 * eps)
+    an = float((gw.double() * (wE * delta).double()).sum())
+    print(f"[gpu-case] central difference {fd:.6e}, <gw, w delta> {an:.6e}")
+    assert abs(fd - an) <= 1e-2 * abs(an)
+
+    say("bfloat16 states, recompute and store")
+    gwb, gXb = G.gr_smooth_vjp(dg, el, colours, nc, X0, Gc, S, False)
+    ew = float((gwb - gw).abs().max() / gw.abs().max())
+    print(f"[gpu-case] bf16-state gw max rel deviation {ew:.2e}")
+    assert ew < 5e-2
+    # gX0 does not depend on the states (summation order may differ with
+    # the lane split of the other storage type)
+    assert float((gXb - gX).abs().max()) <= 1e-6 * float(gX.abs().max())
+    gws, gXs = G.gr_smooth_vjp(dg, el, colours, nc, X0, Gc, S, True)
+    assert torch.equal(gws, gwb) and torch.equal(gXs, gXb)
