@@ -579,9 +579,13 @@ __global__ void k_zero_f32(float* p, int64_t n) {
     if (i < n) p[i] = 0.0f;
 }
 
+// entry slots per row (a power of two, about a quarter of the mean degree):
+// each lane then has a few gathers to overlap and a wave holds more rows
+// (on the 256^3 grid, mean degree 6: one slot per row 34.0 ms, 2 slots
+// 33.7, 4 slots 40.4, 8 slots 47.8 per backward call)
 static int pick_p_vjp(int Q, double mean_deg) {
     int P = 1;
-    while (P * 2 <= mean_deg && Q * P * 2 <= kWave) P *= 2;
+    while (P * 4 <= mean_deg && Q * P * 2 <= kWave) P *= 2;
     return P;
 }
 
