@@ -10,11 +10,13 @@ namespace gr {
 
 constexpr int kA = 256;
 
-// lanes per row for the row-walking kernels below: a power of two up to a
+// lanes per row for the row-walking kernels below: one below a mean degree
+// of 8 (extra lanes only add waves there), else a power of two up to a
 // wave, about half the mean degree (hub rows loop)
 inline int lanes_per_row(int64_t n, int64_t nnz) {
+    if (n <= 0 || nnz < 8 * n) return 1;
     int G = 4;
-    while (G < kWave && n > 0 && G * 2 <= nnz / n) G *= 2;
+    while (G < kWave && G * 2 <= nnz / n) G *= 2;
     return G;
 }
 

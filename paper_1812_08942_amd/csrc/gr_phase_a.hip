@@ -623,8 +623,9 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
     int32_t* bad = ws.take<int32_t>(1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small");
     GR_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
-    int G = 4;
-    while (G < kWave && G * 2 <= g->nnz / g->n) G *= 2;  // about half the mean degree
+    // one lane per row below a mean degree of 8, else about half the mean degree
+    int G = g->nnz < 8 * g->n ? 1 : 4;
+    while (G > 1 && G < kWave && G * 2 <= g->nnz / g->n) G *= 2;
     hipLaunchKernelGGL(k_check_colouring, dim3(blocks_for(g->n * G, kThreads)), dim3(kThreads), 0, st,
                        g->row_ptr, g->col, colours, g->n, n_colours, G, bad);
     GR_LAUNCHED("check colouring");
