@@ -292,3 +292,68 @@ def test_sgd_scale_matches_oracle(case):
     assert np.allclose(rep["lambda_1"], ref.lambda_1, rtol=1e-9)
     assert np.allclose(wP.cpu().numpy(), ref.w_P, rtol=1e-7)
     assert ref.lambda_n[-1] < ref.lambda_n[0]
+
+
+def _wheel_with_isolated(n, n_iso):
+    """The wheel of _wheel(n) followed by n_iso nodes without edges."""
+    g = _wheel(n)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col > rows
+    return W.csr_from_edges(n + n_iso, rows[up], g.col[up], g.w[up],
+                            f"wheel{n}+{n_iso}")
+
+
+@pytest.mark.parametrize("K,dtype,S", [(4, "f32", 1), (64, "f32", 2),
+                                       (8, "bf16", 0), (32, "bf16", 3)])
+def test_smooth_vjp_edge_cases(K, dtype, S):
+    """One lane per row chunk (K = 4 float32, K = 8 bfloat16) up to a whole
+    wave per row (K = 64 float32); no sweep (the cotangent passes through,
+    the weight gradient is zero); a hub row of 599 entries cut into pieces;
+    rows without neighbours, which keep their cotangent."""
+    g = _wheel_with_isolated(600, 5)
+    say(f"vjp edge case {g.name} K={K} {dtype} sweeps={S}")
+    dev = _dev()
+    G = _G()
+    rng = np.random.default_rng(K + S)
+    dg0 = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    el = G.gr_edge_list(dg0)
+    eoe, eu, ev = O.edge_index(g.n, g.row_ptr, g.col)
+    wE = rng.uniform(0.5, 2.0, eu.size).astype(np.float32)
+    dg = G.DeviceGraph(dg0.row_ptr, dg0.col,
+                       G.gr_expand_edge_weights(el, torch.from_numpy(wE).to(dev)))
+    c, nc = O.colour_greedy(g.n, g.row_ptr, g.col, 9)
+    X0 = O.init_vectors(g.n, K, 31)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    X0d = torch.from_numpy(X0).to(dev).to(tdt).contiguous()
+    Gc = rng.standard_normal((g.n, K)).astype(np.float32)
+    gw, gX = G.gr_smooth_vjp(dg, el, torch.from_numpy(c).to(dev), nc, X0d,
+                             torch.from_numpy(Gc).to(dev), S, False)
+    gw, gX = gw.cpu().numpy(), gX.cpu().numpy()
+    rgw, rgX = O.smooth_vjp(g.n, g.row_ptr, g.col, wE.astype(np.float64), c, nc,
+                            X0d.float().cpu().numpy().astype(np.float64),
+                            Gc.astype(np.float64), S)
+    iso = np.arange(600, g.n)
+    assert np.array_equal(gX[iso], Gc[iso])
+    if S == 0:
+        assert np.array_equal(gX, Gc) and not np.any(gw)
+        return
+    tol = 1e-4 if dtype == "f32" else 5e-2
+    assert np.max(np.abs(gw - rgw)) <= tol * np.max(np.abs(rgw))
+    assert np.max(np.abs(gX - rgX)) <= tol * np.max(np.abs(rgX))
+
+
+def test_smooth_vjp_without_edges():
+    """A graph with no edges: every row keeps its cotangent, no gradient."""
+    dev = _dev()
+    G = _G()
+    n, K = 37, 8
+    say("vjp on an edgeless graph")
+    dg = G.DeviceGraph.from_numpy(np.zeros(n + 1, np.int32), np.zeros(0, np.int32),
+                                  np.zeros(0, np.float32), dev)
+    el = G.gr_edge_list(dg)
+    assert el.E == 0
+    X0 = G.gr_init_vectors(n, K, 3, "f32", device=dev)
+    Gc = torch.randn(n, K, device=dev)
+    gw, gX = G.gr_smooth_vjp(dg, el, torch.zeros(n, dtype=torch.int32, device=dev), 1,
+                             X0, Gc, 3, True)
+    assert gw.numel() == 0 and torch.equal(gX, Gc)
