@@ -420,10 +420,92 @@ __global__ void k_flow_batches(const int32_t* __restrict__ pcnt, int64_t n,
     }
 }
 
+// The first positions (the highest priorities: on power-law graphs the dense
+// core of hubs, where most of the dependence chain lies) are coloured first
+// by one workgroup, the same dataflow with the colours in LDS: a link of the
+// chain then costs an LDS poll instead of a device-coherent publish and poll
+// across the chip.  Waves take positions w, w + 16, ... in order, a whole
+// wave per position; the deadlock argument of the device-wide flow holds
+// inside the workgroup, and every wait is bounded the same way.
+#ifndef GR_FLOW_CORE
+#define GR_FLOW_CORE 1024  // positions coloured by the single workgroup
+#endif
+constexpr int kCoreThreads = 1024;
+constexpr int kCoreWaves = kCoreThreads / kWave;
+static_assert(GR_FLOW_CORE % kFlowBatch == 0, "the core ends at a batch boundary");
+
+__device__ inline int32_t ld_lds(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__global__ void __launch_bounds__(kCoreThreads) k_jp_core(const int32_t* __restrict__ pstart,
+                                                          const int32_t* __restrict__ pcnt,
+                                                          const int32_t* __restrict__ uplist,
+                                                          int32_t kc, int32_t* cpos,
+                                                          int32_t* abort_flag,
+                                                          unsigned spin_limit) {
+    __shared__ int32_t lc[GR_FLOW_CORE];
+    for (int32_t i = threadIdx.x; i < kc; i += kCoreThreads) lc[i] = -1;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int32_t i = threadIdx.x / kWave; i < kc; i += kCoreWaves) {
+        const int32_t s = pstart[i], m = pcnt[i];
+        uint64_t used[4] = {0, 0, 0, 0};
+        int stop = 0;
+        for (int32_t b = lane; b < m && !stop; b += kWave * kFlowU) {
+            int32_t u[kFlowU], c[kFlowU];
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k) {
+                const int32_t e = b + k * kWave;
+                u[k] = e < m ? uplist[s + e] : -1;  // ranks below i < kc
+            }
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k) c[k] = u[k] >= 0 ? ld_lds(lc + u[k]) : -2;
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k) {
+                unsigned spins = 0;
+                while (c[k] == -1 && !stop) {
+                    __builtin_amdgcn_s_sleep(1);
+                    c[k] = ld_lds(lc + u[k]);
+                    ++spins;
+                    if (spins >= spin_limit) {
+                        atomicExch(abort_flag, 1);
+                        stop = 1;
+                    } else if ((spins & 255u) == 0 && ld_dev(abort_flag)) {
+                        stop = 1;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kFlowU; ++k)
+                if (c[k] >= 0 && c[k] < 256) used[c[k] >> 6] |= 1ull << (c[k] & 63);
+        }
+        if (__ballot(stop)) return;  // the other waves leave at their next check
+#pragma unroll
+        for (int w = 0; w < 4; ++w) used[w] = wave_or(used[w]);
+        int32_t c = first_free4(used, 0);
+        for (int32_t base = 256; c < 0; base += 256) {  // every listed colour is known
+            uint64_t wu[4] = {0, 0, 0, 0};
+            for (int32_t e = lane; e < m; e += kWave) {
+                const int32_t cj = ld_lds(lc + uplist[s + e]);
+                if (cj >= base && cj < base + 256) wu[(cj - base) >> 6] |= 1ull << ((cj - base) & 63);
+            }
+#pragma unroll
+            for (int w = 0; w < 4; ++w) wu[w] = wave_or(wu[w]);
+            c = first_free4(wu, base);
+        }
+        if (lane == 0) {
+            __hip_atomic_store(lc + i, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            cpos[i] = c;  // read by the device-wide flow after this launch
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restrict__ pstart,
                                                           const int32_t* __restrict__ pcnt,
                                                           const int32_t* __restrict__ uplist,
                                                           const uint32_t* __restrict__ batches,
+                                                          const int32_t* __restrict__ first_batch,
                                                           const int32_t* __restrict__ nbatches,
                                                           int64_t n, int32_t* cpos,
                                                           int32_t* abort_flag,
@@ -431,8 +513,9 @@ __global__ void __launch_bounds__(kFlowThreads) k_jp_flow(const int32_t* __restr
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nw = (int64_t)gridDim.x * kFlowWaves;
     const int32_t nbt = *nbatches;
-    for (int64_t bt = (int64_t)blockIdx.x * kFlowWaves + threadIdx.x / kWave; bt < nbt;
-         bt += nw) {
+    if (ld_dev(abort_flag)) return;  // the core did not finish
+    for (int64_t bt = *first_batch + (int64_t)blockIdx.x * kFlowWaves + threadIdx.x / kWave;
+         bt < nbt; bt += nw) {
         const uint32_t code = batches[bt];
         if (code & kNarrowBatch) {
             const int64_t ig = (int64_t)(code & ~kNarrowBatch) + lane / kFlowG;
@@ -566,6 +649,14 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         GR_LAUNCHED("colour batches");
         hipLaunchKernelGGL(k_col_fill, dim3(nb), dim3(kThreads), 0, st, n, cpos);
         GR_LAUNCHED("colour fill");
+        // the first kc positions in one workgroup, then the rest from the
+        // first batch past them
+        const int32_t kc = (int32_t)std::min<int64_t>(n, GR_FLOW_CORE);
+        hipLaunchKernelGGL(k_jp_core, dim3(1), dim3(kCoreThreads), 0, st, (const int32_t*)pstart,
+                           (const int32_t*)pcnt, (const int32_t*)uplist, kc, cpos, small + 3,
+                           spin_limit);
+        GR_LAUNCHED("colour core");
+        const int32_t* fb = kc < n ? boff + kc / kFlowBatch : small + 5;
         const int32_t* ps = pstart;
         const int32_t* pc = pcnt;
         const int32_t* ul = uplist;
@@ -573,8 +664,8 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         const int32_t* nbt = small + 5;
         int32_t* abort_flag = small + 3;
         int64_t nn = n;
-        void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&bl, (void*)&nbt, (void*)&nn,
-                        (void*)&cpos, (void*)&abort_flag, (void*)&spin_limit};
+        void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&bl, (void*)&fb, (void*)&nbt,
+                        (void*)&nn, (void*)&cpos, (void*)&abort_flag, (void*)&spin_limit};
         GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
                                           args, 0, st));
         hipLaunchKernelGGL(k_flow_colours, dim3(std::min<unsigned>(nb, kGatherBlocks)),
