@@ -438,13 +438,26 @@ __device__ inline int32_t ld_lds(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// It runs only on graphs with hubs (largest degree above kCoreHubRatio times
+// the mean): elsewhere the chain is short and the core would only add its
+// own serial time.  first_batch receives the flow's first batch either way.
+constexpr int32_t kCoreHubRatio = 16;
+
 __global__ void __launch_bounds__(kCoreThreads) k_jp_core(const int32_t* __restrict__ pstart,
                                                           const int32_t* __restrict__ pcnt,
                                                           const int32_t* __restrict__ uplist,
-                                                          int32_t kc, int32_t* cpos,
+                                                          int64_t n, int64_t nnz,
+                                                          const int32_t* __restrict__ maxdeg,
+                                                          const int32_t* __restrict__ boff,
+                                                          const int32_t* __restrict__ nbatches,
+                                                          int32_t* first_batch, int32_t* cpos,
                                                           int32_t* abort_flag,
                                                           unsigned spin_limit) {
     __shared__ int32_t lc[GR_FLOW_CORE];
+    const bool hubs = (int64_t)*maxdeg * n > (int64_t)kCoreHubRatio * nnz;
+    const int32_t kc = hubs ? (int32_t)(n < GR_FLOW_CORE ? n : GR_FLOW_CORE) : 0;
+    if (threadIdx.x == 0) *first_batch = kc == 0 ? 0 : (kc < n ? boff[kc / kFlowBatch] : *nbatches);
+    if (kc == 0) return;
     for (int32_t i = threadIdx.x; i < kc; i += kCoreThreads) lc[i] = -1;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
@@ -586,7 +599,7 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     int32_t* nbat = ws.take<int32_t>(ngroups);
     int32_t* boff = ws.take<int32_t>(ngroups);
     // [0] largest degree, [1] tie flag, [2] wide count, [3] abort flag,
-    // [4] largest colour, [5] batches
+    // [4] largest colour, [5] batches, [6] first batch of the device-wide flow
     int32_t* small = ws.take<int32_t>(8);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
     const int nblk = flow_blocks(n);
@@ -649,14 +662,14 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         GR_LAUNCHED("colour batches");
         hipLaunchKernelGGL(k_col_fill, dim3(nb), dim3(kThreads), 0, st, n, cpos);
         GR_LAUNCHED("colour fill");
-        // the first kc positions in one workgroup, then the rest from the
-        // first batch past them
-        const int32_t kc = (int32_t)std::min<int64_t>(n, GR_FLOW_CORE);
+        // on graphs with hubs the first positions in one workgroup; the flow
+        // then starts at the batch the core kernel leaves in small[6]
         hipLaunchKernelGGL(k_jp_core, dim3(1), dim3(kCoreThreads), 0, st, (const int32_t*)pstart,
-                           (const int32_t*)pcnt, (const int32_t*)uplist, kc, cpos, small + 3,
-                           spin_limit);
+                           (const int32_t*)pcnt, (const int32_t*)uplist, n, nnz,
+                           (const int32_t*)small, (const int32_t*)boff,
+                           (const int32_t*)(small + 5), small + 6, cpos, small + 3, spin_limit);
         GR_LAUNCHED("colour core");
-        const int32_t* fb = kc < n ? boff + kc / kFlowBatch : small + 5;
+        const int32_t* fb = small + 6;
         const int32_t* ps = pstart;
         const int32_t* pc = pcnt;
         const int32_t* ul = uplist;

@@ -110,13 +110,18 @@ def test_init_vectors_match_oracle():
 
 
 def colouring_graphs():
-    """The small graphs plus two that reach the colouring's wide paths: a
-    complete graph (every node waits on all earlier ones; colours above 255
-    need the later colour windows) and a power-law graph with hubs above
-    degree 2048."""
+    """The small graphs plus those that reach the colouring's other paths:
+    a complete graph (every node waits on all earlier ones; colours above
+    255 need the later colour windows), a power-law graph with hubs above
+    degree 2048, and two graphs whose largest degree is far above the mean,
+    which colour their first positions in one workgroup: a star, and K_300
+    with disjoint edges (colours above 255 inside that workgroup, and the
+    device-wide flow after it)."""
     gs = dict(small_graphs())
     gs["complete_300"] = W.complete(300)
     gs["chunglu_hubs_10000"] = W.chung_lu(10000, mean_deg=700.0, seed=7)
+    gs["star_5000"] = W.star(5000)
+    gs["clique_300_pairs"] = _clique_with_pairs(300, 5000)
     return gs
 
 
@@ -146,21 +151,37 @@ def test_greedy_colouring_exact_order_path(monkeypatch):
         assert np.array_equal(c.cpu().numpy(), rc)
 
 
-def test_colouring_wait_limit_fails_cleanly(monkeypatch):
+def _clique_with_pairs(m, pairs):
+    """K_m followed by `pairs` disjoint edges: the largest degree is far above
+    the mean, so the colouring first runs its highest-priority positions (the
+    clique, a dependence chain of m) in one workgroup."""
+    iu, ju = np.triu_indices(m, 1)
+    a = m + 2 * np.arange(pairs)
+    u = np.concatenate([iu, a])
+    v = np.concatenate([ju, a + 1])
+    return W.csr_from_edges(m + 2 * pairs, u, v, np.ones(u.size, np.float32),
+                            f"clique{m}+{pairs}pairs")
+
+
+@pytest.mark.parametrize("which", ["complete_300", "clique_200_pairs"])
+def test_colouring_wait_limit_fails_cleanly(monkeypatch, which):
     """A colouring whose waits run out reports the failure and leaves the
-    device usable: GR_COLOUR_SPIN_LIMIT=1 cuts every wait to one poll (on a
-    complete graph every node waits for the earlier ones), then the same
-    call without it colours as the oracle does."""
+    device usable: GR_COLOUR_SPIN_LIMIT=1 cuts every wait to one poll (in a
+    clique every node waits for the earlier ones: on the complete graph in
+    the device-wide flow, on the clique with pairs in the single-workgroup
+    core), then the same call without it colours as the oracle does."""
     dev = _dev()
     G = _G()
-    g = W.complete(300)
+    g = W.complete(300) if which == "complete_300" else _clique_with_pairs(200, 5000)
+    deg = g.degrees()
+    assert (deg.max() * g.n > 16 * g.nnz) == (which != "complete_300")
     monkeypatch.setenv("GR_COLOUR_SPIN_LIMIT", "1")
-    say("colour complete_300 with one poll per wait")
+    say(f"colour {which} with one poll per wait")
     with pytest.raises(G.GraphReduceError) as err:
         G.gr_colour_greedy(dgraph(g, dev), 5, True)
     assert "timed out" in str(err.value)
     monkeypatch.delenv("GR_COLOUR_SPIN_LIMIT")
-    say("colour complete_300 again")
+    say(f"colour {which} again")
     c, nc = G.gr_colour_greedy(dgraph(g, dev), 5, True)
     rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 5, True)
     assert nc == rnc
