@@ -321,6 +321,10 @@ __global__ void k_row_weight(const int32_t* __restrict__ rp, const float* __rest
     if (lane == 0) dw[r] = d;
 }
 
+// trips (entries per lane) up to which a reverse step keeps the gathered
+// state rows in registers instead of a second pass over the row
+constexpr int kVjpKeep = 4;
+
 // Rows [lo, hi) of colour c with degree <= kLongRow, L = Q*P lanes per row.
 // FINAL = 0: the reverse step (G = the cotangent in the last sweep, else
 // null).  FINAL = 1: gX0 of those rows into out.
@@ -352,6 +356,57 @@ __global__ void __launch_bounds__(256) k_vjp_rows(
     float acc[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) acc[i] = 0.0f;
+    const int32_t trips = (e1 - e0 + P - 1) / P;  // the same for every lane of the row
+    if constexpr (!FINAL) {
+        if (trips <= kVjpKeep) {
+            // one pass: the state rows x_j are gathered with h_j and kept for
+            // the gradient
+            float xj[kVjpKeep][E];
+#pragma unroll
+            for (int t = 0; t < kVjpKeep; ++t) {
+                if (t < trips) {
+                    const int32_t e = e0 + p + t * P;
+                    const bool ok = e < e1;
+                    const int32_t j = ok ? col[e] : (int32_t)r;
+                    Chunk<DT>::load(j < clo ? Xs : Xp, j, K, q, xj[t]);
+                    if (ok) {
+                        float hj[E];
+                        load_f32<E>(H, j, K, q, hj);
+                        const float wt = w[e];
+#pragma unroll
+                        for (int i = 0; i < E; ++i) acc[i] = __fmaf_rn(wt, hj[i], acc[i]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int off = Q; off < L; off <<= 1)
+#pragma unroll
+                for (int i = 0; i < E; ++i) acc[i] += __shfl_xor(acc[i], off, kWave);
+            if (G) {
+                float gi[E];
+                load_f32<E>(G, r, K, q, gi);
+#pragma unroll
+                for (int i = 0; i < E; ++i) acc[i] += gi[i];
+            }
+            float h[E], xi[E];
+#pragma unroll
+            for (int i = 0; i < E; ++i) h[i] = acc[i] / d;
+            if (p == 0) store_f32<E>(H, r, K, q, h);
+            Chunk<DT>::load(Xs, r, K, q, xi);
+#pragma unroll
+            for (int t = 0; t < kVjpKeep; ++t) {
+                if (t < trips) {
+                    const int32_t e = e0 + p + t * P;
+                    float sdot = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < E; ++i) sdot = __fmaf_rn(h[i], xj[t][i] - xi[i], sdot);
+                    sdot = qsum<Q>(sdot);
+                    if (e < e1 && q == 0) ge[e] += sdot;
+                }
+            }
+            return;
+        }
+    }
     for (int32_t e = e0 + p; e < e1; e += P) {
         const int32_t j = col[e];
         if (FINAL && j >= clo) continue;
@@ -379,7 +434,6 @@ __global__ void __launch_bounds__(256) k_vjp_rows(
         for (int i = 0; i < E; ++i) h[i] = acc[i] / d;
         if (p == 0) store_f32<E>(H, r, K, q, h);
         Chunk<DT>::load(Xs, r, K, q, xi);
-        const int32_t trips = (e1 - e0 + P - 1) / P;
         for (int32_t t = 0; t < trips; ++t) {
             const int32_t e = e0 + p + t * P;
             const bool ok = e < e1;
