@@ -322,8 +322,10 @@ __global__ void k_row_weight(const int32_t* __restrict__ rp, const float* __rest
 }
 
 // trips (entries per lane) up to which a reverse step keeps the gathered
-// state rows in registers instead of a second pass over the row
-constexpr int kVjpKeep = 4;
+// state rows in registers instead of a second pass over the row: 32 values
+// per lane (8 float32 or 4 bfloat16 chunks)
+template <int DT>
+constexpr int vjp_keep() { return 32 / Chunk<DT>::E; }
 
 // Rows [lo, hi) of colour c with degree <= kLongRow, L = Q*P lanes per row.
 // FINAL = 0: the reverse step (G = the cotangent in the last sweep, else
@@ -358,12 +360,13 @@ __global__ void __launch_bounds__(256) k_vjp_rows(
     for (int i = 0; i < E; ++i) acc[i] = 0.0f;
     const int32_t trips = (e1 - e0 + P - 1) / P;  // the same for every lane of the row
     if constexpr (!FINAL) {
-        if (trips <= kVjpKeep) {
+        constexpr int kKeep = vjp_keep<DT>();
+        if (trips <= kKeep) {
             // one pass: the state rows x_j are gathered with h_j and kept for
             // the gradient
-            float xj[kVjpKeep][E];
+            float xj[kKeep][E];
 #pragma unroll
-            for (int t = 0; t < kVjpKeep; ++t) {
+            for (int t = 0; t < kKeep; ++t) {
                 if (t < trips) {
                     const int32_t e = e0 + p + t * P;
                     const bool ok = e < e1;
@@ -394,7 +397,7 @@ __global__ void __launch_bounds__(256) k_vjp_rows(
             if (p == 0) store_f32<E>(H, r, K, q, h);
             Chunk<DT>::load(Xs, r, K, q, xi);
 #pragma unroll
-            for (int t = 0; t < kVjpKeep; ++t) {
+            for (int t = 0; t < kKeep; ++t) {
                 if (t < trips) {
                     const int32_t e = e0 + p + t * P;
                     float sdot = 0.0f;
