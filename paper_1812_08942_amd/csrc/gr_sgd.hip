@@ -72,30 +72,55 @@ __global__ void __launch_bounds__(kS) k_sum_final(const double* __restrict__ par
     if (threadIdx.x == 0) *out = s;
 }
 
-// y_v = d_v x_v - sum_j w_vj x_j   (8 lanes per row, fixed reduction tree)
+// The row-walking kernels below take a wave per row, with kSpU loads in
+// flight per lane, and reduce in a fixed tree: hub rows of reduced graphs
+// hold thousands of entries, and fewer lanes would serialise them.
+constexpr int kSpU = 4;
+
+__device__ inline double wave_sum_f64(double s) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) s += __shfl_xor(s, off, kWave);
+    return s;
+}
+
+// y_v = d_v x_v - sum_j w_vj x_j
 __global__ void __launch_bounds__(kS) k_lap_spmv(const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const double* __restrict__ w,
                                                  const double* __restrict__ diag, int64_t n,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y) {
-    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) >> 3;
-    const int l = threadIdx.x & 7;
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
     if (v >= n) return;
+    const int32_t e1 = rp[v + 1];
     double s = 0.0;
-    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) s = fma(w[e], x[col[e]], s);
+    for (int32_t b = rp[v] + l; b < e1; b += kWave * kSpU) {
+        double wv[kSpU], xv[kSpU];
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1) s += __shfl_xor(s, off, kWave);
+        for (int u = 0; u < kSpU; ++u) {
+            const int32_t e = b + u * kWave;
+            const bool ok = e < e1;
+            wv[u] = ok ? w[e] : 0.0;
+            xv[u] = ok ? x[col[e]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSpU; ++u) s = fma(wv[u], xv[u], s);
+    }
+    s = wave_sum_f64(s);
     if (l == 0) y[v] = diag[v] * x[v] - s;
 }
 
-__global__ void k_row_sums(const int32_t* __restrict__ rp, const double* __restrict__ w, int64_t n,
-                           double* __restrict__ d) {
-    int64_t v = (int64_t)blockIdx.x * kS + threadIdx.x;
+__global__ void __launch_bounds__(kS) k_row_sums(const int32_t* __restrict__ rp,
+                                                 const double* __restrict__ w, int64_t n,
+                                                 double* __restrict__ d) {
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
     if (v >= n) return;
     double s = 0.0;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) s += w[e];
-    d[v] = s;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += kWave) s += w[e];
+    s = wave_sum_f64(s);
+    if (l == 0) d[v] = s;
 }
 
 __global__ void k_promote(const float* __restrict__ a, int64_t n, double* __restrict__ b) {
@@ -221,17 +246,20 @@ __global__ void k_set_eta(double* __restrict__ sc, double eta_scale, int64_t E) 
 }
 
 // S_v = sum of the proposals of the P-edges at v (gather over P's rows)
-__global__ void k_node_sums(const int32_t* __restrict__ rp, const int32_t* __restrict__ eoe,
-                            const double* __restrict__ x, int64_t n, int64_t E,
-                            double* __restrict__ S) {
-    int64_t v = (int64_t)blockIdx.x * kS + threadIdx.x;
+__global__ void __launch_bounds__(kS) k_node_sums(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ eoe,
+                                                  const double* __restrict__ x, int64_t n,
+                                                  int64_t E, double* __restrict__ S) {
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
     if (v >= n) return;
     double s = 0.0;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-        int32_t k = eoe[e];
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += kWave) {
+        const int32_t k = eoe[e];
         if (k >= 0 && k < E) s += x[k];
     }
-    S[v] = s;
+    s = wave_sum_f64(s);
+    if (l == 0) S[v] = s;
 }
 
 // caps and update: dw = max(0, min(dw, min(f_p, f_q) * prop)), w += dw,
@@ -309,13 +337,13 @@ struct Sgd {
         return GR_OK;
     }
     int lapG(const double* x, double* yv) {
-        hipLaunchKernelGGL(k_lap_spmv, dim3(blocks_for(n * 8, kS)), dim3(kS), 0, st, rpG, colG,
+        hipLaunchKernelGGL(k_lap_spmv, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, rpG, colG,
                            (const double*)wG, (const double*)dG, n, x, yv);
         GR_LAUNCHED("spmv G");
         return GR_OK;
     }
     int lapP(const double* x, double* yv) {
-        hipLaunchKernelGGL(k_lap_spmv, dim3(blocks_for(n * 8, kS)), dim3(kS), 0, st, rpP, colP,
+        hipLaunchKernelGGL(k_lap_spmv, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, rpP, colP,
                            (const double*)wPent, (const double*)dP, n, x, yv);
         GR_LAUNCHED("spmv P");
         return GR_OK;
@@ -367,7 +395,7 @@ struct Sgd {
         hipLaunchKernelGGL(k_expand_f64, dim3(blocks_for(nnzP, kS)), dim3(kS), 0, st, eoe, nnzP, E,
                            (const double*)w, wPent);
         GR_LAUNCHED("expand P");
-        hipLaunchKernelGGL(k_row_sums, dim3(blocks_for(n, kS)), dim3(kS), 0, st, rpP,
+        hipLaunchKernelGGL(k_row_sums, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, rpP,
                            (const double*)wPent, n, dP);
         GR_LAUNCHED("d_P");
         return GR_OK;
@@ -433,8 +461,8 @@ int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t 
     GR_HIP(hipMemsetAsync(s.dw, 0, sizeof(double) * (E + 1), st));
     hipLaunchKernelGGL(k_promote, dim3(blocks_for(s.nnzG, kS)), dim3(kS), 0, st, G->w, s.nnzG, s.wG);
     GR_LAUNCHED("promote");
-    hipLaunchKernelGGL(k_row_sums, dim3(nb), dim3(kS), 0, st, G->row_ptr, (const double*)s.wG, n,
-                       s.dG);
+    hipLaunchKernelGGL(k_row_sums, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, G->row_ptr,
+                       (const double*)s.wG, n, s.dG);
     GR_LAUNCHED("d_G");
     GR_TRY(s.refresh_P());
     GR_TRY(s.lambda1());
@@ -486,8 +514,8 @@ int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t 
         hipLaunchKernelGGL(k_sgd_propose, dim3(eb), dim3(kS), 0, st, eu, ev, (const double*)s.h, E,
                            prm->alpha, (const double*)s.sc, 0, s.s1, s.dw, s.prop);
         GR_LAUNCHED("propose");
-        hipLaunchKernelGGL(k_node_sums, dim3(nb), dim3(kS), 0, st, s.rpP, eoe, (const double*)s.prop,
-                           n, E, s.S);
+        hipLaunchKernelGGL(k_node_sums, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, s.rpP, eoe,
+                           (const double*)s.prop, n, E, s.S);
         GR_LAUNCHED("node sums");
         hipLaunchKernelGGL(k_sgd_apply, dim3(eb), dim3(kS), 0, st, eu, ev, (const double*)s.dG,
                            (const double*)s.dP, (const double*)s.S, E, delta, (const double*)s.sc,
