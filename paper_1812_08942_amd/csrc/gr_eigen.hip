@@ -34,21 +34,58 @@ constexpr int kGramRows = 32;
 constexpr int kRowBlocks = 128;
 constexpr int kJacobiThreads = 256;
 
-// Y[:, 0:p] = L X[:, 0:p] for row-major blocks of stride ld; lanes (the power
-// of two >= p) lanes per row, 64 / lanes rows per wave
-__global__ void __launch_bounds__(kE) k_lap_spmm(const int32_t* __restrict__ rp,
-                                                 const int32_t* __restrict__ col,
-                                                 const float* __restrict__ w,
-                                                 const double* __restrict__ d, int64_t n, int p,
-                                                 int ld, int lanes, const double* __restrict__ X,
-                                                 double* __restrict__ Y) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t v = (((int64_t)blockIdx.x * kE + threadIdx.x) / kWave) * (kWave / lanes) + lane / lanes;
-    const int c = lane % lanes;
+// Y[:, 0:p] = L X[:, 0:p] for row-major blocks of stride ld.  Every row is
+// cut into pieces of ep consecutive entries (ep >= the mean degree, so that
+// there are at most 2n pieces, and a hub row spreads over many threads): the
+// first kernel writes each piece's partial sums, `lanes` threads (a power of
+// two >= p) per piece, one column each; the second adds a row's pieces in
+// order and applies the diagonal.  Fixed order: deterministic.
+__global__ void __launch_bounds__(kE) k_spmm_pieces(const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const float* __restrict__ w,
+                                                    const int32_t* __restrict__ ppos,
+                                                    const int32_t* __restrict__ prow, int64_t npieces,
+                                                    int32_t ep, int p, int ld, int lanes,
+                                                    const double* __restrict__ X,
+                                                    double* __restrict__ part) {
+    const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
+    const int64_t k = t / lanes;
+    const int c = (int)(t % lanes);
+    if (k >= npieces || c >= p) return;
+    const int32_t v = prow[k];
+    const int32_t e0 = rp[v] + (int32_t)(k - ppos[v]) * ep;
+    const int32_t e1 = min(e0 + ep, rp[v + 1]);
+    double s = 0.0;
+    for (int32_t e = e0; e < e1; ++e) s = fma((double)w[e], X[(int64_t)col[e] * ld + c], s);
+    part[k * p + c] = s;
+}
+
+__global__ void __launch_bounds__(kE) k_spmm_rows(const int32_t* __restrict__ ppos,
+                                                  const double* __restrict__ d, int64_t n, int p,
+                                                  int ld, int lanes,
+                                                  const double* __restrict__ part,
+                                                  const double* __restrict__ X,
+                                                  double* __restrict__ Y) {
+    const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
+    const int64_t v = t / lanes;
+    const int c = (int)(t % lanes);
     if (v >= n || c >= p) return;
     double s = 0.0;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) s = fma((double)w[e], X[(int64_t)col[e] * ld + c], s);
+    for (int32_t k = ppos[v]; k < ppos[v + 1]; ++k) s += part[(int64_t)k * p + c];
     Y[v * ld + c] = d[v] * X[v * ld + c] - s;
+}
+
+// pieces of every row, and the row of every piece
+__global__ void k_piece_counts_e(const int32_t* __restrict__ rp, int64_t n, int32_t ep,
+                                 int32_t* __restrict__ cnt) {
+    const int64_t v = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (v < n) cnt[v] = (rp[v + 1] - rp[v] + ep - 1) / ep;
+}
+
+__global__ void k_piece_rows(const int32_t* __restrict__ ppos, int64_t n, int32_t* __restrict__ prow) {
+    const int64_t v = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (v >= n) return;
+    for (int32_t k = ppos[v]; k < ppos[v + 1]; ++k) prow[k] = (int32_t)v;
 }
 
 // Chebyshev step on contiguous blocks: Z = (2/e) (L Y - c Y) - Z, or
@@ -61,14 +98,22 @@ __global__ void k_cheb(const double* __restrict__ LY, const double* __restrict__
     Z[i] = first ? t : 2.0 * t - Z[i];
 }
 
-__global__ void k_degree_f64(const int32_t* __restrict__ rp, const float* __restrict__ w, int64_t n,
-                             double* __restrict__ d, double* __restrict__ dinv) {
-    int64_t v = (int64_t)blockIdx.x * kE + threadIdx.x;
+// a wave per row (hub rows hold thousands of entries), fixed reduction tree
+__global__ void __launch_bounds__(kE) k_degree_f64(const int32_t* __restrict__ rp,
+                                                   const float* __restrict__ w, int64_t n,
+                                                   double* __restrict__ d,
+                                                   double* __restrict__ dinv) {
+    const int64_t v = ((int64_t)blockIdx.x * kE + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
     if (v >= n) return;
     double s = 0.0;
-    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) s += (double)w[e];
-    d[v] = s;
-    dinv[v] = s > 0.0 ? 1.0 / s : 1.0;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += kWave) s += (double)w[e];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) s += __shfl_xor(s, off, kWave);
+    if (l == 0) {
+        d[v] = s;
+        dinv[v] = s > 0.0 ? 1.0 / s : 1.0;
+    }
 }
 
 // uniform (-1, 1) values from the counter RNG into columns [c0, c0 + p)
@@ -415,6 +460,10 @@ struct Eig {
     int fix_round;
     double *d, *dinv, *S, *LS, *T, *U, *part, *G, *M, *V, *theta, *cs, *res, *small;
     int* flag;
+    int32_t *ppos, *prow;  // row pieces of the Laplacian product
+    double* ppart;         // their partial sums [npieces][p]
+    int64_t npieces;
+    int32_t ep;            // entries per piece
 
     static int lanes_for(int p) {
         int l = 1;
@@ -424,11 +473,16 @@ struct Eig {
     // B[:, 0:p] = L A[:, 0:p]
     int spmm(const double* A, double* B, int p) {
         const int lanes = lanes_for(p);
-        const int64_t rows_per_wave = kWave / lanes;
-        const int64_t waves = (n + rows_per_wave - 1) / rows_per_wave;
-        hipLaunchKernelGGL(k_lap_spmm, dim3(blocks_for(waves * kWave, kE)), dim3(kE), 0, st,
-                           g->row_ptr, g->col, g->w, (const double*)d, n, p, ld, lanes, A, B);
-        GR_LAUNCHED("lap spmm");
+        if (npieces > 0) {
+            hipLaunchKernelGGL(k_spmm_pieces, dim3(blocks_for(npieces * lanes, kE)), dim3(kE), 0, st,
+                               g->row_ptr, g->col, g->w, (const int32_t*)ppos, (const int32_t*)prow,
+                               npieces, ep, p, ld, lanes, A, ppart);
+            GR_LAUNCHED("spmm pieces");
+        }
+        hipLaunchKernelGGL(k_spmm_rows, dim3(blocks_for(n * lanes, kE)), dim3(kE), 0, st,
+                           (const int32_t*)ppos, (const double*)d, n, p, ld, lanes,
+                           (const double*)ppart, A, B);
+        GR_LAUNCHED("spmm rows");
         return GR_OK;
     }
     int project(double* A, int p) {
@@ -510,8 +564,10 @@ static int cheb_block(int n_eig) {
 size_t eig_workspace(int64_t n, int32_t n_eig) {
     (void)n_eig;
     size_t blk = (size_t)(n + 1) * kMaxP * 8;
+    // blocks, degrees, small matrices; row pieces (at most 2n: offsets, rows,
+    // and partial sums of up to kMaxP columns each)
     size_t b = 4 * blk + 16 * (size_t)(n + 1) + 8 * (size_t)kRowBlocks * kMaxP * kMaxP +
-               8 * 4 * kMaxP * kMaxP;
+               8 * 4 * kMaxP * kMaxP + 16 * (size_t)(n + 1) + 2 * blk;
     return b + b / 16 + (1u << 20);
 }
 
@@ -670,11 +726,34 @@ int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
     s.res = ws.take<double>(kMaxP);
     s.small = ws.take<double>(8);
     s.flag = ws.take<int>(4);
+    s.ppos = ws.take<int32_t>(n + 1);
+    s.prow = ws.take<int32_t>(2 * (size_t)n + 1);
+    s.ppart = ws.take<double>((2 * (size_t)n + 1) * kMaxP);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (eigen)");
     GR_HIP(hipMemsetAsync(s.flag, 0, sizeof(int) * 4, st));
-    hipLaunchKernelGGL(k_degree_f64, dim3(blocks_for(n, kE)), dim3(kE), 0, st, g->row_ptr, g->w, n, s.d,
-                       s.dinv);
+    hipLaunchKernelGGL(k_degree_f64, dim3(blocks_for(n * kWave, kE)), dim3(kE), 0, st, g->row_ptr,
+                       g->w, n, s.d, s.dinv);
     GR_LAUNCHED("degrees");
+    // row pieces of at least the mean degree: at most n + nnz / ep <= 2n
+    s.ep = (int32_t)std::max<int64_t>(64, (g->nnz + n - 1) / n);
+    {
+        const size_t mark = ws.used;
+        int32_t* cnt = ws.take<int32_t>(n);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (eigen pieces)");
+        hipLaunchKernelGGL(k_piece_counts_e, dim3(blocks_for(n, kE)), dim3(kE), 0, st, g->row_ptr, n,
+                           s.ep, cnt);
+        GR_LAUNCHED("piece counts");
+        GR_TRY(scan_exclusive_i32(cnt, s.ppos, n, s.ppos + n, ws, st));
+        ws.used = mark;
+    }
+    hipLaunchKernelGGL(k_piece_rows, dim3(blocks_for(n, kE)), dim3(kE), 0, st, (const int32_t*)s.ppos,
+                       n, s.prow);
+    GR_LAUNCHED("piece rows");
+    int32_t np32 = 0;
+    GR_HIP(hipMemcpyAsync(&np32, s.ppos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    s.npieces = np32;
+    if (s.npieces > 2 * n) return set_error(GR_EINVAL, "row pieces exceed 2n");
     hipLaunchKernelGGL(k_deg_stats, dim3(1), dim3(kE), 0, st, (const double*)s.d, n, s.small);
     GR_LAUNCHED("degree stats");
     double dstat[2] = {0.0, 0.0};
