@@ -32,7 +32,7 @@ constexpr int kE = 256;
 constexpr int kMaxP = 64;  // widest block (columns)
 constexpr int kGramRows = 32;
 constexpr int kRowBlocks = 128;
-constexpr int kJacobiThreads = 256;
+constexpr int kJacobiThreads = 1024;
 
 // Y[:, 0:p] = L X[:, 0:p] for row-major blocks of stride ld.  Every row is
 // cut into pieces of ep consecutive entries (ep >= the mean degree, so that
@@ -280,12 +280,16 @@ __global__ void k_right_mul(const double* __restrict__ A, int lda, int k, const 
 // cyclic Jacobi (round-robin ordering: each round rotates p/2 disjoint
 // pairs at once), one workgroup.  Eigenvalues ascending into theta, the
 // eigenvectors into the columns of Q (p x p); V is p x p scratch.
+// row stride of the LDS matrices: one double of padding, so that the column
+// updates (consecutive rows, one column) fall in different banks
+constexpr int kJs = kMaxP + 1;
+
 __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restrict__ H, int p,
                                                            int max_sweeps,
                                                            double* __restrict__ theta,
-                                                           double* __restrict__ Q,
-                                                           double* __restrict__ V) {
-    __shared__ double A[kMaxP * kMaxP];
+                                                           double* __restrict__ Q) {
+    __shared__ double A[kJs * kMaxP];
+    __shared__ double V[kJs * kMaxP];  // the rotations
     __shared__ double rc[kMaxP / 2], rs[kMaxP / 2];
     __shared__ int rl[kMaxP / 2], rh[kMaxP / 2];
     __shared__ double red_off[kJacobiThreads], red_tot[kJacobiThreads];
@@ -293,8 +297,8 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
     const int t = threadIdx.x;
     for (int i = t; i < p * p; i += kJacobiThreads) {
         int r = i / p, c = i % p;
-        A[r * kMaxP + c] = 0.5 * (H[r * p + c] + H[c * p + r]);
-        V[i] = (r == c) ? 1.0 : 0.0;
+        A[r * kJs + c] = 0.5 * (H[r * p + c] + H[c * p + r]);
+        V[r * kJs + c] = (r == c) ? 1.0 : 0.0;
     }
     const int p2 = p + (p & 1);
     const int npairs = p2 / 2;
@@ -303,7 +307,7 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
         double off = 0.0, tot = 0.0;
         for (int i = t; i < p * p; i += kJacobiThreads) {
             int r = i / p, c = i % p;
-            double a2 = A[r * kMaxP + c] * A[r * kMaxP + c];
+            double a2 = A[r * kJs + c] * A[r * kJs + c];
             tot += a2;
             if (r != c) off += a2;
         }
@@ -333,9 +337,9 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
                 const int lo = min(a, b), hi = max(a, b);
                 double c = 1.0, s = 0.0;
                 if (hi < p) {
-                    const double apq = A[lo * kMaxP + hi];
+                    const double apq = A[lo * kJs + hi];
                     if (apq != 0.0) {
-                        const double tau = (A[hi * kMaxP + hi] - A[lo * kMaxP + lo]) / (2.0 * apq);
+                        const double tau = (A[hi * kJs + hi] - A[lo * kJs + lo]) / (2.0 * apq);
                         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + tt * tt);
                         s = tt * c;
@@ -354,9 +358,9 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
                 if (s == 0.0) continue;
                 const double c = rc[k];
                 const int lo = rl[k], hi = rh[k];
-                const double ap = A[lo * kMaxP + j], aq = A[hi * kMaxP + j];
-                A[lo * kMaxP + j] = c * ap - s * aq;
-                A[hi * kMaxP + j] = s * ap + c * aq;
+                const double ap = A[lo * kJs + j], aq = A[hi * kJs + j];
+                A[lo * kJs + j] = c * ap - s * aq;
+                A[hi * kJs + j] = s * ap + c * aq;
             }
             __syncthreads();
             // columns lo, hi of every pair, in A and in V (disjoint columns)
@@ -366,12 +370,12 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
                 if (s == 0.0) continue;
                 const double c = rc[k];
                 const int lo = rl[k], hi = rh[k];
-                const double ap = A[j * kMaxP + lo], aq = A[j * kMaxP + hi];
-                A[j * kMaxP + lo] = c * ap - s * aq;
-                A[j * kMaxP + hi] = s * ap + c * aq;
-                const double vp = V[j * p + lo], vq = V[j * p + hi];
-                V[j * p + lo] = c * vp - s * vq;
-                V[j * p + hi] = s * vp + c * vq;
+                const double ap = A[j * kJs + lo], aq = A[j * kJs + hi];
+                A[j * kJs + lo] = c * ap - s * aq;
+                A[j * kJs + hi] = s * ap + c * aq;
+                const double vp = V[j * kJs + lo], vq = V[j * kJs + hi];
+                V[j * kJs + lo] = c * vp - s * vq;
+                V[j * kJs + hi] = s * vp + c * vq;
             }
             __syncthreads();
         }
@@ -381,7 +385,7 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
         for (int i = 0; i < p; ++i) order[i] = i;
         for (int i = 1; i < p; ++i) {
             int x = order[i], j = i - 1;
-            while (j >= 0 && A[order[j] * kMaxP + order[j]] > A[x * kMaxP + x]) {
+            while (j >= 0 && A[order[j] * kJs + order[j]] > A[x * kJs + x]) {
                 order[j + 1] = order[j];
                 --j;
             }
@@ -391,9 +395,9 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double* __restr
     __syncthreads();
     for (int i = t; i < p * p; i += kJacobiThreads) {
         const int r = i / p, c = i % p;
-        Q[r * p + c] = V[r * p + order[c]];
+        Q[r * p + c] = V[r * kJs + order[c]];
     }
-    for (int i = t; i < p; i += kJacobiThreads) theta[i] = A[order[i] * kMaxP + order[i]];
+    for (int i = t; i < p; i += kJacobiThreads) theta[i] = A[order[i] * kJs + order[i]];
 }
 
 // residual R = L X - X diag(theta) of the first m columns: its per-block
@@ -458,7 +462,7 @@ struct Eig {
     hipStream_t st;
     uint64_t seed;
     int fix_round;
-    double *d, *dinv, *S, *LS, *T, *U, *part, *G, *M, *V, *theta, *cs, *res, *small;
+    double *d, *dinv, *S, *LS, *T, *U, *part, *G, *M, *theta, *cs, *res, *small;
     int* flag;
     int32_t *ppos, *prow;  // row pieces of the Laplacian product
     double* ppart;         // their partial sums [npieces][p]
@@ -539,7 +543,7 @@ struct Eig {
     int ritz_small(const double* A, const double* LA, int p) {
         GR_TRY(gram(A, LA, p, p, G));
         hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(kJacobiThreads), 0, st, (const double*)G, p, 40,
-                           theta, M, V);
+                           theta, M);
         GR_LAUNCHED("jacobi");
         return GR_OK;
     }
@@ -720,7 +724,6 @@ int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
     s.part = ws.take<double>((size_t)kRowBlocks * kMaxP * kMaxP);
     s.G = ws.take<double>(kMaxP * kMaxP);
     s.M = ws.take<double>(kMaxP * kMaxP);
-    s.V = ws.take<double>(kMaxP * kMaxP);
     s.theta = ws.take<double>(kMaxP);
     s.cs = ws.take<double>(kMaxP);
     s.res = ws.take<double>(kMaxP);
