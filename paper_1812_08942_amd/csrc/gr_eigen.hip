@@ -56,7 +56,18 @@ __global__ void __launch_bounds__(kE) k_spmm_pieces(const int32_t* __restrict__ 
     const int32_t e0 = rp[v] + (int32_t)(k - ppos[v]) * ep;
     const int32_t e1 = min(e0 + ep, rp[v + 1]);
     double s = 0.0;
-    for (int32_t e = e0; e < e1; ++e) s = fma((double)w[e], X[(int64_t)col[e] * ld + c], s);
+    int32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {  // four gathers in flight, summed in entry order
+        double xv[4], wv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            wv[u] = (double)w[e + u];
+            xv[u] = X[(int64_t)col[e + u] * ld + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = fma(wv[u], xv[u], s);
+    }
+    for (; e < e1; ++e) s = fma((double)w[e], X[(int64_t)col[e] * ld + c], s);
     part[k * p + c] = s;
 }
 
