@@ -316,6 +316,20 @@ def prolongation_dense(agg, n_coarse):
     return P
 
 
+def restrict_mean(agg, n_coarse, F):
+    """The reduced data set of Alg. 6, F_R = H_G^R F, with H_G^R read as the
+    averaging restriction for data (row I of F_R is the mean of the rows of
+    F over the nodes of aggregate I).  FP64 sums in node order, then one
+    rounding to float32, as the library returns it."""
+    agg = np.asarray(agg, np.int64)
+    F = np.asarray(F, np.float64)
+    sums = np.zeros((n_coarse, F.shape[1]))
+    for v in range(agg.size):          # node order, one row at a time
+        sums[agg[v]] += F[v]
+    cnt = np.bincount(agg, minlength=n_coarse).astype(np.float64)
+    return (sums / cnt[:, None]).astype(np.float32)
+
+
 def n_components(n, row_ptr, col) -> int:
     import scipy.sparse as sp
     import scipy.sparse.csgraph as cg

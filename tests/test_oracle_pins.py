@@ -613,3 +613,40 @@ def test_sgd_power_vector_and_sensitivity_against_dense_eigen():
         wm[e] -= hh
         fd = (gen(wp)[0][-1] - gen(wm)[0][-1]) / (2 * hh)
         assert abs(fd - sens[e]) <= 1e-5 * max(1.0, abs(fd))
+
+
+# -------------------------------------------------- data restriction (Alg. 6)
+
+def test_restrict_mean_closed_forms():
+    """F_R = H_G^R F as the averaging restriction: constant data stays
+    constant, the identity aggregation returns F, indicator data gives the
+    fraction of each aggregate's members in the set, and count-weighted rows
+    of F_R add up to the column sums of F."""
+    rng = np.random.default_rng(3)
+    n, nc, d = 500, 37, 5
+    agg = np.concatenate([np.arange(nc), rng.integers(0, nc, n - nc)]).astype(np.int32)
+    rng.shuffle(agg)
+    cnt = np.bincount(agg, minlength=nc)
+    # constant columns (values exact in float32)
+    F = np.tile(np.array([1.5, -2.0, 0.25, 3.0, 0.0], np.float32), (n, 1))
+    assert np.array_equal(O.restrict_mean(agg, nc, F), F[:nc])
+    # identity aggregation
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    assert np.array_equal(O.restrict_mean(np.arange(n, dtype=np.int32), n, X), X)
+    # indicator of a node set: the fraction of members inside it
+    inset = rng.random(n) < 0.3
+    frac = np.array([inset[agg == i].mean() for i in range(nc)])
+    got = O.restrict_mean(agg, nc, inset.astype(np.float32)[:, None])[:, 0]
+    assert np.allclose(got, frac, rtol=1e-7, atol=0)
+    # sum preservation
+    R = O.restrict_mean(agg, nc, X).astype(np.float64)
+    assert np.allclose((R * cnt[:, None]).sum(axis=0), X.astype(np.float64).sum(axis=0),
+                       rtol=1e-6, atol=1e-5)
+
+
+def test_restrict_mean_hand_example():
+    """Three nodes in aggregate 0 and one in aggregate 1, worked by hand."""
+    agg = np.array([0, 1, 0, 0], np.int32)
+    F = np.array([[1.0, 10.0], [7.0, -1.0], [2.0, 20.0], [6.0, 0.0]], np.float32)
+    R = O.restrict_mean(agg, 2, F)
+    assert np.array_equal(R, np.array([[3.0, 10.0], [7.0, -1.0]], np.float32))
