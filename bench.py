@@ -306,13 +306,14 @@ def extras_report(G, wl, dg, r, ldf):
     * Rayleigh quotients of 10 vectors and their edge gradients on the
       reduced graph (random FP64 vectors and edge weights: timing only);
     * Alg. 1 edge scaling of a spanning sparsifier P of the reduced graph G
-      (maximum spanning forest plus the heaviest 10% of the other edges).
+      (maximum spanning forest plus the heaviest 10% of the other edges);
+    * the data restriction of Alg. 6 through the reduction's final map.
     A failure is reported in place of the figures."""
     import torch
 
     from workloads import graphs as W
 
-    out = {}
+    out = {"restrict_mean": restrict_report(G, r.agg, r.coarse.n)}
     try:
         K, S = wl.K, wl.sweeps
         el = G.gr_edge_list(dg)
@@ -363,13 +364,31 @@ def extras_report(G, wl, dg, r, ldf):
     return out
 
 
+def restrict_report(G, agg, n_coarse, d=64):
+    """Wall time of the data restriction of Alg. 6 (F_R = H_G^R F, the mean
+    of F over each aggregate) through the reduction's final map, for random
+    float32 data of d columns; bytes = one read of F and one write of F_R."""
+    import torch
+
+    try:
+        n = agg.numel()
+        gen = torch.Generator(device=agg.device).manual_seed(5)
+        F = torch.randn(n, d, generator=gen, device=agg.device)
+        ms, _ = _timed(lambda: G.gr_restrict_mean(agg, n_coarse, F), 5)
+        gbs = (n * d * 4 + n_coarse * d * 4 + n * 4) / (ms * 1e-3) / 1e9
+        log(f"data restriction ({n} x {d} -> {n_coarse}): {ms:.3f} ms")
+        return {"ms": ms, "n": n, "n_coarse": int(n_coarse), "d": d,
+                "compulsory_GB_per_s": gbs}
+    except Exception as e:  # keep the other figures
+        return {"error": repr(e)}
+
+
 def secondary_extras(G, keep):
     """The GS backward on the second workload, in its own configuration
     (vector storage type, K, sweeps; its colouring when it prescribes one)."""
     import torch
 
     g, wl, r, dg = keep
-    del r
     try:
         el = G.gr_edge_list(dg)
         if g.colours is not None:
@@ -377,7 +396,8 @@ def secondary_extras(G, keep):
             nc = g.n_colours
         else:
             colours, nc = G.gr_colour_greedy(dg, 1, True)
-        return {"gs_vjp": vjp_report(G, dg, el, colours, nc, wl.K, wl.sweeps, wl.dtype)}
+        return {"gs_vjp": vjp_report(G, dg, el, colours, nc, wl.K, wl.sweeps, wl.dtype),
+                "restrict_mean": restrict_report(G, r.agg, r.coarse.n)}
     except Exception as e:  # keep the other figures
         return {"gs_vjp": {"error": repr(e)}}
 

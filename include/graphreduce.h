@@ -248,6 +248,26 @@ int gr_galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t
                 int32_t* c_col, float* c_w, int64_t* nnz_coarse, void* ws, size_t ws_bytes,
                 void* stream);
 
+/*
+ * gr_restrict_mean — the reduced data set of the multilevel data
+ * visualisation (Alg. 6): F_R = H_G^R F, with the G-to-R mapping read as
+ * the averaging restriction for data.  Row I of F_R is the mean of the rows
+ * of F over the nodes v with agg[v] = I.
+ *   agg  int32[n] (device): the aggregate of every node, in [0, n_coarse);
+ *        every aggregate must have a member.
+ *   F    float32[n][d] (device, row-major): one data point per node.
+ *   F_R  float32[n_coarse][d] (device, caller-owned): the output.
+ * Sums are taken in FP64, with the members of an aggregate in node order
+ * and in fixed pieces of 256; each row is divided by the member count and
+ * rounded once to float32.  Deterministic.  Errors: GR_EINVAL for bad
+ * sizes, an id out of range or an empty aggregate (F_R is then
+ * unspecified).  Workspace: gr_restrict_workspace.  Synchronises (reads
+ * the validity flags and the piece count).
+ */
+int gr_restrict_workspace(int64_t n, int64_t n_coarse, int32_t d, size_t* bytes);
+int gr_restrict_mean(const int32_t* agg, int64_t n, int64_t n_coarse, int32_t d, const float* F,
+                     float* F_R, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------
  * Edge-weight derivatives (serving the SGD edge scaling of Sec. 3.3.4).
  * Edge weights are one FP64 value per undirected edge: edge e = (p, q),

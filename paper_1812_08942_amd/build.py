@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgraphreduce.so")
-SOURCES = ["gr_prims.hip", "gr_phase_a.hip", "gr_affinity.hip", "gr_aggregate.hip", "gr_autograd.hip",
+SOURCES = ["gr_prims.hip", "gr_phase_a.hip", "gr_affinity.hip", "gr_aggregate.hip", "gr_restrict.hip", "gr_autograd.hip",
            "gr_sgd.hip", "gr_eigen.hip", "gr_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

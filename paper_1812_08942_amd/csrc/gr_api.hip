@@ -248,6 +248,27 @@ int gr_galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t
                     S(stream));
 }
 
+int gr_restrict_workspace(int64_t n, int64_t n_coarse, int32_t d, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || n_coarse < 0 || d < 1) return set_error(GR_EINVAL, "bad size");
+    *bytes = restrict_workspace(n, n_coarse, d);
+    return GR_OK;
+}
+
+int gr_restrict_mean(const int32_t* agg, int64_t n, int64_t n_coarse, int32_t d, const float* F,
+                     float* F_R, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (n < 0 || d < 1) return set_error(GR_EINVAL, "bad size");
+    if (n >= (int64_t(1) << 31)) return set_error(GR_EINVAL, "n must be below 2^31");
+    if (n_coarse < 0 || n_coarse > n || (n > 0 && n_coarse < 1))
+        return set_error(GR_EINVAL, "n_coarse out of range");
+    if (n == 0) return GR_OK;
+    if (!agg || !F || !F_R || !ws) return set_error(GR_EINVAL, "NULL argument");
+    Arena A(ws, ws_bytes);
+    return restrict_mean(agg, n, n_coarse, d, F, F_R, A, S(stream));
+}
+
 int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws, size_t ws_bytes,
               void* stream) {
     clear_error();

@@ -183,6 +183,11 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c
              int32_t* c_col, float* c_w, int64_t* nnz_coarse, const int32_t* long_rows,
              int64_t n_long, Arena& ws, hipStream_t st);
 
+// ------------------------------------------------ data restriction (Alg. 6)
+size_t restrict_workspace(int64_t n, int64_t nc, int32_t d);
+int restrict_mean(const int32_t* agg, int64_t n, int64_t nc, int32_t d, const float* F, float* FR,
+                  Arena& ws, hipStream_t st);
+
 // ------------------------------------------------------ edge derivatives
 int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t* n_edges,
               Arena& ws, hipStream_t st);

@@ -120,6 +120,8 @@ _SIGNATURES = {
                      ctypes.c_int),
     "gr_galerkin": ([_G, _P, _I64, _P, _P, _P, ctypes.POINTER(_I64), _P, _SZ,
                      _P], ctypes.c_int),
+    "gr_restrict_workspace": ([_I64, _I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_restrict_mean": ([_P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
     "gr_edge_list": ([_G, _P, _P, _P, ctypes.POINTER(_I64), _P, _SZ, _P],
                      ctypes.c_int),
     "gr_rq_forward": ([_I64, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P, _P,
@@ -380,6 +382,28 @@ def gr_galerkin(g: DeviceGraph, agg, n_coarse, ws=None):
                               _stream()))
     k = int(m.value)
     return DeviceGraph(c_rp, c_col[:k].clone(), c_w[:k].clone())
+
+
+def gr_restrict_workspace(n, n_coarse, d) -> int:
+    out = _SZ(0)
+    _check(load().gr_restrict_workspace(int(n), int(n_coarse), int(d), ctypes.byref(out)))
+    return int(out.value)
+
+
+def gr_restrict_mean(agg, n_coarse, F):
+    """F_R (float32 [n_coarse][d]): the mean of the rows of F (float32
+    [n][d], device) over each aggregate of `agg` (int32 [n], device)."""
+    if F.dtype != torch.float32 or F.dim() != 2 or not F.is_contiguous():
+        raise ValueError("F must be a contiguous float32 [n][d] tensor")
+    if agg.dtype != torch.int32 or agg.numel() != F.shape[0]:
+        raise ValueError("agg must be int32 [n]")
+    n, d = F.shape
+    nbytes = gr_restrict_workspace(n, n_coarse, d)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=F.device)
+    FR = torch.empty((max(int(n_coarse), 1), d), dtype=torch.float32, device=F.device)
+    _check(load().gr_restrict_mean(_ptr(agg), n, int(n_coarse), d, _ptr(F), _ptr(FR),
+                                   _ptr(ws), nbytes, _stream()))
+    return FR[:int(n_coarse)]
 
 
 @dataclasses.dataclass
