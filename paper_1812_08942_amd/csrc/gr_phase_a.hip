@@ -28,13 +28,17 @@ __global__ void k_check_rowptr(const int32_t* __restrict__ rp, int64_t n, int64_
     if (!ok) atomicOr(bad, 1);
 }
 
+// G lanes per row (one below a mean degree of 8, else about half the mean
+// degree, at most a wave): every entry is checked on its own
 __global__ void k_check_entries(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                const float* __restrict__ w, int64_t n, int32_t* __restrict__ bad) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                const float* __restrict__ w, int64_t n, int G,
+                                int32_t* __restrict__ bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = t / G;
     if (v >= n) return;
-    int32_t e0 = rp[v], e1 = rp[v + 1];
+    const int32_t e0 = rp[v], e1 = rp[v + 1];
     int flags = 0;
-    for (int32_t e = e0; e < e1; ++e) {
+    for (int32_t e = e0 + (int32_t)(t % G); e < e1; e += G) {
         int32_t j = col[e];
         float wv = w[e];
         if (j < 0 || j >= n || j == v) { flags |= 2; break; }
@@ -65,8 +69,10 @@ int validate_graph(const gr_graph* g, Arena& ws, hipStream_t st) {
     GR_HIP(hipStreamSynchronize(st));
     if (hb) return set_error(GR_ECSR, "row_ptr is not a monotone offset array with row_ptr[0]=0, row_ptr[n]=nnz");
     if (g->n > 0) {
-        hipLaunchKernelGGL(k_check_entries, dim3(blocks_for(g->n, kThreads)), dim3(kThreads), 0, st,
-                           g->row_ptr, g->col, g->w, g->n, bad);
+        int G = g->nnz < 8 * g->n ? 1 : 4;
+        while (G > 1 && G < kWave && G * 2 <= g->nnz / g->n) G *= 2;
+        hipLaunchKernelGGL(k_check_entries, dim3(blocks_for(g->n * G, kThreads)), dim3(kThreads), 0,
+                           st, g->row_ptr, g->col, g->w, g->n, G, bad);
         GR_LAUNCHED("check entries");
         GR_HIP(hipMemcpyAsync(&hb, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));

@@ -85,11 +85,23 @@ def test_validate_accepts_and_rejects():
         ("negative weight", g.row_ptr, g.col, -g.w),
         ("row_ptr not monotone", np.array([0, 1, 3, 2, 5, 9, 10]), g.col, g.w),
     ]
+    # the same on a dense graph, whose rows are checked by several lanes each
+    k = W.complete(40)
+    swapped = k.col.copy()
+    e0 = k.row_ptr[7] + 10
+    swapped[e0], swapped[e0 + 1] = swapped[e0 + 1], swapped[e0]
+    bad += [
+        ("asymmetric weight (dense)", k.row_ptr, k.col,
+         np.where(np.arange(k.nnz) == 777, 2.0, 1.0)),
+        ("columns out of order (dense)", k.row_ptr, swapped, k.w),
+    ]
     for what, rp, cl, w in bad:
         say(f"validate rejects {what}")
         with pytest.raises(G.GraphReduceError) as e:
             G.gr_validate(G.DeviceGraph.from_numpy(rp, cl, w, dev))
         assert e.value.code == -2, what
+    say("validate accepts complete_40")
+    G.gr_validate(dgraph(k, dev))
 
 
 def test_init_vectors_match_oracle():
