@@ -380,6 +380,19 @@ int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double t
                       int32_t max_iter, int32_t degree, uint64_t seed, double* eig,
                       gr_eig_report* report, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * gr_laplacian_eigpairs — gr_laplacian_eigs with the eigenvectors: the same
+ * solve (same arguments, same eig and report), and U double[n][n_eig]
+ * (device, row-major, caller-owned) receives the Ritz vector of eig[i] in
+ * column i: orthonormal, orthogonal to the all-one vector, each to within
+ * the solve's residual (sign arbitrary; within a repeated eigenvalue any
+ * orthonormal basis of its space).  Columns past the block are NaN, like
+ * their eigenvalues.  Workspace: gr_eig_workspace.  Synchronises.
+ */
+int gr_laplacian_eigpairs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+                          int32_t max_iter, int32_t degree, uint64_t seed, double* eig, double* U,
+                          gr_eig_report* report, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------
  * Constrained-SGD edge scaling (Alg. 1, Sec. 3.3.4), FP64.
  * ------------------------------------------------------------------- */

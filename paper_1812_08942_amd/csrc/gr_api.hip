@@ -485,10 +485,9 @@ int gr_eig_workspace(int64_t n, int32_t n_eig, size_t* bytes) {
     return GR_OK;
 }
 
-int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
-                      int32_t max_iter, int32_t degree, uint64_t seed, double* eig,
-                      gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
-    clear_error();
+static int eigs_common(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+                       int32_t max_iter, int32_t degree, uint64_t seed, double* eig, double* U,
+                       gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
     GR_TRY(check_graph_args(g));
     if (n_eig < 1 || n_eig > 32) return set_error(GR_EINVAL, "n_eig must lie in [1, 32]");
     if (method < GR_EIG_AUTO || method > GR_EIG_LOBPCG) return set_error(GR_EINVAL, "unknown method");
@@ -498,10 +497,32 @@ int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double t
     if (report) memset(report, 0, sizeof(*report));
     if (g->n < 2) {
         for (int i = 0; i < n_eig; ++i) eig[i] = NAN;
+        if (U && g->n == 1) {  // all-ones bytes: NaN
+            GR_HIP(hipMemsetAsync(U, 0xff, sizeof(double) * n_eig, S(stream)));
+            GR_HIP(hipStreamSynchronize(S(stream)));
+        }
         return GR_OK;
     }
     Arena A(ws, ws_bytes);
-    return laplacian_eigs(g, n_eig, method, tol, max_iter, degree, seed, eig, report, A, S(stream));
+    return laplacian_eigs(g, n_eig, method, tol, max_iter, degree, seed, eig, U, report, A,
+                          S(stream));
+}
+
+int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+                      int32_t max_iter, int32_t degree, uint64_t seed, double* eig,
+                      gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    return eigs_common(g, n_eig, method, tol, max_iter, degree, seed, eig, nullptr, report, ws,
+                       ws_bytes, stream);
+}
+
+int gr_laplacian_eigpairs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+                          int32_t max_iter, int32_t degree, uint64_t seed, double* eig, double* U,
+                          gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!U && g && g->n > 0) return set_error(GR_EINVAL, "U is NULL");
+    return eigs_common(g, n_eig, method, tol, max_iter, degree, seed, eig, U, report, ws,
+                       ws_bytes, stream);
 }
 
 int gr_sgd_workspace(int64_t n, int64_t nnz_g, int64_t nnz_p, int64_t p_edges, size_t* bytes) {

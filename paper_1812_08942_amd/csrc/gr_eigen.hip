@@ -717,9 +717,19 @@ static int run_lobpcg(Eig& s, int n_eig, int m, double b, double tol, int max_it
     return GR_OK;
 }
 
+// U[v][i] = the Ritz vector i (column i of the block, stride ld), NaN past m
+__global__ void k_copy_vectors(const double* __restrict__ S, int ld, int m, int64_t n, int k,
+                               double* __restrict__ U) {
+    const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t v = t / k;
+    const int i = (int)(t % k);
+    U[t] = i < m ? S[v * ld + i] : __builtin_nan("");
+}
+
 int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol, int32_t max_iter,
-                   int32_t degree, uint64_t seed, double* eig_out, gr_eig_report* rep, Arena& ws,
-                   hipStream_t st) {
+                   int32_t degree, uint64_t seed, double* eig_out, double* vec_out,
+                   gr_eig_report* rep, Arena& ws, hipStream_t st) {
     Eig s{};
     s.g = g;
     s.n = g->n;
@@ -800,6 +810,12 @@ int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
     GR_HIP(hipMemcpyAsync(&flag, s.flag, sizeof(int), hipMemcpyDeviceToHost, st));
     GR_HIP(hipStreamSynchronize(st));
     for (int i = 0; i < n_eig; ++i) eig_out[i] = i < m ? th[i] : NAN;
+    if (vec_out) {  // the block holds the Ritz vectors of th, in ascending order
+        hipLaunchKernelGGL(k_copy_vectors, dim3(blocks_for(n * n_eig, kE)), dim3(kE), 0, st,
+                           (const double*)s.S, s.ld, m, n, n_eig, vec_out);
+        GR_LAUNCHED("copy vectors");
+        GR_HIP(hipStreamSynchronize(st));
+    }
     if (rep) {
         rep->iterations = it;
         rep->block = m;

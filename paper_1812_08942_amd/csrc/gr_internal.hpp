@@ -198,8 +198,8 @@ int expand_weights(const int32_t* eoe, int64_t nnz, int64_t E, const float* wE, 
                    hipStream_t st);
 size_t eig_workspace(int64_t n, int32_t n_eig);
 int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol, int32_t max_iter,
-                   int32_t degree, uint64_t seed, double* eig_out, gr_eig_report* rep, Arena& ws,
-                   hipStream_t st);
+                   int32_t degree, uint64_t seed, double* eig_out, double* vec_out,
+                   gr_eig_report* rep, Arena& ws, hipStream_t st);
 size_t sgd_workspace(int64_t n, int64_t nnzG, int64_t nnzP, int64_t E);
 int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t E,
               const int32_t* eu, const int32_t* ev, double* wP, const gr_sgd_params* prm,

@@ -133,6 +133,10 @@ _SIGNATURES = {
                            ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(gr_eig_report), _P, _SZ, _P],
                           ctypes.c_int),
+    "gr_laplacian_eigpairs": ([_G, _I32, _I32, ctypes.c_double, _I32, _I32, _U64,
+                               ctypes.POINTER(ctypes.c_double), _P,
+                               ctypes.POINTER(gr_eig_report), _P, _SZ, _P],
+                              ctypes.c_int),
     "gr_sgd_workspace": ([_I64, _I64, _I64, _I64, ctypes.POINTER(_SZ)],
                          ctypes.c_int),
     "gr_sgd_scale": ([_G, _G, _P, _I64, _P, _P, _P,
@@ -590,6 +594,35 @@ EIG_METHODS = {"auto": GR_EIG_AUTO, "chebyshev": GR_EIG_CHEBYSHEV,
                "lobpcg": GR_EIG_LOBPCG}
 
 
+def _eig_report(rep):
+    names = {GR_EIG_CHEBYSHEV: "chebyshev", GR_EIG_LOBPCG: "lobpcg"}
+    return {"iterations": int(rep.iterations), "block": int(rep.block),
+            "residual": float(rep.residual),
+            "lambda_max_bound": float(rep.lambda_max_bound),
+            "cholesky_warnings": int(rep.cholesky_warnings),
+            "method": names.get(int(rep.method), "none"),
+            "restarts": int(rep.restarts)}
+
+
+def gr_laplacian_eigpairs(g: DeviceGraph, n_eig=10, method="auto", tol=1e-12,
+                          max_iter=1000, degree=80, seed=1):
+    """As gr_laplacian_eigs, plus the eigenvectors: returns (numpy array of
+    eigenvalues, float64 device tensor U [n][n_eig], report dict)."""
+    import numpy as np
+
+    nbytes = gr_eig_workspace(g.n, n_eig)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.row_ptr.device)
+    U = torch.empty((max(g.n, 1), n_eig), dtype=torch.float64, device=g.row_ptr.device)
+    out = (ctypes.c_double * n_eig)()
+    rep = gr_eig_report()
+    cg = g.c()
+    _check(load().gr_laplacian_eigpairs(ctypes.byref(cg), n_eig, EIG_METHODS[method],
+                                        float(tol), int(max_iter), int(degree),
+                                        seed & (2**64 - 1), out, _ptr(U), ctypes.byref(rep),
+                                        _ptr(ws), nbytes, _stream()))
+    return np.array(out[:], dtype=np.float64), U[:g.n], _eig_report(rep)
+
+
 def gr_laplacian_eigs(g: DeviceGraph, n_eig=10, method="auto", tol=1e-12,
                       max_iter=1000, degree=80, seed=1):
     """The n_eig smallest Laplacian eigenvalues on the complement of the
@@ -605,11 +638,4 @@ def gr_laplacian_eigs(g: DeviceGraph, n_eig=10, method="auto", tol=1e-12,
                                     float(tol), int(max_iter), int(degree),
                                     seed & (2**64 - 1), out, ctypes.byref(rep),
                                     _ptr(ws), nbytes, _stream()))
-    names = {GR_EIG_CHEBYSHEV: "chebyshev", GR_EIG_LOBPCG: "lobpcg"}
-    return np.array(out[:], dtype=np.float64), {
-        "iterations": int(rep.iterations), "block": int(rep.block),
-        "residual": float(rep.residual),
-        "lambda_max_bound": float(rep.lambda_max_bound),
-        "cholesky_warnings": int(rep.cholesky_warnings),
-        "method": names.get(int(rep.method), "none"),
-        "restarts": int(rep.restarts)}
+    return np.array(out[:], dtype=np.float64), _eig_report(rep)

@@ -120,3 +120,37 @@ def test_seed_independent():
     a, _ = _eigs(g, seed=1)
     b, _ = _eigs(g, seed=2)
     assert np.allclose(a, b, rtol=RTOL, atol=0)
+
+
+@pytest.mark.parametrize("method", ["chebyshev", "lobpcg"])
+def test_eigenvectors_match_oracle(method):
+    """The Ritz vectors returned with the eigenvalues: orthonormal,
+    orthogonal to the all-one vector, L u = lambda u to the solve's
+    tolerance, and (for eigenvalues separated from their neighbours) the
+    dense oracle's eigenvector up to sign."""
+    from paper_1812_08942_amd import graphreduce as G
+    for g in (W.knn2d(3000, 10, seed=4), W.chung_lu(5000, mean_deg=30.0, seed=3)):
+        say(f"eigpairs {g.name} {method}")
+        lam, U, rep = G.gr_laplacian_eigpairs(
+            G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, _dev()), 10, method=method)
+        assert rep["method"] == method
+        U = U.cpu().numpy()
+        L = O.laplacian_dense(g.n, g.row_ptr, g.col, g.w)
+        rlam, rU = O.laplacian_eigpairs(g.n, g.row_ptr, g.col, g.w, 10)
+        assert np.allclose(lam, rlam, rtol=RTOL, atol=0)
+        assert np.allclose(U.T @ U, np.eye(10), atol=1e-10)
+        assert np.max(np.abs(U.sum(axis=0))) <= 1e-9 * np.sqrt(g.n)
+        res = np.linalg.norm(L @ U - U * lam, axis=0)
+        assert np.all(res <= 1e-6 * 2 * np.max(np.diag(L))), res
+        gap = np.minimum(np.diff(np.r_[0.0, rlam]), np.diff(np.r_[rlam, np.inf]))
+        for i in np.flatnonzero(gap > 1e-3 * rlam):
+            assert abs(abs(U[:, i] @ rU[:, i]) - 1.0) <= 1e-8, (g.name, i)
+
+
+def test_eigenvectors_of_a_one_node_graph_are_nan():
+    from paper_1812_08942_amd import graphreduce as G
+    say("eigpairs of a single node")
+    g1 = G.DeviceGraph.from_numpy(np.zeros(2, np.int32), np.zeros(0, np.int32),
+                                  np.zeros(0, np.float32), _dev())
+    lam, U, _ = G.gr_laplacian_eigpairs(g1, 3)
+    assert np.all(np.isnan(lam)) and U.shape == (1, 3) and bool(torch.isnan(U).all())
