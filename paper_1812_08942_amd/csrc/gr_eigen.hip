@@ -168,12 +168,26 @@ __global__ void __launch_bounds__(kE) k_colsum_part(const double* __restrict__ X
     }
 }
 
+// s = sum over b of part[b * stride + idx], in b order, eight loads in flight
+__device__ inline double strided_sum(const double* __restrict__ part, int nb, int64_t stride,
+                                     int64_t idx) {
+    double s = 0.0;
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * stride + idx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; b < nb; ++b) s += part[(int64_t)b * stride + idx];
+    return s;
+}
+
 __global__ void k_colsum_final(const double* __restrict__ part, int nb, int p, double* __restrict__ out) {
     int c = threadIdx.x;
     if (c >= p) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * p + c];
-    out[c] = s;
+    out[c] = strided_sum(part, nb, p, c);
 }
 
 __global__ void k_sub_colmean(double* __restrict__ X, int64_t n, int p, int ld,
@@ -222,9 +236,7 @@ __global__ void __launch_bounds__(kE) k_gram_part(const double* __restrict__ A,
 __global__ void k_gram_final(const double* __restrict__ part, int nb, int cnt, double* __restrict__ out) {
     int idx = blockIdx.x * kE + threadIdx.x;
     if (idx >= cnt) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * cnt + idx];
-    out[idx] = s;
+    out[idx] = strided_sum(part, nb, cnt, idx);
 }
 
 // Column-scaled Cholesky QR factor: with S = diag(G)^{-1/2}, factor
