@@ -248,11 +248,15 @@ __global__ void __launch_bounds__(kMaxP) k_chol_inv(const double* __restrict__ G
                                                     double shift, double* __restrict__ M,
                                                     int* __restrict__ flag) {
     __shared__ double R[kMaxP * kMaxP];
+    __shared__ double Gs[kMaxP * kMaxP];  // G, staged once (row stride p)
+    __shared__ double Xs[kMaxP * kMaxP];  // column t of R^{-1} in Xs[.. * kMaxP + t]
     __shared__ double sc[kMaxP];
     __shared__ double tj[kMaxP];
     const int t = threadIdx.x;
+    for (int i = t; i < p * p; i += kMaxP) Gs[i] = G[i];
+    __syncthreads();
     if (t < p) {
-        const double g = G[t * p + t];
+        const double g = Gs[t * p + t];
         sc[t] = g > 0.0 ? 1.0 / sqrt(g) : 1.0;
     }
     __syncthreads();
@@ -260,7 +264,7 @@ __global__ void __launch_bounds__(kMaxP) k_chol_inv(const double* __restrict__ G
     for (int j = 0; j < p; ++j) {
         double s = 0.0;
         if (t >= j && t < p) {
-            s = G[j * p + t] * sc[j] * sc[t] + (t == j ? sh : 0.0);
+            s = Gs[j * p + t] * sc[j] * sc[t] + (t == j ? sh : 0.0);
             for (int k = 0; k < j; ++k) s -= R[k * kMaxP + j] * R[k * kMaxP + t];
             tj[t] = s;
         }
@@ -276,13 +280,12 @@ __global__ void __launch_bounds__(kMaxP) k_chol_inv(const double* __restrict__ G
     }
     // column t of R^{-1} by back substitution, scaled rows into M
     if (t < p) {
-        double x[kMaxP];
         for (int i = t; i >= 0; --i) {
             double s = (i == t) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= t; ++k) s -= R[i * kMaxP + k] * x[k];
-            x[i] = s / R[i * kMaxP + i];
+            for (int k = i + 1; k <= t; ++k) s -= R[i * kMaxP + k] * Xs[k * kMaxP + t];
+            Xs[i * kMaxP + t] = s / R[i * kMaxP + i];
         }
-        for (int i = 0; i < p; ++i) M[i * p + t] = i <= t ? sc[i] * x[i] : 0.0;
+        for (int i = 0; i < p; ++i) M[i * p + t] = i <= t ? sc[i] * Xs[i * kMaxP + t] : 0.0;
     }
 }
 
