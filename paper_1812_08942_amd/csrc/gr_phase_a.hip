@@ -792,7 +792,22 @@ __global__ void k_perm_entries(const int32_t* __restrict__ rp, const int32_t* __
     const int l = threadIdx.x % G;
     if (v >= n) return;
     const int32_t e0 = rp[v], e1 = rp[v + 1], o = nrp[iperm[v]];
-    for (int32_t e = e0 + l; e < e1; e += G) {
+    int32_t e = e0 + l;
+    for (; e + 3 * G < e1; e += 4 * G) {  // four entries in flight per lane (hub rows)
+        int32_t c[4];
+        float x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = iperm[col[e + u * G]];
+            x[u] = w[e + u * G];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ncol[o + (e + u * G - e0)] = c[u];
+            nw[o + (e + u * G - e0)] = x[u];
+        }
+    }
+    for (; e < e1; e += G) {
         ncol[o + (e - e0)] = iperm[col[e]];
         nw[o + (e - e0)] = w[e];
     }
