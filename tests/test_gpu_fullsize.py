@@ -166,6 +166,20 @@ def test_power_law_full_size_multilevel_and_eigenvalues(power_law):
     ref = O.laplacian_eigs(n_c, crp, ccl, ccw, 10)
     assert np.allclose(lam, ref, rtol=1e-9, atol=0), (lam, ref)
 
+    say("eigenvectors of the reduced graph")
+    lam2, U, rep2 = G.gr_laplacian_eigpairs(out.coarse, 10)
+    assert np.array_equal(lam2, lam)                   # the same solve
+    U = U.cpu().numpy()
+    import scipy.sparse as sp
+    rows = np.repeat(np.arange(n_c), np.diff(crp))
+    A = sp.csr_matrix((ccw.astype(np.float64), (rows, ccl)), shape=(n_c, n_c))
+    d = np.asarray(A.sum(axis=1)).ravel()
+    LU = d[:, None] * U - A @ U
+    assert np.allclose(U.T @ U, np.eye(10), atol=1e-10)
+    assert np.max(np.abs(U.sum(axis=0))) <= 1e-9 * np.sqrt(n_c)
+    res = np.linalg.norm(LU - U * lam, axis=0)
+    assert np.all(res <= 2.0 * rep2["residual"] + 1e-9 * rep2["lambda_max_bound"]), res
+
 
 @pytest.mark.timeout(900)
 def test_grid256_full_size_bf16(grid256):
@@ -246,6 +260,20 @@ def test_grid256_full_size_reduce(grid256):
     say(f"  {rep}")
     ref = O.laplacian_eigs(n_c, crp, ccl, ccw, 10)
     assert np.allclose(lam, ref, rtol=1e-9, atol=0), (lam, ref)
+
+    say("eigenvectors of the reduced graph")
+    lam2, U, rep2 = G.gr_laplacian_eigpairs(out.coarse, 10)
+    assert np.array_equal(lam2, lam)                   # the same solve
+    U = U.cpu().numpy()
+    import scipy.sparse as sp
+    rows = np.repeat(np.arange(n_c), np.diff(crp))
+    A = sp.csr_matrix((ccw.astype(np.float64), (rows, ccl)), shape=(n_c, n_c))
+    d = np.asarray(A.sum(axis=1)).ravel()
+    LU = d[:, None] * U - A @ U
+    assert np.allclose(U.T @ U, np.eye(10), atol=1e-10)
+    assert np.max(np.abs(U.sum(axis=0))) <= 1e-9 * np.sqrt(n_c)
+    res = np.linalg.norm(LU - U * lam, axis=0)
+    assert np.all(res <= 2.0 * rep2["residual"] + 1e-9 * rep2["lambda_max_bound"]), res
 
 
 @pytest.mark.timeout(600)
