@@ -585,6 +585,108 @@ def test_sgd_constraint_monotone_weights_and_falling_lambda_n():
     assert gen_lmax(r.w_P) < gen_lmax(w[keep])
 
 
+def _cycle5_path():
+    """G = the 5-cycle with unit weights, P = its path 0-1-2-3-4.  The
+    vector u = (2, 1, 0, -1, -2) is the dominant generalised eigenvector of
+    (L_G, L_P) whenever P's four weights are equal (L_P u = c (e_0 - e_4),
+    L_G u = 5 (e_0 - e_4)), so h_t stays parallel to u and every quantity of
+    Alg. 1 has a closed form."""
+    g_eu = np.array([0, 0, 1, 2, 3], np.int32)
+    g_ev = np.array([1, 4, 2, 3, 4], np.int32)
+    p_eu = np.array([0, 1, 2, 3], np.int32)
+    p_ev = np.array([1, 2, 3, 4], np.int32)
+    u = np.array([2.0, 1.0, 0.0, -1.0, -2.0])
+    return g_eu, g_ev, np.ones(5), p_eu, p_ev, np.ones(4), u
+
+
+def test_sgd_hand_worked_momentum_and_step_schedule():
+    """Three iterations of Alg. 1 worked by hand on the 5-cycle and its path
+    (Delta_bar = 0.03, K_max = 3: no guard trips).  With equal path weights
+    c: lambda_n = h^T L_G h = 5 / c (h = u / (2 sqrt c)), every path edge has
+    s = -lambda_n / (4c) = -5 / (4 c^2), and lambda_1 = min d_G/d_P = 1/c.
+      k = 1: eta_max = 0.1 * 1 / 1.25 = 0.08, dw = 0.08 * 1.25 = 0.1, c = 1.1
+      k = 2: eta = eta_max (lambda_n^(1) = lambda_n^(0));
+             dw = 0.9 * 0.1 + 0.08 * 5 / (4 * 1.1^2) = 0.09 + 0.1 / 1.21
+      k = 3: eta = (lambda_n^(2) / lambda_n^(0)) eta_max = 0.08 / 1.1;
+             dw = 0.9 dw_2 + (0.08 / 1.1) * 5 / (4 c_2^2)
+    A dropped or sign-flipped momentum term changes k = 2; an inverted or
+    missing step-size schedule changes k = 3.  Both modes agree bit for bit."""
+    from oracle import sgd as S
+
+    g_eu, g_ev, g_w, p_eu, p_ev, w0, u = _cycle5_path()
+    prm = S.SgdParams(alpha=0.9, eta_scale=0.1, eps=1e-3, k_max=3, delta_bar=0.03, t=2)
+    c1 = 1.1
+    dw2 = 0.09 + 0.1 / 1.21
+    c2 = c1 + dw2
+    dw3 = 0.9 * dw2 + (0.08 / 1.1) * 5.0 / (4.0 * c2 * c2)
+    c3 = c2 + dw3
+    res = {}
+    for mode in ("parallel", "sequential"):
+        r = S.sgd_scale(5, g_eu, g_ev, g_w, p_eu, p_ev, w0, prm, mode=mode, h0=u)
+        assert r.iterations == 3
+        assert np.allclose(r.w_P, c3, rtol=1e-13, atol=0), (mode, r.w_P, c3)
+        assert np.allclose(r.lambda_n, [5.0, 5.0 / c1, 5.0 / c2], rtol=1e-12, atol=0)
+        assert np.allclose(r.lambda_1, [1.0, 1.0 / c1, 1.0 / c2, 1.0 / c3], rtol=1e-13, atol=0)
+        res[mode] = r
+    assert np.array_equal(res["parallel"].w_P, res["sequential"].w_P)
+    assert res["parallel"].lambda_1 == res["sequential"].lambda_1
+
+
+def test_sgd_hand_worked_guard_both_modes():
+    """One iteration on the same pair with Delta_bar = 0.5, K_max = 20
+    (Delta = 2^-0.05): every path edge proposes dw = 0.1, and the guard
+    trips at the inner nodes, whose cap is 2/Delta - 2.
+      parallel: node 1 (likewise 2, 3) shares its cap between its two edges,
+        so every edge gets (2/Delta - 2)/2 and w = 1/Delta = 2^0.05;
+      sequential (the paper's edge loop, running d_P): edge (0,1) takes
+        min(2/Delta - 1, 2/Delta - 2) = 2/Delta - 2, which exhausts node 1,
+        so edge (1,2) gets 0; edge (2,3) again gets 2/Delta - 2 and (3,4) 0.
+    Either way lambda_1 lands exactly on lambda_1^(0) Delta = Delta."""
+    from oracle import sgd as S
+
+    g_eu, g_ev, g_w, p_eu, p_ev, w0, u = _cycle5_path()
+    prm = S.SgdParams(alpha=0.9, eta_scale=0.1, eps=1.0, k_max=20, delta_bar=0.5, t=2)
+    delta = 0.5 ** (1.0 / 20)
+    par = S.sgd_scale(5, g_eu, g_ev, g_w, p_eu, p_ev, w0, prm, mode="parallel", h0=u)
+    seq = S.sgd_scale(5, g_eu, g_ev, g_w, p_eu, p_ev, w0, prm, mode="sequential", h0=u)
+    assert par.iterations == 1 and seq.iterations == 1
+    assert np.allclose(par.w_P, 2.0 ** 0.05, rtol=1e-14, atol=0)
+    full = 1.0 + (2.0 / delta - 2.0)
+    assert np.allclose(seq.w_P, [full, 1.0, full, 1.0], rtol=0, atol=1e-14), seq.w_P
+    assert abs(par.lambda_1[1] - delta) < 1e-14 and abs(seq.lambda_1[1] - delta) < 1e-14
+
+
+def test_sgd_modes_agree_without_guard_and_keep_the_bound():
+    """On a random graph and a spanning sparsifier: with a loose guard
+    (Delta_bar small enough that it never trips) the two modes give equal
+    bits; with the default guard both keep every lambda_1 estimate at or
+    above lambda_1^(0) Delta_bar and both lower the dense generalised
+    lambda_n."""
+    import scipy.linalg as sl
+    from oracle import sgd as S
+
+    g, eu, ev, w, keep = _sgd_setup()
+    loose = S.SgdParams(k_max=6, delta_bar=1e-9)
+    a = S.sgd_scale(g.n, eu, ev, w, eu[keep], ev[keep], w[keep], loose, mode="parallel")
+    b = S.sgd_scale(g.n, eu, ev, w, eu[keep], ev[keep], w[keep], loose, mode="sequential")
+    assert a.iterations == b.iterations >= 2
+    assert np.array_equal(a.w_P, b.w_P)
+
+    def gen_lmax(wp):
+        Lg = S._lap(g.n, eu, ev, w)
+        Lp = S._lap(g.n, eu[keep], ev[keep], wp)
+        J = np.ones((g.n, g.n)) / g.n
+        return sl.eigh(Lg + J, Lp + J, eigvals_only=True)[-1]
+
+    p = S.SgdParams(k_max=15)
+    lam0 = gen_lmax(w[keep])
+    for mode in ("parallel", "sequential"):
+        r = S.sgd_scale(g.n, eu, ev, w, eu[keep], ev[keep], w[keep], p, mode=mode)
+        assert np.all(np.array(r.lambda_1) >= r.lambda_1[0] * p.delta_bar * (1 - 1e-12))
+        assert np.all(r.w_P >= w[keep])
+        assert gen_lmax(r.w_P) < lam0
+
+
 def test_sgd_power_vector_and_sensitivity_against_dense_eigen():
     """h_t approaches the dominant generalised eigenvector, and the
     sensitivity -lambda_n (e_pq^T u_n)^2 (u_n^T L_P u_n = 1) matches finite
