@@ -17,7 +17,7 @@ def build(force: bool = True) -> str:
         return LIB
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-           "-o", tmp, SRC, "-lm"]
+           "-ffp-contract=off", "-fopenmp", "-o", tmp, SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -3,9 +3,14 @@
  * Zhao, Wang & Feng, "Nearly-Linear Time Spectral Graph Reduction for
  * Scalable Graph Partitioning and Data Visualization", Sec. 3.2).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, single-threaded
- * FP64 restatement of what the reduction computes, used to check the GPU
- * library.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow FP64 restatement
+ * of what the reduction computes, used to check the GPU library.  It runs
+ * single-threaded by default; or_set_threads(t) lets the smoothing and the
+ * affinity visit the nodes of one colour (resp. all nodes) on t OpenMP
+ * threads.  Each node's arithmetic is the same sequence of operations in
+ * either case and no node reads a value written in the same parallel loop
+ * (a colour class has no inner edges), so the results are bit-identical
+ * for every thread count.  Only the test suite, the smoke check and the CPU-baseline leg of
  * the benchmark may load it.  It shares no code, header or constant table
  * with the GPU library.
  *
@@ -19,9 +24,16 @@
  * reading taken is stated at the step.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int g_threads = 1;
+
+/* Threads of the node loops of or_smooth and or_affinity (default 1). */
+void or_set_threads(int32_t t) { g_threads = t < 1 ? 1 : t; }
+int32_t or_get_threads(void) { return g_threads; }
 
 #define OR_OK 0
 #define OR_EINVAL -1
@@ -210,28 +222,35 @@ int or_smooth(int64_t n, const int32_t *row_ptr, const int32_t *col,
               int32_t K, int32_t sweeps, double *X, int32_t bf16_store)
 {
     if (K <= 0 || sweeps < 0 || n_colours < 0) return OR_EINVAL;
-    double *acc = (double *)malloc(sizeof(double) * (size_t)K);
-    if (!acc) return OR_ENOMEM;
     if (bf16_store)
         for (int64_t i = 0; i < n * K; ++i) X[i] = or_round_bf16(X[i]);
+    int failed = 0;
     for (int32_t s = 0; s < sweeps; ++s)
-        for (int32_t c = 0; c < n_colours; ++c)
-            for (int64_t v = 0; v < n; ++v) {
-                if (colours[v] != c) continue;
-                double d = 0.0;
-                for (int32_t k = 0; k < K; ++k) acc[k] = 0.0;
-                for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-                    d += w[e];
-                    const double *xj = X + (int64_t)col[e] * K;
-                    for (int32_t k = 0; k < K; ++k) acc[k] += w[e] * xj[k];
-                }
-                if (d > 0.0)
-                    for (int32_t k = 0; k < K; ++k) {
-                        double y = acc[k] / d;
-                        X[v * K + k] = bf16_store ? or_round_bf16(y) : y;
+        for (int32_t c = 0; c < n_colours; ++c) {
+#pragma omp parallel num_threads(g_threads) reduction(|| : failed)
+            {
+                double *acc = (double *)malloc(sizeof(double) * (size_t)K);
+                if (!acc) failed = 1;
+#pragma omp for schedule(dynamic, 4096)
+                for (int64_t v = 0; v < n; ++v) {
+                    if (!acc || colours[v] != c) continue;
+                    double d = 0.0;
+                    for (int32_t k = 0; k < K; ++k) acc[k] = 0.0;
+                    for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                        d += w[e];
+                        const double *xj = X + (int64_t)col[e] * K;
+                        for (int32_t k = 0; k < K; ++k) acc[k] += w[e] * xj[k];
                     }
+                    if (d > 0.0)
+                        for (int32_t k = 0; k < K; ++k) {
+                            double y = acc[k] / d;
+                            X[v * K + k] = bf16_store ? or_round_bf16(y) : y;
+                        }
+                }
+                free(acc);
             }
-    free(acc);
+            if (failed) return OR_ENOMEM;
+        }
     return OR_OK;
 }
 
@@ -246,6 +265,7 @@ int or_smooth(int64_t n, const int32_t *row_ptr, const int32_t *col,
 void or_affinity(int64_t n, const int32_t *row_ptr, const int32_t *col,
                  int32_t K, const double *X, double *a, double *d)
 {
+#pragma omp parallel for num_threads(g_threads) schedule(dynamic, 1024)
     for (int64_t v = 0; v < n; ++v) {
         const double *xv = X + v * K;
         double nv = 0.0;

@@ -68,6 +68,10 @@ def lib():
                                   _i32p, _i32p, _f64p, ctypes.POINTER(_i64)]
         L.or_edge_index.restype = _i64
         L.or_edge_index.argtypes = [_i64, _i32p, _i32p, _i32p, _i32p, _i32p]
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [_i32]
+        L.or_get_threads.restype = _i32
+        L.or_get_threads.argtypes = []
         L.or_smooth_vjp.restype = ctypes.c_int
         L.or_smooth_vjp.argtypes = [_i64, _i32p, _i32p, _i32p, _i64, _f64p,
                                     _i32p, _i32, _i32, _i32, _f64p, _f64p,
@@ -103,6 +107,23 @@ def splitmix64(seed: int, i: int) -> int:
 def level_seed(seed: int, level: int) -> int:
     """Seed of level `level` of the multilevel driver."""
     return splitmix64(seed, level)
+
+
+class threads:
+    """Context manager: the smoothing and affinity node loops run on `t`
+    OpenMP threads inside the block (bit-identical results for any t)."""
+
+    def __init__(self, t: int):
+        self.t = int(t)
+
+    def __enter__(self):
+        self.old = int(lib().or_get_threads())
+        lib().or_set_threads(self.t)
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_set_threads(self.old)
+        return False
 
 
 def validate_csr(n, row_ptr, col, w) -> int:
@@ -250,6 +271,10 @@ class ReduceResult:
     w: np.ndarray            # float64 coarse weights
     levels: list
     no_progress: bool
+    # the hierarchy (Alg. 5 input): maps[l] sends level-l nodes to level
+    # l+1 nodes (H_{l+1}^{l} = P_l), graphs[l] = level l+1's CSR
+    maps: list = dataclasses.field(default_factory=list)
+    graphs: list = dataclasses.field(default_factory=list)
 
 
 def target_size(n0: int, ratio: float) -> int:
@@ -271,6 +296,7 @@ def reduce(n, row_ptr, col, w, K, sweeps, ratio, vec_seed, colour_seed,
     rp, cl, ww = _ai32(row_ptr), _ai32(col), _af64(w)
     cur_n = n
     levels = []
+    maps, graphs = [], []
     no_progress = False
     ell = 0
     while cur_n > T and ell < max_levels:
@@ -293,9 +319,11 @@ def reduce(n, row_ptr, col, w, K, sweeps, ratio, vec_seed, colour_seed,
             break
         if fp32_coarse:
             c_w = c_w.astype(np.float32).astype(np.float64)
+        maps.append(ag.agg.copy())
+        graphs.append((c_rp, c_col, c_w))
         rp, cl, ww, cur_n = c_rp, c_col, c_w, ag.n_coarse
         ell += 1
-    return ReduceResult(total, cur_n, rp, cl, ww, levels, no_progress)
+    return ReduceResult(total, cur_n, rp, cl, ww, levels, no_progress, maps, graphs)
 
 
 # ------------------------------------------------------- dense linear algebra

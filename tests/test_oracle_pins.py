@@ -752,3 +752,21 @@ def test_restrict_mean_hand_example():
     F = np.array([[1.0, 10.0], [7.0, -1.0], [2.0, 20.0], [6.0, 0.0]], np.float32)
     R = O.restrict_mean(agg, 2, F)
     assert np.array_equal(R, np.array([[3.0, 10.0], [7.0, -1.0]], np.float32))
+
+
+# -------------------------------------------------- threaded oracle loops
+
+def test_threaded_oracle_loops_are_bit_identical():
+    """The smoothing and affinity node loops give the same bits on 1 and on
+    several threads (each node's arithmetic is unchanged, and a colour class
+    has no inner edges), in float64 and with bfloat16 rounding."""
+    g = G.random_weighted(2000, 0.01, seed=11)
+    cols, nc = O.colour_greedy(g.n, g.row_ptr, g.col, 5)
+    X = O.init_vectors(g.n, 16, 3)
+    for bf16 in (False, True):
+        a = O.smooth(g.n, g.row_ptr, g.col, g.w, cols, nc, X, 5, bf16=bf16)
+        da = O.distance(g.n, g.row_ptr, g.col, a)
+        with O.threads(4):
+            b = O.smooth(g.n, g.row_ptr, g.col, g.w, cols, nc, X, 5, bf16=bf16)
+            db = O.distance(g.n, g.row_ptr, g.col, b)
+        assert np.array_equal(a, b) and np.array_equal(da, db)
