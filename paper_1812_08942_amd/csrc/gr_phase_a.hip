@@ -369,7 +369,7 @@ __device__ inline bool flow_narrow(const int32_t* __restrict__ uplist, int32_t s
                 const int32_t c = ld_dev(cpos + u[k]);
                 if (c >= 0) {
                     if (c < 64) used0 |= 1ull << c;
-                    else used1 |= 1ull << (c - 64);
+                    else if (c < 128) used1 |= 1ull << (c - 64);
                     pend &= ~(1u << k);
                 }
             }

@@ -67,33 +67,44 @@ void end(hipStream_t st, int phase, double bytes, int64_t launches) {
     g_open = nullptr;
 }
 
-void start() {
-    g_on = true;
+// Every event is destroyed when a profile stops, so no HIP object of the
+// profiler outlives a start/stop pair (nothing is left for the runtime to
+// tear down at process exit).
+static void release_all() {
     for (auto& r : g_recs) {
-        g_pool.push_back(r.a);
-        g_pool.push_back(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     g_recs.clear();
+    for (hipEvent_t e : g_pool) (void)hipEventDestroy(e);
+    g_pool.clear();
+    if (g_open) (void)hipEventDestroy(g_open);
+    g_open = nullptr;
+}
+
+void start() {
+    g_on = true;
+    release_all();
 }
 
 int stop(gr_profile* out) {
     g_on = false;
     memset(out, 0, sizeof(*out));
     for (auto& r : g_recs) {
-        GR_HIP(hipEventSynchronize(r.b));
         float ms = 0.0f;
-        GR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        int rc = check_hip(hipEventSynchronize(r.b), "profile event");
+        if (rc == GR_OK) rc = check_hip(hipEventElapsedTime(&ms, r.a, r.b), "profile event");
+        if (rc != GR_OK) {
+            release_all();
+            return rc;
+        }
         out->phase_ms[r.phase] += ms;
         out->phase_bytes[r.phase] += r.bytes;
         out->phase_launches[r.phase] += r.launches;
         if (ms > out->phase_max_ms[r.phase]) out->phase_max_ms[r.phase] = ms;
         out->records += 1;
     }
-    for (auto& r : g_recs) {
-        g_pool.push_back(r.a);
-        g_pool.push_back(r.b);
-    }
-    g_recs.clear();
+    release_all();
     return GR_OK;
 }
 }  // namespace prof

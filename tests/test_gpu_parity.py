@@ -398,12 +398,14 @@ def test_reduce_end_to_end_multilevel(case, dtype):
     to end; the per-step decisions are pinned bit-exactly elsewhere (the
     oracle fed the GPU's affinities).  Here: the GPU result is a valid
     aggregation, its coarse graph is exactly P^T L P of its own map, and its
-    first 10 nontrivial eigenvalues agree with the oracle's to 1e-4, or, where
-    rounding flipped near-ties, lie within 4 standard deviations of the
-    oracle's spread over 5 vector seeds.  With bfloat16 vectors the oracle
-    rounds every stored update the same way; the bfloat16 result is also
-    reported against the float32 oracle's spread (the accuracy the storage
-    format costs)."""
+    first 10 nontrivial eigenvalues lambda_i agree with the oracle's (same
+    seeds) within max(1e-4 lambda_i, half the range of the oracle's lambda_i
+    over 5 vector seeds): where rounding flips near-ties, the GPU's
+    reduction may differ from the oracle's by no more than changing the
+    random test vectors does.  With bfloat16 vectors the oracle rounds every
+    stored update the same way; the bfloat16 result is also reported
+    against the float32 oracle's spread (the accuracy the storage format
+    costs)."""
     g = small_graphs()[case]
     ratio = {"knn2d_3000": 32.0, "chunglu_20000": 33.4, "grid3d_12": 20.0}[case]
     say(f"reduce {case} ratio {ratio} {dtype}")
@@ -437,15 +439,13 @@ def test_reduce_end_to_end_multilevel(case, dtype):
         print(f"[gpu-case] {case}: bf16 GPU eigenvalues vs the float32 oracle: "
               f"max |dlambda| = {dev32:.2f} seed standard deviations")
     lams = np.array(lams)
-    mean, std = lams.mean(0), lams.std(0, ddof=1)
+    spread = lams.max(0) - lams.min(0)
+    gate = np.maximum(1e-4 * lams[0], 0.5 * spread)
     err = np.abs(lam_gpu - lams[0])
     print(f"[gpu-case] {case}: max |dlambda|/lambda {np.max(err / lams[0]):.3e}, "
-          f"max seed std/lambda {np.max(std / mean):.3e}")
-    # where ids agree the eigenvalues agree to float32 accuracy; where
-    # near-ties flipped, the GPU result must look like one more draw of the
-    # oracle's test vectors: within 4 seed standard deviations of their mean
-    assert np.all((err <= 1e-4 * lams[0]) |
-                  (np.abs(lam_gpu - mean) <= 4 * std + 1e-4 * mean))
+          f"max seed range/lambda {np.max(spread / lams[0]):.3e}, "
+          f"max |dlambda|/gate {np.max(err / gate):.3f}")
+    assert np.all(err <= gate), (err / gate).round(3)
     if agree == 1.0:
         assert np.array_equal(agg, ref.agg)
 
