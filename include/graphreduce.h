@@ -17,8 +17,9 @@
  * Memory.  Every array argument is a DEVICE pointer owned by the caller
  *   unless it is documented as host.  The library never allocates device
  *   memory: scratch comes from the caller's workspace `ws` of `ws_bytes`
- *   bytes (size it with gr_workspace_size).  Outputs have caller-allocated
- *   upper-bound sizes.
+ *   bytes (size it with gr_workspace_size), except for the one fixed static
+ *   array that gr_rq_forward_noalloc uses instead of a workspace.  Outputs
+ *   have caller-allocated upper-bound sizes.
  * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Work is
  *   enqueued on it; an entry point returns only after the device-to-host
  *   size reads it documents, otherwise asynchronously.
@@ -296,6 +297,24 @@ int gr_edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* edge_of_e
 int gr_rq_forward(int64_t n, int64_t n_edges, const int32_t* eu, const int32_t* ev,
                   const double* w_E, const double* U, int32_t m, int32_t mode, double* R,
                   double* den, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_rq_forward_noalloc — gr_rq_forward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same arguments minus ws/ws_bytes,
+ * the same kernels and the same bits.  Its scratch (three arrays of 512
+ * per-block partial sums per column) lives in a library-owned static
+ * device array of gr_rq_forward_noalloc_scratch_bytes() = 786,432 bytes
+ * per GPU (room for m = 64, so every valid m fits; GR_EINVAL if a call
+ * ever needed more), held until the process ends.  Every call rewrites
+ * what it reads of the array, so nothing carries over between calls, but
+ * calls that overlap on one GPU (two streams, two threads) share it and
+ * race: serialise them.  Allocates nothing; R and den as in gr_rq_forward.
+ */
+int gr_rq_forward_noalloc(int64_t n, int64_t n_edges, const int32_t* eu, const int32_t* ev,
+                          const double* w_E, const double* U, int32_t m, int32_t mode, double* R,
+                          double* den, void* stream);
+size_t gr_rq_forward_noalloc_scratch_bytes(void);
 
 /*
  * gr_rq_backward — edge-weight gradient of sum_i gR_i R_i:

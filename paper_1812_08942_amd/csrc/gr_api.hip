@@ -429,6 +429,17 @@ int gr_rq_forward(int64_t n, int64_t n_edges, const int32_t* eu, const int32_t* 
     return rq_forward(n, n_edges, eu, ev, w_E, U, m, mode, R, den, A, S(stream));
 }
 
+int gr_rq_forward_noalloc(int64_t n, int64_t n_edges, const int32_t* eu, const int32_t* ev,
+                          const double* w_E, const double* U, int32_t m, int32_t mode, double* R,
+                          double* den, void* stream) {
+    clear_error();
+    GR_TRY(check_rq_args(n, n_edges, eu, ev, U, m, mode));
+    if (!R || (n_edges > 0 && !w_E)) return set_error(GR_EINVAL, "NULL argument");
+    return rq_forward_noalloc(n, n_edges, eu, ev, w_E, U, m, mode, R, den, S(stream));
+}
+
+size_t gr_rq_forward_noalloc_scratch_bytes(void) { return rq_forward_scratch_capacity(); }
+
 int gr_rq_backward(int64_t n_edges, const int32_t* eu, const int32_t* ev, const double* U,
                    int32_t m, int32_t mode, const double* R, const double* den, const double* gR,
                    double* gw_E, void* stream) {

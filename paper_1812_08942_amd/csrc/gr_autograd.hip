@@ -6,6 +6,8 @@
 #include "gr_internal.hpp"
 #include "gr_device.hpp"
 
+#include <mutex>
+
 namespace gr {
 
 constexpr int kA = 256;
@@ -241,6 +243,58 @@ int rq_forward(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev, const
     GR_LAUNCHED("rq final");
     ws.used = mark;
     return GR_OK;
+}
+
+// ------------------------------------- Rayleigh quotients, no allocation
+// The scratch of rq_forward (three per-block partial-sum arrays) for the
+// widest block, m = 64, in a file-scope device array: one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to
+// a kernel (in host code it is a stand-in, not a device address); it looks
+// up the array's address on each device once, with that device current,
+// and passes that pointer instead.
+constexpr size_t kRqScratchPart = ((size_t)kRqBlocks * 64 * sizeof(double) + 255) & ~size_t(255);
+constexpr size_t kRqScratchBytes = 3 * kRqScratchPart;
+static __device__ __align__(256) unsigned char scratch[kRqScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_on_current_device(void** out) {
+    int dev = 0;
+    GR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(GR_EINVAL, "device %d: at most %d devices are supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        GR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(GR_EHIP, "no device address for the static scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GR_OK;
+}
+
+size_t rq_forward_scratch_bytes(int32_t m) {
+    Arena sizing(nullptr, ~size_t(0));
+    for (int i = 0; i < 3; ++i) sizing.take<double>((size_t)kRqBlocks * (size_t)(m > 0 ? m : 0));
+    return sizing.used;
+}
+
+size_t rq_forward_scratch_capacity() { return kRqScratchBytes; }
+
+int rq_forward_noalloc(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev, const double* w,
+                       const double* U, int32_t m, int32_t mode, double* R, double* den,
+                       hipStream_t st) {
+    const size_t need = rq_forward_scratch_bytes(m);
+    if (need > kRqScratchBytes)
+        return set_error(GR_EINVAL, "m = %d needs %zu scratch bytes; the static scratch holds %zu",
+                         m, need, kRqScratchBytes);
+    void* p = nullptr;
+    GR_TRY(scratch_on_current_device(&p));
+    Arena A(p, kRqScratchBytes);
+    return rq_forward(n, E, eu, ev, w, U, m, mode, R, den, A, st);
 }
 
 int rq_backward(int64_t E, const int32_t* eu, const int32_t* ev, const double* U, int32_t m,

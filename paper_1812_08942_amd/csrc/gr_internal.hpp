@@ -208,6 +208,11 @@ size_t vjp_workspace(int64_t n, int64_t nnz, int32_t K, int32_t dtype, int32_t S
 int smooth_vjp(const gr_graph* g, const int32_t* eoe, int64_t E, const int32_t* colours, int32_t C,
                int32_t K, int32_t S, int32_t dtype, const void* X0, const float* Gc, float* gw,
                float* gX0, int32_t store, Arena& ws, hipStream_t st);
+int rq_forward_noalloc(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev, const double* w,
+                       const double* U, int32_t m, int32_t mode, double* R, double* den,
+                       hipStream_t st);
+size_t rq_forward_scratch_bytes(int32_t m);
+size_t rq_forward_scratch_capacity();
 int rq_backward(int64_t E, const int32_t* eu, const int32_t* ev, const double* U, int32_t m,
                 int32_t mode, const double* R, const double* den, const double* gR, double* gw,
                 hipStream_t st);

@@ -128,6 +128,9 @@ _SIGNATURES = {
                        _SZ, _P], ctypes.c_int),
     "gr_rq_backward": ([_I64, _P, _P, _P, _I32, _I32, _P, _P, _P, _P, _P],
                        ctypes.c_int),
+    "gr_rq_forward_noalloc": ([_I64, _I64, _P, _P, _P, _P, _I32, _I32, _P, _P,
+                               _P], ctypes.c_int),
+    "gr_rq_forward_noalloc_scratch_bytes": ([], _SZ),
     "gr_eig_workspace": ([_I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
     "gr_laplacian_eigs": ([_G, _I32, _I32, ctypes.c_double, _I32, _I32, _U64,
                            ctypes.POINTER(ctypes.c_double),
@@ -502,6 +505,29 @@ def gr_rq_forward(edges: EdgeList, w_E, U, mode=GR_RQ_IDENTITY, ws=None):
                                 _ptr(w_E), _ptr(U), m, int(mode), _ptr(R),
                                 _ptr(den), _ptr(ws), ws.numel(), _stream()))
     return R, den
+
+
+def gr_rq_forward_noalloc(edges: EdgeList, w_E, U, mode=GR_RQ_IDENTITY, R=None,
+                          den=None):
+    """(R, den) as gr_rq_forward, with the library's static scratch instead
+    of a workspace.  R and den may be passed in (float64 [m], on U's device)
+    so that the call itself allocates nothing."""
+    _f64c(w_E)
+    _f64c(U)
+    n, m = U.shape
+    if R is None:
+        R = torch.empty(m, dtype=torch.float64, device=U.device)
+    if den is None:
+        den = torch.empty(m, dtype=torch.float64, device=U.device)
+    _check(load().gr_rq_forward_noalloc(n, edges.E, _ptr(edges.eu), _ptr(edges.ev),
+                                        _ptr(w_E), _ptr(U), m, int(mode), _ptr(R),
+                                        _ptr(den), _stream()))
+    return R, den
+
+
+def gr_rq_forward_noalloc_scratch_bytes() -> int:
+    """Bytes of the static device array that gr_rq_forward_noalloc uses."""
+    return int(load().gr_rq_forward_noalloc_scratch_bytes())
 
 
 def gr_rq_backward(edges: EdgeList, U, R, den, gR, mode=GR_RQ_IDENTITY):
