@@ -413,6 +413,120 @@ int gr_laplacian_eigpairs(const gr_graph* g, int32_t n_eig, int32_t method, doub
                           gr_eig_report* report, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------
+ * The reduction hierarchy, the generalised eigenproblem L u = lambda B u,
+ * the weighted-Jacobi solution refinement (Alg. 3, Sec. 3.5) and the
+ * multilevel Laplacian eigensolver (Alg. 5, Sec. 4.1), all in FP64.
+ * B is always diagonal, passed as its diagonal b (device double[n],
+ * positive and finite), or NULL for B = I.
+ * ------------------------------------------------------------------- */
+#define GR_MAX_LEVELS 32
+
+typedef struct gr_hierarchy {
+    int32_t* maps;      /* device int32[maps_cap]: the node-to-aggregate map of
+                           level l (H_{l+1}^{l} = P_l, values in [0, n[l+1])),
+                           n[l] entries from maps_off[l]                      */
+    int64_t maps_cap;
+    int32_t* row_ptr;   /* device int32[rp_cap]: row pointers of level l+1,
+                           n[l+1] + 1 entries from rp_off[l] (starting at 0)  */
+    int64_t rp_cap;
+    int32_t* col;       /* device int32[ent_cap]: columns of level l+1,
+                           nnz[l+1] entries from ent_off[l]                   */
+    float* w;           /* device float32[ent_cap]: weights, as col           */
+    int64_t ent_cap;
+    int32_t levels;     /* coarse levels held (level 0 is the input graph)    */
+    int64_t n[GR_MAX_LEVELS + 1];    /* nodes of level l                      */
+    int64_t nnz[GR_MAX_LEVELS + 1];  /* stored entries of level l             */
+    int64_t maps_off[GR_MAX_LEVELS];
+    int64_t rp_off[GR_MAX_LEVELS];
+    int64_t ent_off[GR_MAX_LEVELS];
+} gr_hierarchy;
+
+/*
+ * gr_reduce_hierarchy — gr_reduce (same arguments, same results) that also
+ * keeps the hierarchy Alg. 5 walks (Sec. 4.1: every level's Laplacian and
+ * its mapping operator): each level that shrank the graph appends its map
+ * and the coarse graph it produced to *h (caller-allocated device arrays
+ * with the capacities in *h; a level that made no progress is not kept).
+ * Outputs: h->levels, h->n, h->nnz and the offsets.  GR_ENOMEM when a
+ * capacity is too small (the message gives the totals needed so far); the
+ * maps of a reduction total at most 2 n plus the isolated nodes once per
+ * level, and its coarse graphs rarely more than nnz entries.
+ */
+int gr_reduce_hierarchy(const gr_graph* g, const gr_params* p, gr_result* res, gr_hierarchy* h,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_laplacian_geigpairs — gr_laplacian_eigpairs for the generalised
+ * problem L u = lambda B u with B = diag(b) (the B_G of Alg. 4 and 5):
+ * the n_eig smallest eigenvalues with u B-orthogonal to the all-one vector
+ * (its null vector), and U (device double[n][n_eig]) B-orthonormal.  The
+ * solvers run on S L S, S = B^-1/2, in the complement of B^1/2 1 (same
+ * methods, block sizes and stopping rule as gr_laplacian_eigs, with the
+ * Gershgorin bound of S L S in place of 2 max degree).  b = NULL is the
+ * plain problem.  GR_EINVAL if some b is not positive and finite.
+ * Workspace: gr_eig_workspace.  Synchronises.
+ */
+int gr_laplacian_geigpairs(const gr_graph* g, const double* bdiag, int32_t n_eig, int32_t method,
+                           double tol, int32_t max_iter, int32_t degree, uint64_t seed,
+                           double* eig, double* U, gr_eig_report* report, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/*
+ * gr_jacobi_filter — `iters` weighted-Jacobi steps on every column i of Y
+ * (device double[n][k], in place, 1 <= k <= 64):
+ *     y <- y - theta D^-1 (L y - lambda_i B y),
+ * D the weighted degrees of g.  With lambda = NULL this is the solution
+ * refinement of Alg. 3, y <- (1 - theta) y + theta D^-1 A y; with the
+ * eigenvalues lambda (HOST double[k]) and B = diag(bdiag) (or I) it is the
+ * eigenvector filter of Alg. 5 on (L - lambda_i B) y = 0.  Rows with d = 0
+ * are left unchanged.  Workspace: gr_jacobi_workspace.  Synchronises once
+ * (to size the row pieces) and at the end.
+ */
+int gr_jacobi_workspace(int64_t n, int32_t k, size_t* bytes);
+int gr_jacobi_filter(const gr_graph* g, int32_t k, double* Y, const double* lambda,
+                     const double* bdiag, double theta, int32_t iters, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * gr_orthonormalize — Gram-Schmidt over [1, u_1, .., u_k] in the B inner
+ * product (B = diag(bdiag), or I), keeping the k columns after the
+ * constant: U (device double[n][k], in place) becomes B-orthonormal and
+ * B-orthogonal to the all-one vector, each column in the span of the
+ * constant and the columns before it (the final step of Alg. 5).
+ * Computed as a projection and two Cholesky QR passes, which give the same
+ * factor.  GR_EINVAL if the columns are linearly dependent (with the
+ * constant).  Workspace: gr_orthonormalize_workspace.  Synchronises.
+ */
+int gr_orthonormalize_workspace(int64_t n, int32_t k, size_t* bytes);
+int gr_orthonormalize(int64_t n, int32_t k, double* U, const double* bdiag, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/*
+ * gr_multilevel_eigs — the multilevel Laplacian eigensolver (Alg. 5,
+ * Sec. 4.1) on the hierarchy *h of graph g (as gr_reduce_hierarchy keeps
+ * it; h->n[0] must be g->n):
+ *  1. the first k nontrivial eigenpairs (lambda_i, u_i) of the coarsest
+ *     problem L^Y u = lambda B^Y u (gr_laplacian_geigpairs, seed, tol,
+ *     max_iter);
+ *  2. for each level from the coarsest up: U <- H U (the level's 0/1 map),
+ *     then `iters` steps of gr_jacobi_filter with the coarsest lambda_i and
+ *     that level's B;
+ *  3. gr_orthonormalize in the finest B.
+ * B of the finest level is I (mode GR_RQ_IDENTITY, ratio cut) or D
+ * (GR_RQ_DEGREE, normalized cut); each coarser level's B is the one the
+ * prolongation induces, P^T B P (the sums of B over each aggregate), so a
+ * coarse vector's quotient equals that of its prolongation.  Outputs:
+ * eig HOST double[k] (the coarsest lambda_i), U device double[n][k].
+ * 1 <= k <= 32, theta > 0.  Workspace: gr_multilevel_workspace.
+ * Synchronises.
+ */
+int gr_multilevel_workspace(int64_t n, int64_t nnz, int32_t k, size_t* bytes);
+int gr_multilevel_eigs(const gr_graph* g, const gr_hierarchy* h, int32_t k, int32_t mode,
+                       double theta, int32_t iters, double tol, int32_t max_iter, uint64_t seed,
+                       double* eig, double* U, gr_eig_report* report, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* ---------------------------------------------------------------------
  * Constrained-SGD edge scaling (Alg. 1, Sec. 3.3.4), FP64.
  * ------------------------------------------------------------------- */
 #define GR_SGD_MAX_ITER 64
@@ -458,6 +572,109 @@ int gr_sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* p_edge_of_
                  int64_t p_edges, const int32_t* p_eu, const int32_t* p_ev, double* w_P,
                  const gr_sgd_params* params, gr_sgd_report* report, void* ws, size_t ws_bytes,
                  void* stream);
+
+/* ---------------------------------------------------------------------
+ * Phase B, spectral sparsification (Sec. 3.3.2-3.3.3), and the flow of
+ * Alg. 2.  Edge flags and edge values are indexed by the undirected edge
+ * numbering of gr_edge_list (upper entries in CSR order).
+ * ------------------------------------------------------------------- */
+#define GR_SPARSIFY_MAX_ROUNDS 64
+
+typedef struct gr_sparsify_params {
+    int32_t t;             /* generalised power iterations per estimate (the paper: 2) */
+    int32_t rounds;        /* densification rounds at most (<= GR_SPARSIFY_MAX_ROUNDS) */
+    double add_frac;       /* edges added per round: ceil(add_frac * n)          */
+    double lambda_target;  /* stop once the estimate of lambda_n is at most this */
+    uint64_t seed;         /* h_0: one column of the test-vector generator       */
+    int32_t cg_max_iter;   /* 0 = 20000                                          */
+    double cg_tol;         /* relative residual of the L_P solves; 0 = 1e-12     */
+} gr_sparsify_params;
+
+typedef struct gr_sparsify_report {
+    int32_t rounds;          /* densification rounds run                       */
+    int32_t n_lambda;        /* entries of lambda_n                            */
+    int64_t tree_edges;      /* edges of the spanning forest                   */
+    int64_t edges;           /* edges of the sparsifier at the end             */
+    int32_t cg_iterations_max;
+    double lambda_n[GR_SPARSIFY_MAX_ROUNDS + 1]; /* h_t^T L_G h_t after the tree
+                                                    and after each round       */
+} gr_sparsify_report;
+
+/*
+ * gr_spanning_forest — the spanning tree that Phase B starts from
+ * (Sec. 3.3.2), read as the maximum-weight spanning forest: edges ordered by
+ * weight descending, ties by the smaller, then the larger endpoint, taken
+ * greedily (the unique forest of that order, found by Boruvka rounds).
+ * Output: in_tree int32[nnz/2] (device, 1 = in the forest), *n_tree HOST.
+ * Workspace: gr_sparsify_workspace.  Synchronises every round.
+ */
+int gr_spanning_forest(const gr_graph* g, int32_t* in_tree, int64_t* n_tree, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/*
+ * gr_sparsify — Phase B's sparsifier P of g (Sec. 3.3.2-3.3.3): the
+ * spanning forest above, then rounds of densification.  Each round forms
+ * h_t (t generalised power iterations h <- L_P^+ L_G h from h_0, L_P solves
+ * by Jacobi-preconditioned CG, normalised to h^T L_P h = 1), records
+ * lambda_n = h^T L_G h, and adds the ceil(add_frac n) edges outside P of
+ * largest criticality w_G(p,q) (h_p - h_q)^2 (ties to the smaller edge
+ * number); it stops after `rounds` rounds or once lambda_n <= lambda_target.
+ * Outputs: in_P int32[nnz/2] (device, 1 = in P); criticality double[nnz/2]
+ * (device, may be NULL): the final P's criticalities (0 on P's edges);
+ * *rep HOST.  Workspace: gr_sparsify_workspace.  Synchronises.
+ */
+int gr_sparsify_workspace(int64_t n, int64_t nnz, size_t* bytes);
+int gr_sparsify(const gr_graph* g, const gr_sparsify_params* p, int32_t* in_P, double* criticality,
+                gr_sparsify_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * gr_subgraph — the subgraph of g on the edges flagged in keep (int32[nnz/2],
+ * device): CSR p_row_ptr int32[n+1], p_col int32[<= nnz], p_w float32[<= nnz]
+ * with g's weights, entries in g's order; optionally (non-NULL) its edge list
+ * p_eu/p_ev int32[<= nnz/2] (the kept edges in g's edge order) and
+ * p_edge_of_entry int32[<= nnz] (P's edge of each P entry).  *p_nnz and
+ * *p_edges HOST.  Workspace: gr_sparsify_workspace.  Synchronises.
+ */
+int gr_subgraph(const gr_graph* g, const int32_t* keep, int32_t* p_row_ptr, int32_t* p_col,
+                float* p_w, int32_t* p_edge_of_entry, int32_t* p_eu, int32_t* p_ev, int64_t* p_nnz,
+                int64_t* p_edges, void* ws, size_t ws_bytes, void* stream);
+
+typedef struct gr_flow_params {
+    gr_params phase_a;           /* the node reduction (Phase A)                 */
+    gr_sparsify_params phase_b;  /* the sparsification (Phase B)                 */
+    gr_sgd_params scaling;       /* Alg. 1 on the sparsifier                     */
+    double gamma_max;            /* density threshold of Alg. 2 (the paper: 40)   */
+} gr_flow_params;
+
+typedef struct gr_flow_result {
+    int32_t* agg;           /* device int32[n]: the node of S of every node of g  */
+    int32_t* s_row_ptr;     /* device int32[n+1] (upper bound): S as CSR           */
+    int32_t* s_col;         /* device int32[nnz] (upper bound)                     */
+    float* s_w;             /* device float32[nnz] (upper bound)                   */
+    int64_t n_s;            /* out */
+    int64_t nnz_s;          /* out */
+    int32_t dense;          /* out: 1 when Phase B ran first (gamma >= gamma_max)  */
+    double gamma;           /* out: |E_G| / |V|, undirected edges                  */
+    int32_t levels;         /* out: Phase A levels                                 */
+    uint32_t warnings;      /* out: Phase A's GR_W* bits                           */
+    gr_sparsify_report sparsify;  /* out */
+    gr_sgd_report scaling;        /* out */
+} gr_flow_result;
+
+/*
+ * gr_spectral_reduce — Alg. 2: gamma = |E_G| / |V|; below gamma_max,
+ * Phase A reduces g to R, then Phase B sparsifies R and Alg. 1 scales the
+ * sparsifier's weights, giving S; otherwise Phase B and Alg. 1 first give P
+ * (g's nodes, scaled weights rounded to float32) and Phase A reduces P to
+ * S.  Phase A is gr_reduce with p->phase_a (a prescribed colouring is used
+ * only when Phase A runs on g itself), Phase B gr_sparsify, Alg. 1
+ * gr_sgd_scale.  Outputs in *res (device arrays caller-allocated, sizes as
+ * gr_reduce's).  Workspace: gr_spectral_reduce_workspace.  Synchronises.
+ */
+int gr_spectral_reduce_workspace(int64_t n, int64_t nnz, int32_t K, int32_t vec_dtype,
+                                 size_t* bytes);
+int gr_spectral_reduce(const gr_graph* g, const gr_flow_params* p, gr_flow_result* res, void* ws,
+                       size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

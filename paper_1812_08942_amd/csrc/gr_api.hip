@@ -97,6 +97,16 @@ __global__ void k_best_from_d(const int32_t* __restrict__ rp, const int32_t* __r
     dbest[v] = bd;
 }
 
+__global__ void k_f64_to_f32(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ a, int64_t n, double* __restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}
+
 }  // namespace gr
 
 using namespace gr;
@@ -269,9 +279,8 @@ int gr_restrict_mean(const int32_t* agg, int64_t n, int64_t n_coarse, int32_t d,
     return restrict_mean(agg, n, n_coarse, d, F, F_R, A, S(stream));
 }
 
-int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws, size_t ws_bytes,
-              void* stream) {
-    clear_error();
+static int reduce_impl(const gr_graph* g, const gr_params* p_in, gr_result* res, gr_hierarchy* hier,
+                       void* ws, size_t ws_bytes, void* stream) {
     GR_TRY(check_graph_args(g));
     if (!p_in || !res) return set_error(GR_EINVAL, "NULL params or result");
     gr_params p;
@@ -287,6 +296,15 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
     res->nnz_coarse = 0;
     res->levels = 0;
     res->warnings = 0;
+    if (hier) {
+        if (hier->maps_cap < 0 || hier->rp_cap < 0 || hier->ent_cap < 0)
+            return set_error(GR_EINVAL, "negative hierarchy capacity");
+        hier->levels = 0;
+        for (int l = 0; l <= GR_MAX_LEVELS; ++l) hier->n[l] = hier->nnz[l] = 0;
+        hier->n[0] = g->n;
+        hier->nnz[0] = g->nnz;
+    }
+    int64_t h_maps = 0, h_rp = 0, h_ent = 0;  // hierarchy totals so far
     hipStream_t st = S(stream);
     Arena A(ws, ws_bytes);
     const int64_t n0 = g->n;
@@ -374,8 +392,39 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
         hipLaunchKernelGGL(k_compose, dim3(blocks_for(n0, 256)), dim3(256), 0, st, aggl, n0,
                            res->agg);
         GR_LAUNCHED("compose");
-        ++level;
         bool stuck = ncoarse == cur.n;
+        if (hier && !stuck) {  // keep this level's map and the graph it made
+            const int l = hier->levels;
+            if (l >= GR_MAX_LEVELS) return set_error(GR_ENOMEM, "more than %d levels", GR_MAX_LEVELS);
+            if (h_maps + cur.n > hier->maps_cap || h_rp + ncoarse + 1 > hier->rp_cap ||
+                h_ent + nnzc > hier->ent_cap || !hier->maps || !hier->row_ptr ||
+                (nnzc > 0 && (!hier->col || !hier->w)))
+                return set_error(GR_ENOMEM,
+                                 "hierarchy buffers too small at level %d: need maps %lld, row "
+                                 "pointers %lld, entries %lld so far",
+                                 l, (long long)(h_maps + cur.n), (long long)(h_rp + ncoarse + 1),
+                                 (long long)(h_ent + nnzc));
+            hier->maps_off[l] = h_maps;
+            hier->rp_off[l] = h_rp;
+            hier->ent_off[l] = h_ent;
+            GR_HIP(hipMemcpyAsync(hier->maps + h_maps, aggl, sizeof(int32_t) * cur.n,
+                                  hipMemcpyDeviceToDevice, st));
+            GR_HIP(hipMemcpyAsync(hier->row_ptr + h_rp, next.row_ptr,
+                                  sizeof(int32_t) * (ncoarse + 1), hipMemcpyDeviceToDevice, st));
+            if (nnzc > 0) {
+                GR_HIP(hipMemcpyAsync(hier->col + h_ent, next.col, sizeof(int32_t) * nnzc,
+                                      hipMemcpyDeviceToDevice, st));
+                GR_HIP(hipMemcpyAsync(hier->w + h_ent, next.w, sizeof(float) * nnzc,
+                                      hipMemcpyDeviceToDevice, st));
+            }
+            h_maps += cur.n;
+            h_rp += ncoarse + 1;
+            h_ent += nnzc;
+            hier->levels = l + 1;
+            hier->n[l + 1] = ncoarse;
+            hier->nnz[l + 1] = nnzc;
+        }
+        ++level;
         cur = next;
         which ^= 1;
         if (stuck) {
@@ -394,7 +443,21 @@ int gr_reduce(const gr_graph* g, const gr_params* p_in, gr_result* res, void* ws
     res->n_coarse = cur.n;
     res->nnz_coarse = cur.nnz;
     res->levels = level;
+    if (hier) GR_HIP(hipStreamSynchronize(st));
     return GR_OK;
+}
+
+int gr_reduce(const gr_graph* g, const gr_params* p, gr_result* res, void* ws, size_t ws_bytes,
+              void* stream) {
+    clear_error();
+    return reduce_impl(g, p, res, nullptr, ws, ws_bytes, stream);
+}
+
+int gr_reduce_hierarchy(const gr_graph* g, const gr_params* p, gr_result* res, gr_hierarchy* h,
+                        void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!h) return set_error(GR_EINVAL, "hierarchy is NULL");
+    return reduce_impl(g, p, res, h, ws, ws_bytes, stream);
 }
 
 int gr_edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* edge_of_entry,
@@ -496,7 +559,7 @@ int gr_eig_workspace(int64_t n, int32_t n_eig, size_t* bytes) {
     return GR_OK;
 }
 
-static int eigs_common(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
+static int eigs_common(const gr_graph* g, const double* bdiag, int32_t n_eig, int32_t method, double tol,
                        int32_t max_iter, int32_t degree, uint64_t seed, double* eig, double* U,
                        gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
     GR_TRY(check_graph_args(g));
@@ -515,7 +578,7 @@ static int eigs_common(const gr_graph* g, int32_t n_eig, int32_t method, double 
         return GR_OK;
     }
     Arena A(ws, ws_bytes);
-    return laplacian_eigs(g, n_eig, method, tol, max_iter, degree, seed, eig, U, report, A,
+    return laplacian_eigs(g, bdiag, n_eig, method, tol, max_iter, degree, seed, eig, U, report, A,
                           S(stream));
 }
 
@@ -523,8 +586,8 @@ int gr_laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double t
                       int32_t max_iter, int32_t degree, uint64_t seed, double* eig,
                       gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
-    return eigs_common(g, n_eig, method, tol, max_iter, degree, seed, eig, nullptr, report, ws,
-                       ws_bytes, stream);
+    return eigs_common(g, nullptr, n_eig, method, tol, max_iter, degree, seed, eig, nullptr, report,
+                       ws, ws_bytes, stream);
 }
 
 int gr_laplacian_eigpairs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
@@ -532,8 +595,318 @@ int gr_laplacian_eigpairs(const gr_graph* g, int32_t n_eig, int32_t method, doub
                           gr_eig_report* report, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (!U && g && g->n > 0) return set_error(GR_EINVAL, "U is NULL");
-    return eigs_common(g, n_eig, method, tol, max_iter, degree, seed, eig, U, report, ws,
+    return eigs_common(g, nullptr, n_eig, method, tol, max_iter, degree, seed, eig, U, report, ws,
                        ws_bytes, stream);
+}
+
+int gr_laplacian_geigpairs(const gr_graph* g, const double* bdiag, int32_t n_eig, int32_t method,
+                           double tol, int32_t max_iter, int32_t degree, uint64_t seed,
+                           double* eig, double* U, gr_eig_report* report, void* ws,
+                           size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!U && g && g->n > 0) return set_error(GR_EINVAL, "U is NULL");
+    return eigs_common(g, bdiag, n_eig, method, tol, max_iter, degree, seed, eig, U, report, ws,
+                       ws_bytes, stream);
+}
+
+int gr_jacobi_workspace(int64_t n, int32_t k, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || k < 1 || k > 64) return set_error(GR_EINVAL, "bad size");
+    *bytes = jacobi_workspace(n, k);
+    return GR_OK;
+}
+
+int gr_jacobi_filter(const gr_graph* g, int32_t k, double* Y, const double* lambda,
+                     const double* bdiag, double theta, int32_t iters, void* ws, size_t ws_bytes,
+                     void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (k < 1 || k > 64) return set_error(GR_EINVAL, "k must lie in [1, 64]");
+    if (iters < 0 || !(theta > 0.0) || !isfinite(theta))
+        return set_error(GR_EINVAL, "bad theta or iters");
+    if (g->n == 0 || iters == 0) return GR_OK;
+    if (!Y || !ws) return set_error(GR_EINVAL, "NULL Y or workspace");
+    Arena A(ws, ws_bytes);
+    return jacobi_filter(g, k, Y, lambda, bdiag, theta, iters, A, S(stream));
+}
+
+int gr_orthonormalize_workspace(int64_t n, int32_t k, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || k < 1 || k > 64) return set_error(GR_EINVAL, "bad size");
+    *bytes = orthonormalize_workspace(n, k);
+    return GR_OK;
+}
+
+int gr_orthonormalize(int64_t n, int32_t k, double* U, const double* bdiag, void* ws,
+                      size_t ws_bytes, void* stream) {
+    clear_error();
+    if (n < 0 || k < 1 || k > 64) return set_error(GR_EINVAL, "bad size");
+    if (n <= k) return set_error(GR_EINVAL, "need n > k (the constant takes one dimension)");
+    if (!U || !ws) return set_error(GR_EINVAL, "NULL U or workspace");
+    Arena A(ws, ws_bytes);
+    return orthonormalize(n, k, U, bdiag, A, S(stream));
+}
+
+int gr_multilevel_workspace(int64_t n, int64_t nnz, int32_t k, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || nnz < 0 || k < 1 || k > 32) return set_error(GR_EINVAL, "bad size");
+    *bytes = multilevel_workspace(n, nnz, k);
+    return GR_OK;
+}
+
+int gr_multilevel_eigs(const gr_graph* g, const gr_hierarchy* h, int32_t k, int32_t mode,
+                       double theta, int32_t iters, double tol, int32_t max_iter, uint64_t seed,
+                       double* eig, double* U, gr_eig_report* report, void* ws, size_t ws_bytes,
+                       void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!h) return set_error(GR_EINVAL, "hierarchy is NULL");
+    if (h->levels < 0 || h->levels > GR_MAX_LEVELS) return set_error(GR_EINVAL, "bad level count");
+    if (h->n[0] != g->n) return set_error(GR_EINVAL, "h->n[0] must be the graph's node count");
+    for (int l = 1; l <= h->levels; ++l) {
+        if (h->n[l] < 1 || h->n[l] > h->n[l - 1] || h->nnz[l] < 0)
+            return set_error(GR_EINVAL, "bad sizes at level %d", l);
+        if (!h->maps || !h->row_ptr || (h->nnz[l] > 0 && (!h->col || !h->w)))
+            return set_error(GR_EINVAL, "NULL hierarchy arrays");
+    }
+    if (k < 1 || k > 32) return set_error(GR_EINVAL, "k must lie in [1, 32]");
+    if (mode != GR_RQ_IDENTITY && mode != GR_RQ_DEGREE) return set_error(GR_EINVAL, "bad mode");
+    if (iters < 0 || !(theta > 0.0) || !isfinite(theta) || !(tol > 0.0) || max_iter < 0)
+        return set_error(GR_EINVAL, "bad theta, iters, tol or max_iter");
+    if (!eig || !U || !ws) return set_error(GR_EINVAL, "NULL argument");
+    if (h->n[h->levels] <= k + 1)
+        return set_error(GR_EINVAL, "the coarsest level needs more than k + 1 nodes");
+    if (report) memset(report, 0, sizeof(*report));
+    Arena A(ws, ws_bytes);
+    return multilevel_eigs(g, h, k, mode, theta, iters, tol, max_iter, seed, eig, U, report, A,
+                           S(stream));
+}
+
+static int check_sparsify_params(const gr_sparsify_params* p) {
+    if (!p) return set_error(GR_EINVAL, "params is NULL");
+    if (p->t < 1 || p->rounds < 0 || p->rounds > GR_SPARSIFY_MAX_ROUNDS || !(p->add_frac >= 0.0) ||
+        !isfinite(p->add_frac) || !isfinite(p->lambda_target) || p->cg_max_iter < 0 ||
+        !(p->cg_tol >= 0.0))
+        return set_error(GR_EINVAL, "bad sparsification parameters");
+    return GR_OK;
+}
+
+int gr_sparsify_workspace(int64_t n, int64_t nnz, size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || nnz < 0) return set_error(GR_EINVAL, "negative size");
+    *bytes = sparsify_workspace(n, nnz);
+    return GR_OK;
+}
+
+int gr_spanning_forest(const gr_graph* g, int32_t* in_tree, int64_t* n_tree, void* ws,
+                       size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!n_tree) return set_error(GR_EINVAL, "n_tree is NULL");
+    *n_tree = 0;
+    if (g->nnz % 2) return set_error(GR_ECSR, "odd nnz: graph not symmetric");
+    if (g->nnz == 0) return GR_OK;
+    if (!in_tree || !ws) return set_error(GR_EINVAL, "NULL in_tree or workspace");
+    hipStream_t st = S(stream);
+    Arena A(ws, ws_bytes);
+    const int64_t E0 = g->nnz / 2;
+    int32_t* eu = A.take<int32_t>(E0 + 1);
+    int32_t* ev = A.take<int32_t>(E0 + 1);
+    int32_t* eoe = A.take<int32_t>(g->nnz + 1);
+    if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (spanning forest)");
+    int64_t E = 0;
+    GR_TRY(edge_list(g, eu, ev, eoe, &E, A, st));
+    return spanning_forest(g, eu, ev, eoe, in_tree, E, n_tree, A, st);
+}
+
+int gr_sparsify(const gr_graph* g, const gr_sparsify_params* p, int32_t* in_P, double* criticality,
+                gr_sparsify_report* rep, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    GR_TRY(check_sparsify_params(p));
+    if (!rep) return set_error(GR_EINVAL, "report is NULL");
+    memset(rep, 0, sizeof(*rep));
+    if (g->nnz % 2) return set_error(GR_ECSR, "odd nnz: graph not symmetric");
+    if (g->nnz == 0) return GR_OK;
+    if (!in_P || !ws) return set_error(GR_EINVAL, "NULL in_P or workspace");
+    Arena A(ws, ws_bytes);
+    return sparsify(g, p, in_P, criticality, rep, A, S(stream));
+}
+
+int gr_subgraph(const gr_graph* g, const int32_t* keep, int32_t* p_row_ptr, int32_t* p_col,
+                float* p_w, int32_t* p_edge_of_entry, int32_t* p_eu, int32_t* p_ev, int64_t* p_nnz,
+                int64_t* p_edges, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!p_nnz || !p_edges) return set_error(GR_EINVAL, "NULL size outputs");
+    *p_nnz = *p_edges = 0;
+    if (g->nnz % 2) return set_error(GR_ECSR, "odd nnz: graph not symmetric");
+    if (!p_row_ptr || !ws || (g->nnz > 0 && (!keep || !p_col || !p_w)))
+        return set_error(GR_EINVAL, "NULL argument");
+    if ((p_eu == nullptr) != (p_ev == nullptr)) return set_error(GR_EINVAL, "p_eu and p_ev go together");
+    hipStream_t st = S(stream);
+    if (g->nnz == 0) {
+        GR_TRY(fill_i32(p_row_ptr, 0, g->n + 1, st));
+        return GR_OK;
+    }
+    Arena A(ws, ws_bytes);
+    const int64_t E0 = g->nnz / 2;
+    int32_t* eu = A.take<int32_t>(E0 + 1);
+    int32_t* ev = A.take<int32_t>(E0 + 1);
+    int32_t* eoe = A.take<int32_t>(g->nnz + 1);
+    if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (subgraph)");
+    int64_t E = 0;
+    GR_TRY(edge_list(g, eu, ev, eoe, &E, A, st));
+    return subgraph(g, eoe, keep, E, eu, ev, p_row_ptr, p_col, p_w, p_edge_of_entry, p_eu, p_ev,
+                    p_nnz, p_edges, A, st);
+}
+
+// the flow's own buffers: one subgraph (CSR, edge list, entry -> edge),
+// its flags and weights
+static size_t flow_buffers(int64_t n, int64_t nnz) {
+    const size_t N = (size_t)n + 1, M = (size_t)nnz + 1, E = M / 2 + 1;
+    return 4 * N + 4 * M + 4 * M + 4 * M + 8 * E + 4 * E + 8 * E + 4 * E + 4 * N + 4 * M + 4 * M +
+           32 * 256;
+}
+
+int gr_spectral_reduce_workspace(int64_t n, int64_t nnz, int32_t K, int32_t vec_dtype,
+                                 size_t* bytes) {
+    clear_error();
+    if (!bytes) return set_error(GR_EINVAL, "bytes is NULL");
+    if (n < 0 || nnz < 0) return set_error(GR_EINVAL, "negative size");
+    GR_TRY(check_vec_args(K, vec_dtype));
+    size_t inner = plan_bytes(n, nnz, K, vec_dtype);
+    inner = std::max(inner, sparsify_workspace(n, nnz));
+    inner = std::max(inner, sgd_workspace(n, nnz, nnz, nnz / 2));
+    *bytes = flow_buffers(n, nnz) + inner + (4u << 20);
+    return GR_OK;
+}
+
+int gr_spectral_reduce(const gr_graph* g, const gr_flow_params* p, gr_flow_result* res, void* ws,
+                       size_t ws_bytes, void* stream) {
+    clear_error();
+    GR_TRY(check_graph_args(g));
+    if (!p || !res || !ws) return set_error(GR_EINVAL, "NULL params, result or workspace");
+    GR_TRY(check_sparsify_params(&p->phase_b));
+    if (!(p->gamma_max > 0.0)) return set_error(GR_EINVAL, "gamma_max must be positive");
+    const gr_sgd_params* sp = &p->scaling;
+    if (sp->k_max < 1 || sp->k_max > GR_SGD_MAX_ITER || sp->t < 1 || !(sp->delta_bar > 0.0) ||
+        !(sp->delta_bar <= 1.0))
+        return set_error(GR_EINVAL, "bad scaling parameters");
+    if (!res->agg || !res->s_row_ptr || (g->nnz > 0 && (!res->s_col || !res->s_w)))
+        return set_error(GR_EINVAL, "NULL output");
+    if (g->nnz % 2) return set_error(GR_ECSR, "odd nnz: graph not symmetric");
+    memset(&res->sparsify, 0, sizeof(res->sparsify));
+    memset(&res->scaling, 0, sizeof(res->scaling));
+    res->n_s = res->nnz_s = 0;
+    res->levels = 0;
+    res->warnings = 0;
+    hipStream_t st = S(stream);
+    const int64_t n = g->n, nnz = g->nnz, E0 = nnz / 2;
+    res->gamma = n > 0 ? (double)E0 / (double)n : 0.0;
+    res->dense = res->gamma >= p->gamma_max ? 1 : 0;
+    Arena F(ws, ws_bytes);
+    // one subgraph's arrays, flags and weights; the rest is the inner workspace
+    int32_t* Rrp = F.take<int32_t>(n + 1);   // R (sparse branch)
+    int32_t* Rcol = F.take<int32_t>(nnz + 1);
+    float* Rw = F.take<float>(nnz + 1);
+    int32_t* keep = F.take<int32_t>(E0 + 1);
+    int32_t* peu = F.take<int32_t>(E0 + 1);
+    int32_t* pev = F.take<int32_t>(E0 + 1);
+    int32_t* peoe = F.take<int32_t>(nnz + 1);
+    double* wP = F.take<double>(E0 + 1);
+    float* wPf = F.take<float>(E0 + 1);
+    int32_t* Prp = F.take<int32_t>(n + 1);
+    int32_t* Pcol = F.take<int32_t>(nnz + 1);
+    float* Pw = F.take<float>(nnz + 1);
+    if (F.overflow) return set_error(GR_ENOMEM, "workspace too small (flow buffers)");
+    char* inner = (char*)ws + F.used;
+    const size_t inner_bytes = ws_bytes - F.used;
+    gr_params pa;
+    copy_params(&p->phase_a, &pa);
+    gr_result ra;
+    memset(&ra, 0, sizeof(ra));
+    // Phase B then Alg. 1 on graph h (g or R): the scaled sparsifier into
+    // Prp/Pcol/Pw (float32 weights)
+    auto phase_b = [&](const gr_graph* h, int64_t* pnnz_out) -> int {
+        Arena A(inner, inner_bytes);
+        GR_TRY(sparsify(h, &p->phase_b, keep, nullptr, &res->sparsify, A, st));
+        int32_t* eu = A.take<int32_t>(h->nnz / 2 + 1);
+        int32_t* ev = A.take<int32_t>(h->nnz / 2 + 1);
+        int32_t* eoe = A.take<int32_t>(h->nnz + 1);
+        if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (flow sparsifier)");
+        int64_t E = 0, pnnz = 0, pedges = 0;
+        GR_TRY(edge_list(h, eu, ev, eoe, &E, A, st));
+        GR_TRY(subgraph(h, eoe, keep, E, eu, ev, Prp, Pcol, Pw, peoe, peu, pev, &pnnz, &pedges, A,
+                        st));
+        gr_graph P{h->n, pnnz, Prp, Pcol, Pw};
+        // w_P <- the subgraph's weights, one per P edge, then Alg. 1
+        {
+            Arena B(inner, inner_bytes);
+            float* wEf = B.take<float>(pedges + 1);
+            if (B.overflow) return set_error(GR_ENOMEM, "workspace too small (flow weights)");
+            // the P edges' weights from their upper entries
+            GR_TRY(edge_weights(&P, peoe, wEf, st));
+            hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks_for(pedges, 256)), dim3(256), 0, st,
+                               (const float*)wEf, pedges, wP);
+            GR_LAUNCHED("flow weights f64");
+        }
+        {
+            Arena B(inner, inner_bytes);
+            GR_TRY(sgd_scale(h, &P, peoe, pedges, peu, pev, wP, &p->scaling, &res->scaling, B, st));
+        }
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(blocks_for(pedges, 256)), dim3(256), 0, st,
+                           (const double*)wP, pedges, wPf);
+        GR_LAUNCHED("flow scaled weights");
+        GR_TRY(expand_weights(peoe, pnnz, pedges, wPf, Pw, st));
+        *pnnz_out = pnnz;
+        return GR_OK;
+    };
+    if (!res->dense) {
+        // Phase A on g, into R; then Phase B and Alg. 1 on R
+        ra.agg = res->agg;
+        ra.c_row_ptr = Rrp;
+        ra.c_col = Rcol;
+        ra.c_w = Rw;
+        GR_TRY(reduce_impl(g, &pa, &ra, nullptr, inner, inner_bytes, stream));
+        gr_graph R{ra.n_coarse, ra.nnz_coarse, Rrp, Rcol, Rw};
+        int64_t pnnz = 0;
+        if (R.nnz > 0) {
+            GR_TRY(phase_b(&R, &pnnz));
+        } else {
+            GR_TRY(fill_i32(Prp, 0, R.n + 1, st));
+        }
+        GR_HIP(hipMemcpyAsync(res->s_row_ptr, Prp, sizeof(int32_t) * (R.n + 1),
+                              hipMemcpyDeviceToDevice, st));
+        if (pnnz > 0) {
+            GR_HIP(hipMemcpyAsync(res->s_col, Pcol, sizeof(int32_t) * pnnz, hipMemcpyDeviceToDevice, st));
+            GR_HIP(hipMemcpyAsync(res->s_w, Pw, sizeof(float) * pnnz, hipMemcpyDeviceToDevice, st));
+        }
+        res->n_s = R.n;
+        res->nnz_s = pnnz;
+    } else {
+        // Phase B and Alg. 1 on g, then Phase A on the scaled sparsifier
+        int64_t pnnz = 0;
+        GR_TRY(phase_b(g, &pnnz));
+        gr_graph P{n, pnnz, Prp, Pcol, Pw};
+        pa.colours = nullptr;  // a prescribed colouring belongs to g, not P
+        pa.n_colours = 0;
+        ra.agg = res->agg;
+        ra.c_row_ptr = res->s_row_ptr;
+        ra.c_col = res->s_col;
+        ra.c_w = res->s_w;
+        GR_TRY(reduce_impl(&P, &pa, &ra, nullptr, inner, inner_bytes, stream));
+        res->n_s = ra.n_coarse;
+        res->nnz_s = ra.nnz_coarse;
+    }
+    res->levels = ra.levels;
+    res->warnings = ra.warnings;
+    GR_HIP(hipStreamSynchronize(st));
+    return GR_OK;
 }
 
 int gr_sgd_workspace(int64_t n, int64_t nnz_g, int64_t nnz_p, int64_t p_edges, size_t* bytes) {

@@ -47,6 +47,7 @@ __global__ void __launch_bounds__(kE) k_spmm_pieces(const int32_t* __restrict__ 
                                                     const int32_t* __restrict__ prow, int64_t npieces,
                                                     int32_t ep, int p, int ld, int lanes,
                                                     const double* __restrict__ X,
+                                                    const double* __restrict__ sc,
                                                     double* __restrict__ part) {
     const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
     const int64_t k = t / lanes;
@@ -59,15 +60,25 @@ __global__ void __launch_bounds__(kE) k_spmm_pieces(const int32_t* __restrict__ 
     int32_t e = e0;
     for (; e + 4 <= e1; e += 4) {  // four gathers in flight, summed in entry order
         double xv[4], wv[4];
+        int32_t j[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             wv[u] = (double)w[e + u];
-            xv[u] = X[(int64_t)col[e + u] * ld + c];
+            j[u] = col[e + u];
+            xv[u] = X[(int64_t)j[u] * ld + c];
+        }
+        if (sc) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] *= sc[j[u]];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) s = fma(wv[u], xv[u], s);
     }
-    for (; e < e1; ++e) s = fma((double)w[e], X[(int64_t)col[e] * ld + c], s);
+    for (; e < e1; ++e) {
+        const int32_t j = col[e];
+        const double x = sc ? X[(int64_t)j * ld + c] * sc[j] : X[(int64_t)j * ld + c];
+        s = fma((double)w[e], x, s);
+    }
     part[k * p + c] = s;
 }
 
@@ -76,6 +87,7 @@ __global__ void __launch_bounds__(kE) k_spmm_rows(const int32_t* __restrict__ pp
                                                   int ld, int lanes,
                                                   const double* __restrict__ part,
                                                   const double* __restrict__ X,
+                                                  const double* __restrict__ sc,
                                                   double* __restrict__ Y) {
     const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
     const int64_t v = t / lanes;
@@ -83,7 +95,10 @@ __global__ void __launch_bounds__(kE) k_spmm_rows(const int32_t* __restrict__ pp
     if (v >= n || c >= p) return;
     double s = 0.0;
     for (int32_t k = ppos[v]; k < ppos[v + 1]; ++k) s += part[(int64_t)k * p + c];
-    Y[v * ld + c] = d[v] * X[v * ld + c] - s;
+    if (sc)  // S L S X with S = diag(sc)
+        Y[v * ld + c] = sc[v] * (d[v] * (sc[v] * X[v * ld + c]) - s);
+    else
+        Y[v * ld + c] = d[v] * X[v * ld + c] - s;
 }
 
 // pieces of every row, and the row of every piece
@@ -156,14 +171,19 @@ __global__ void k_fix_zero_cols(const double* __restrict__ G, int64_t n, int p, 
     if (!(gc > 1e-200 * gmax)) X[v * ld + c] = block_rand(seed, v, c);
 }
 
-// per-block partial column sums of X[:, 0:p] (stride ld)
+// per-block partial column sums of X[:, 0:p] (stride ld), weighted by q
+// when q is given (the products q^T X)
 __global__ void __launch_bounds__(kE) k_colsum_part(const double* __restrict__ X, int64_t n, int p,
-                                                    int ld, double* __restrict__ part) {
+                                                    int ld, const double* __restrict__ q,
+                                                    double* __restrict__ part) {
     const int64_t R = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * R, hi = min(n, lo + R);
     for (int c = threadIdx.x; c < p; c += kE) {
         double s = 0.0;
-        for (int64_t v = lo; v < hi; ++v) s += X[v * ld + c];
+        if (q)
+            for (int64_t v = lo; v < hi; ++v) s = fma(q[v], X[v * ld + c], s);
+        else
+            for (int64_t v = lo; v < hi; ++v) s += X[v * ld + c];
         part[(int64_t)blockIdx.x * p + c] = s;
     }
 }
@@ -190,13 +210,18 @@ __global__ void k_colsum_final(const double* __restrict__ part, int nb, int p, d
     out[c] = strided_sum(part, nb, p, c);
 }
 
+// X <- X - 1 (1^T X) / n, or X - q (q^T X) / (q^T q) when q is given
 __global__ void k_sub_colmean(double* __restrict__ X, int64_t n, int p, int ld,
-                              const double* __restrict__ cs) {
+                              const double* __restrict__ cs, const double* __restrict__ q,
+                              const double* __restrict__ qq) {
     int64_t i = (int64_t)blockIdx.x * kE + threadIdx.x;
     if (i >= n * p) return;
     int64_t v = i / p;
     int c = (int)(i - v * p);
-    X[v * ld + c] -= cs[c] / (double)n;
+    if (q)
+        X[v * ld + c] -= q[v] * (cs[c] / *qq);
+    else
+        X[v * ld + c] -= cs[c] / (double)n;
 }
 
 // per-block partials of A[:, 0:pa]^T B[:, 0:pb] (both of stride ld), rows
@@ -494,6 +519,12 @@ struct Eig {
     double* ppart;         // their partial sums [npieces][p]
     int64_t npieces;
     int32_t ep;            // entries per piece
+    // generalised problem L u = lambda B u with B = diag(b) > 0: the solver
+    // works on S L S (S = diag(b)^-1/2) in the complement of q = b^1/2,
+    // its null vector; u = S v.  All three NULL for B = I.
+    const double* sc = nullptr;  // b^-1/2
+    const double* q = nullptr;   // b^1/2
+    double* qq = nullptr;        // q^T q = sum of b (device scalar)
 
     static int lanes_for(int p) {
         int l = 1;
@@ -506,24 +537,24 @@ struct Eig {
         if (npieces > 0) {
             hipLaunchKernelGGL(k_spmm_pieces, dim3(blocks_for(npieces * lanes, kE)), dim3(kE), 0, st,
                                g->row_ptr, g->col, g->w, (const int32_t*)ppos, (const int32_t*)prow,
-                               npieces, ep, p, ld, lanes, A, ppart);
+                               npieces, ep, p, ld, lanes, A, sc, ppart);
             GR_LAUNCHED("spmm pieces");
         }
         hipLaunchKernelGGL(k_spmm_rows, dim3(blocks_for(n * lanes, kE)), dim3(kE), 0, st,
                            (const int32_t*)ppos, (const double*)d, n, p, ld, lanes,
-                           (const double*)ppart, A, B);
+                           (const double*)ppart, A, sc, B);
         GR_LAUNCHED("spmm rows");
         return GR_OK;
     }
     int project(double* A, int p) {
         hipLaunchKernelGGL(k_colsum_part, dim3(kRowBlocks), dim3(kE), 0, st, (const double*)A, n, p,
-                           ld, part);
+                           ld, q, part);
         GR_LAUNCHED("colsum");
         hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(kMaxP), 0, st, (const double*)part,
                            kRowBlocks, p, cs);
         GR_LAUNCHED("colsum final");
         hipLaunchKernelGGL(k_sub_colmean, dim3(blocks_for(n * p, kE)), dim3(kE), 0, st, A, n, p, ld,
-                           (const double*)cs);
+                           (const double*)cs, q, (const double*)qq);
         GR_LAUNCHED("project");
         return GR_OK;
     }
@@ -597,7 +628,8 @@ size_t eig_workspace(int64_t n, int32_t n_eig) {
     // blocks, degrees, small matrices; row pieces (at most 2n: offsets, rows,
     // and partial sums of up to kMaxP columns each)
     size_t b = 4 * blk + 16 * (size_t)(n + 1) + 8 * (size_t)kRowBlocks * kMaxP * kMaxP +
-               8 * 4 * kMaxP * kMaxP + 16 * (size_t)(n + 1) + 2 * blk;
+               8 * 4 * kMaxP * kMaxP + 16 * (size_t)(n + 1) + 2 * blk +
+               16 * (size_t)(n + 1);  // b^-1/2 and b^1/2 of a generalised problem
     return b + b / 16 + (1u << 20);
 }
 
@@ -732,49 +764,72 @@ static int run_lobpcg(Eig& s, int n_eig, int m, double b, double tol, int max_it
     return GR_OK;
 }
 
-// U[v][i] = the Ritz vector i (column i of the block, stride ld), NaN past m
+// U[v][i] = the Ritz vector i (column i of the block, stride ld), NaN past
+// m; times sc[v] for the generalised problem (u = S v)
 __global__ void k_copy_vectors(const double* __restrict__ S, int ld, int m, int64_t n, int k,
-                               double* __restrict__ U) {
+                               const double* __restrict__ sc, double* __restrict__ U) {
     const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
     if (t >= n * k) return;
     const int64_t v = t / k;
     const int i = (int)(t % k);
-    U[t] = i < m ? S[v * ld + i] : __builtin_nan("");
+    U[t] = i < m ? (sc ? sc[v] * S[v * ld + i] : S[v * ld + i]) : __builtin_nan("");
 }
 
-int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol, int32_t max_iter,
-                   int32_t degree, uint64_t seed, double* eig_out, double* vec_out,
-                   gr_eig_report* rep, Arena& ws, hipStream_t st) {
-    Eig s{};
-    s.g = g;
-    s.n = g->n;
-    s.st = st;
-    s.seed = seed;
+// B = diag(b): sc = b^-1/2, q = b^1/2, and the Jacobi preconditioner of
+// S L S, b / d (1 where d = 0); flag[1] = 1 if some b is not positive and
+// finite
+__global__ void k_b_setup(const double* __restrict__ b, const double* __restrict__ d, int64_t n,
+                          double* __restrict__ sc, double* __restrict__ q, double* __restrict__ dinv,
+                          int* flag) {
+    const int64_t v = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (v >= n) return;
+    const double bv = b[v];
+    if (!(bv > 0.0) || !(bv < INFINITY)) {
+        atomicOr(flag + 1, 1);
+        sc[v] = q[v] = 1.0;
+        return;
+    }
+    const double r = sqrt(bv);
+    q[v] = r;
+    sc[v] = 1.0 / r;
+    dinv[v] = d[v] > 0.0 ? bv / d[v] : 1.0;
+}
+
+// Gershgorin bound of each row of S L S: sc_v (d_v sc_v + sum_j w_vj sc_j),
+// a wave per row
+__global__ void __launch_bounds__(kE) k_gersh_rows(const int32_t* __restrict__ rp,
+                                                   const float* __restrict__ w,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ d,
+                                                   const double* __restrict__ sc, int64_t n,
+                                                   double* __restrict__ out) {
+    const int64_t v = ((int64_t)blockIdx.x * kE + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
+    if (v >= n) return;
+    double s = 0.0;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += kWave) s = fma((double)w[e], sc[col[e]], s);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) s += __shfl_xor(s, off, kWave);
+    if (l == 0) out[v] = sc[v] * (d[v] * sc[v] + s);
+}
+
+// degrees and row pieces of the Laplacian product of s.g for blocks of up
+// to maxp columns (d, dinv, ppos, prow, ppart taken from ws)
+static int setup_operator(Eig& s, int maxp, Arena& ws) {
+    const gr_graph* g = s.g;
     const int64_t n = g->n;
+    hipStream_t st = s.st;
     s.d = ws.take<double>(n + 1);
     s.dinv = ws.take<double>(n + 1);
-    s.S = ws.take<double>((size_t)n * kMaxP + 1);
-    s.LS = ws.take<double>((size_t)n * kMaxP + 1);
-    s.T = ws.take<double>((size_t)n * kMaxP + 1);
-    s.U = ws.take<double>((size_t)n * kMaxP + 1);
-    s.part = ws.take<double>((size_t)kRowBlocks * kMaxP * kMaxP);
-    s.G = ws.take<double>(kMaxP * kMaxP);
-    s.M = ws.take<double>(kMaxP * kMaxP);
-    s.theta = ws.take<double>(kMaxP);
-    s.cs = ws.take<double>(kMaxP);
-    s.res = ws.take<double>(kMaxP);
-    s.small = ws.take<double>(8);
-    s.flag = ws.take<int>(4);
     s.ppos = ws.take<int32_t>(n + 1);
     s.prow = ws.take<int32_t>(2 * (size_t)n + 1);
-    s.ppart = ws.take<double>((2 * (size_t)n + 1) * kMaxP);
-    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (eigen)");
-    GR_HIP(hipMemsetAsync(s.flag, 0, sizeof(int) * 4, st));
+    s.ppart = ws.take<double>((2 * (size_t)n + 1) * maxp);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (Laplacian product)");
     hipLaunchKernelGGL(k_degree_f64, dim3(blocks_for(n * kWave, kE)), dim3(kE), 0, st, g->row_ptr,
                        g->w, n, s.d, s.dinv);
     GR_LAUNCHED("degrees");
     // row pieces of at least the mean degree: at most n + nnz / ep <= 2n
-    s.ep = (int32_t)std::max<int64_t>(64, (g->nnz + n - 1) / n);
+    s.ep = (int32_t)std::max<int64_t>(64, (g->nnz + n - 1) / (n > 0 ? n : 1));
     {
         const size_t mark = ws.used;
         int32_t* cnt = ws.take<int32_t>(n);
@@ -793,13 +848,71 @@ int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
     GR_HIP(hipStreamSynchronize(st));
     s.npieces = np32;
     if (s.npieces > 2 * n) return set_error(GR_EINVAL, "row pieces exceed 2n");
+    return GR_OK;
+}
+
+int laplacian_eigs(const gr_graph* g, const double* bdiag, int32_t n_eig, int32_t method,
+                   double tol, int32_t max_iter, int32_t degree, uint64_t seed, double* eig_out,
+                   double* vec_out, gr_eig_report* rep, Arena& ws, hipStream_t st) {
+    Eig s{};
+    s.g = g;
+    s.n = g->n;
+    s.st = st;
+    s.seed = seed;
+    const int64_t n = g->n;
+    s.S = ws.take<double>((size_t)n * kMaxP + 1);
+    s.LS = ws.take<double>((size_t)n * kMaxP + 1);
+    s.T = ws.take<double>((size_t)n * kMaxP + 1);
+    s.U = ws.take<double>((size_t)n * kMaxP + 1);
+    s.part = ws.take<double>((size_t)kRowBlocks * kMaxP * kMaxP);
+    s.G = ws.take<double>(kMaxP * kMaxP);
+    s.M = ws.take<double>(kMaxP * kMaxP);
+    s.theta = ws.take<double>(kMaxP);
+    s.cs = ws.take<double>(kMaxP);
+    s.res = ws.take<double>(kMaxP);
+    s.small = ws.take<double>(8);
+    s.flag = ws.take<int>(4);
+    double* bsc = bdiag ? ws.take<double>(n + 1) : nullptr;
+    double* bq = bdiag ? ws.take<double>(n + 1) : nullptr;
+    double* bqq = bdiag ? ws.take<double>(8) : nullptr;
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (eigen)");
+    GR_HIP(hipMemsetAsync(s.flag, 0, sizeof(int) * 4, st));
+    GR_TRY(setup_operator(s, kMaxP, ws));
     hipLaunchKernelGGL(k_deg_stats, dim3(1), dim3(kE), 0, st, (const double*)s.d, n, s.small);
     GR_LAUNCHED("degree stats");
     double dstat[2] = {0.0, 0.0};
     GR_HIP(hipMemcpyAsync(dstat, s.small, sizeof(dstat), hipMemcpyDeviceToHost, st));
     GR_HIP(hipStreamSynchronize(st));
-    const double b = 2.0 * dstat[0] * (1.0 + 1e-12) + 1e-300;  // lambda_max <= 2 max degree
+    double b = 2.0 * dstat[0] * (1.0 + 1e-12) + 1e-300;  // lambda_max <= 2 max degree
     const double mean = dstat[1] / (double)n;
+    if (bdiag) {  // the generalised problem: S L S in the complement of b^1/2
+        hipLaunchKernelGGL(k_b_setup, dim3(blocks_for(n, kE)), dim3(kE), 0, st, bdiag,
+                           (const double*)s.d, n, bsc, bq, s.dinv, s.flag);
+        GR_LAUNCHED("generalised set-up");
+        // q^T q = sum of b, in the fixed order of the column sums
+        hipLaunchKernelGGL(k_colsum_part, dim3(kRowBlocks), dim3(kE), 0, st, bdiag, n, 1, 1,
+                           (const double*)nullptr, s.part);
+        GR_LAUNCHED("sum of b");
+        hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(kMaxP), 0, st, (const double*)s.part,
+                           kRowBlocks, 1, bqq);
+        GR_LAUNCHED("sum of b final");
+        // Gershgorin bound of lambda_max(S L S), rows into the T block
+        hipLaunchKernelGGL(k_gersh_rows, dim3(blocks_for(n * kWave, kE)), dim3(kE), 0, st,
+                           g->row_ptr, g->w, g->col, (const double*)s.d, (const double*)bsc, n, s.T);
+        GR_LAUNCHED("gershgorin rows");
+        hipLaunchKernelGGL(k_deg_stats, dim3(1), dim3(kE), 0, st, (const double*)s.T, n, s.small);
+        GR_LAUNCHED("gershgorin bound");
+        double gs[2] = {0.0, 0.0};
+        int fl[2] = {0, 0};
+        GR_HIP(hipMemcpyAsync(gs, s.small, sizeof(gs), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipMemcpyAsync(fl, s.flag, sizeof(fl), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+        if (fl[1]) return set_error(GR_EINVAL, "the diagonal of B must be positive and finite");
+        b = gs[0] * (1.0 + 1e-12) + 1e-300;
+        s.sc = bsc;
+        s.q = bq;
+        s.qq = bqq;
+    }
     // method choice: LOBPCG where a few hubs dominate the spectrum and the
     // block fits well inside the space; the filter otherwise
     const int ml = lobpcg_block(n_eig);
@@ -827,7 +940,7 @@ int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
     for (int i = 0; i < n_eig; ++i) eig_out[i] = i < m ? th[i] : NAN;
     if (vec_out) {  // the block holds the Ritz vectors of th, in ascending order
         hipLaunchKernelGGL(k_copy_vectors, dim3(blocks_for(n * n_eig, kE)), dim3(kE), 0, st,
-                           (const double*)s.S, s.ld, m, n, n_eig, vec_out);
+                           (const double*)s.S, s.ld, m, n, n_eig, s.sc, vec_out);
         GR_LAUNCHED("copy vectors");
         GR_HIP(hipStreamSynchronize(st));
     }
@@ -840,6 +953,234 @@ int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol,
         rep->method = use_lobpcg ? GR_EIG_LOBPCG : GR_EIG_CHEBYSHEV;
         rep->restarts = restarts;
     }
+    return GR_OK;
+}
+
+// ------------------------------------- solution refinement and Alg. 5
+// Alg. 3 filters approximate solutions by weighted Jacobi,
+// x <- (1 - theta) x + theta D^-1 A x; Alg. 5 applies the same smoother to
+// (L - lambda_i B) y = 0 on every level of the hierarchy.  The step used for
+// both keeps the Laplacian's own diagonal: y <- y - theta D^-1 (L y - lambda_i B y),
+// which is Alg. 3's step when lambda = 0 (rows with d = 0 stay).
+
+// U[v][i] = Uc[agg[v]][i] (H = the 0/1 node-to-aggregate map)
+__global__ void k_prolong(const int32_t* __restrict__ agg, int64_t n, int k,
+                          const double* __restrict__ Uc, double* __restrict__ U) {
+    const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t v = t / k;
+    const int i = (int)(t - v * k);
+    U[t] = Uc[(int64_t)agg[v] * k + i];
+}
+
+__global__ void k_jacobi_update(const double* __restrict__ LY, double* __restrict__ Y,
+                                const double* __restrict__ d, const double* __restrict__ b,
+                                const double* __restrict__ lam, int64_t n, int k, double theta) {
+    const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t v = t / k;
+    const int i = (int)(t - v * k);
+    const double dv = d[v];
+    if (!(dv > 0.0)) return;
+    const double y = Y[t];
+    double r = LY[t];
+    if (lam) r -= ((b ? b[v] : 1.0) * y) * lam[i];
+    Y[t] = y - (theta * r) / dv;
+}
+
+// X[v][i] *= f[v], or /= f[v]
+__global__ void k_row_scale(double* __restrict__ X, const double* __restrict__ f, int64_t n, int k,
+                            int divide) {
+    const int64_t t = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t v = t / k;
+    X[t] = divide ? X[t] / f[v] : X[t] * f[v];
+}
+
+__global__ void k_sqrt_vec(const double* __restrict__ b, int64_t n, double* __restrict__ r,
+                           int* bad) {
+    const int64_t v = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (v >= n) return;
+    const double x = b[v];
+    if (!(x > 0.0) || !(x < INFINITY)) {
+        atomicOr(bad, 1);
+        r[v] = 1.0;
+    } else {
+        r[v] = sqrt(x);
+    }
+}
+
+size_t jacobi_workspace(int64_t n, int32_t k) {
+    const size_t N = (size_t)n + 1;
+    size_t b = 16 * N + 4 * N + 4 * (2 * N) + 8 * (2 * N) * (size_t)k   // operator
+               + 8 * N * (size_t)k + 8 * 64 + 4 * N + (64u << 10);      // L Y, lambda, scan
+    return b + b / 16 + (1u << 20);
+}
+
+int jacobi_filter(const gr_graph* g, int32_t k, double* Y, const double* lam_host,
+                  const double* bdiag, double theta, int32_t iters, Arena& ws, hipStream_t st) {
+    const int64_t n = g->n;
+    if (n == 0 || iters == 0) return GR_OK;
+    const size_t mark = ws.used;
+    Eig s{};
+    s.g = g;
+    s.n = n;
+    s.st = st;
+    s.ld = k;
+    GR_TRY(setup_operator(s, k, ws));
+    double* LY = ws.take<double>((size_t)n * k + 1);
+    double* lam = lam_host ? ws.take<double>(k) : nullptr;
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (Jacobi filter)");
+    if (lam) GR_HIP(hipMemcpyAsync(lam, lam_host, sizeof(double) * k, hipMemcpyHostToDevice, st));
+    for (int32_t it = 0; it < iters; ++it) {
+        GR_TRY(s.spmm(Y, LY, k));
+        hipLaunchKernelGGL(k_jacobi_update, dim3(blocks_for(n * k, kE)), dim3(kE), 0, st,
+                           (const double*)LY, Y, (const double*)s.d, bdiag, (const double*)lam, n, k,
+                           theta);
+        GR_LAUNCHED("Jacobi update");
+    }
+    GR_HIP(hipStreamSynchronize(st));  // lam_host may be released on return
+    ws.used = mark;
+    return GR_OK;
+}
+
+size_t orthonormalize_workspace(int64_t n, int32_t k) {
+    const size_t N = (size_t)n + 1;
+    size_t b = 8 * N * (size_t)k + 8 * N + 8 * (size_t)kRowBlocks * kMaxP * kMaxP +
+               8 * 4 * kMaxP * kMaxP + 8 * 64;
+    return b + b / 16 + (1u << 20);
+}
+
+// Gram-Schmidt over [1, U] in the B inner product (B = diag(b), or I): with
+// V = B^1/2 U and q = B^1/2 1 it is the plain process on [q, V], computed
+// as a projection against q and Cholesky QR (the same Q: Gram-Schmidt and
+// Cholesky QR both give the QR factor with a positive diagonal).
+int orthonormalize(int64_t n, int32_t k, double* U, const double* bdiag, Arena& ws,
+                   hipStream_t st) {
+    if (n == 0) return GR_OK;
+    if (k < 1 || k > kMaxP) return set_error(GR_EINVAL, "k must lie in [1, %d]", kMaxP);
+    const size_t mark = ws.used;
+    Eig s{};
+    s.n = n;
+    s.st = st;
+    s.ld = k;
+    s.seed = 0x9e3779b97f4a7c15ull;
+    s.T = ws.take<double>((size_t)n * k + 1);
+    s.part = ws.take<double>((size_t)kRowBlocks * kMaxP * kMaxP);
+    s.G = ws.take<double>(kMaxP * kMaxP);
+    s.M = ws.take<double>(kMaxP * kMaxP);
+    s.cs = ws.take<double>(kMaxP);
+    s.flag = ws.take<int>(4);
+    double* q = bdiag ? ws.take<double>(n + 1) : nullptr;
+    double* qq = bdiag ? ws.take<double>(8) : nullptr;
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (orthonormalisation)");
+    GR_HIP(hipMemsetAsync(s.flag, 0, sizeof(int) * 4, st));
+    if (bdiag) {
+        hipLaunchKernelGGL(k_sqrt_vec, dim3(blocks_for(n, kE)), dim3(kE), 0, st, bdiag, n, q,
+                           s.flag + 1);
+        GR_LAUNCHED("B^1/2");
+        hipLaunchKernelGGL(k_colsum_part, dim3(kRowBlocks), dim3(kE), 0, st, bdiag, n, 1, 1,
+                           (const double*)nullptr, s.part);
+        GR_LAUNCHED("sum of b");
+        hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(kMaxP), 0, st, (const double*)s.part,
+                           kRowBlocks, 1, qq);
+        GR_LAUNCHED("sum of b final");
+        hipLaunchKernelGGL(k_row_scale, dim3(blocks_for(n * k, kE)), dim3(kE), 0, st, U,
+                           (const double*)q, n, k, 0);
+        GR_LAUNCHED("B^1/2 U");
+        s.q = q;
+        s.qq = qq;
+    }
+    GR_TRY(s.orthonormalise(U, k));
+    if (bdiag) {
+        hipLaunchKernelGGL(k_row_scale, dim3(blocks_for(n * k, kE)), dim3(kE), 0, st, U,
+                           (const double*)q, n, k, 1);
+        GR_LAUNCHED("B^-1/2 V");
+    }
+    int fl[2] = {0, 0};
+    GR_HIP(hipMemcpyAsync(fl, s.flag, sizeof(fl), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    ws.used = mark;
+    if (fl[1]) return set_error(GR_EINVAL, "the diagonal of B must be positive and finite");
+    if (fl[0]) return set_error(GR_EINVAL, "the columns are linearly dependent");
+    return GR_OK;
+}
+
+__global__ void k_fill_f64(double* __restrict__ x, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * kE + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+size_t multilevel_workspace(int64_t n, int64_t nnz, int32_t k) {
+    (void)nnz;
+    const size_t N = (size_t)n + 1;
+    size_t b = eig_workspace(n, k) + 2 * 8 * N * (size_t)k + 2 * 8 * N + jacobi_workspace(n, k) +
+               orthonormalize_workspace(n, k) + restrict_workspace(n, n, 1);
+    return b + b / 16 + (1u << 20);
+}
+
+int multilevel_eigs(const gr_graph* g, const gr_hierarchy* h, int32_t k, int32_t cut, double theta,
+                    int32_t iters, double tol, int32_t max_iter, uint64_t seed, double* lam_out,
+                    double* U, gr_eig_report* rep, Arena& ws, hipStream_t st) {
+    const int L = h->levels;
+    const int64_t n0 = g->n;
+    // level graphs: 0 = g, l >= 1 from the hierarchy
+    std::vector<gr_graph> lv(L + 1);
+    lv[0] = *g;
+    for (int l = 1; l <= L; ++l) {
+        lv[l].n = h->n[l];
+        lv[l].nnz = h->nnz[l];
+        lv[l].row_ptr = h->row_ptr + h->rp_off[l - 1];
+        lv[l].col = h->col + h->ent_off[l - 1];
+        lv[l].w = h->w + h->ent_off[l - 1];
+    }
+    // B on every level: B^1 = I (ratio cut) or D (normalized cut), then
+    // B^{l+1} = P_l^T B^l P_l, the sums of B^l over each aggregate
+    std::vector<double*> B(L + 1);
+    for (int l = 0; l <= L; ++l) B[l] = ws.take<double>(lv[l].n + 1);
+    double* Ua = ws.take<double>((size_t)n0 * k + 1);
+    double* Ub = ws.take<double>((size_t)n0 * k + 1);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (multilevel eigensolver)");
+    if (cut == GR_RQ_IDENTITY) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n0, kE)), dim3(kE), 0, st, B[0], n0, 1.0);
+        GR_LAUNCHED("B = I");
+    } else {
+        double* dinv = ws.take<double>(n0 + 1);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (multilevel eigensolver)");
+        hipLaunchKernelGGL(k_degree_f64, dim3(blocks_for(n0 * kWave, kE)), dim3(kE), 0, st,
+                           g->row_ptr, g->w, n0, B[0], dinv);
+        GR_LAUNCHED("B = D");
+    }
+    for (int l = 0; l < L; ++l)
+        GR_TRY(restrict_sum_f64(h->maps + h->maps_off[l], lv[l].n, lv[l + 1].n, B[l], B[l + 1], ws,
+                                st));
+    // the coarsest eigenpairs (lambda_i, u_i) of L^Y u = lambda B^Y u
+    const bool plain = L == 0 && cut == GR_RQ_IDENTITY;
+    {
+        const size_t mark = ws.used;
+        GR_TRY(laplacian_eigs(&lv[L], plain ? nullptr : B[L], k, GR_EIG_AUTO, tol, max_iter, 16,
+                              seed, lam_out, Ua, rep, ws, st));
+        ws.used = mark;
+    }
+    for (int i = 0; i < k; ++i)
+        if (!(lam_out[i] == lam_out[i]))
+            return set_error(GR_EINVAL, "the coarsest level has fewer than %d nontrivial eigenpairs", k);
+    // down the hierarchy: prolong, then filter with the coarsest lambda_i
+    double* cur = Ua;
+    double* nxt = Ub;
+    for (int l = L; l >= 1; --l) {
+        const int64_t nf = lv[l - 1].n;
+        hipLaunchKernelGGL(k_prolong, dim3(blocks_for(nf * k, kE)), dim3(kE), 0, st,
+                           (const int32_t*)(h->maps + h->maps_off[l - 1]), nf, k, (const double*)cur,
+                           nxt);
+        GR_LAUNCHED("prolong");
+        GR_TRY(jacobi_filter(&lv[l - 1], k, nxt, lam_out, B[l - 1], theta, iters, ws, st));
+        std::swap(cur, nxt);
+    }
+    // Gram-Schmidt of the finest vectors (B^1 inner product, after 1)
+    GR_TRY(orthonormalize(n0, k, cur, cut == GR_RQ_IDENTITY ? nullptr : B[0], ws, st));
+    GR_HIP(hipMemcpyAsync(U, cur, sizeof(double) * n0 * k, hipMemcpyDeviceToDevice, st));
+    GR_HIP(hipStreamSynchronize(st));
     return GR_OK;
 }
 

@@ -187,6 +187,8 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_coarse, int32_t* c
 size_t restrict_workspace(int64_t n, int64_t nc, int32_t d);
 int restrict_mean(const int32_t* agg, int64_t n, int64_t nc, int32_t d, const float* F, float* FR,
                   Arena& ws, hipStream_t st);
+int restrict_sum_f64(const int32_t* agg, int64_t n, int64_t nc, const double* b, double* bc,
+                     Arena& ws, hipStream_t st);
 
 // ------------------------------------------------------ edge derivatives
 int edge_list(const gr_graph* g, int32_t* eu, int32_t* ev, int32_t* eoe, int64_t* n_edges,
@@ -197,9 +199,29 @@ int rq_forward(int64_t n, int64_t E, const int32_t* eu, const int32_t* ev, const
 int expand_weights(const int32_t* eoe, int64_t nnz, int64_t E, const float* wE, float* w,
                    hipStream_t st);
 size_t eig_workspace(int64_t n, int32_t n_eig);
-int laplacian_eigs(const gr_graph* g, int32_t n_eig, int32_t method, double tol, int32_t max_iter,
-                   int32_t degree, uint64_t seed, double* eig_out, double* vec_out,
-                   gr_eig_report* rep, Arena& ws, hipStream_t st);
+int laplacian_eigs(const gr_graph* g, const double* bdiag, int32_t n_eig, int32_t method,
+                   double tol, int32_t max_iter, int32_t degree, uint64_t seed, double* eig_out,
+                   double* vec_out, gr_eig_report* rep, Arena& ws, hipStream_t st);
+size_t jacobi_workspace(int64_t n, int32_t k);
+int jacobi_filter(const gr_graph* g, int32_t k, double* Y, const double* lam_host,
+                  const double* bdiag, double theta, int32_t iters, Arena& ws, hipStream_t st);
+size_t orthonormalize_workspace(int64_t n, int32_t k);
+int orthonormalize(int64_t n, int32_t k, double* U, const double* bdiag, Arena& ws,
+                   hipStream_t st);
+size_t multilevel_workspace(int64_t n, int64_t nnz, int32_t k);
+int multilevel_eigs(const gr_graph* g, const gr_hierarchy* h, int32_t k, int32_t cut, double theta,
+                    int32_t iters, double tol, int32_t max_iter, uint64_t seed, double* lam_out,
+                    double* U, gr_eig_report* rep, Arena& ws, hipStream_t st);
+size_t sparsify_workspace(int64_t n, int64_t nnz);
+int edge_weights(const gr_graph* g, const int32_t* eoe, float* wE, hipStream_t st);
+int spanning_forest(const gr_graph* g, const int32_t* eu, const int32_t* ev, const int32_t* eoe,
+                    int32_t* in_tree, int64_t E, int64_t* n_tree, Arena& ws, hipStream_t st);
+int subgraph(const gr_graph* g, const int32_t* eoe, const int32_t* keep, int64_t E,
+             const int32_t* eu, const int32_t* ev, int32_t* prp, int32_t* pcol, float* pw,
+             int32_t* peoe, int32_t* peu, int32_t* pev, int64_t* p_nnz, int64_t* p_edges,
+             Arena& ws, hipStream_t st);
+int sparsify(const gr_graph* g, const gr_sparsify_params* prm, int32_t* keep, double* crit_out,
+             gr_sparsify_report* rep, Arena& ws, hipStream_t st);
 size_t sgd_workspace(int64_t n, int64_t nnzG, int64_t nnzP, int64_t E);
 int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t E,
               const int32_t* eu, const int32_t* ev, double* wP, const gr_sgd_params* prm,

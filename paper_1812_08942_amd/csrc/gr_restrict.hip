@@ -55,11 +55,12 @@ __global__ void k_restrict_piece_rows(const int32_t* __restrict__ ppos, int64_t 
 }
 
 // a thread per (piece, column): the FP64 sum of the piece's members in order
+template <class T>
 __global__ void k_restrict_pieces(const uint32_t* __restrict__ members,
                                   const int32_t* __restrict__ mstart,
                                   const int32_t* __restrict__ ppos,
                                   const int32_t* __restrict__ prow, int64_t npieces, int32_t d,
-                                  const float* __restrict__ F, double* __restrict__ part) {
+                                  const T* __restrict__ F, double* __restrict__ part) {
     const int64_t t = (int64_t)blockIdx.x * kRT + threadIdx.x;
     const int64_t k = t / d;
     const int32_t col = (int32_t)(t % d);
@@ -70,7 +71,7 @@ __global__ void k_restrict_pieces(const uint32_t* __restrict__ members,
     double s = 0.0;
     int32_t m = m0;
     for (; m + 4 <= m1; m += 4) {  // four rows in flight, added in member order
-        float x[4];
+        T x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) x[u] = F[(int64_t)members[m + u] * d + col];
 #pragma unroll
@@ -80,7 +81,8 @@ __global__ void k_restrict_pieces(const uint32_t* __restrict__ members,
     part[k * d + col] = s;
 }
 
-// a thread per (aggregate, column): its pieces in order, over the member count
+// a thread per (aggregate, column): its pieces in order, over the member
+// count (the mean, float32) or not (the sum, FP64)
 __global__ void k_restrict_final(const int32_t* __restrict__ mstart,
                                  const int32_t* __restrict__ ppos, int64_t nc, int32_t d,
                                  const double* __restrict__ part, float* __restrict__ FR) {
@@ -91,6 +93,17 @@ __global__ void k_restrict_final(const int32_t* __restrict__ mstart,
     double s = 0.0;
     for (int32_t k = ppos[c]; k < ppos[c + 1]; ++k) s += part[(int64_t)k * d + col];
     FR[c * d + col] = (float)(s / (double)(mstart[c + 1] - mstart[c]));
+}
+
+__global__ void k_restrict_final_sum(const int32_t* __restrict__ ppos, int64_t nc, int32_t d,
+                                     const double* __restrict__ part, double* __restrict__ FR) {
+    const int64_t t = (int64_t)blockIdx.x * kRT + threadIdx.x;
+    const int64_t c = t / d;
+    const int32_t col = (int32_t)(t % d);
+    if (c >= nc) return;
+    double s = 0.0;
+    for (int32_t k = ppos[c]; k < ppos[c + 1]; ++k) s += part[(int64_t)k * d + col];
+    FR[c * d + col] = s;
 }
 
 size_t restrict_workspace(int64_t n, int64_t nc, int32_t d) {
@@ -104,8 +117,10 @@ size_t restrict_workspace(int64_t n, int64_t nc, int32_t d) {
     return b + b / 8 + (1u << 20);
 }
 
-int restrict_mean(const int32_t* agg, int64_t n, int64_t nc, int32_t d, const float* F, float* FR,
-                  Arena& ws, hipStream_t st) {
+// mean (FR32 != NULL) or FP64 sum (FR64 != NULL) of F's rows per aggregate
+template <class T>
+static int restrict_rows(const int32_t* agg, int64_t n, int64_t nc, int32_t d, const T* F,
+                         float* FR32, double* FR64, Arena& ws, hipStream_t st) {
     const size_t mark = ws.used;
     uint64_t* k0 = ws.take<uint64_t>(n);
     uint32_t* v0 = ws.take<uint32_t>(n);
@@ -141,15 +156,34 @@ int restrict_mean(const int32_t* agg, int64_t n, int64_t nc, int32_t d, const fl
     hipLaunchKernelGGL(k_restrict_piece_rows, dim3(blocks_for(nc, kRT)), dim3(kRT), 0, st,
                        (const int32_t*)ppos, nc, prow);
     GR_LAUNCHED("piece rows");
-    hipLaunchKernelGGL(k_restrict_pieces, dim3(blocks_for(np * d, kRT)), dim3(kRT), 0, st,
+    hipLaunchKernelGGL(k_restrict_pieces<T>, dim3(blocks_for(np * d, kRT)), dim3(kRT), 0, st,
                        (const uint32_t*)v1, (const int32_t*)mstart, (const int32_t*)ppos,
                        (const int32_t*)prow, np, d, F, part);
     GR_LAUNCHED("restrict pieces");
-    hipLaunchKernelGGL(k_restrict_final, dim3(blocks_for(nc * d, kRT)), dim3(kRT), 0, st,
-                       (const int32_t*)mstart, (const int32_t*)ppos, nc, d, (const double*)part, FR);
+    if (FR32) {
+        hipLaunchKernelGGL(k_restrict_final, dim3(blocks_for(nc * d, kRT)), dim3(kRT), 0, st,
+                           (const int32_t*)mstart, (const int32_t*)ppos, nc, d, (const double*)part,
+                           FR32);
+    } else {
+        hipLaunchKernelGGL(k_restrict_final_sum, dim3(blocks_for(nc * d, kRT)), dim3(kRT), 0, st,
+                           (const int32_t*)ppos, nc, d, (const double*)part, FR64);
+    }
     GR_LAUNCHED("restrict final");
     ws.used = mark;
     return GR_OK;
+}
+
+int restrict_mean(const int32_t* agg, int64_t n, int64_t nc, int32_t d, const float* F, float* FR,
+                  Arena& ws, hipStream_t st) {
+    return restrict_rows<float>(agg, n, nc, d, F, FR, nullptr, ws, st);
+}
+
+// B^{l+1} = P^T B^l P for a diagonal B: the FP64 sum of b over each
+// aggregate's members, in node order (in fixed pieces of kRPiece)
+int restrict_sum_f64(const int32_t* agg, int64_t n, int64_t nc, const double* b, double* bc,
+                     Arena& ws, hipStream_t st) {
+    if (n == 0) return GR_OK;
+    return restrict_rows<double>(agg, n, nc, 1, b, nullptr, bc, ws, st);
 }
 
 }  // namespace gr

@@ -391,6 +391,29 @@ struct Sgd {
         GR_HIP(hipMemcpyAsync(out, y, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         return centre(out);
     }
+    // h_t: t generalised power iterations h <- L_P^+ L_G h from the centred
+    // h_0, normalised to h^T L_P h = 1 (into h); lambda_n = h^T L_G h
+    // (device slot SC_LAMN and *lam)
+    int power_vector(uint64_t seed, int t_iters, double* lam) {
+        const unsigned nb = blocks_for(n, kS);
+        hipLaunchKernelGGL(k_init_h, dim3(nb), dim3(kS), 0, st, n, seed, h);
+        GR_LAUNCHED("h0");
+        GR_TRY(centre(h));
+        for (int t = 0; t < t_iters; ++t) {
+            GR_TRY(lapG(h, t1));
+            GR_TRY(centre(t1));
+            GR_TRY(solve(t1, h));
+        }
+        GR_TRY(lapP(h, t1));
+        GR_TRY(dot(h, t1, n, SC_HLH));
+        hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(kS), 0, st, h, n, (const double*)sc);
+        GR_LAUNCHED("normalise");
+        GR_TRY(lapG(h, t1));
+        GR_TRY(dot(h, t1, n, SC_LAMN));
+        *lam = read(SC_LAMN);
+        if (!(*lam == *lam)) return set_error(GR_EHIP, "lambda_n is not finite");
+        return GR_OK;
+    }
     int refresh_P() {
         hipLaunchKernelGGL(k_expand_f64, dim3(blocks_for(nnzP, kS)), dim3(kS), 0, st, eoe, nnzP, E,
                            (const double*)w, wPent);
@@ -456,7 +479,7 @@ int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t 
     s.part = ws.take<double>(kRedBlocks + 1);
     s.sc = ws.take<double>(32);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (sgd)");
-    const unsigned nb = blocks_for(n, kS), eb = blocks_for(E, kS);
+    const unsigned eb = blocks_for(E, kS);
     GR_HIP(hipMemsetAsync(s.sc, 0, sizeof(double) * 32, st));
     GR_HIP(hipMemsetAsync(s.dw, 0, sizeof(double) * (E + 1), st));
     hipLaunchKernelGGL(k_promote, dim3(blocks_for(s.nnzG, kS)), dim3(kS), 0, st, G->w, s.nnzG, s.wG);
@@ -472,23 +495,8 @@ int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t 
     rep->lambda_1[0] = s.read(SC_LAM1);
     double lam_prev = 0.0;
     for (int k = 0; k < prm->k_max && k < GR_SGD_MAX_ITER; ++k) {
-        // h_t: t generalised power iterations from the centred h_0
-        hipLaunchKernelGGL(k_init_h, dim3(nb), dim3(kS), 0, st, n, prm->seed, s.h);
-        GR_LAUNCHED("h0");
-        GR_TRY(s.centre(s.h));
-        for (int t = 0; t < prm->t; ++t) {
-            GR_TRY(s.lapG(s.h, s.t1));
-            GR_TRY(s.centre(s.t1));
-            GR_TRY(s.solve(s.t1, s.h));
-        }
-        GR_TRY(s.lapP(s.h, s.t1));
-        GR_TRY(s.dot(s.h, s.t1, n, SC_HLH));
-        hipLaunchKernelGGL(k_normalise, dim3(nb), dim3(kS), 0, st, s.h, n, (const double*)s.sc);
-        GR_LAUNCHED("normalise");
-        GR_TRY(s.lapG(s.h, s.t1));
-        GR_TRY(s.dot(s.h, s.t1, n, SC_LAMN));
-        const double lam = s.read(SC_LAMN);
-        if (!(lam == lam)) return set_error(GR_EHIP, "lambda_n is not finite");
+        double lam = 0.0;
+        GR_TRY(s.power_vector(prm->seed, prm->t, &lam));
         rep->lambda_n[k] = lam;
         if (k == 0) {
             hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, st, s.sc, (int)SC_LAMN,
@@ -529,6 +537,408 @@ int sgd_scale(const gr_graph* G, const gr_graph* P, const int32_t* eoe, int64_t 
         rep->iterations = k + 1;
     }
     rep->cg_iterations_max = (int32_t)s.cg_iters_max;
+    return GR_OK;
+}
+
+// =====================================================================
+// Phase B: spectral sparsification (Sec. 3.3.2-3.3.3).  A spanning tree of
+// G, then rounds of densification: the approximate criticality
+// c_pq = w_G(p, q) (h_p - h_q)^2 of every edge outside the subgraph P, from
+// the same h_t as Alg. 1 (t generalised power iterations), ranks the edges,
+// and the most critical join P.  The tree is the maximum-weight spanning
+// forest, found by Boruvka rounds: every component takes its heaviest edge
+// to another component (ties to the smaller edge number, i.e. the smaller
+// endpoints), the components hook along those edges and are flattened by
+// pointer jumping.  With the edges in a strict order that forest is unique,
+// so the result equals sequential Kruskal on the same order bit for bit.
+// =====================================================================
+
+// heavier first, then the smaller edge number
+__device__ inline uint64_t tree_key(float w, int32_t e) {
+    return ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(~(uint32_t)e);
+}
+
+// per row (a wave): the best key of an entry leaving the row's component;
+// one atomic maximum per row on the component's slot
+__global__ void __launch_bounds__(kS) k_bv_best(const int32_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col,
+                                                const float* __restrict__ w,
+                                                const int32_t* __restrict__ eoe,
+                                                const int32_t* __restrict__ comp, int64_t n,
+                                                unsigned long long* __restrict__ best) {
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
+    if (v >= n) return;
+    const int32_t cv = comp[v];
+    uint64_t m = 0;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += kWave)
+        if (comp[col[e]] != cv) {
+            const uint64_t k = tree_key(w[e], eoe[e]);
+            m = k > m ? k : m;
+        }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(m >> 32), off, kWave) << 32) |
+                           (uint32_t)__shfl_xor((int)(uint32_t)m, off, kWave);
+        m = o > m ? o : m;
+    }
+    if (l == 0 && m) atomicMax(best + cv, (unsigned long long)m);
+}
+
+// every root takes its best edge: nxt[c] = the component across it, the
+// edge joins the forest
+__global__ void k_bv_hook(const unsigned long long* __restrict__ best,
+                          const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                          const int32_t* __restrict__ comp, int64_t n, int32_t* __restrict__ nxt,
+                          int32_t* __restrict__ in_tree, int32_t* changed) {
+    const int64_t c = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (c >= n) return;
+    nxt[c] = (int32_t)c;
+    if (comp[c] != c || best[c] == 0) return;
+    const int32_t e = (int32_t)(~(uint32_t)(best[c] & 0xffffffffull));
+    const int32_t a = comp[eu[e]], b = comp[ev[e]];
+    nxt[c] = a == (int32_t)c ? b : a;
+    in_tree[e] = 1;
+    *changed = 1;
+}
+
+// two components that took the same edge point at each other: the smaller
+// id stays a root
+__global__ void k_bv_pairs(int32_t* __restrict__ nxt, int64_t n) {
+    const int64_t c = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (c >= n) return;
+    const int32_t d = nxt[c];
+    if (d != (int32_t)c && nxt[d] == (int32_t)c && (int32_t)c < d) nxt[c] = (int32_t)c;
+}
+
+__global__ void k_bv_jump(int32_t* __restrict__ nxt, int64_t n, int32_t* changed) {
+    const int64_t c = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (c >= n) return;
+    const int32_t x = nxt[c], y = nxt[x];
+    if (x != y) {
+        nxt[c] = y;
+        *changed = 1;
+    }
+}
+
+__global__ void k_bv_relabel(int32_t* __restrict__ comp, const int32_t* __restrict__ nxt,
+                             int64_t n) {
+    const int64_t v = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (v < n) comp[v] = nxt[comp[v]];
+}
+
+__global__ void k_iota32(int32_t* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (i < n) x[i] = (int32_t)i;
+}
+
+// number of nonzero flags (0/1 values) among E
+static int count_flags(const int32_t* flags, int64_t E, int64_t* out, Arena& ws, hipStream_t st) {
+    *out = 0;
+    if (E <= 0) return GR_OK;
+    const size_t mark = ws.used;
+    int32_t* tmp = ws.take<int32_t>(E + 1);
+    int32_t* tot = ws.take<int32_t>(4);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (count)");
+    GR_TRY(scan_exclusive_i32(flags, tmp, E, tot, ws, st));
+    int32_t h = 0;
+    GR_HIP(hipMemcpyAsync(&h, tot, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    *out = h;
+    ws.used = mark;
+    return GR_OK;
+}
+
+int spanning_forest(const gr_graph* g, const int32_t* eu, const int32_t* ev, const int32_t* eoe,
+                    int32_t* in_tree, int64_t E, int64_t* n_tree, Arena& ws, hipStream_t st) {
+    const int64_t n = g->n;
+    const size_t mark = ws.used;
+    int32_t* comp = ws.take<int32_t>(n + 1);
+    int32_t* nxt = ws.take<int32_t>(n + 1);
+    unsigned long long* best = ws.take<unsigned long long>(n + 1);
+    int32_t* flag = ws.take<int32_t>(4);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (spanning forest)");
+    const unsigned nb = blocks_for(n, kS);
+    GR_HIP(hipMemsetAsync(in_tree, 0, sizeof(int32_t) * (E > 0 ? E : 1), st));
+    hipLaunchKernelGGL(k_iota32, dim3(nb), dim3(kS), 0, st, comp, n);
+    GR_LAUNCHED("forest components");
+    for (int round = 0; round < 64; ++round) {
+        GR_HIP(hipMemsetAsync(best, 0, sizeof(unsigned long long) * n, st));
+        GR_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_bv_best, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, g->row_ptr,
+                           g->col, g->w, eoe, (const int32_t*)comp, n, best);
+        GR_LAUNCHED("forest best edges");
+        hipLaunchKernelGGL(k_bv_hook, dim3(nb), dim3(kS), 0, st, (const unsigned long long*)best, eu,
+                           ev, (const int32_t*)comp, n, nxt, in_tree, flag);
+        GR_LAUNCHED("forest hook");
+        int32_t hooked = 0;
+        GR_HIP(hipMemcpyAsync(&hooked, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GR_HIP(hipStreamSynchronize(st));
+        if (!hooked) break;
+        hipLaunchKernelGGL(k_bv_pairs, dim3(nb), dim3(kS), 0, st, nxt, n);
+        GR_LAUNCHED("forest pairs");
+        for (;;) {  // flatten: four jumps per check
+            GR_HIP(hipMemsetAsync(flag + 1, 0, sizeof(int32_t), st));
+            for (int k = 0; k < 4; ++k) {
+                hipLaunchKernelGGL(k_bv_jump, dim3(nb), dim3(kS), 0, st, nxt, n, flag + 1);
+                GR_LAUNCHED("forest jump");
+            }
+            int32_t moved = 0;
+            GR_HIP(hipMemcpyAsync(&moved, flag + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            GR_HIP(hipStreamSynchronize(st));
+            if (!moved) break;
+        }
+        hipLaunchKernelGGL(k_bv_relabel, dim3(nb), dim3(kS), 0, st, comp, (const int32_t*)nxt, n);
+        GR_LAUNCHED("forest relabel");
+    }
+    GR_TRY(count_flags(in_tree, E, n_tree, ws, st));
+    ws.used = mark;
+    return GR_OK;
+}
+
+// ------------------------------------------------- subgraph from edge flags
+// rows of P: the entries of G whose edge is kept, in G's order (a wave per
+// row; ballots keep the order)
+__global__ void __launch_bounds__(kS) k_sub_count(const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ eoe,
+                                                  const int32_t* __restrict__ keep, int64_t n,
+                                                  int32_t* __restrict__ cnt) {
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
+    if (v >= n) return;
+    int32_t c = 0;
+    for (int32_t b = rp[v]; b < rp[v + 1]; b += kWave) {
+        const int32_t e = b + l;
+        c += __popcll(__ballot(e < rp[v + 1] && keep[eoe[e]]));
+    }
+    if (l == 0) cnt[v] = c;
+}
+
+__global__ void __launch_bounds__(kS) k_sub_fill(const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col,
+                                                 const float* __restrict__ w,
+                                                 const int32_t* __restrict__ eoe,
+                                                 const int32_t* __restrict__ keep,
+                                                 const int32_t* __restrict__ prp,
+                                                 const int32_t* __restrict__ pid, int64_t n,
+                                                 int32_t* __restrict__ pcol, float* __restrict__ pw,
+                                                 int32_t* __restrict__ peoe) {
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
+    if (v >= n) return;
+    int32_t o = prp[v];
+    for (int32_t b = rp[v]; b < rp[v + 1]; b += kWave) {
+        const int32_t e = b + l;
+        const bool k = e < rp[v + 1] && keep[eoe[e]];
+        const uint64_t m = __ballot(k);
+        if (k) {
+            const int32_t at = o + (int32_t)__popcll(m & ((1ull << l) - 1ull));
+            pcol[at] = col[e];
+            pw[at] = w[e];
+            if (peoe) peoe[at] = pid[eoe[e]];
+        }
+        o += (int32_t)__popcll(m);
+    }
+}
+
+// P's own edge list: the kept edges of G in G's edge order
+__global__ void k_sub_edges(const int32_t* __restrict__ keep, const int32_t* __restrict__ pid,
+                            const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            int64_t E, int32_t* __restrict__ peu, int32_t* __restrict__ pev) {
+    const int64_t e = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (e >= E || !keep[e]) return;
+    peu[pid[e]] = eu[e];
+    pev[pid[e]] = ev[e];
+}
+
+int subgraph(const gr_graph* g, const int32_t* eoe, const int32_t* keep, int64_t E,
+             const int32_t* eu, const int32_t* ev, int32_t* prp, int32_t* pcol, float* pw,
+             int32_t* peoe, int32_t* peu, int32_t* pev, int64_t* p_nnz, int64_t* p_edges,
+             Arena& ws, hipStream_t st) {
+    const int64_t n = g->n;
+    const size_t mark = ws.used;
+    int32_t* cnt = ws.take<int32_t>(n + 1);
+    int32_t* pid = ws.take<int32_t>(E + 1);
+    int32_t* tot = ws.take<int32_t>(4);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (subgraph)");
+    hipLaunchKernelGGL(k_sub_count, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, g->row_ptr,
+                       eoe, keep, n, cnt);
+    GR_LAUNCHED("subgraph counts");
+    GR_TRY(scan_exclusive_i32(cnt, prp, n, prp + n, ws, st));
+    GR_TRY(scan_exclusive_i32(keep, pid, E, tot, ws, st));
+    hipLaunchKernelGGL(k_sub_fill, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, g->row_ptr,
+                       g->col, g->w, eoe, keep, (const int32_t*)prp, (const int32_t*)pid, n, pcol,
+                       pw, peoe);
+    GR_LAUNCHED("subgraph fill");
+    if (peu && pev && E > 0) {
+        hipLaunchKernelGGL(k_sub_edges, dim3(blocks_for(E, kS)), dim3(kS), 0, st, keep,
+                           (const int32_t*)pid, eu, ev, E, peu, pev);
+        GR_LAUNCHED("subgraph edges");
+    }
+    int32_t h[2] = {0, 0};
+    GR_HIP(hipMemcpyAsync(&h[0], prp + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipMemcpyAsync(&h[1], tot, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    *p_nnz = h[0];
+    *p_edges = h[1];
+    ws.used = mark;
+    return GR_OK;
+}
+
+// --------------------------------------------------- criticality and rounds
+// weight of every undirected edge from its upper entry
+__global__ void __launch_bounds__(kS) k_edge_w(const int32_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col,
+                                               const float* __restrict__ w,
+                                               const int32_t* __restrict__ eoe, int64_t n,
+                                               float* __restrict__ wE) {
+    const int64_t v = ((int64_t)blockIdx.x * kS + threadIdx.x) / kWave;
+    const int l = threadIdx.x & (kWave - 1);
+    if (v >= n) return;
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += kWave)
+        if (col[e] > v) wE[eoe[e]] = w[e];
+}
+
+int edge_weights(const gr_graph* g, const int32_t* eoe, float* wE, hipStream_t st) {
+    if (g->n == 0) return GR_OK;
+    hipLaunchKernelGGL(k_edge_w, dim3(blocks_for(g->n * kWave, kS)), dim3(kS), 0, st, g->row_ptr,
+                       g->col, g->w, eoe, g->n, wE);
+    GR_LAUNCHED("edge weights");
+    return GR_OK;
+}
+
+// c_e = w_e (h_p - h_q)^2 outside P; sort keys ascending = c descending
+// (edges of P last)
+__global__ void k_crit_keys(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                            const float* __restrict__ wE, const int32_t* __restrict__ keep,
+                            const double* __restrict__ h, int64_t E, double* __restrict__ crit,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t e = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (e >= E) return;
+    double c = 0.0;
+    if (!keep[e]) {
+        const double d = h[eu[e]] - h[ev[e]];
+        c = (double)wE[e] * (d * d);
+    }
+    if (crit) crit[e] = c;
+    keys[e] = keep[e] ? ~0ull : ~(uint64_t)__double_as_longlong(c);
+    vals[e] = (uint32_t)e;
+}
+
+__global__ void k_mark_top(const uint32_t* __restrict__ vals, int64_t m, int32_t* __restrict__ keep) {
+    const int64_t i = (int64_t)blockIdx.x * kS + threadIdx.x;
+    if (i < m) keep[vals[i]] = 1;
+}
+
+size_t sparsify_workspace(int64_t n, int64_t nnz) {
+    const size_t N = (size_t)n + 1, M = (size_t)nnz + 1, E = M / 2 + 1;
+    size_t b = 12 * E + 4 * M                       // edge list, entry -> edge
+               + 4 * N + 8 * M                      // P's CSR
+               + 4 * E                              // edge weights
+               + 16 * M + 80 * N                    // Alg. 1 machinery (G, P, vectors)
+               + 16 * N + 8 * E                     // forest state, counts
+               + 8 * E + 2 * 12 * E                 // criticality, sort keys and values
+               + 4 * N + 4 * E                      // subgraph counts and edge ranks
+               + 2 * 256 * 4 * (M / 2048 + 1) + M / 32 + 512 * 1024 + 8 * 4096;
+    return b + b / 8 + (2u << 20);
+}
+
+int sparsify(const gr_graph* g, const gr_sparsify_params* prm, int32_t* keep, double* crit_out,
+             gr_sparsify_report* rep, Arena& ws, hipStream_t st) {
+    const int64_t n = g->n, nnz = g->nnz;
+    const int64_t E0 = nnz / 2;
+    const size_t mark = ws.used;
+    int32_t* eu = ws.take<int32_t>(E0 + 1);
+    int32_t* ev = ws.take<int32_t>(E0 + 1);
+    int32_t* eoe = ws.take<int32_t>(nnz + 1);
+    int32_t* prp = ws.take<int32_t>(n + 1);
+    int32_t* pcol = ws.take<int32_t>(nnz + 1);
+    float* pw = ws.take<float>(nnz + 1);
+    float* wE = ws.take<float>(E0 + 1);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (sparsify)");
+    int64_t E = 0;
+    GR_TRY(edge_list(g, eu, ev, eoe, &E, ws, st));
+    hipLaunchKernelGGL(k_edge_w, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, g->row_ptr,
+                       g->col, g->w, (const int32_t*)eoe, n, wE);
+    GR_LAUNCHED("edge weights");
+    int64_t ntree = 0;
+    GR_TRY(spanning_forest(g, eu, ev, eoe, keep, E, &ntree, ws, st));
+    rep->tree_edges = ntree;
+    rep->edges = ntree;
+    rep->rounds = 0;
+    rep->n_lambda = 0;
+    // the power-vector machinery of Alg. 1 on G and the current P
+    Sgd s{};
+    s.n = n;
+    s.nnzG = nnz;
+    s.rpG = g->row_ptr;
+    s.colG = g->col;
+    s.rpP = prp;
+    s.colP = pcol;
+    s.st = st;
+    s.cg_max = prm->cg_max_iter > 0 ? prm->cg_max_iter : 20000;
+    s.cg_tol = prm->cg_tol > 0.0 ? prm->cg_tol : 1e-12;
+    s.wG = ws.take<double>(nnz + 1);
+    s.dG = ws.take<double>(n + 1);
+    s.wPent = ws.take<double>(nnz + 1);
+    s.dP = ws.take<double>(n + 1);
+    s.h = ws.take<double>(n + 1);
+    s.t1 = ws.take<double>(n + 1);
+    s.y = ws.take<double>(n + 1);
+    s.r = ws.take<double>(n + 1);
+    s.z = ws.take<double>(n + 1);
+    s.p = ws.take<double>(n + 1);
+    s.q = ws.take<double>(n + 1);
+    s.part = ws.take<double>(kRedBlocks + 1);
+    s.sc = ws.take<double>(32);
+    double* crit = ws.take<double>(E + 1);
+    uint64_t* k0 = ws.take<uint64_t>(E + 1);
+    uint32_t* v0 = ws.take<uint32_t>(E + 1);
+    uint64_t* k1 = ws.take<uint64_t>(E + 1);
+    uint32_t* v1 = ws.take<uint32_t>(E + 1);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (sparsify rounds)");
+    GR_HIP(hipMemsetAsync(s.sc, 0, sizeof(double) * 32, st));
+    hipLaunchKernelGGL(k_promote, dim3(blocks_for(nnz, kS)), dim3(kS), 0, st, g->w, nnz, s.wG);
+    GR_LAUNCHED("promote");
+    hipLaunchKernelGGL(k_row_sums, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, g->row_ptr,
+                       (const double*)s.wG, n, s.dG);
+    GR_LAUNCHED("d_G");
+    const int64_t per = (int64_t)ceil(prm->add_frac * (double)n);
+    for (int round = 0;; ++round) {
+        int64_t pnnz = 0, pedges = 0;
+        GR_TRY(subgraph(g, eoe, keep, E, nullptr, nullptr, prp, pcol, pw, nullptr, nullptr,
+                        nullptr, &pnnz, &pedges, ws, st));
+        s.nnzP = pnnz;
+        hipLaunchKernelGGL(k_promote, dim3(blocks_for(pnnz, kS)), dim3(kS), 0, st, (const float*)pw,
+                           pnnz, s.wPent);
+        GR_LAUNCHED("promote P");
+        hipLaunchKernelGGL(k_row_sums, dim3(blocks_for(n * kWave, kS)), dim3(kS), 0, st, prp,
+                           (const double*)s.wPent, n, s.dP);
+        GR_LAUNCHED("d_P");
+        double lam = 0.0;
+        GR_TRY(s.power_vector(prm->seed, prm->t, &lam));
+        if (rep->n_lambda < GR_SPARSIFY_MAX_ROUNDS + 1) rep->lambda_n[rep->n_lambda++] = lam;
+        rep->edges = pedges;
+        const bool last = round >= prm->rounds || lam <= prm->lambda_target || pedges >= E;
+        if (last && !crit_out) break;
+        hipLaunchKernelGGL(k_crit_keys, dim3(blocks_for(E, kS)), dim3(kS), 0, st, (const int32_t*)eu,
+                           (const int32_t*)ev, (const float*)wE, (const int32_t*)keep,
+                           (const double*)s.h, E, crit, k0, v0);
+        GR_LAUNCHED("criticality");
+        if (last) {  // the criticality of the final P's outside edges
+            GR_HIP(hipMemcpyAsync(crit_out, crit, sizeof(double) * E, hipMemcpyDeviceToDevice, st));
+            break;
+        }
+        GR_TRY(radix_sort_pairs(k0, v0, k1, v1, E, 64, ws, st));
+        const int64_t m = std::min<int64_t>(per, E - pedges);
+        hipLaunchKernelGGL(k_mark_top, dim3(blocks_for(m, kS)), dim3(kS), 0, st, (const uint32_t*)v1,
+                           m, keep);
+        GR_LAUNCHED("densify");
+        rep->rounds = round + 1;
+    }
+    rep->cg_iterations_max = (int32_t)s.cg_iters_max;
+    GR_HIP(hipStreamSynchronize(st));
+    ws.used = mark;
     return GR_OK;
 }
 

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgraphreduce.so")
 
 GR_OK = 0
+GR_ENOMEM = -4
 GR_F32 = 0
 GR_BF16 = 1
 GR_VALIDATE = 1
@@ -79,11 +80,57 @@ class gr_eig_report(ctypes.Structure):
                 ("method", ctypes.c_int32), ("restarts", ctypes.c_int32)]
 
 
+GR_MAX_LEVELS = 32
+
+
+class gr_hierarchy(ctypes.Structure):
+    _fields_ = [("maps", ctypes.c_void_p), ("maps_cap", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("rp_cap", ctypes.c_int64),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("ent_cap", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("n", ctypes.c_int64 * (GR_MAX_LEVELS + 1)),
+                ("nnz", ctypes.c_int64 * (GR_MAX_LEVELS + 1)),
+                ("maps_off", ctypes.c_int64 * GR_MAX_LEVELS),
+                ("rp_off", ctypes.c_int64 * GR_MAX_LEVELS),
+                ("ent_off", ctypes.c_int64 * GR_MAX_LEVELS)]
+
+
 class gr_sgd_report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("n_lambda", ctypes.c_int32),
                 ("cg_iterations_max", ctypes.c_int32),
                 ("lambda_n", ctypes.c_double * GR_SGD_MAX_ITER),
                 ("lambda_1", ctypes.c_double * (GR_SGD_MAX_ITER + 1))]
+
+
+GR_SPARSIFY_MAX_ROUNDS = 64
+
+
+class gr_sparsify_params(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("add_frac", ctypes.c_double), ("lambda_target", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("cg_max_iter", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double)]
+
+
+class gr_sparsify_report(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("n_lambda", ctypes.c_int32),
+                ("tree_edges", ctypes.c_int64), ("edges", ctypes.c_int64),
+                ("cg_iterations_max", ctypes.c_int32),
+                ("lambda_n", ctypes.c_double * (GR_SPARSIFY_MAX_ROUNDS + 1))]
+
+
+class gr_flow_params(ctypes.Structure):
+    _fields_ = [("phase_a", gr_params), ("phase_b", gr_sparsify_params),
+                ("scaling", gr_sgd_params), ("gamma_max", ctypes.c_double)]
+
+
+class gr_flow_result(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_void_p), ("s_row_ptr", ctypes.c_void_p),
+                ("s_col", ctypes.c_void_p), ("s_w", ctypes.c_void_p),
+                ("n_s", ctypes.c_int64), ("nnz_s", ctypes.c_int64),
+                ("dense", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("levels", ctypes.c_int32), ("warnings", ctypes.c_uint32),
+                ("sparsify", gr_sparsify_report), ("scaling", gr_sgd_report)]
 
 
 PHASES = ("colour", "relabel", "init", "smooth", "affinity", "aggregate",
@@ -132,6 +179,21 @@ _SIGNATURES = {
                                _P], ctypes.c_int),
     "gr_rq_forward_noalloc_scratch_bytes": ([], _SZ),
     "gr_eig_workspace": ([_I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_reduce_hierarchy": ([_G, ctypes.POINTER(gr_params), ctypes.POINTER(gr_result),
+                             ctypes.POINTER(gr_hierarchy), _P, _SZ, _P], ctypes.c_int),
+    "gr_laplacian_geigpairs": ([_G, _P, _I32, _I32, ctypes.c_double, _I32, _I32, _U64,
+                                ctypes.POINTER(ctypes.c_double), _P,
+                                ctypes.POINTER(gr_eig_report), _P, _SZ, _P], ctypes.c_int),
+    "gr_jacobi_workspace": ([_I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_jacobi_filter": ([_G, _I32, _P, ctypes.POINTER(ctypes.c_double), _P,
+                          ctypes.c_double, _I32, _P, _SZ, _P], ctypes.c_int),
+    "gr_orthonormalize_workspace": ([_I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_orthonormalize": ([_I64, _I32, _P, _P, _P, _SZ, _P], ctypes.c_int),
+    "gr_multilevel_workspace": ([_I64, _I64, _I32, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_multilevel_eigs": ([_G, ctypes.POINTER(gr_hierarchy), _I32, _I32, ctypes.c_double,
+                            _I32, ctypes.c_double, _I32, _U64,
+                            ctypes.POINTER(ctypes.c_double), _P,
+                            ctypes.POINTER(gr_eig_report), _P, _SZ, _P], ctypes.c_int),
     "gr_laplacian_eigs": ([_G, _I32, _I32, ctypes.c_double, _I32, _I32, _U64,
                            ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(gr_eig_report), _P, _SZ, _P],
@@ -146,6 +208,16 @@ _SIGNATURES = {
                       ctypes.POINTER(gr_sgd_params),
                       ctypes.POINTER(gr_sgd_report), _P, _SZ, _P], ctypes.c_int),
     "gr_expand_edge_weights": ([_P, _I64, _I64, _P, _P, _P], ctypes.c_int),
+    "gr_sparsify_workspace": ([_I64, _I64, ctypes.POINTER(_SZ)], ctypes.c_int),
+    "gr_spanning_forest": ([_G, _P, ctypes.POINTER(_I64), _P, _SZ, _P], ctypes.c_int),
+    "gr_sparsify": ([_G, ctypes.POINTER(gr_sparsify_params), _P, _P,
+                     ctypes.POINTER(gr_sparsify_report), _P, _SZ, _P], ctypes.c_int),
+    "gr_subgraph": ([_G, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_I64),
+                     ctypes.POINTER(_I64), _P, _SZ, _P], ctypes.c_int),
+    "gr_spectral_reduce_workspace": ([_I64, _I64, _I32, _I32, ctypes.POINTER(_SZ)],
+                                     ctypes.c_int),
+    "gr_spectral_reduce": ([_G, ctypes.POINTER(gr_flow_params), ctypes.POINTER(gr_flow_result),
+                            _P, _SZ, _P], ctypes.c_int),
     "gr_smooth_vjp_workspace": ([_I64, _I64, _I32, _I32, _I32, _I32,
                                  ctypes.POINTER(_SZ)], ctypes.c_int),
     "gr_smooth_vjp": ([_G, _P, _I64, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
@@ -422,13 +494,77 @@ class ReduceOut:
     level_n: list
     level_nnz: list
     level_colours: list
+    hierarchy: "Hierarchy | None" = None
+
+
+class Hierarchy:
+    """The levels Alg. 5 walks: device buffers plus the gr_hierarchy
+    struct that describes them (filled by gr_reduce_hierarchy, or built
+    from host arrays with from_numpy)."""
+
+    def __init__(self, maps, row_ptr, col, w):
+        self.maps, self.row_ptr, self.col, self.w = maps, row_ptr, col, w
+        self.h = gr_hierarchy(maps.data_ptr(), maps.numel(), row_ptr.data_ptr(),
+                              row_ptr.numel(), col.data_ptr(), w.data_ptr(), col.numel(), 0)
+
+    @classmethod
+    def empty(cls, n, maps_cap, rp_cap, ent_cap, device):
+        return cls(torch.empty(maps_cap, dtype=torch.int32, device=device),
+                   torch.empty(rp_cap, dtype=torch.int32, device=device),
+                   torch.empty(ent_cap, dtype=torch.int32, device=device),
+                   torch.empty(ent_cap, dtype=torch.float32, device=device))
+
+    @classmethod
+    def from_numpy(cls, n0, maps, graphs, device):
+        """maps[l] (level l -> l+1) and graphs[l] = (row_ptr, col, w) of
+        level l+1, as host arrays."""
+        import numpy as np
+
+        cat = lambda xs, dt: torch.from_numpy(  # noqa: E731
+            np.concatenate([np.asarray(x, dt) for x in xs]) if xs else np.zeros(1, dt)).to(device)
+        h = cls(cat(maps, np.int32), cat([gr[0] for gr in graphs], np.int32),
+                cat([gr[1] for gr in graphs], np.int32), cat([gr[2] for gr in graphs], np.float32))
+        h.h.levels = len(maps)
+        h.h.n[0] = n0
+        om = orp = oe = 0
+        for l, (m, gr) in enumerate(zip(maps, graphs)):
+            h.h.maps_off[l], h.h.rp_off[l], h.h.ent_off[l] = om, orp, oe
+            h.h.n[l + 1] = len(gr[0]) - 1
+            h.h.nnz[l + 1] = len(gr[1])
+            om += len(m)
+            orp += len(gr[0])
+            oe += len(gr[1])
+        return h
+
+    @property
+    def levels(self) -> int:
+        return int(self.h.levels)
+
+    @property
+    def n(self) -> list:
+        return [int(x) for x in self.h.n[:self.levels + 1]]
+
+    def level(self, l):
+        """(map of level l, (row_ptr, col, w) of level l + 1) as device views."""
+        h = self.h
+        n0, n1, m1 = int(h.n[l]), int(h.n[l + 1]), int(h.nnz[l + 1])
+        mo, ro, eo = int(h.maps_off[l]), int(h.rp_off[l]), int(h.ent_off[l])
+        return (self.maps[mo:mo + n0],
+                (self.row_ptr[ro:ro + n1 + 1], self.col[eo:eo + m1], self.w[eo:eo + m1]))
+
+    def graph(self, l) -> "DeviceGraph":
+        """Level l >= 1 as a DeviceGraph."""
+        _, (rp, col, w) = self.level(l - 1)
+        return DeviceGraph(rp, col, w)
 
 
 def gr_reduce(g: DeviceGraph, K, sweeps, ratio, vec_seed, colour_seed,
               dtype=GR_F32, colours=None, n_colours=0, max_levels=0,
               validate=False, largest_degree_first=False, ws=None,
-              out=None) -> ReduceOut:
-    """graph_reduce(csr, K, sweeps, ratio) -> aggregate ids + coarse CSR."""
+              out=None, keep_hierarchy=False) -> ReduceOut:
+    """graph_reduce(csr, K, sweeps, ratio) -> aggregate ids + coarse CSR;
+    with keep_hierarchy, gr_reduce_hierarchy also keeps every level's map
+    and graph (ReduceOut.hierarchy)."""
     code = vec_dtype_code(dtype)
     ws = ws if ws is not None else workspace(g.n, g.nnz, K, code)
     dev = g.row_ptr.device
@@ -447,14 +583,28 @@ def gr_reduce(g: DeviceGraph, K, sweeps, ratio, vec_seed, colour_seed,
     r = gr_result(agg.data_ptr(), c_rp.data_ptr(), c_col.data_ptr(),
                   c_w.data_ptr())
     cg = g.c()
-    _check(load().gr_reduce(ctypes.byref(cg), ctypes.byref(p), ctypes.byref(r),
-                            _ptr(ws), ws.numel(), _stream()))
+    hier = None
+    if keep_hierarchy:
+        caps = (2 * g.n + 64, 2 * g.n + 128, g.nnz + 1024)
+        while True:
+            hier = Hierarchy.empty(g.n, *caps, device=dev)
+            rc = load().gr_reduce_hierarchy(ctypes.byref(cg), ctypes.byref(p), ctypes.byref(r),
+                                            ctypes.byref(hier.h), _ptr(ws), ws.numel(),
+                                            _stream())
+            if rc != GR_ENOMEM or caps[0] > 64 * (g.n + 64):
+                _check(rc)
+                break
+            caps = tuple(2 * c for c in caps)
+        hier.h.n[0] = g.n
+    else:
+        _check(load().gr_reduce(ctypes.byref(cg), ctypes.byref(p), ctypes.byref(r),
+                                _ptr(ws), ws.numel(), _stream()))
     nc, m = int(r.n_coarse), int(r.nnz_coarse)
     L = int(r.levels)
     return ReduceOut(agg[:g.n], DeviceGraph(c_rp[:nc + 1], c_col[:m], c_w[:m]),
                      L, int(r.warnings), list(r.level_n[:min(L, 32)]),
                      list(r.level_nnz[:min(L, 32)]),
-                     list(r.level_colours[:min(L, 32)]))
+                     list(r.level_colours[:min(L, 32)]), hier)
 
 
 # ------------------------------------------------------- edge derivatives
@@ -609,6 +759,129 @@ def gr_sgd_scale(G_graph: DeviceGraph, P_graph: DeviceGraph, p_edges: EdgeList,
             "cg_iterations_max": int(rep.cg_iterations_max)}
 
 
+# ------------------------------------------------------------ Phase B
+
+def gr_sparsify_workspace(n, nnz) -> int:
+    out = _SZ(0)
+    _check(load().gr_sparsify_workspace(n, nnz, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gr_spanning_forest(g: DeviceGraph):
+    """(in_tree int32 [E] device, number of forest edges)."""
+    dev = g.row_ptr.device
+    nb = gr_sparsify_workspace(g.n, g.nnz)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    flags = torch.empty(max(g.nnz // 2, 1), dtype=torch.int32, device=dev)
+    nt = _I64(0)
+    cg = g.c()
+    _check(load().gr_spanning_forest(ctypes.byref(cg), _ptr(flags), ctypes.byref(nt), _ptr(ws),
+                                     nb, _stream()))
+    return flags[:g.nnz // 2], int(nt.value)
+
+
+def _sparsify_params(t=2, rounds=5, add_frac=0.02, lambda_target=0.0, seed=1,
+                     cg_max_iter=0, cg_tol=0.0):
+    return gr_sparsify_params(int(t), int(rounds), float(add_frac), float(lambda_target),
+                              seed & (2**64 - 1), int(cg_max_iter), float(cg_tol))
+
+
+def _sparsify_report(r):
+    return {"rounds": int(r.rounds), "tree_edges": int(r.tree_edges), "edges": int(r.edges),
+            "lambda_n": list(r.lambda_n[:r.n_lambda]),
+            "cg_iterations_max": int(r.cg_iterations_max)}
+
+
+def gr_sparsify(g: DeviceGraph, want_criticality=False, **kw):
+    """Phase B's sparsifier: (in_P int32 [E], criticality float64 [E] or
+    None, report dict)."""
+    dev = g.row_ptr.device
+    nb = gr_sparsify_workspace(g.n, g.nnz)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    E = g.nnz // 2
+    flags = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+    crit = torch.empty(max(E, 1), dtype=torch.float64, device=dev) if want_criticality else None
+    prm = _sparsify_params(**kw)
+    rep = gr_sparsify_report()
+    cg = g.c()
+    _check(load().gr_sparsify(ctypes.byref(cg), ctypes.byref(prm), _ptr(flags), _ptr(crit),
+                              ctypes.byref(rep), _ptr(ws), nb, _stream()))
+    return flags[:E], (crit[:E] if crit is not None else None), _sparsify_report(rep)
+
+
+def gr_subgraph(g: DeviceGraph, keep):
+    """(P as a DeviceGraph, P's EdgeList) for the edge flags keep."""
+    dev = g.row_ptr.device
+    nb = gr_sparsify_workspace(g.n, g.nnz)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    rp = torch.empty(g.n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    w = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev)
+    eoe = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    eu = torch.empty(max(g.nnz // 2, 1), dtype=torch.int32, device=dev)
+    ev = torch.empty(max(g.nnz // 2, 1), dtype=torch.int32, device=dev)
+    m, E = _I64(0), _I64(0)
+    cg = g.c()
+    _check(load().gr_subgraph(ctypes.byref(cg), _ptr(keep), _ptr(rp), _ptr(col), _ptr(w),
+                              _ptr(eoe), _ptr(eu), _ptr(ev), ctypes.byref(m), ctypes.byref(E),
+                              _ptr(ws), nb, _stream()))
+    m, E = int(m.value), int(E.value)
+    return DeviceGraph(rp, col[:m], w[:m]), EdgeList(eu[:E], ev[:E], eoe[:m], g.n)
+
+
+def gr_spectral_reduce_workspace(n, nnz, K, dtype=GR_F32) -> int:
+    nb = _SZ(0)
+    _check(load().gr_spectral_reduce_workspace(n, nnz, K, vec_dtype_code(dtype), ctypes.byref(nb)))
+    return int(nb.value)
+
+
+@dataclasses.dataclass
+class FlowOut:
+    agg: torch.Tensor
+    S: DeviceGraph
+    dense: bool
+    gamma: float
+    levels: int
+    warnings: int
+    sparsify: dict
+    scaling: dict
+
+
+def gr_spectral_reduce(g: DeviceGraph, K, sweeps, ratio, vec_seed, colour_seed, dtype=GR_F32,
+                       colours=None, n_colours=0, largest_degree_first=False, gamma_max=40.0,
+                       sparsify=None, scaling=None) -> FlowOut:
+    """Alg. 2 (Phase A and Phase B in the order the density selects);
+    sparsify/scaling: keyword dicts of gr_sparsify and gr_sgd_scale."""
+    code = vec_dtype_code(dtype)
+    dev = g.row_ptr.device
+    nb = _SZ(gr_spectral_reduce_workspace(g.n, g.nnz, K, code))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    pa = gr_params(K, sweeps, float(ratio), vec_seed & (2**64 - 1), colour_seed & (2**64 - 1),
+                   code, colours.data_ptr() if colours is not None else None, int(n_colours), 0,
+                   GR_COLOUR_LDF if largest_degree_first else 0)
+    sk = dict(alpha=0.9, eta_scale=0.1, eps=1e-3, delta_bar=0.5, k_max=20, t=2, seed=1,
+              cg_max_iter=0, cg_tol=0.0)
+    sk.update(scaling or {})
+    ps = gr_sgd_params(sk["alpha"], sk["eta_scale"], sk["eps"], sk["delta_bar"], sk["k_max"],
+                       sk["t"], sk["seed"] & (2**64 - 1), sk["cg_max_iter"], sk["cg_tol"])
+    prm = gr_flow_params(pa, _sparsify_params(**(sparsify or {})), ps, float(gamma_max))
+    agg = torch.empty(max(g.n, 1), dtype=torch.int32, device=dev)
+    srp = torch.empty(g.n + 1, dtype=torch.int32, device=dev)
+    scol = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    sw = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev)
+    res = gr_flow_result(agg.data_ptr(), srp.data_ptr(), scol.data_ptr(), sw.data_ptr())
+    cg = g.c()
+    _check(load().gr_spectral_reduce(ctypes.byref(cg), ctypes.byref(prm), ctypes.byref(res),
+                                     _ptr(ws), nb.value, _stream()))
+    ns, ms = int(res.n_s), int(res.nnz_s)
+    sc = res.scaling
+    return FlowOut(agg[:g.n], DeviceGraph(srp[:ns + 1], scol[:ms], sw[:ms]), bool(res.dense),
+                   float(res.gamma), int(res.levels), int(res.warnings),
+                   _sparsify_report(res.sparsify),
+                   {"iterations": int(sc.iterations), "lambda_n": list(sc.lambda_n[:sc.n_lambda]),
+                    "lambda_1": list(sc.lambda_1[:sc.iterations + 1])})
+
+
 def gr_eig_workspace(n, n_eig) -> int:
     out = _SZ(0)
     _check(load().gr_eig_workspace(n, n_eig, ctypes.byref(out)))
@@ -646,6 +919,102 @@ def gr_laplacian_eigpairs(g: DeviceGraph, n_eig=10, method="auto", tol=1e-12,
                                         float(tol), int(max_iter), int(degree),
                                         seed & (2**64 - 1), out, _ptr(U), ctypes.byref(rep),
                                         _ptr(ws), nbytes, _stream()))
+    return np.array(out[:], dtype=np.float64), U[:g.n], _eig_report(rep)
+
+
+def gr_laplacian_geigpairs(g: DeviceGraph, bdiag, n_eig=10, method="auto", tol=1e-12,
+                           max_iter=1000, degree=80, seed=1):
+    """Eigenpairs of L u = lambda B u, B = diag(bdiag) (float64 device
+    tensor, or None for B = I): (numpy eigenvalues, U [n][n_eig], report)."""
+    import numpy as np
+
+    if bdiag is not None:
+        _f64c(bdiag)
+    nbytes = gr_eig_workspace(g.n, n_eig)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=g.row_ptr.device)
+    U = torch.empty((max(g.n, 1), n_eig), dtype=torch.float64, device=g.row_ptr.device)
+    out = (ctypes.c_double * n_eig)()
+    rep = gr_eig_report()
+    cg = g.c()
+    _check(load().gr_laplacian_geigpairs(ctypes.byref(cg), _ptr(bdiag), n_eig,
+                                         EIG_METHODS[method], float(tol), int(max_iter),
+                                         int(degree), seed & (2**64 - 1), out, _ptr(U),
+                                         ctypes.byref(rep), _ptr(ws), nbytes, _stream()))
+    return np.array(out[:], dtype=np.float64), U[:g.n], _eig_report(rep)
+
+
+def gr_jacobi_workspace(n, k) -> int:
+    nb = _SZ(0)
+    _check(load().gr_jacobi_workspace(n, k, ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def gr_orthonormalize_workspace(n, k) -> int:
+    nb = _SZ(0)
+    _check(load().gr_orthonormalize_workspace(n, k, ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def gr_multilevel_workspace(n, nnz, k) -> int:
+    nb = _SZ(0)
+    _check(load().gr_multilevel_workspace(n, nnz, k, ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def gr_reduce_hierarchy(g: DeviceGraph, K, sweeps, ratio, vec_seed, colour_seed, **kw):
+    """gr_reduce with the hierarchy kept (ReduceOut.hierarchy)."""
+    return gr_reduce(g, K, sweeps, ratio, vec_seed, colour_seed, keep_hierarchy=True, **kw)
+
+
+def gr_jacobi_filter(g: DeviceGraph, Y, lam=None, bdiag=None, theta=2.0 / 3.0, iters=4):
+    """Weighted-Jacobi steps on the columns of Y (float64 [n, k], in place):
+    Alg. 3 when lam is None, the shifted filter of Alg. 5 otherwise."""
+    _f64c(Y)
+    if bdiag is not None:
+        _f64c(bdiag)
+    n, k = Y.shape
+    nb = _SZ(0)
+    _check(load().gr_jacobi_workspace(n, k, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=Y.device)
+    lam_c = (ctypes.c_double * k)(*[float(x) for x in lam]) if lam is not None else None
+    cg = g.c()
+    _check(load().gr_jacobi_filter(ctypes.byref(cg), k, _ptr(Y), lam_c, _ptr(bdiag),
+                                   float(theta), int(iters), _ptr(ws), nb.value, _stream()))
+    return Y
+
+
+def gr_orthonormalize(U, bdiag=None):
+    """Gram-Schmidt of [1, U] in the B inner product (U float64 [n, k], in
+    place); returns U."""
+    _f64c(U)
+    if bdiag is not None:
+        _f64c(bdiag)
+    n, k = U.shape
+    nb = _SZ(0)
+    _check(load().gr_orthonormalize_workspace(n, k, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=U.device)
+    _check(load().gr_orthonormalize(n, k, _ptr(U), _ptr(bdiag), _ptr(ws), nb.value, _stream()))
+    return U
+
+
+def gr_multilevel_eigs(g: DeviceGraph, hier: "Hierarchy", k=10, cut=GR_RQ_IDENTITY,
+                       theta=2.0 / 3.0, iters=4, tol=1e-10, max_iter=2000, seed=1):
+    """Alg. 5 on a kept hierarchy: (numpy coarsest eigenvalues, U float64
+    [n, k] on the device, report dict)."""
+    import numpy as np
+
+    nb = _SZ(0)
+    _check(load().gr_multilevel_workspace(g.n, g.nnz, k, ctypes.byref(nb)))
+    dev = g.row_ptr.device
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    U = torch.empty((max(g.n, 1), k), dtype=torch.float64, device=dev)
+    out = (ctypes.c_double * k)()
+    rep = gr_eig_report()
+    cg = g.c()
+    _check(load().gr_multilevel_eigs(ctypes.byref(cg), ctypes.byref(hier.h), k, int(cut),
+                                     float(theta), int(iters), float(tol), int(max_iter),
+                                     seed & (2**64 - 1), out, _ptr(U), ctypes.byref(rep),
+                                     _ptr(ws), nb.value, _stream()))
     return np.array(out[:], dtype=np.float64), U[:g.n], _eig_report(rep)
 
 

@@ -1,0 +1,166 @@
+"""GPU parity of Phase B (Sec. 3.3.2-3.3.3) and the flow of Alg. 2 against
+the oracle: the maximum-weight spanning forest bit for bit (ties
+included), subgraph extraction, the criticality of the edges outside the
+subgraph, the densification rounds, and both branches of Alg. 2 with the
+edge scaling of Alg. 1."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import sgd as SG
+from oracle import sparsify as PB
+from workloads import graphs as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return "cuda:0"
+
+
+def _G():
+    from paper_1812_08942_amd import graphreduce as G
+    return G
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _edges(g):
+    eoe, eu, ev = O.edge_index(g.n, g.row_ptr, g.col)
+    w = np.zeros(eu.size)
+    w[eoe] = g.w
+    return eu, ev, w
+
+
+def _graphs():
+    rng = np.random.default_rng(5)
+    star = W.csr_from_edges(3000, np.zeros(2999, np.int64), np.arange(1, 3000),
+                            rng.uniform(0.5, 2.0, 2999))
+    return [W.random_weighted(300, 0.05, seed=3), W.knn2d(3000, 10, seed=4),
+            W.chung_lu(5000, mean_deg=30.0, seed=6), W.grid2d(40, 30),
+            W.disjoint_union(W.random_weighted(200, 0.05, seed=7), W.grid2d(10, 10)), star,
+            W.with_isolated(W.cycle(50), 3)]
+
+
+def test_spanning_forest_bit_exact():
+    dev, G = _dev(), _G()
+    for g in _graphs():
+        say(f"spanning forest {g.name} n={g.n}")
+        flags, nt = G.gr_spanning_forest(G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev))
+        eu, ev, w = _edges(g)
+        ref = PB.max_spanning_forest(g.n, eu, ev, w)
+        assert nt == ref.sum()
+        assert np.array_equal(flags.cpu().numpy().astype(bool), ref)
+
+
+def test_subgraph_extraction():
+    dev, G = _dev(), _G()
+    g = W.chung_lu(4000, mean_deg=25.0, seed=2)
+    eu, ev, w = _edges(g)
+    keep = np.random.default_rng(1).random(eu.size) < 0.3
+    say("subgraph chung_lu_4000")
+    P, pe = G.gr_subgraph(G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev),
+                          torch.from_numpy(keep.astype(np.int32)).to(dev))
+    rp, cl, ww = PB.csr_of_edges(g.n, eu[keep], ev[keep], w[keep])
+    assert np.array_equal(P.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(P.col.cpu().numpy(), cl)
+    assert np.array_equal(P.w.cpu().numpy().astype(np.float64), ww)
+    assert np.array_equal(pe.eu.cpu().numpy(), eu[keep]) and np.array_equal(pe.ev.cpu().numpy(), ev[keep])
+    eoe, _, _ = O.edge_index(g.n, rp, cl)
+    assert np.array_equal(pe.edge_of_entry.cpu().numpy(), eoe)
+
+
+@pytest.mark.parametrize("case", ["er", "knn"])
+def test_criticality_and_rounds_match_oracle(case):
+    dev, G = _dev(), _G()
+    g = W.random_weighted(400, 0.04, seed=11) if case == "er" else W.knn2d(2000, 8, seed=12)
+    eu, ev, w = _edges(g)
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    say(f"criticality on the tree {g.name}")
+    flags, crit, rep = G.gr_sparsify(dg, want_criticality=True, rounds=0, seed=7, cg_tol=1e-13)
+    tree = PB.max_spanning_forest(g.n, eu, ev, w)
+    assert np.array_equal(flags.cpu().numpy().astype(bool), tree)
+    h, lam = PB.power_vector(g.n, eu, ev, w, tree, O.init_vectors(g.n, 1, 7)[:, 0], 2)
+    ref = PB.criticality(eu, ev, w, tree, h)
+    c = crit.cpu().numpy()
+    assert np.allclose(c, ref, rtol=1e-7, atol=1e-9 * ref.max()), np.max(np.abs(c - ref))
+    assert abs(rep["lambda_n"][0] - lam) <= 1e-8 * lam
+    say(f"densification rounds {g.name}")
+    prm = PB.SparsifyParams(rounds=3, add_frac=0.05, seed=7)
+    r = PB.sparsify(g.n, eu, ev, w, prm)
+    flags, _, rep = G.gr_sparsify(dg, rounds=3, add_frac=0.05, seed=7, cg_tol=1e-13)
+    assert rep["rounds"] == r.rounds == 3 and rep["tree_edges"] == tree.sum()
+    assert np.array_equal(flags.cpu().numpy().astype(bool), r.in_P)
+    assert np.allclose(rep["lambda_n"], r.lambda_n, rtol=1e-8, atol=0)
+
+
+def test_alg2_sparse_branch_matches_oracle():
+    """grid 32 x 32 (gamma = 1.94 < 40): Phase A on G (parity colouring, bit
+    for bit), then Phase B on R and Alg. 1 (parallel mode) on its
+    sparsifier."""
+    dev, G = _dev(), _G()
+    g = W.grid2d(32, 32, weights="lognormal", seed=4)
+    sp = dict(rounds=2, add_frac=0.05, seed=3, cg_tol=1e-13)
+    sk = dict(k_max=6, eps=1e-4, cg_tol=1e-14)
+    say("Alg. 2 sparse branch grid32")
+    out = G.gr_spectral_reduce(G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev), 8, 5, 8.0,
+                               11, 21, colours=torch.from_numpy(g.colours).to(dev), n_colours=2,
+                               sparsify=sp, scaling=sk)
+    assert not out.dense
+    r = O.reduce(g.n, g.row_ptr, g.col, g.w.astype(np.float64), 8, 5, 8.0, 11, 21,
+                 colours=g.colours, n_colours=2, fp32_coarse=True)
+    assert np.array_equal(out.agg.cpu().numpy(), r.agg)
+    # Phase B and Alg. 1 are checked on the GPU's own R (the same reduction
+    # again: bit-identical), whose float32 Galerkin sums differ from the
+    # oracle's in the last bits; Alg. 1 would carry that difference on
+    R = G.gr_reduce(G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev), 8, 5, 8.0, 11, 21,
+                    colours=torch.from_numpy(g.colours).to(dev), n_colours=2).coarse
+    assert np.array_equal(R.row_ptr.cpu().numpy(), r.row_ptr)
+    assert np.array_equal(R.col.cpu().numpy(), r.col)
+    assert np.allclose(R.w.cpu().numpy(), r.w, rtol=1e-5, atol=0)
+    eo2, ru, rv = O.edge_index(r.n_coarse, r.row_ptr, r.col)
+    rw = np.zeros(ru.size)
+    rw[eo2] = R.w.cpu().numpy().astype(np.float64)
+    spr = PB.sparsify(r.n_coarse, ru, rv, rw, PB.SparsifyParams(rounds=2, add_frac=0.05, seed=3))
+    keep = spr.in_P
+    sg = SG.sgd_scale(r.n_coarse, ru, rv, rw, ru[keep], rv[keep], rw[keep],
+                      SG.SgdParams(k_max=6, eps=1e-4))
+    rp, cl, ww = PB.csr_of_edges(r.n_coarse, ru[keep], rv[keep], sg.w_P)
+    assert out.S.n == r.n_coarse
+    assert np.array_equal(out.S.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(out.S.col.cpu().numpy(), cl)
+    err = np.max(np.abs(out.S.w.cpu().numpy() - ww) / ww)
+    print(f"[gpu-case] Alg. 2 sparse branch: max relative weight difference {err:.2e}")
+    assert err <= 1e-6
+    assert out.scaling["iterations"] == sg.iterations
+
+
+def test_alg2_dense_branch_matches_oracle():
+    """K_100 with random weights (gamma = 49.5 >= 40): Phase B and Alg. 1 on
+    G first, then Phase A on the scaled sparsifier."""
+    dev, G = _dev(), _G()
+    k = W.complete(100)
+    eoe, eu, ev = O.edge_index(k.n, k.row_ptr, k.col)
+    wE = np.random.default_rng(2).uniform(0.5, 2.0, eu.size).astype(np.float32).astype(np.float64)
+    rp, cl, ww = PB.csr_of_edges(k.n, eu, ev, wE)
+    sp = dict(rounds=3, add_frac=0.05, seed=3, cg_tol=1e-13)
+    sk = dict(k_max=5, eps=1e-4, cg_tol=1e-14)
+    say("Alg. 2 dense branch K100")
+    out = G.gr_spectral_reduce(G.DeviceGraph.from_numpy(rp, cl, ww.astype(np.float32), dev), 8, 5,
+                               4.0, 11, 21, sparsify=sp, scaling=sk)
+    assert out.dense and abs(out.gamma - 49.5) < 1e-12
+    ref = PB.spectral_reduce(k.n, rp, cl, ww, 8, 5, 4.0, 11, 21,
+                             sp=PB.SparsifyParams(rounds=3, add_frac=0.05, seed=3),
+                             sgd=SG.SgdParams(k_max=5, eps=1e-4))
+    assert ref.dense
+    assert out.sparsify["edges"] == ref.sparsify.in_P.sum()
+    assert out.S.n == ref.n_S
+    assert np.array_equal(out.agg.cpu().numpy(), ref.agg)
+    assert np.array_equal(out.S.row_ptr.cpu().numpy(), ref.row_ptr)
+    assert np.array_equal(out.S.col.cpu().numpy(), ref.col)
+    assert np.allclose(out.S.w.cpu().numpy(), ref.w, rtol=1e-5, atol=0)
