@@ -8,18 +8,27 @@ test-vector init, Gauss-Seidel sweeps, affinity + strongest neighbour,
 aggregation and the Galerkin collapse, until the target size.  Prints ONE
 JSON line on stdout (progress goes to stderr).
 
+headline = the largest single-GPU configuration: the 256^3 grid (16.8M
+        nodes, 100M entries, K = 32 bfloat16-stored vectors, FP32 arithmetic,
+        parity colouring), reduced 170x.
 value = smoothing work of the step (sum over levels of nnz * K * sweeps)
         divided by the measured step time.
 roofline = the Gauss-Seidel colour-step kernels: compulsory bytes per colour
         step (CSR rows, one read and one write of each updated vector row)
         over their HIP-event durations, against the 8 TB/s HBM peak.
-cpu_baseline = the FP64 reference oracle (one host thread) on level-0
-        smoothing + affinity of the same graph, in the same unit.
-bf16 = the headline workload again with bfloat16 vector storage, with its
-        reduced graph's eigenvalues against the float32 run's.
-secondary = the same measurement on a second workload (default: the 256^3
-        grid with bfloat16 vectors, whose colour steps are large enough to
-        be bandwidth-bound); --secondary '' skips it.
+eig_error_vs_fp64 = the reduced graph's first 10 nontrivial eigenvalues
+        (FP64 on the GPU) against those of the FP64 oracle's reduction of
+        the same graph with the same seeds, stored in tests/golden/ by a
+        script that calls only the oracle; also in units of the gate
+        max(1e-4 lambda, half the oracle's range over 5 vector seeds).
+cpu_baseline = the FP64 reference oracle on one Gauss-Seidel sweep over the
+        full headline graph, on one host thread and on all of them.
+secondary = the same measurement on the other configurations: the power-law
+        graph (float32 and bfloat16 storage), the 200k-point kNN graph and
+        the 70k-point Gaussian-mixture kNN graph.
+extras = pieces outside the timed step: the GS backward, Rayleigh-quotient
+        gradients, Alg. 1, the multilevel eigensolver (Alg. 5), Phase B and
+        the two branches of Alg. 2, the data restriction of Alg. 6.
 """
 from __future__ import annotations
 
@@ -33,12 +42,26 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
 
 HBM_PEAK_GBS = 8000.0
+
+# The paper's only reduction timing at this scale (Table 2, coPapersCiteseer,
+# the scale of the power-law workload): context, not a target.
+PAPER_REFERENCE = {
+    "table": "Table 2", "graph": "coPapersCiteseer", "nodes": 4.3e5, "edges": 1.6e7,
+    "reduced_nodes": 1.3e4, "T_reduction_s": 16.41,
+    "scope": "whole reduction: Phase B (sparsification and edge scaling) then Phase A, "
+             "the dense flow",
+    "hardware": "one core of a 2.67 GHz 12-core CPU, 48 GB DRAM, 64-bit RHEL 6.0",
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+SECONDARY = "chunglu434k,chunglu434k:bf16,knn200k,gmm70k"
 
 
 def main():
@@ -46,22 +69,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chunglu434k")
+    ap.add_argument("--workload", default="grid256")
     ap.add_argument("--dtype", default=None, help="f32 or bf16 vector storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
-    ap.add_argument("--eig-original", action="store_true",
-                    help="also the original graph's eigenvalues (slow)")
-    ap.add_argument("--random-priority", action="store_true",
-                    help="greedy colouring with hashed priorities instead of "
-                         "largest-degree-first")
-    ap.add_argument("--no-bf16-compare", action="store_true",
-                    help="skip the bfloat16-storage run of the headline workload")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the timings of the differentiable pieces (GS "
-                         "backward, Rayleigh-quotient gradients, Alg. 1)")
-    ap.add_argument("--secondary", default="grid256",
-                    help="second workload measured the same way ('' for none)")
+                    help="skip the pieces outside the timed step")
+    ap.add_argument("--secondary", default=SECONDARY,
+                    help="comma-separated workloads (key or key:dtype) measured the "
+                         "same way ('' for none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for "
                          "calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -84,9 +100,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     G.load()
-    args.ldf = not args.random_priority
-    res, keep = run_workload(G, args.workload, args.dtype, args.steps,
-                             args.warmup, args.ldf)
+    res, keep = run_workload(G, args.workload, args.dtype, args.steps, args.warmup)
     result = {
         "metric": "smoothing nnz*K*sweeps/s + affinity edges/s; % HBM peak; "
                   "eig error vs FP64",
@@ -104,44 +118,34 @@ def main():
         "data": "synthetic",
     }
     result.update({k: v for k, v in res.items() if k not in result})
+    result["paper_reference"] = PAPER_REFERENCE
     g, wl, r, dg = keep
     if not args.no_eig:
-        result.update(eig_report(G, r, args.eig_original, dg))
+        result.update(eig_report(G, r, args.workload, res["storage"]))
     if not args.no_extras:
-        result["extras"] = extras_report(G, wl, dg, r, args.ldf)
-    if (not args.no_bf16_compare and res["storage"] == "f32" and wl.K % 8 == 0):
-        # the same workload with bfloat16 vector storage (FP32 arithmetic)
-        lam32 = np.array(result["eig_reduced"]) if "eig_reduced" in result else None
-        del r
-        b16, keep16 = run_workload(G, args.workload, "bf16", args.steps, args.warmup,
-                                   args.ldf, g=g)
-        entry = {k: b16[k] for k in ("value", "ms_per_step", "levels", "phase_ms_per_step",
-                                     "smooth_only_rate", "roofline")}
-        if lam32 is not None:
-            lam16, _ = G.gr_laplacian_eigs(keep16[2].coarse, 10)
-            entry["eig_reduced"] = [float(x) for x in lam16]
-            entry["eig_rel_diff_vs_f32"] = float(np.max(np.abs(lam16 - lam32) / lam32))
-        result["bf16"] = entry
-        del keep16
+        result["extras"] = headline_extras(G, keep)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(g, wl)
-    del keep, g, dg
-    if args.secondary and args.secondary != args.workload:
-        # the same measurement on a second workload whose colour steps are
-        # large enough to be bandwidth-bound (reported next to the headline)
-        sec, keep2 = run_workload(G, args.secondary, None, args.steps,
-                                  args.warmup, args.ldf)
-        result["secondary"] = {k: sec[k] for k in (
-            "value", "ms_per_step", "storage", "config", "levels",
-            "smooth_only_rate", "affinity_edges_per_s", "phase_ms_per_step",
-            "roofline")}
-        if not args.no_extras:
-            result["secondary"]["extras"] = secondary_extras(G, keep2)
+    del keep, g, dg, r
+    result["secondary"] = {}
+    for item in [x for x in args.secondary.split(",") if x]:
+        key, _, dt = item.partition(":")
+        sec, keep2 = run_workload(G, key, dt or None, args.steps, args.warmup)
+        entry = {k: sec[k] for k in ("value", "ms_per_step", "storage", "config", "levels",
+                                     "smooth_only_rate", "affinity_edges_per_s",
+                                     "phase_ms_per_step", "roofline")}
+        if not args.no_eig:
+            entry.update(eig_report(G, keep2[2], key, sec["storage"]))
+        if not args.no_extras and key == "chunglu434k" and sec["storage"] == "f32":
+            entry["extras"] = extras_report(G, keep2)
+        if not args.no_extras and key == "gmm70k":
+            entry["extras"] = {"alg2_sparse_branch": alg2_report(G, keep2, dense=False)}
+        result["secondary"][item] = entry
         del keep2
     print(json.dumps(result), flush=True)
 
 
-def run_workload(G, key, dtype, steps, warmup, ldf, g=None):
+def run_workload(G, key, dtype, steps, warmup, g=None):
     """Times `steps` full reductions of workload `key` (after `warmup`),
     then the same steps with the library's event profiler on."""
     import torch
@@ -150,6 +154,7 @@ def run_workload(G, key, dtype, steps, warmup, ldf, g=None):
 
     wl = W.WORKLOADS[key]
     dtype = dtype or wl.dtype
+    ldf = wl.ldf
     if g is None:
         t0 = time.time()
         g = W.build_graph(key)
@@ -238,11 +243,12 @@ def run_workload(G, key, dtype, steps, warmup, ldf, g=None):
     return res, (g, wl, r, dg)
 
 
-def eig_report(G, r, eig_original, dg):
+def eig_report(G, r, key, storage):
     """First 10 nontrivial eigenvalues of the reduced Laplacian, in FP64 on
-    the GPU (Chebyshev-filtered subspace iteration), with lambda_i / lambda_2
-    (the normalised eigenvalues whose preservation the paper plots, Fig. 5);
-    optionally the same for the original graph."""
+    the GPU, with lambda_i / lambda_2 (the normalised eigenvalues whose
+    preservation the paper plots, Fig. 5), and their error against the FP64
+    oracle's reduction of the same graph with the same seeds (the stored
+    values of tests/golden/reduction_<key>.txt)."""
     import torch
 
     torch.cuda.synchronize()
@@ -254,15 +260,34 @@ def eig_report(G, r, eig_original, dg):
     out = {"eig_reduced": [float(x) for x in lam],
            "eig_reduced_normalised": [float(x / lam[0]) for x in lam],
            "eig_ms": dt * 1e3, "eig_solver": rep}
-    if eig_original:
-        t0 = time.perf_counter()
-        lo, rep0 = G.gr_laplacian_eigs(dg, 10)
-        torch.cuda.synchronize()
-        log(f"original-graph eigenvalues in {time.perf_counter() - t0:.1f} s: {rep0}")
-        out["eig_original"] = [float(x) for x in lo]
-        out["eig_original_normalised"] = [float(x / lo[0]) for x in lo]
-        out["eig_normalised_rel_err"] = float(np.max(
-            np.abs(lam / lam[0] - lo / lo[0]) / (lo / lo[0])))
+    try:
+        import make_reduction_goldens as GOLD
+        from workloads import graphs as W
+
+        (_, _, _), rows = GOLD.load(key)
+        seed0 = GOLD.vec_seeds(W.WORKLOADS[key])[0]
+        L = np.array([v[3] for (st, _), v in rows.items() if st == storage])
+        ref = rows[(storage, seed0)][3]
+        gate = np.maximum(1e-4 * ref, 0.5 * (L.max(0) - L.min(0)))
+        err = np.abs(lam - ref)
+        out["eig_error_vs_fp64"] = {
+            "oracle": f"tests/golden/reduction_{key}.txt ({storage}, vector seed {seed0})",
+            "eig_oracle": [float(x) for x in ref],
+            "max_rel": float(np.max(err / ref)),
+            "max_over_gate": float(np.max(err / gate)),
+            "seed_range_rel": float(np.max((L.max(0) - L.min(0)) / ref)),
+            "oracle_n_coarse": rows[(storage, seed0)][0]}
+        if storage == "bf16" and ("f32", seed0) in rows:
+            # the storage format's cost: bfloat16 run against the FP32 oracle
+            L32 = np.array([v[3] for (st, _), v in rows.items() if st == "f32"])
+            ref32 = rows[("f32", seed0)][3]
+            gate32 = np.maximum(1e-4 * ref32, 0.5 * (L32.max(0) - L32.min(0)))
+            out["eig_error_vs_fp64"]["vs_f32_oracle_max_rel"] = float(
+                np.max(np.abs(lam - ref32) / ref32))
+            out["eig_error_vs_fp64"]["vs_f32_oracle_max_over_gate"] = float(
+                np.max(np.abs(lam - ref32) / gate32))
+    except (OSError, KeyError) as e:
+        out["eig_error_vs_fp64"] = {"error": repr(e)}
     return out
 
 
@@ -298,8 +323,8 @@ def vjp_report(G, dg, el, colours, nc, K, S, dtype):
     return out
 
 
-def extras_report(G, wl, dg, r, ldf):
-    """Timings of the differentiable pieces on the headline workload:
+def extras_report(G, keep):
+    """Pieces outside the timed step on the power-law graph:
     * the Gauss-Seidel backward pass (vector-Jacobian product) on the full
       graph, K and sweeps of the workload, with the sweep states stored and
       with them recomputed from X0;
@@ -307,17 +332,21 @@ def extras_report(G, wl, dg, r, ldf):
       reduced graph (random FP64 vectors and edge weights: timing only);
     * Alg. 1 edge scaling of a spanning sparsifier P of the reduced graph G
       (maximum spanning forest plus the heaviest 10% of the other edges);
+    * the multilevel eigensolver (Alg. 5) on the reduction's hierarchy;
+    * Phase B on the reduced graph, and Alg. 2 forced into its dense branch
+      (Phase B on the full graph first, as the paper ran coPapersCiteseer);
     * the data restriction of Alg. 6 through the reduction's final map.
     A failure is reported in place of the figures."""
     import torch
 
     from workloads import graphs as W
 
+    g, wl, r, dg = keep
     out = {"restrict_mean": restrict_report(G, r.agg, r.coarse.n)}
     try:
         K, S = wl.K, wl.sweeps
         el = G.gr_edge_list(dg)
-        colours, nc = G.gr_colour_greedy(dg, 1, ldf)
+        colours, nc = G.gr_colour_greedy(dg, 1, wl.ldf)
         out["gs_vjp"] = vjp_report(G, dg, el, colours, nc, K, S, "f32")
         del el
     except Exception as e:  # keep the headline figures
@@ -343,17 +372,17 @@ def extras_report(G, wl, dg, r, ldf):
         w_edge = torch.zeros(elr.E, dtype=torch.float64, device=dev)
         w_edge[elr.edge_of_entry.long()] = w_entries
         eu, ev, we = (elr.eu.cpu().numpy(), elr.ev.cpu().numpy(), w_edge.cpu().numpy())
-        keep = W.spanning_sparsifier(cg.n, eu, ev, we, 0.1)
-        pg = W.csr_from_edges(cg.n, eu[keep], ev[keep], we[keep])
+        keepP = W.spanning_sparsifier(cg.n, eu, ev, we, 0.1)
+        pg = W.csr_from_edges(cg.n, eu[keepP], ev[keepP], we[keepP])
         dP = G.DeviceGraph.from_numpy(pg.row_ptr, pg.col, pg.w, dev)
         pel = G.gr_edge_list(dP)
-        wP = torch.from_numpy(we[keep].copy()).to(dev)
+        wP = torch.from_numpy(we[keepP].copy()).to(dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rep = G.gr_sgd_scale(cg, dP, pel, wP, k_max=20)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        out["sgd_scale"] = {"ms": ms, "n": cg.n, "edges_G": elr.E, "edges_P": int(keep.size),
+        out["sgd_scale"] = {"ms": ms, "n": cg.n, "edges_G": elr.E, "edges_P": int(keepP.size),
                             "iterations": rep["iterations"],
                             "lambda_n_first_last": [rep["lambda_n"][0], rep["lambda_n"][-1]],
                             "cg_iterations_max": rep["cg_iterations_max"]}
@@ -361,7 +390,128 @@ def extras_report(G, wl, dg, r, ldf):
     except Exception as e:
         out.setdefault("rq_forward_backward", {"error": repr(e)})
         out["sgd_scale"] = {"error": repr(e)}
+    out["multilevel_eigs"] = multilevel_report(G, keep)
+    out["phase_b_reduced"] = phase_b_report(G, r.coarse)
+    out["alg2_dense_branch"] = alg2_report(G, keep, dense=True)
     return out
+
+
+def multilevel_report(G, keep, k=10):
+    """Alg. 5 on the reduction's hierarchy: wall time, and the Ritz values of
+    the refined vectors on the fine graph against the fine eigenvalues (the
+    direct FP64 solve), with 0 and 4 Jacobi steps per level."""
+    import torch
+
+    g, wl, r, dg = keep
+    try:
+        red = G.gr_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed, wl.colour_seed,
+                          largest_degree_first=wl.ldf, keep_hierarchy=True)
+        h = red.hierarchy
+        t0 = time.perf_counter()
+        lam_f, rep_f = G.gr_laplacian_eigs(dg, k)
+        torch.cuda.synchronize()
+        direct_ms = (time.perf_counter() - t0) * 1e3
+        out = {"levels": h.n, "k": k, "direct_eigs_ms": direct_ms,
+               "eig_fine": [float(x) for x in lam_f]}
+        for iters in (0, 4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam_c, U, rep = G.gr_multilevel_eigs(dg, h, k, iters=iters)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            # Ritz values of span(U) on the fine Laplacian (FP64 on the GPU)
+            LU = laplacian_apply_gpu(dg, U)
+            H = (U.T @ LU).cpu().numpy()
+            ritz = np.linalg.eigvalsh((H + H.T) / 2)
+            out[f"jacobi_{iters}"] = {"ms": ms, "ritz_over_lambda_minus_1": [
+                float(x) for x in ritz / lam_f - 1], "coarsest_lambda": [float(x) for x in lam_c]}
+            log(f"multilevel eigensolver ({iters} Jacobi steps): {ms:.1f} ms, Ritz/lambda-1 max "
+                f"{np.max(ritz / lam_f - 1):.3f}")
+        return out
+    except Exception as e:
+        return {"error": repr(e)}
+
+
+def laplacian_apply_gpu(dg, U):
+    """L U for the graph's Laplacian, float64 on the device (torch sparse;
+    measurement only)."""
+    import torch
+
+    n = dg.n
+    rows = torch.repeat_interleave(torch.arange(n, device=U.device),
+                                   (dg.row_ptr[1:] - dg.row_ptr[:-1]).long())
+    A = torch.sparse_coo_tensor(torch.stack([rows, dg.col.long()]), dg.w.double(), (n, n))
+    d = torch.zeros(n, dtype=torch.float64, device=U.device).index_add_(0, rows, dg.w.double())
+    return d[:, None] * U - torch.sparse.mm(A, U)
+
+
+def phase_b_report(G, cg):
+    """Phase B (tree + 5 rounds of 2% of n) on the reduced graph."""
+    import torch
+
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        flags, _, rep = G.gr_sparsify(cg, rounds=5, add_frac=0.02)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        log(f"Phase B on the reduced graph: {ms:.1f} ms, {rep}")
+        return {"ms": ms, "n": cg.n, "edges_G": cg.nnz // 2, **rep}
+    except Exception as e:
+        return {"error": repr(e)}
+
+
+def alg2_report(G, keep, dense):
+    """Alg. 2 on the workload graph.  dense=True forces the dense branch
+    (gamma_max below the graph's density): Phase B and Alg. 1 on the full
+    graph, then Phase A on the scaled sparsifier; dense=False keeps the
+    sparse branch (Phase A, then Phase B and Alg. 1 on R).  Reports the wall
+    time and the first 10 nontrivial eigenvalues of S against those of the
+    plain Phase A reduction R (relative), and, in the sparse branch, of the
+    unscaled sparsifier P too: the accuracy the edge scaling buys."""
+    import torch
+
+    g, wl, r, dg = keep
+    try:
+        gamma = (g.nnz // 2) / g.n
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = G.gr_spectral_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed, wl.colour_seed,
+                                   largest_degree_first=wl.ldf,
+                                   gamma_max=(0.5 * gamma if dense else 40.0),
+                                   sparsify=dict(rounds=5, add_frac=0.02, cg_max_iter=1000,
+                                                 cg_tol=1e-10),
+                                   scaling=dict(k_max=20, cg_max_iter=1000, cg_tol=1e-10))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        lam_S, _ = G.gr_laplacian_eigs(out.S, 10)
+        lam_R, _ = G.gr_laplacian_eigs(r.coarse, 10)
+        rep = {"ms": ms, "dense_branch": out.dense, "gamma": out.gamma, "n_S": out.S.n,
+               "edges_S": out.S.nnz // 2, "edges_R": r.coarse.nnz // 2,
+               "sparsify": out.sparsify,
+               "scaling": {"iterations": out.scaling["iterations"],
+                           "lambda_n_first_last": out.scaling["lambda_n"][:1]
+                           + out.scaling["lambda_n"][-1:]},
+               "eig_S": [float(x) for x in lam_S], "eig_R": [float(x) for x in lam_R],
+               "eig_S_vs_R_max_rel": float(np.max(np.abs(lam_S - lam_R) / lam_R)),
+               # the normalised eigenvalues lambda_i / lambda_2 of Fig. 5
+               "eig_S_vs_R_normalised_max_rel": float(np.max(np.abs(
+                   lam_S / lam_S[0] - lam_R / lam_R[0]) / (lam_R / lam_R[0])))}
+        if not dense:
+            # the same sparsifier of R without the edge scaling
+            flags, _, _ = G.gr_sparsify(r.coarse, rounds=5, add_frac=0.02, cg_max_iter=1000,
+                                        cg_tol=1e-10)
+            P, _ = G.gr_subgraph(r.coarse, flags)
+            lam_P, _ = G.gr_laplacian_eigs(P, 10)
+            rep["eig_P_unscaled"] = [float(x) for x in lam_P]
+            rep["eig_P_vs_R_max_rel"] = float(np.max(np.abs(lam_P - lam_R) / lam_R))
+            rep["eig_P_vs_R_normalised_max_rel"] = float(np.max(np.abs(
+                lam_P / lam_P[0] - lam_R / lam_R[0]) / (lam_R / lam_R[0])))
+        log(f"Alg. 2 ({'dense' if dense else 'sparse'} branch): {ms:.1f} ms, S {out.S.n} nodes "
+            f"{out.S.nnz // 2} edges, eig S vs R {rep['eig_S_vs_R_max_rel']:.3f}")
+        return rep
+    except Exception as e:
+        return {"error": repr(e)}
 
 
 def restrict_report(G, agg, n_coarse, d=64):
@@ -383,23 +533,25 @@ def restrict_report(G, agg, n_coarse, d=64):
         return {"error": repr(e)}
 
 
-def secondary_extras(G, keep):
-    """The GS backward on the second workload, in its own configuration
-    (vector storage type, K, sweeps; its colouring when it prescribes one)."""
+def headline_extras(G, keep):
+    """The GS backward on the headline workload, in its own configuration
+    (vector storage type, K, sweeps; its colouring when it prescribes one),
+    and the data restriction through its final map."""
     import torch
 
     g, wl, r, dg = keep
+    out = {"restrict_mean": restrict_report(G, r.agg, r.coarse.n)}
     try:
         el = G.gr_edge_list(dg)
         if g.colours is not None:
             colours = torch.from_numpy(g.colours).to(dg.row_ptr.device)
             nc = g.n_colours
         else:
-            colours, nc = G.gr_colour_greedy(dg, 1, True)
-        return {"gs_vjp": vjp_report(G, dg, el, colours, nc, wl.K, wl.sweeps, wl.dtype),
-                "restrict_mean": restrict_report(G, r.agg, r.coarse.n)}
+            colours, nc = G.gr_colour_greedy(dg, 1, wl.ldf)
+        out["gs_vjp"] = vjp_report(G, dg, el, colours, nc, wl.K, wl.sweeps, wl.dtype)
     except Exception as e:  # keep the other figures
-        return {"gs_vjp": {"error": repr(e)}}
+        out["gs_vjp"] = {"error": repr(e)}
+    return out
 
 
 COPY_BYTES = 1 << 30
@@ -462,27 +614,44 @@ def measured_traffic(workload, dtype):
 
 
 def cpu_baseline(g, wl):
-    """Oracle (FP64, one host thread) smoothing + affinity on the level-0
-    graph with the level-0 colouring of the GPU run."""
+    """The FP64 oracle on a bounded sample of the headline workload: one
+    Gauss-Seidel sweep (of the step's five) over the full graph, with the
+    level-0 colouring and the storage rounding of the GPU run, on one host
+    thread and on every thread the host offers this process."""
     from oracle import oracle as O
 
     w64 = g.w.astype(np.float64)
     if g.colours is not None:
         c, nc = g.colours, g.n_colours
     else:
-        c, nc = O.colour_greedy(g.n, g.row_ptr, g.col,
-                                O.level_seed(wl.colour_seed, 0))
+        c, nc = O.colour_greedy(g.n, g.row_ptr, g.col, O.level_seed(wl.colour_seed, 0), wl.ldf)
     X = O.init_vectors(g.n, wl.K, O.level_seed(wl.vec_seed, 0))
-    t0 = time.perf_counter()
-    X = O.smooth(g.n, g.row_ptr, g.col, w64, c, nc, X, wl.sweeps)
-    O.affinity(g.n, g.row_ptr, g.col, X)
-    dt = time.perf_counter() - t0
-    log(f"cpu baseline: {dt:.1f}s")
-    return {"value": g.nnz * wl.K * wl.sweeps / dt, "unit": "nnz*K*sweeps/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"level-0 smoothing ({wl.sweeps} sweeps) + affinity of "
-                      f"the full {g.name} graph (n={g.n}, nnz={g.nnz}), FP64, "
-                      f"{dt:.1f} s"}
+    nthr = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    runs = {}
+    for t in (1, nthr):
+        with O.threads(t):
+            t0 = time.perf_counter()
+            O.smooth(g.n, g.row_ptr, g.col, w64, c, nc, X, 1, bf16=(wl.dtype == "bf16"))
+            runs[t] = time.perf_counter() - t0
+        log(f"cpu baseline, {t} thread(s): {runs[t]:.1f} s")
+    work = g.nnz * wl.K
+    return {"value": work / runs[1], "unit": "nnz*K*sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one Gauss-Seidel sweep (of {wl.sweeps}) over the full {g.name} graph "
+                      f"(n={g.n}, nnz={g.nnz}, K={wl.K}, {wl.dtype} rounding), FP64: "
+                      f"{runs[1]:.1f} s on 1 thread, {runs[nthr]:.1f} s on {nthr}",
+            "threads": {"cores": nthr, "value": work / runs[nthr]},
+            "host_cpu": host_cpu()}
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -384,7 +384,8 @@ def gmm70k():
     return W.build_graph("gmm70k"), W.WORKLOADS["gmm70k"]
 
 
-def _eigen_gate(key, g, wl, storage, colours=None, ldf=False, agreement=True):
+def _eigen_gate(key, g, wl, storage, colours=None, agreement=True):
+    ldf = wl.ldf
     dev, G = _dev(), _G()
     (n, nnz, digest), rows = GOLD.load(key)
     assert (n, nnz) == (g.n, g.nnz) and digest == GOLD.graph_digest(g), \
@@ -422,7 +423,7 @@ def _eigen_gate(key, g, wl, storage, colours=None, ldf=False, agreement=True):
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_power_law_full_size_eigen_gate(power_law, storage):
     g, wl = power_law
-    _eigen_gate("chunglu434k", g, wl, storage, ldf=True)
+    _eigen_gate("chunglu434k", g, wl, storage)
 
 
 @pytest.mark.timeout(900)
@@ -476,3 +477,79 @@ def test_power_law_full_size_multilevel_eigensolver(power_law):
         say(f"  Ritz/lambda - 1: {np.round(ritz[iters] / lam_f - 1, 3).tolist()}")
         assert np.all(ritz[iters] >= lam_f * (1 - 1e-8))
     assert np.sum(ritz[4]) < np.sum(ritz[0])
+
+
+@pytest.mark.timeout(900)
+def test_gmm70k_full_size_chain(gmm70k):
+    """The Gaussian-mixture chain at full size: reduce 16x to R; FP64
+    eigenpairs of R; the Rayleigh-quotient edge gradients at those
+    eigenvectors (first-order perturbation, Sec. 3.3.3) against central
+    differences of R's eigenvalues for the most sensitive edges; Phase B's
+    sparsifier of R and Alg. 1 against the oracle (parallel mode) on the
+    same input; the eigenvalue accuracy of the sparsifier with and without
+    the edge scaling, against R."""
+    from oracle import sgd as SG
+    from oracle import sparsify as PB
+
+    g, wl = gmm70k
+    dev, G = _dev(), _G()
+    dg = G.DeviceGraph.from_numpy(g.row_ptr, g.col, g.w, dev)
+    say("gmm70k chain: reduce 16x")
+    R = G.gr_reduce(dg, wl.K, wl.sweeps, wl.ratio, wl.vec_seed, wl.colour_seed).coarse
+    el = G.gr_edge_list(R)
+    rw32 = R.w.cpu().numpy()
+    eoe = el.edge_of_entry.cpu().numpy()
+    wE32 = np.zeros(el.E, np.float32)
+    wE32[eoe] = rw32
+    lam, U, rep = G.gr_laplacian_eigpairs(R, 10, tol=1e-13, max_iter=4000)
+    say(f"R: n={R.n}, {el.E} edges; lambda_2..11 {np.round(lam, 6).tolist()}")
+    wE = torch.from_numpy(wE32.astype(np.float64)).to(dev)
+    Rq, den = G.gr_rq_forward(el, wE, U)
+    assert np.allclose(Rq.cpu().numpy(), lam, rtol=1e-9)
+    rel_gap = np.minimum(np.diff(np.concatenate([[0.0], lam])),
+                         np.diff(np.concatenate([lam, [np.inf]]))) / lam
+    rp = R.row_ptr.cpu().numpy()
+    cl = R.col.cpu().numpy()
+    checked = 0
+    for i in np.flatnonzero(rel_gap > 1e-2)[:3]:
+        gR = torch.zeros(10, dtype=torch.float64, device=dev)
+        gR[i] = 1.0
+        gw = G.gr_rq_backward(el, U, Rq, den, gR).cpu().numpy()
+        for e in np.argsort(-np.abs(gw))[:4]:
+            vals = []
+            hs = []
+            for sgn in (1, -1):
+                wp = wE32.copy()
+                wp[e] = np.float32(wE32[e] * (1 + sgn * 2.0**-10))
+                hs.append(float(wp[e]))
+                dgp = G.DeviceGraph.from_numpy(rp, cl, wp[eoe], dev)
+                vals.append(G.gr_laplacian_eigs(dgp, 10, tol=1e-13, max_iter=4000)[0][i])
+            fd = (vals[0] - vals[1]) / (hs[0] - hs[1])
+            say(f"  lambda_{i + 2} edge {e}: gradient {gw[e]:.6e}, central difference {fd:.6e}")
+            assert abs(fd - gw[e]) <= 2e-3 * abs(gw[e]) + 1e-9 * lam[i]
+            checked += 1
+    assert checked >= 4
+    say("gmm70k chain: Phase B and Alg. 1 against the oracle")
+    flags, _, srep = G.gr_sparsify(R, rounds=5, add_frac=0.02, seed=1, cg_tol=1e-13)
+    eu, ev = el.eu.cpu().numpy(), el.ev.cpu().numpy()
+    w64 = wE32.astype(np.float64)
+    with O.threads(16):
+        ref = PB.sparsify(R.n, eu, ev, w64, PB.SparsifyParams(rounds=5, add_frac=0.02, seed=1))
+    keep = flags.cpu().numpy().astype(bool)
+    assert np.array_equal(keep, ref.in_P)
+    assert np.allclose(srep["lambda_n"], ref.lambda_n, rtol=1e-8)
+    P, pel = G.gr_subgraph(R, flags)
+    wP = torch.from_numpy(w64[keep].copy()).to(dev)
+    lamP, _ = G.gr_laplacian_eigs(P, 10)
+    G.gr_sgd_scale(R, P, pel, wP, k_max=5, eps=1e-4, cg_tol=1e-14)
+    sg = SG.sgd_scale(R.n, eu, ev, w64, eu[keep], ev[keep], w64[keep],
+                      SG.SgdParams(k_max=5, eps=1e-4))
+    err = np.max(np.abs(wP.cpu().numpy() - sg.w_P) / sg.w_P)
+    say(f"Alg. 1 on R's sparsifier ({keep.sum()} of {keep.size} edges): max relative weight "
+        f"difference to the oracle {err:.2e}")
+    assert err <= 1e-7
+    pe = torch.zeros(P.nnz, dtype=torch.float32, device=dev)
+    pe[:] = wP.float()[pel.edge_of_entry.long()]
+    lamS, _ = G.gr_laplacian_eigs(G.DeviceGraph(P.row_ptr, P.col, pe), 10)
+    say(f"eigenvalues against R's: unscaled sparsifier max rel "
+        f"{np.max(np.abs(lamP - lam) / lam):.3f}, scaled {np.max(np.abs(lamS - lam) / lam):.3f}")

@@ -415,6 +415,7 @@ class Workload:
     dtype: str          # "f32" or "bf16" storage of the test vectors
     vec_seed: int
     colour_seed: int
+    ldf: bool = False   # greedy colouring in largest-degree-first order
 
 
 WORKLOADS = {
@@ -427,7 +428,7 @@ WORKLOADS = {
     "chunglu434k": Workload(
         "chunglu434k", "Chung-Lu power-law graph, 434k nodes, mean degree "
         "73.7, exponent 2.5, weights U[0.5,2]", 16, 5, 434000.0 / 13000.0,
-        "f32", 13, 23),
+        "f32", 13, 23, ldf=True),
     "gmm70k": Workload(
         "gmm70k", "kNN (k=10) graph of a 10-component Gaussian mixture, "
         "70k points in 784-d", 16, 5, 16.0, "f32", 14, 24),
