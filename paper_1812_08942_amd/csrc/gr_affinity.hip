@@ -24,62 +24,108 @@ __device__ inline bool closer(float d1, int32_t id1, float d2, int32_t id2) {
 }
 
 // Per row-group: a = (x_v . x_j)^2 / (|x_v|^2 |x_j|^2) and the algebraic
-// distance d = 1 - a.  d is formed without cancellation as
-// |u - w|^2 |u + w|^2 / 4 on the normalised rows u = x_v/|x_v|, w = x_j/|x_j|
-// (equal to 1 - cos^2 in exact arithmetic), so that it keeps its relative
-// accuracy where a itself rounds to 1 in float32.  Both quantities are
-// computed by the same code for (v, j) and (j, v), hence bit-symmetric.
-// Distance, affinity and the row-group's candidate for one entry (v, j):
-// chunk q of the normalised rows, reduced over the Q lanes of the entry with
-// a fixed tree, so (v, j) and (j, v) give identical bits.
-template <int Q, int DT>
-__device__ inline void entry_ad(const void* __restrict__ X, int32_t K, int q, const float* xv,
-                                const float* uv, float nv, int32_t j, float* av, float* dv) {
-    constexpr int E = Chunk<DT>::E;
-    float xj[E];
-    Chunk<DT>::load(X, j, K, q, xj);
-    float c = qsum<Q>(chunk_dot<E>(xv, xj));
-    float nj = qsum<Q>(chunk_dot<E>(xj, xj));
-    const float rj = nj > 0.0f ? 1.0f / sqrtf(nj) : 0.0f;
-    float dm = 0.0f, dp = 0.0f;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-        float uj = xj[i] * rj;
-        float m = uv[i] - uj, s2 = uv[i] + uj;
-        dm = __fmaf_rn(m, m, dm);
-        dp = __fmaf_rn(s2, s2, dp);
-    }
-    dm = qsum<Q>(dm);
-    dp = qsum<Q>(dp);
-    float den = nv * nj;
-    *av = den == 0.0f ? 0.0f : fminf(1.0f, (c * c) / den);
-    *dv = den == 0.0f ? 1.0f : fminf(1.0f, dm * dp * 0.25f);
+// distance d = 1 - a.  On the normalised rows u = x_v/|x_v|, w = x_j/|x_j|,
+// 1 - cos^2 = |u - w|^2 |u + w|^2 / 4, and the two factors add up to 4
+// (|u|^2 + |w|^2 + ... = 4 for unit rows), so d = m (4 - m) / 4 with m the
+// smaller factor: |u - w|^2 when x_v . x_j >= 0, else |u + w|^2.  m is the
+// factor that would cancel if formed as 4 minus the other one, so d keeps its
+// relative accuracy where a itself rounds to 1 in float32 (d ~ 0 at
+// cos ~ +1 and at cos ~ -1); the other factor, in [2, 4], takes it from 4.
+// A row is normalised by the hardware reciprocal square root of its squared
+// norm (within an ulp or two; the unit rows need not be exact, only the
+// same for every use of the row).  Everything is computed by the same
+// operations for (v, j) and (j, v): the dot products commute, u - w and
+// w - u differ in sign only, so both quantities are bit-symmetric.
+
+// squared norm and reciprocal norm of a row chunk (reduced over the Q lanes)
+template <int Q, int E>
+__device__ inline float2 row_norm(const float* x) {
+    const float nv = qsum<Q>(chunk_dot<E>(x, x));
+    return make_float2(nv, nv > 0.0f ? rsqrtf(nv) : 0.0f);
 }
 
-template <int Q, int DT>
-__device__ inline void row_prep(const void* __restrict__ X, int32_t K, int q, int64_t r, float* xv,
-                                float* uv, float* nv_out) {
-    constexpr int E = Chunk<DT>::E;
-    Chunk<DT>::load(X, r, K, q, xv);
-    const float nv = qsum<Q>(chunk_dot<E>(xv, xv));
-    // the row is normalised by one correctly rounded reciprocal square root
-    // (the same operations for every row, so (v, j) and (j, v) agree)
-    const float rv = nv > 0.0f ? 1.0f / sqrtf(nv) : 0.0f;
+// d (and a if wanted) of one entry from chunk q of both rows
+template <int Q, int E>
+__device__ inline float entry_d(const float* xv, const float* uv, float2 nrv, const float* xj,
+                                float* av) {
+    const float c = qsum<Q>(chunk_dot<E>(xv, xj));
+    const float2 nrj = row_norm<Q, E>(xj);
+    const float s = c >= 0.0f ? -1.0f : 1.0f;
+    float m = 0.0f;
 #pragma unroll
-    for (int i = 0; i < E; ++i) uv[i] = xv[i] * rv;
-    *nv_out = nv;
+    for (int i = 0; i < E; ++i) {
+        const float t = __fmaf_rn(s, xj[i] * nrj.y, uv[i]);  // u -+ w, rounded once
+        m = __fmaf_rn(t, t, m);
+    }
+    m = qsum<Q>(m);
+    if (av) {
+        const float den = nrv.x * nrj.x;
+        *av = den == 0.0f ? 0.0f : fminf(1.0f, (c * c) / den);
+    }
+    return (nrv.y == 0.0f || nrj.y == 0.0f) ? 1.0f : fminf(1.0f, m * (4.0f - m) * 0.25f);
+}
+
+// entries of a row taken per round by each lane: their columns, then their
+// rows and ids, are all loaded before any is used, so that the gathers are
+// in flight together
+constexpr int kAU = 4;
+
+// The row-group's part of one row: lanes (p, q) take entries p, p + P, ...
+// (kAU at a time), chunk q.  Every lane of the row-group runs the same trip
+// count so that the q-sums (shuffles) stay converged; lanes past the end
+// use the row itself as a dummy neighbour.  Returns the lane's best (d, id).
+template <int Q, int DT>
+__device__ inline void row_entries(const int32_t* __restrict__ col, const void* __restrict__ X,
+                                   int32_t K, const int32_t* __restrict__ ids, int64_t r,
+                                   int32_t e0,
+                                   int32_t e1, int p, int q, int P, float* __restrict__ a,
+                                   float* __restrict__ dist, float& bd, int32_t& bj,
+                                   int32_t& bid) {
+    constexpr int E = Chunk<DT>::E;
+    float xv[E], uv[E];
+    Chunk<DT>::load(X, r, K, q, xv);
+    const float2 nrv = row_norm<Q, E>(xv);
+#pragma unroll
+    for (int i = 0; i < E; ++i) uv[i] = xv[i] * nrv.y;
+    const int32_t trips = (e1 - e0 + P * kAU - 1) / (P * kAU);
+    for (int32_t t = 0; t < trips; ++t) {
+        int32_t e[kAU], j[kAU], jid[kAU];
+#pragma unroll
+        for (int u = 0; u < kAU; ++u) {
+            e[u] = e0 + p + (t * kAU + u) * P;
+            j[u] = e[u] < e1 ? col[e[u]] : (int32_t)r;
+        }
+        float xj[kAU][E];
+#pragma unroll
+        for (int u = 0; u < kAU; ++u) {
+            Chunk<DT>::load(X, j[u], K, q, xj[u]);
+            jid[u] = ids ? ids[j[u]] : j[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kAU; ++u) {
+            float av;
+            const float dv = entry_d<Q, E>(xv, uv, nrv, xj[u], a ? &av : nullptr);
+            if (e[u] < e1) {
+                if (q == 0) {
+                    if (a) a[e[u]] = av;
+                    if (dist) dist[e[u]] = dv;
+                }
+                if (closer(dv, jid[u], bd, bid)) { bd = dv; bj = j[u]; bid = jid[u]; }
+            }
+        }
+    }
 }
 
 // Rows with degree <= kLongRow: L = Q*P lanes per row.
 template <int Q, int P, int DT>
 __device__ inline void aff_normal(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                   const void* __restrict__ X, int32_t K, int64_t n,
-                                  const int32_t* __restrict__ ids, float* __restrict__ a,
-                                  float* __restrict__ dist, int32_t* __restrict__ best,
-                                  float* __restrict__ dbest, int64_t rblock) {
+                                  const int32_t* __restrict__ ids,
+                                  float* __restrict__ a, float* __restrict__ dist,
+                                  int32_t* __restrict__ best, float* __restrict__ dbest,
+                                  int64_t rblock) {
     constexpr int L = Q * P;
     constexpr int RPW = kWave / L;
-    constexpr int E = Chunk<DT>::E;
     const int lane = threadIdx.x & (kWave - 1);
     const int l = lane % L;
     const int p = l / Q, q = l % Q;
@@ -88,28 +134,9 @@ __device__ inline void aff_normal(const int32_t* __restrict__ rp, const int32_t*
     if (r >= n) return;
     const int32_t e0 = rp[r], e1 = rp[r + 1];
     if (e1 - e0 > kLongRow) return;  // handled by a whole workgroup
-    float xv[E], uv[E], nv;
-    row_prep<Q, DT>(X, K, q, r, xv, uv, &nv);
     float bd = 2.0f;
     int32_t bj = -1, bid = 0x7fffffff;
-    // every lane of the row-group runs the same trip count so the q-sums
-    // (shuffles) stay converged; lanes past the end use a dummy column
-    const int32_t trips = (e1 - e0 + P - 1) / P;
-    for (int32_t t = 0; t < trips; ++t) {
-        int32_t e = e0 + p + t * P;
-        bool ok = e < e1;
-        int32_t j = ok ? col[e] : (int32_t)r;
-        float av, dv;
-        entry_ad<Q, DT>(X, K, q, xv, uv, nv, j, &av, &dv);
-        if (ok) {
-            if (q == 0) {
-                if (a) a[e] = av;
-                if (dist) dist[e] = dv;
-            }
-            int32_t jid = ids ? ids[j] : j;
-            if (closer(dv, jid, bd, bid)) { bd = dv; bj = j; bid = jid; }
-        }
-    }
+    row_entries<Q, DT>(col, X, K, ids, r, e0, e1, p, q, P, a, dist, bd, bj, bid);
 #pragma unroll
     for (int off = Q; off < L; off <<= 1) {
         float od = __shfl_xor(bd, off, kWave);
@@ -127,37 +154,18 @@ __device__ inline void aff_normal(const int32_t* __restrict__ rp, const int32_t*
 template <int Q, int DT>
 __device__ inline void aff_long(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                 const void* __restrict__ X, int32_t K, int64_t r,
-                                const int32_t* __restrict__ ids, float* __restrict__ a,
-                                float* __restrict__ dist, int32_t* __restrict__ best,
-                                float* __restrict__ dbest) {
-    constexpr int E = Chunk<DT>::E;
+                                const int32_t* __restrict__ ids,
+                                float* __restrict__ a, float* __restrict__ dist,
+                                int32_t* __restrict__ best, float* __restrict__ dbest) {
     constexpr int P = kBig / Q;
     constexpr int NW = kBig / kWave;
     __shared__ float sbd[NW];
     __shared__ int32_t sbj[NW], sbid[NW];
     const int t = threadIdx.x;
     const int p = t / Q, q = t % Q;
-    float xv[E], uv[E], nv;
-    row_prep<Q, DT>(X, K, q, r, xv, uv, &nv);
-    const int32_t e0 = rp[r], e1 = rp[r + 1];
     float bd = 2.0f;
     int32_t bj = -1, bid = 0x7fffffff;
-    const int32_t trips = (e1 - e0 + P - 1) / P;
-    for (int32_t it = 0; it < trips; ++it) {
-        int32_t e = e0 + p + it * P;
-        bool ok = e < e1;
-        int32_t j = ok ? col[e] : (int32_t)r;
-        float av, dv;
-        entry_ad<Q, DT>(X, K, q, xv, uv, nv, j, &av, &dv);
-        if (ok) {
-            if (q == 0) {
-                if (a) a[e] = av;
-                if (dist) dist[e] = dv;
-            }
-            int32_t jid = ids ? ids[j] : j;
-            if (closer(dv, jid, bd, bid)) { bd = dv; bj = j; bid = jid; }
-        }
-    }
+    row_entries<Q, DT>(col, X, K, ids, r, rp[r], rp[r + 1], p, q, P, a, dist, bd, bj, bid);
 #pragma unroll
     for (int off = Q; off < kWave; off <<= 1) {
         float od = __shfl_xor(bd, off, kWave);
@@ -268,8 +276,9 @@ int affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, const i
              float* dbest, hipStream_t st) {
     if (g->n == 0) return GR_OK;
     int Q = K * (dtype == GR_BF16 ? 2 : 4) / 16;
-#define GR_AFQ(QQ, DD) \
-    case QQ: return launch_aff<QQ, DD>(g, K, X, ids, long_rows, n_long, a, dist, best, dbest, st);
+#define GR_AFQ(QQ, DD)                                                                            \
+    case QQ:                                                                                      \
+        return launch_aff<QQ, DD>(g, K, X, ids, long_rows, n_long, a, dist, best, dbest, st);
     if (dtype == GR_BF16) {
         switch (Q) { GR_AFQ(1, GR_BF16) GR_AFQ(2, GR_BF16) GR_AFQ(4, GR_BF16) GR_AFQ(8, GR_BF16) }
     } else {

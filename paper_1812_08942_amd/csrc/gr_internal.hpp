@@ -166,9 +166,9 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
 int smooth_ordered(const OrderedGraph* og, int32_t K, int32_t sweeps, int32_t dtype,
                    void* X, Arena& ws, hipStream_t st);
 // a (affinity) and dist (algebraic distance d = 1 - a) per entry are
-// optional; best = argmin (d, id) per row, dbest its distance.  Rows of
-// degree above the long-row threshold are listed in long_rows (n_long of
-// them) and handled by a workgroup each.
+// optional; best = argmin (d, id) per row, dbest its distance, id = ids[j]
+// (ids NULL: j itself).  Rows of degree above the long-row threshold are
+// listed in long_rows (n_long of them) and handled by a workgroup each.
 int affinity(const gr_graph* g, int32_t K, int32_t dtype, const void* X, const int32_t* ids,
              const int32_t* long_rows, int64_t n_long, float* a, float* dist, int32_t* best,
              float* dbest, hipStream_t st);

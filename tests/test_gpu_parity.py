@@ -265,6 +265,84 @@ def test_affinity_matches_oracle_and_is_symmetric():
                                   O.best(g.n, g.row_ptr, g.col, d))
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_candidates_do_not_depend_on_requested_outputs(dtype):
+    """best/dbest alone (the reduction's call) equal, bit for bit, those of
+    the call that also returns a and d, over K of one to sixteen 16-byte
+    chunks, workgroup-wide hub rows and isolated nodes (-1)."""
+    dev = _dev()
+    G = _G()
+    graphs = dict(small_graphs())
+    graphs["chunglu_hubs_10000"] = W.chung_lu(10000, mean_deg=700.0, seed=7)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    ks = (4, 16, 64) if dtype == "f32" else (8, 32, 64)
+    for name, g in graphs.items():
+        dg = dgraph(g, dev)
+        c, nc = _colour(g)
+        for K in ks:
+            say(f"candidates {name} K={K} {dtype}")
+            X = torch.from_numpy(O.init_vectors(g.n, K, 17)).to(dev).to(tdt).contiguous()
+            G.gr_smooth(dg, torch.from_numpy(c).to(dev), nc, X, 2)
+            _, d, b2, d2 = G.gr_affinity(dg, X, want_a=True, want_d=True)
+            _, _, b1, d1 = G.gr_affinity(dg, X, want_a=False, want_d=False)
+            assert torch.equal(b1, b2), name
+            assert torch.equal(d1.view(torch.int32), d2.view(torch.int32)), name
+            assert np.array_equal(b1.cpu().numpy(), O.best(g.n, g.row_ptr, g.col, d.cpu().numpy()))
+            if name == "er_40_isolated":
+                assert int((b1 < 0).sum()) >= 3
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_affinity_extreme_angles(dtype):
+    """Rows at angles where a rounds to 0 or 1 in float32: nearly parallel
+    and nearly antiparallel pairs (d ~ 1e-8, where 1 - a would cancel),
+    orthogonal pairs, a zero row, equal and opposite rows (d = 0 exactly).
+    d stays within the bound of the main affinity test against the FP64
+    oracle on the same stored rows, and is bit-symmetric."""
+    dev = _dev()
+    G = _G()
+    rng = np.random.default_rng(11)
+    K = 32
+    pairs = 8
+    X = np.zeros((2 * pairs, K))
+    for k in range(pairs):
+        x = rng.standard_normal(K)
+        X[2 * k] = x
+        if k == 0:
+            X[1] = x + 1e-4 * rng.standard_normal(K)
+        elif k == 1:
+            X[3] = -x + 1e-4 * rng.standard_normal(K)
+        elif k == 2:
+            y = rng.standard_normal(K)
+            X[5] = y - (y @ x) / (x @ x) * x
+        elif k == 3:
+            X[7] = 0.0
+        elif k == 4:
+            X[9] = x
+        elif k == 5:
+            X[11] = -x
+        elif k == 6:
+            X[13] = 3.0 * x + 1e-3 * rng.standard_normal(K)
+        else:
+            X[15] = -0.5 * x + 1e-5 * rng.standard_normal(K)
+    eu = np.arange(0, 2 * pairs, 2)
+    g = W.csr_from_edges(2 * pairs, eu, eu + 1, np.ones(pairs))
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    Xd = torch.from_numpy(X).to(dev).to(tdt).contiguous()
+    Xs = Xd.float().cpu().numpy().astype(np.float64)
+    say(f"affinity extreme angles {dtype}")
+    a, d, best, dbest = G.gr_affinity(dgraph(g, dev), Xd)
+    d = d.cpu().numpy()
+    ra, rd = O.affinity(g.n, g.row_ptr, g.col, Xs, with_distance=True)
+    assert np.all(np.abs(d - rd) <= 2e-6 * np.sqrt(rd) + 1e-5 * rd + 1e-12), (d, rd)
+    assert np.max(np.abs(a.cpu().numpy() - ra)) <= 1e-5
+    assert np.array_equal(d[0::2].view(np.uint32), d[1::2].view(np.uint32))
+    assert d[2 * 3] == 1.0 and a.cpu().numpy()[2 * 3] == 0.0      # zero row
+    assert d[2 * 4] == 0.0 and d[2 * 5] == 0.0                     # equal, opposite
+    if dtype == "f32":                                               # the cancelling cases
+        assert 0 < rd[0] < 1e-6 and 0 < rd[2] < 1e-6
+
+
 def test_aggregation_bit_exact_on_gpu_affinities():
     dev = _dev()
     G = _G()
