@@ -183,6 +183,10 @@ int gr_validate(const gr_graph* g, void* ws, size_t ws_bytes, void* stream);
  * nodes are sorted by priority and each waits for its higher-priority
  * neighbours' colours (a bounded wait; GR_EHIP if it ever runs out).
  * Output: colours int32[n] (device), *n_colours (HOST).  Synchronises.
+ * The waiting kernel is a cooperative launch (all its workgroups resident);
+ * with the environment variable GR_COLOUR_PLAIN_LAUNCH=1 it is an ordinary
+ * launch of the same grid instead, for profilers that fault on cooperative
+ * launches (same result; on a busy device the bounded waits may then fail).
  */
 int gr_colour_greedy(const gr_graph* g, uint64_t seed, int32_t largest_degree_first,
                      int32_t* colours, int32_t* n_colours, void* ws, size_t ws_bytes,

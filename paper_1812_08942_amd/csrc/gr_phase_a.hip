@@ -622,6 +622,14 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         const long v = atol(sl);
         if (v > 0 && v < (long)kFlowSpinLimit) spin_limit = (unsigned)v;
     }
+    // GR_COLOUR_PLAIN_LAUNCH=1 launches the flow kernel as an ordinary
+    // launch of the same grid (at most the blocks the device keeps resident,
+    // so on an otherwise idle device all of them run at once; if they did
+    // not, the bounded waits would end the call with GR_EHIP, never hang).
+    // It exists for profiling: rocprofv3 faults in its own exit handlers
+    // after a cooperative launch, once its results are written.
+    const char* plain_env = getenv("GR_COLOUR_PLAIN_LAUNCH");
+    const bool plain = plain_env && plain_env[0] == '1';
     for (int exact = first; exact < 2; ++exact) {
         GR_HIP(hipMemsetAsync(small, 0, sizeof(int32_t) * 8, st));
         GR_HIP(hipMemsetAsync(small + 4, 0xff, sizeof(int32_t), st));
@@ -685,8 +693,12 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         int64_t nn = n;
         void* args[] = {(void*)&ps, (void*)&pc, (void*)&ul, (void*)&bl, (void*)&fb, (void*)&nbt,
                         (void*)&nn, (void*)&cpos, (void*)&abort_flag, (void*)&spin_limit};
-        GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads),
-                                          args, 0, st));
+        if (plain)
+            GR_HIP(hipLaunchKernel((const void*)k_jp_flow, dim3(nblk), dim3(kFlowThreads), args, 0,
+                                   st));
+        else
+            GR_HIP(hipLaunchCooperativeKernel((const void*)k_jp_flow, dim3(nblk),
+                                              dim3(kFlowThreads), args, 0, st));
         hipLaunchKernelGGL(k_flow_colours, dim3(std::min<unsigned>(nb, kGatherBlocks)),
                            dim3(kThreads), 0, st, (const int32_t*)rank, (const int32_t*)cpos, n,
                            colours, small + 4);

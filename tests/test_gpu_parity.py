@@ -163,6 +163,21 @@ def test_greedy_colouring_exact_order_path(monkeypatch):
         assert np.array_equal(c.cpu().numpy(), rc)
 
 
+def test_greedy_colouring_plain_launch(monkeypatch):
+    """GR_COLOUR_PLAIN_LAUNCH=1 (an ordinary launch of the waiting kernel, for
+    profiling runs) colours exactly as the cooperative launch does."""
+    dev = _dev()
+    G = _G()
+    monkeypatch.setenv("GR_COLOUR_PLAIN_LAUNCH", "1")
+    for name, g in colouring_graphs().items():
+        for ldf in (False, True):
+            say(f"colour (plain launch) {name} ldf={ldf}")
+            c, nc = G.gr_colour_greedy(dgraph(g, dev), 31, ldf)
+            rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 31, ldf)
+            assert nc == rnc
+            assert np.array_equal(c.cpu().numpy(), rc)
+
+
 def _clique_with_pairs(m, pairs):
     """K_m followed by `pairs` disjoint edges: the largest degree is far above
     the mean, so the colouring first runs its highest-priority positions (the
