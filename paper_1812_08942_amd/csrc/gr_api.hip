@@ -53,7 +53,11 @@ static size_t plan_bytes(int64_t n, int64_t nnz, int32_t K, int32_t dtype) {
     // colouring: sort keys and values, ranks, positions, batches, up-lists
     size_t colour = 46 * N + 4 * M + sort_scratch(N) + 8192;
     size_t agg = 24 * N + 44 * N + sort_scratch(N);
-    size_t gal = 8 * M + 4 * N + 36 * M + sort_scratch(M);
+    // per fine row: counts, positions, sort keys and values (twice);
+    // per coarse row: bounds, segments, lists, runs, counts; per kept entry
+    // (at most M/2): column, weight, run column, run sum, and for hub rows
+    // the sort and segmented sums; per run (at most M/2): the mirror sort
+    size_t gal = 64 * N + 64 * N + 24 * M + 36 * (M / 2) + 36 * (M / 2) + sort_scratch(M);
     size_t temp = relabel;
     if (colour > temp) temp = colour;
     if (agg > temp) temp = agg;

@@ -410,6 +410,49 @@ def test_galerkin_matches_oracle():
             assert_bitwise_symmetric(rp, cl, cg.w.cpu().numpy())
 
 
+def test_galerkin_segment_classes():
+    """Coarse rows of every size class of the collapse (lane groups of 16 and
+    64, a workgroup in LDS, and hub rows above 2048 kept entries through the
+    global sort, several of them at once), coarse ids without members, and
+    a run twice: the same graph as the oracle's, bitwise-symmetric weights,
+    bitwise-equal repeats."""
+    dev = _dev()
+    G = _G()
+    rng = np.random.default_rng(17)
+    graphs = {"chunglu_20000": W.chung_lu(20000, mean_deg=40.0, seed=6),
+              "grid2d_200x150": W.grid2d(200, 150, "lognormal", 8)}
+    for name, g in graphs.items():
+        n = g.n
+        maps = {}
+        # two hub aggregates (a quarter of the nodes each), the rest singletons
+        a = np.arange(n, dtype=np.int64)
+        perm = rng.permutation(n)
+        a[perm[: n // 4]] = 0
+        a[perm[n // 4: n // 2]] = 1
+        rest = perm[n // 2:]
+        a[rest] = 2 + np.arange(rest.size)
+        maps["two_hubs"] = (a, 2 + rest.size)
+        # aggregates of mixed sizes, 1 to 300 nodes, over unused ids too
+        sizes = np.minimum(rng.geometric(0.05, n), 300)
+        ids = np.repeat(np.arange(n), sizes)[:n]
+        nc = int(ids.max()) + 1
+        spread = rng.permutation(2 * nc)[:nc]          # ids with gaps
+        maps["mixed_with_gaps"] = (spread[ids][rng.permutation(n)], 2 * nc)
+        for mname, (agg, nc) in maps.items():
+            agg = agg.astype(np.int32)
+            say(f"galerkin classes {name} {mname} n_c={nc}")
+            dg = dgraph(g, dev)
+            da = torch.from_numpy(agg).to(dev)
+            c1 = G.gr_galerkin(dg, da, nc)
+            c2 = G.gr_galerkin(dg, da, nc)
+            rp, cl, w = O.galerkin(g.n, g.row_ptr, g.col, g.w.astype(np.float64), agg, nc)
+            assert np.array_equal(c1.row_ptr.cpu().numpy(), rp)
+            assert np.array_equal(c1.col.cpu().numpy(), cl)
+            assert np.allclose(c1.w.cpu().numpy(), w, rtol=1e-5, atol=0)
+            assert_bitwise_symmetric(rp, cl, c1.w.cpu().numpy())
+            assert torch.equal(c1.w.view(torch.int32), c2.w.view(torch.int32))
+
+
 def assert_bitwise_symmetric(rp, cl, w):
     """Both stored directions of every coarse edge carry the same bits."""
     n = rp.size - 1
