@@ -146,14 +146,36 @@ __device__ inline T block_exclusive_scan(T v, T* total) {
     return off + inc - v;
 }
 
+// A thread's kScanItems consecutive values: 16-byte vector loads when the
+// array is 16-byte aligned and the thread's items are all in range (each
+// lane then moves whole 16-byte chunks), else one value at a time.
+template <class T>
+__device__ inline void scan_load(const T* __restrict__ in, int64_t base, int64_t n, bool vec,
+                                 T* vals) {
+    constexpr int V = 16 / sizeof(T);
+    if (vec && base + kScanItems <= n) {
+#pragma unroll
+        for (int i = 0; i < kScanItems; i += V) {
+            const uint4 u = *reinterpret_cast<const uint4*>(in + base + i);
+            const T* t = reinterpret_cast<const T*>(&u);
+#pragma unroll
+            for (int k = 0; k < V; ++k) vals[i + k] = t[k];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) vals[i] = (base + i < n) ? in[base + i] : T(0);
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kScanThreads) k_tile_sums(const T* __restrict__ in, int64_t n,
-                                                            T* __restrict__ part) {
+                                                            T* __restrict__ part, int vec) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T vals[kScanItems];
+    scan_load<T>(in, base, n, vec != 0, vals);
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) s += in[base + i];
+    for (int i = 0; i < kScanItems; ++i) s += vals[i];
     T tot;
     block_exclusive_scan(s, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -162,21 +184,34 @@ __global__ void __launch_bounds__(kScanThreads) k_tile_sums(const T* __restrict_
 template <class T>
 __global__ void __launch_bounds__(kScanThreads) k_tile_scan(const T* __restrict__ in, T* __restrict__ out,
                                                             int64_t n, const T* __restrict__ part_off,
-                                                            T* __restrict__ total) {
+                                                            T* __restrict__ total, int vec) {
+    constexpr int V = 16 / sizeof(T);
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T vals[kScanItems];
+    scan_load<T>(in, base, n, vec != 0, vals);
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        vals[i] = (base + i < n) ? in[base + i] : T(0);
-        s += vals[i];
-    }
+    for (int i = 0; i < kScanItems; ++i) s += vals[i];
     T tot;
     T run = block_exclusive_scan(s, &tot) + (part_off ? part_off[blockIdx.x] : T(0));
+    if (vec && base + kScanItems <= n) {
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < n) out[base + i] = run;
-        run += vals[i];
+        for (int i = 0; i < kScanItems; i += V) {
+            uint4 u;
+            T* t = reinterpret_cast<T*>(&u);
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                t[k] = run;
+                run += vals[i + k];
+            }
+            *reinterpret_cast<uint4*>(out + base + i) = u;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < n) out[base + i] = run;
+            run += vals[i];
+        }
     }
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) *total = run;
 }
@@ -188,10 +223,11 @@ static int scan_exclusive(const T* in, T* out, int64_t n, T* total, Arena& ws, h
         return GR_OK;
     }
     unsigned nb = blocks_for(n, kScanTile);
+    const int vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     if (nb == 1) {
         if (ws.sizing()) return GR_OK;
         hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kScanThreads), 0, st, in, out, n,
-                           (const T*)nullptr, total);
+                           (const T*)nullptr, total, vec);
         GR_LAUNCHED("scan");
         return GR_OK;
     }
@@ -200,13 +236,13 @@ static int scan_exclusive(const T* in, T* out, int64_t n, T* total, Arena& ws, h
     T* part_off = ws.take<T>(nb);
     if (!ws.sizing() && ws.overflow) return set_error(GR_ENOMEM, "workspace too small (scan)");
     if (!ws.sizing()) {
-        hipLaunchKernelGGL(k_tile_sums<T>, dim3(nb), dim3(kScanThreads), 0, st, in, n, part);
+        hipLaunchKernelGGL(k_tile_sums<T>, dim3(nb), dim3(kScanThreads), 0, st, in, n, part, vec);
         GR_LAUNCHED("scan partials");
     }
     GR_TRY(scan_exclusive<T>(part, part_off, nb, (T*)nullptr, ws, st));
     if (!ws.sizing()) {
         hipLaunchKernelGGL(k_tile_scan<T>, dim3(nb), dim3(kScanThreads), 0, st, in, out, n,
-                           (const T*)part_off, total);
+                           (const T*)part_off, total, vec);
         GR_LAUNCHED("scan");
     }
     if (!ws.sizing()) ws.used = mark;  // scratch released (stream order keeps it valid)
