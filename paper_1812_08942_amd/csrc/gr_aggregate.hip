@@ -72,17 +72,29 @@ __global__ void k_parent(const int32_t* __restrict__ best, const int32_t* __rest
     par[v] = p;
 }
 
-// one pointer-jumping round; `changed` (when given) is raised by one lane
-// per wave that moved a pointer (a benign same-value race)
-__global__ void k_jump(const int32_t* __restrict__ pa, int64_t n, int32_t* __restrict__ pb,
-                       int32_t* __restrict__ changed) {
+// Pointer jumping in place: each node follows up to kHops parent links and
+// stores the farthest node reached.  Links that other threads shorten in the
+// meantime are read as they are: every value ever stored is an ancestor, so
+// any interleaving only moves a node closer to its root.  `changed` (when
+// given) is raised by one lane per wave that moved a pointer (a benign
+// same-value race); a launch that moves nothing leaves every node pointing
+// at a root.
+constexpr int kHops = 8;
+__global__ void k_jump(int32_t* __restrict__ pa, int64_t n, int32_t* __restrict__ changed) {
     const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
     bool ch = false;
     if (v < n) {
-        const int32_t p = pa[v];
-        const int32_t q = pa[p];
-        pb[v] = q;
-        ch = q != p;
+        const int32_t p0 = pa[v];
+        int32_t x = p0;
+        for (int h = 0; h < kHops; ++h) {
+            const int32_t y = pa[x];
+            if (y == x) break;
+            x = y;
+        }
+        if (x != p0) {
+            pa[v] = x;
+            ch = true;
+        }
     }
     if (changed && __ballot(ch) && (threadIdx.x & (kWave - 1)) == 0) *changed = 1;
 }
@@ -174,19 +186,19 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
     }
     hipLaunchKernelGGL(k_parent, dim3(gb), dim3(kT), 0, st, best, ids, acc, n, pa);
     GR_LAUNCHED("parent");
-    // pointer jumping to the roots; the depth halves each round.  Rounds go
-    // in batches of kJumpBatch with one host check: only the batch's last
-    // round reports, and a round that moves nothing means every later one
-    // moves nothing too (extra rounds on converged pointers are no-ops)
-    constexpr int kJumpBatch = 4;
+    // pointer jumping to the roots, in place, kHops links per node and
+    // launch (a launch at least multiplies the distance covered by kHops).
+    // Launches go in batches of kJumpBatch with one host check: only the
+    // batch's last launch reports, and a launch that moves nothing means
+    // every later one moves nothing too
+    constexpr int kJumpBatch = 2;
     for (int round = 0;; round += kJumpBatch) {
-        if (round > 64) return set_error(GR_EHIP, "pointer jumping did not converge");
+        if (round > 32) return set_error(GR_EHIP, "pointer jumping did not converge");
         GR_HIP(hipMemsetAsync(small, 0, sizeof(int32_t), st));
         for (int b = 0; b < kJumpBatch; ++b) {
-            hipLaunchKernelGGL(k_jump, dim3(gb), dim3(kT), 0, st, pa, n, pb,
+            hipLaunchKernelGGL(k_jump, dim3(gb), dim3(kT), 0, st, pa, n,
                                b == kJumpBatch - 1 ? small : (int32_t*)nullptr);
             GR_LAUNCHED("jump");
-            int32_t* t = pa; pa = pb; pb = t;
         }
         int32_t ch = 0;
         GR_HIP(hipMemcpyAsync(&ch, small, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -377,6 +377,25 @@ def test_aggregation_bit_exact_on_gpu_affinities():
             assert np.array_equal(agg.cpu().numpy(), r.agg), (name, T)
 
 
+def test_aggregation_long_chain_bit_exact():
+    """A path whose distances fall along it: every node's strongest neighbour
+    is the next one, so the forest is one chain of 200k nodes (the pointer
+    jumping runs several batches of launches)."""
+    dev = _dev()
+    G = _G()
+    n = 200_000
+    g = W.path(n)
+    rows = np.repeat(np.arange(n), g.degrees())
+    lo = np.minimum(rows, g.col)
+    d = (1.0 - (lo + 1.0) / (n + 1.0)).astype(np.float32)   # edge {i, i+1}: decreasing in i
+    dg = dgraph(g, dev)
+    for T in (1, n // 3, n - 10):
+        say(f"aggregate chain T={T}")
+        agg, nc = G.gr_aggregate(dg, torch.from_numpy(d).to(dev), T)
+        r = O.aggregate(g.n, g.row_ptr, g.col, d, T)
+        assert nc == r.n_coarse and np.array_equal(agg.cpu().numpy(), r.agg), T
+
+
 def test_aggregation_ties_bit_exact():
     """All-equal distances: every decision is a tie broken by index."""
     dev = _dev()
