@@ -235,13 +235,15 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
 // one), which lays every coarse row's kept entries out as one segment in
 // (fine row, entry) order.  A segment of at most kGalCap entries is then
 // sorted by (J, position in the segment) -- in registers, a lane per entry,
-// when it has at most 8, 16 or 64 entries, else in LDS -- and each run of
+// when it has at most 8, 16, 32 or 64 entries, else in LDS -- and each run of
 // equal J is summed in that order.  Longer segments (hub aggregates) go
 // through one stable radix sort by (segment, J) and tiled segmented sums.
 // The runs of every coarse row are compacted into one list ordered by
 // (I, J), and a stable sort of that list by J places the mirrored entries.
 constexpr int kGalCap = 2048;
-enum { kGalNone = 0, kGalG8 = 1, kGalG16 = 2, kGalG64 = 3, kGalLds = 4, kGalBig = 5, kGalClasses = 6 };
+enum {
+    kGalNone = 0, kGalG8, kGalG16, kGalG32, kGalG64, kGalLds, kGalBig, kGalClasses
+};
 
 // 8 lanes per fine row: the number of the row's kept entries
 __global__ void k_rap_count(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -322,8 +324,8 @@ __global__ void k_agg_segments(const int32_t* __restrict__ afirst, const int32_t
     const int32_t c = t0 >= 0 ? pos_s[aend[I]] - o : 0;
     uoff[I] = o;
     ucnt[I] = c;
-    cls[I] = c == 0 ? kGalNone : c <= 8 ? kGalG8 : c <= 16 ? kGalG16 : c <= 64 ? kGalG64
-           : c <= kGalCap ? kGalLds : kGalBig;
+    cls[I] = c == 0 ? kGalNone : c <= 8 ? kGalG8 : c <= 16 ? kGalG16 : c <= 32 ? kGalG32
+           : c <= 64 ? kGalG64 : c <= kGalCap ? kGalLds : kGalBig;
 }
 
 // The coarse rows of every class, each class in row order, the classes one
@@ -440,7 +442,7 @@ __global__ void __launch_bounds__(kT) k_place_long(const int32_t* __restrict__ r
     }
 }
 
-// G lanes per coarse row (G = 8, 16 or 64, a segment of at most G entries):
+// G lanes per coarse row (G = 8, 16, 32 or 64, a segment of at most G entries):
 // bitonic sort of (J, position) across the lanes, then each run's first
 // lane adds the run's weights in position order; the runs go to the front
 // of the segment (J to rj, sums to rw) and their number to rc.
@@ -488,7 +490,7 @@ __global__ void __launch_bounds__(kT) k_seg_sort_lanes(const int32_t* __restrict
     const int32_t Jprev = __shfl(J, gbase + (i > 0 ? i - 1 : 0), kWave);
     const bool valid = i < c;
     const bool head = valid && (i == 0 || Jprev != J);
-    // the run sums, in position order
+    // the run sums, in position order (until no run of the wave is open)
     float acc = val;
     bool open = head;
     for (int m = 1; m < G; ++m) {
@@ -497,6 +499,7 @@ __global__ void __launch_bounds__(kT) k_seg_sort_lanes(const int32_t* __restrict
         const float wm = __shfl(val, src, kWave);
         open = open && i + m < c && Jm == J;
         if (open) acc += wm;
+        if (!__ballot(open)) break;  // the same for the whole wave
     }
     const uint64_t hm = __ballot(head);
     const uint64_t gmask = (G == kWave ? ~0ull : ((1ull << G) - 1ull)) << gbase;
@@ -940,6 +943,12 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
                            dim3(kT), 0, st, cls_list(kGalG16), cls_n(kGalG16), (const int32_t*)uoff,
                            (const int32_t*)ucnt, (const int32_t*)ej, (const float*)ew, rj, rw, rc);
         GR_LAUNCHED("segments of <= 16");
+    }
+    if (cls_n(kGalG32) > 0) {
+        hipLaunchKernelGGL(k_seg_sort_lanes<32>, dim3(blocks_for((int64_t)cls_n(kGalG32) * 32, kT)),
+                           dim3(kT), 0, st, cls_list(kGalG32), cls_n(kGalG32), (const int32_t*)uoff,
+                           (const int32_t*)ucnt, (const int32_t*)ej, (const float*)ew, rj, rw, rc);
+        GR_LAUNCHED("segments of <= 32");
     }
     if (cls_n(kGalG64) > 0) {
         hipLaunchKernelGGL(k_seg_sort_lanes<64>, dim3(blocks_for((int64_t)cls_n(kGalG64) * 64, kT)),
