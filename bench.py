@@ -276,6 +276,14 @@ def eig_report(G, r, key, storage):
             "max_rel": float(np.max(err / ref)),
             "max_over_gate": float(np.max(err / gate)),
             "seed_range_rel": float(np.max((L.max(0) - L.min(0)) / ref)),
+            # against the oracle's spread over its seeds: inside the seeds'
+            # envelope widened by one range (the full-size grid's gate), and
+            # the largest deviation from the seeds' mean in their standard
+            # deviations
+            "within_seed_envelope": bool(np.all(
+                (lam >= L.min(0) - (L.max(0) - L.min(0))) &
+                (lam <= L.max(0) + (L.max(0) - L.min(0))))),
+            "max_abs_z": float(np.max(np.abs(lam - L.mean(0)) / L.std(0, ddof=1))),
             "oracle_n_coarse": rows[(storage, seed0)][0]}
         if storage == "bf16" and ("f32", seed0) in rows:
             # the storage format's cost: bfloat16 run against the FP32 oracle
