@@ -166,22 +166,47 @@ __device__ inline int degree_bits(int32_t maxdeg) {
     return maxdeg > 0 ? 32 - __clz(maxdeg) : 1;
 }
 
-// Sort keys whose ascending order is decreasing priority.  mode 0: h(v)
-// alone (a bijection of v, so no ties); mode 1 (largest degree first): the
-// degree in the top bd bits, the top 64 - bd bits of h(v) below it (ties of
-// the truncated key are detected after the sort).
+// Sort keys whose ascending order is decreasing priority.  mode 0: the top
+// hb bits of h(v), complemented, in the low bits of the key (h is a
+// bijection of v, so nodes tie only on the truncated key; k_order_ties puts
+// each run of equal keys in decreasing h after the sort); mode 1 (largest
+// degree first): the degree in the top bd bits, the top 64 - bd bits of h(v)
+// below it (ties of the truncated key are detected after the sort).
 __global__ void k_prio_keys(const int32_t* __restrict__ rp, int64_t n, uint64_t seed, int mode,
-                            const int32_t* __restrict__ maxdeg, uint64_t* __restrict__ keys,
-                            uint32_t* __restrict__ vals) {
+                            int hb, const int32_t* __restrict__ maxdeg,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     uint64_t k = splitmix64(seed, (uint64_t)v);
     if (mode) {
         const int bd = degree_bits(*maxdeg);
         k = ((uint64_t)(rp[v + 1] - rp[v]) << (64 - bd)) | (k >> bd);
+        keys[v] = ~k;
+    } else {
+        keys[v] = ~(k >> (64 - hb)) & ((1ull << hb) - 1ull);
     }
-    keys[v] = ~k;
     vals[v] = (uint32_t)v;
+}
+
+// mode 0 after the sort: every run of equal truncated keys (a thread at the
+// head of each run) in decreasing full h(v), by insertion sort (runs are
+// short: a few nodes share the top 32 bits of h in millions)
+__global__ void k_order_ties(const uint64_t* __restrict__ keys, uint32_t* __restrict__ order,
+                             int64_t n, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + 1 >= n || keys[i] != keys[i + 1] || (i > 0 && keys[i - 1] == keys[i])) return;
+    int64_t j = i + 2;
+    while (j < n && keys[j] == keys[i]) ++j;
+    for (int64_t a = i + 1; a < j; ++a) {
+        const uint32_t v = order[a];
+        const uint64_t hv = splitmix64(seed, v);
+        int64_t b = a - 1;
+        while (b >= i && splitmix64(seed, order[b]) < hv) {
+            order[b + 1] = order[b];
+            --b;
+        }
+        order[b + 1] = v;
+    }
 }
 
 // second key of the exact largest-degree-first order: decreasing degree
@@ -628,6 +653,14 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     // not, the bounded waits would end the call with GR_EHIP, never hang).
     // It exists for profiling: rocprofv3 faults in its own exit handlers
     // after a cooperative launch, once its results are written.
+    // bits of h in the sort key of the plain priority order (32; the
+    // variable GR_COLOUR_KEY_BITS=b, 8 <= b <= 32, makes ties of the
+    // truncated keys frequent, for tests of their exact order)
+    int hbits = 32;
+    if (const char* kb_env = getenv("GR_COLOUR_KEY_BITS")) {
+        const int b = atoi(kb_env);
+        if (b >= 8 && b <= 32) hbits = b;
+    }
     const char* plain_env = getenv("GR_COLOUR_PLAIN_LAUNCH");
     const bool plain = plain_env && plain_env[0] == '1';
     for (int exact = first; exact < 2; ++exact) {
@@ -636,10 +669,16 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         hipLaunchKernelGGL(k_max_degree, dim3(256), dim3(kThreads), 0, st, g->row_ptr, n, small);
         GR_LAUNCHED("colour max degree");
         // the priority order
-        hipLaunchKernelGGL(k_prio_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, n, seed,
-                           (ldf && !exact) ? 1 : 0, (const int32_t*)small, ka, va);
+        const int mode = (ldf && !exact) ? 1 : 0;
+        hipLaunchKernelGGL(k_prio_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, n, seed, mode,
+                           hbits, (const int32_t*)small, ka, va);
         GR_LAUNCHED("colour keys");
-        GR_TRY(radix_sort_pairs(ka, va, kb, order, n, 64, ws, st));
+        GR_TRY(radix_sort_pairs(ka, va, kb, order, n, mode ? 64 : hbits, ws, st));
+        if (!mode) {
+            hipLaunchKernelGGL(k_order_ties, dim3(nb), dim3(kThreads), 0, st, (const uint64_t*)kb,
+                               order, n, seed);
+            GR_LAUNCHED("colour key ties (exact order)");
+        }
         if (ldf && !exact) {
             hipLaunchKernelGGL(k_adjacent_ties, dim3(nb), dim3(kThreads), 0, st, (const uint64_t*)kb,
                                n, small + 1);
