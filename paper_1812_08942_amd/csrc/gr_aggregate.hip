@@ -284,11 +284,11 @@ __global__ void __launch_bounds__(kT) k_rap_count_long(const int32_t* __restrict
 }
 
 // sort keys of the fine rows: their aggregate
-__global__ void k_agg_keys(const int32_t* __restrict__ agg, int64_t n, uint64_t* __restrict__ key,
+__global__ void k_agg_keys(const int32_t* __restrict__ agg, int64_t n, uint32_t* __restrict__ key,
                            uint32_t* __restrict__ val) {
     const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (v >= n) return;
-    key[v] = (uint64_t)(uint32_t)agg[v];
+    key[v] = (uint32_t)agg[v];
     val[v] = (uint32_t)v;
 }
 
@@ -304,7 +304,7 @@ __global__ void k_sorted_counts(const uint32_t* __restrict__ rows, const int32_t
 
 // each coarse row's first and one-past-last sorted fine row (-1 for a coarse
 // row without members, which a map given from outside may have)
-__global__ void k_agg_bounds(const uint64_t* __restrict__ skey, int64_t n,
+__global__ void k_agg_bounds(const uint32_t* __restrict__ skey, int64_t n,
                              int32_t* __restrict__ afirst, int32_t* __restrict__ aend) {
     const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (t >= n) return;
@@ -713,11 +713,12 @@ __global__ void k_big_runs(const uint64_t* __restrict__ keys, const int32_t* __r
 
 // first and one-past-last position of every row in a key array sorted by
 // row (row = key >> shift)
-__global__ void k_row_bounds(const uint64_t* __restrict__ keys, int64_t cnt, int shift,
+template <class KT>
+__global__ void k_row_bounds(const KT* __restrict__ keys, int64_t cnt, int shift,
                              int32_t* __restrict__ rfirst, int32_t* __restrict__ rend) {
     int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (r >= cnt) return;
-    uint64_t I = keys[r] >> shift;
+    const KT I = keys[r] >> shift;
     if (r == 0 || (keys[r - 1] >> shift) != I) rfirst[I] = (int32_t)r;
     if (r == cnt - 1 || (keys[r + 1] >> shift) != I) rend[I] = (int32_t)(r + 1);
 }
@@ -737,7 +738,7 @@ __global__ void k_compact_runs(const int32_t* __restrict__ uoff, const int32_t* 
                                const int32_t* __restrict__ roff, int64_t n_c, int jbits,
                                const int32_t* __restrict__ rj, const float* __restrict__ rw,
                                uint64_t* __restrict__ ukey, float* __restrict__ uw,
-                               uint64_t* __restrict__ mkey, uint32_t* __restrict__ midx) {
+                               uint32_t* __restrict__ mkey, uint32_t* __restrict__ midx) {
     const int64_t I = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
     const int l = threadIdx.x & 7;
     if (I >= n_c || ucnt[I] > 64) return;  // longer rows: k_compact_long
@@ -747,7 +748,7 @@ __global__ void k_compact_runs(const int32_t* __restrict__ uoff, const int32_t* 
         const int32_t J = rj[o + k];
         ukey[d + k] = ((uint64_t)I << jbits) | (uint64_t)(uint32_t)J;
         uw[d + k] = rw[o + k];
-        mkey[d + k] = (uint64_t)(uint32_t)J;
+        mkey[d + k] = (uint32_t)J;
         midx[d + k] = (uint32_t)(d + k);
     }
 }
@@ -759,7 +760,7 @@ __global__ void k_compact_long(const int32_t* __restrict__ hlist, int32_t nh,
                                const int32_t* __restrict__ uoff, const int32_t* __restrict__ roff,
                                int jbits, const int32_t* __restrict__ rj,
                                const float* __restrict__ rw, uint64_t* __restrict__ ukey,
-                               float* __restrict__ uw, uint64_t* __restrict__ mkey,
+                               float* __restrict__ uw, uint32_t* __restrict__ mkey,
                                uint32_t* __restrict__ midx) {
     const int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (t >= hr) return;
@@ -770,7 +771,7 @@ __global__ void k_compact_long(const int32_t* __restrict__ hlist, int32_t nh,
     const int32_t J = rj[uoff[I] + k];
     ukey[d] = ((uint64_t)I << jbits) | (uint64_t)(uint32_t)J;
     uw[d] = rw[uoff[I] + k];
-    mkey[d] = (uint64_t)(uint32_t)J;
+    mkey[d] = (uint32_t)J;
     midx[d] = (uint32_t)d;
 }
 
@@ -782,17 +783,17 @@ __global__ void k_long_runs(const int32_t* __restrict__ hlist, int32_t nh,
 
 // coarse row I = [lower part: mirrored entries (I, J < I)] ++ [upper part:
 // summed runs (I, J > I)]; both parts already ascending in J
-__global__ void k_row_counts(const int32_t* __restrict__ ufirst, const int32_t* __restrict__ uend,
-                             const int32_t* __restrict__ lfirst, const int32_t* __restrict__ lend,
-                             int64_t n_c, int32_t* __restrict__ cnt) {
+__global__ void k_row_counts(const int32_t* __restrict__ rc, const int32_t* __restrict__ lfirst,
+                             const int32_t* __restrict__ lend, int64_t n_c,
+                             int32_t* __restrict__ cnt) {
     int64_t I = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (I >= n_c) return;
-    cnt[I] = (ufirst[I] >= 0 ? uend[I] - ufirst[I] : 0) + (lfirst[I] >= 0 ? lend[I] - lfirst[I] : 0);
+    cnt[I] = rc[I] + (lfirst[I] >= 0 ? lend[I] - lfirst[I] : 0);
 }
 
 __global__ void k_place_upper(const uint64_t* __restrict__ ukey, const float* __restrict__ uw,
                               int64_t runs, int jbits, const int32_t* __restrict__ c_row_ptr,
-                              const int32_t* __restrict__ ufirst, const int32_t* __restrict__ lfirst,
+                              const int32_t* __restrict__ roff, const int32_t* __restrict__ lfirst,
                               const int32_t* __restrict__ lend, int32_t* __restrict__ c_col,
                               float* __restrict__ c_w) {
     int64_t r = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -800,12 +801,12 @@ __global__ void k_place_upper(const uint64_t* __restrict__ ukey, const float* __
     const uint64_t k = ukey[r];
     const int64_t I = (int64_t)(k >> jbits);
     const int32_t nlow = lfirst[I] >= 0 ? lend[I] - lfirst[I] : 0;
-    const int64_t p = (int64_t)c_row_ptr[I] + nlow + (r - ufirst[I]);
+    const int64_t p = (int64_t)c_row_ptr[I] + nlow + (r - roff[I]);
     c_col[p] = (int32_t)(k & ((1ull << jbits) - 1));
     c_w[p] = uw[r];
 }
 
-__global__ void k_place_lower(const uint64_t* __restrict__ mkey, const uint32_t* __restrict__ midx,
+__global__ void k_place_lower(const uint32_t* __restrict__ mkey, const uint32_t* __restrict__ midx,
                               const uint64_t* __restrict__ ukey, const float* __restrict__ uw,
                               int64_t runs, int jbits, const int32_t* __restrict__ c_row_ptr,
                               const int32_t* __restrict__ lfirst, int32_t* __restrict__ c_col,
@@ -830,9 +831,9 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     int32_t* cnt_s = ws.take<int32_t>(n + 1);
     int32_t* pos_s = ws.take<int32_t>(n + 1);
     int32_t* tpos = ws.take<int32_t>(n + 1);
-    uint64_t* akey = ws.take<uint64_t>(n);
+    uint32_t* akey = ws.take<uint32_t>(n);
     uint32_t* aval = ws.take<uint32_t>(n);
-    uint64_t* skey = ws.take<uint64_t>(n);
+    uint32_t* skey = ws.take<uint32_t>(n);
     uint32_t* rows = ws.take<uint32_t>(n);
     int32_t* small = ws.take<int32_t>(16);
     int32_t* afirst = ws.take<int32_t>(n_c + 1);
@@ -843,8 +844,6 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     int32_t* roff = ws.take<int32_t>(n_c + 1);
     int32_t* lists = ws.take<int32_t>(n_c + 1);
     int32_t* row_cnt = ws.take<int32_t>(n_c + 1);
-    int32_t* ufirst = ws.take<int32_t>(n_c + 1);
-    int32_t* uend = ws.take<int32_t>(n_c + 1);
     int32_t* lfirst = ws.take<int32_t>(n_c + 1);
     int32_t* lend = ws.take<int32_t>(n_c + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin)");
@@ -865,14 +864,14 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     }
     hipLaunchKernelGGL(k_agg_keys, dim3(nb), dim3(kT), 0, st, agg, n, akey, aval);
     GR_LAUNCHED("aggregate keys");
-    GR_TRY(radix_sort_pairs(akey, aval, skey, rows, n, bits_for(n_c), ws, st));
+    GR_TRY(radix_sort_pairs32(akey, aval, skey, rows, n, bits_for(n_c), ws, st));
     hipLaunchKernelGGL(k_sorted_counts, dim3(nb), dim3(kT), 0, st, (const uint32_t*)rows,
                        (const int32_t*)rcnt, n, cnt_s, tpos);
     GR_LAUNCHED("sorted counts");
     GR_TRY(scan_exclusive_i32(cnt_s, pos_s, n, pos_s + n, ws, st));
     GR_TRY(fill_i32(small, 0, 16, st));
     GR_TRY(fill_i32(afirst, -1, n_c, st));
-    hipLaunchKernelGGL(k_agg_bounds, dim3(nb), dim3(kT), 0, st, (const uint64_t*)skey, n, afirst,
+    hipLaunchKernelGGL(k_agg_bounds, dim3(nb), dim3(kT), 0, st, (const uint32_t*)skey, n, afirst,
                        aend);
     GR_LAUNCHED("aggregate row bounds");
     // the class of every coarse row (rc holds it until the runs are counted)
@@ -904,8 +903,6 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     int32_t m = 0;
     GR_HIP(hipMemcpyAsync(&m, pos_s + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GR_HIP(hipStreamSynchronize(st));
-    GR_TRY(fill_i32(ufirst, -1, n_c + 1, st));
-    GR_TRY(fill_i32(uend, -1, n_c + 1, st));
     GR_TRY(fill_i32(lfirst, -1, n_c + 1, st));
     GR_TRY(fill_i32(lend, -1, n_c + 1, st));
     if (m == 0) {
@@ -1015,7 +1012,7 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         GR_LAUNCHED("run keys");
         GR_TRY(fill_i32(bfirst, -1, nbig, st));
         GR_TRY(fill_i32(bend, -1, nbig, st));
-        hipLaunchKernelGGL(k_row_bounds, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
+        hipLaunchKernelGGL(k_row_bounds<uint64_t>, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
                            (const uint64_t*)rkey, (int64_t)bruns, jbits, bfirst, bend);
         GR_LAUNCHED("long segment run bounds");
         hipLaunchKernelGGL(k_big_runs, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
@@ -1035,9 +1032,9 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     GR_HIP(hipStreamSynchronize(st));
     uint64_t* ukey = ws.take<uint64_t>(runs);
     float* uw = ws.take<float>(runs);
-    uint64_t* mk0 = ws.take<uint64_t>(runs);
+    uint32_t* mk0 = ws.take<uint32_t>(runs);
     uint32_t* mi0 = ws.take<uint32_t>(runs);
-    uint64_t* mk1 = ws.take<uint64_t>(runs);
+    uint32_t* mk1 = ws.take<uint32_t>(runs);
     uint32_t* mi1 = ws.take<uint32_t>(runs);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin mirror)");
     hipLaunchKernelGGL(k_compact_runs, dim3(blocks_for(n_c * 8, kT)), dim3(kT), 0, st,
@@ -1067,25 +1064,23 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         }
         ws.used = mk;
     }
-    GR_TRY(radix_sort_pairs(mk0, mi0, mk1, mi1, runs, jbits, ws, st));
+    GR_TRY(radix_sort_pairs32(mk0, mi0, mk1, mi1, runs, jbits, ws, st));
     const unsigned nbr = blocks_for(runs, kT);
-    hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, (const uint64_t*)ukey, (int64_t)runs,
-                       jbits, ufirst, uend);
-    GR_LAUNCHED("upper row bounds");
-    hipLaunchKernelGGL(k_row_bounds, dim3(nbr), dim3(kT), 0, st, (const uint64_t*)mk1, (int64_t)runs, 0,
-                       lfirst, lend);
+    // row I's runs sit at [roff[I], roff[I] + rc[I]) of the upper list
+    hipLaunchKernelGGL(k_row_bounds<uint32_t>, dim3(nbr), dim3(kT), 0, st, (const uint32_t*)mk1,
+                       (int64_t)runs, 0, lfirst, lend);
     GR_LAUNCHED("lower row bounds");
     hipLaunchKernelGGL(k_row_counts, dim3(blocks_for(n_c, kT)), dim3(kT), 0, st,
-                       (const int32_t*)ufirst, (const int32_t*)uend, (const int32_t*)lfirst,
-                       (const int32_t*)lend, n_c, row_cnt);
+                       (const int32_t*)rc, (const int32_t*)lfirst, (const int32_t*)lend, n_c,
+                       row_cnt);
     GR_LAUNCHED("row counts");
     GR_TRY(scan_exclusive_i32(row_cnt, c_row_ptr, n_c, c_row_ptr + n_c, ws, st));
     hipLaunchKernelGGL(k_place_upper, dim3(nbr), dim3(kT), 0, st, (const uint64_t*)ukey,
                        (const float*)uw, (int64_t)runs, jbits, (const int32_t*)c_row_ptr,
-                       (const int32_t*)ufirst, (const int32_t*)lfirst, (const int32_t*)lend, c_col,
+                       (const int32_t*)roff, (const int32_t*)lfirst, (const int32_t*)lend, c_col,
                        c_w);
     GR_LAUNCHED("place upper");
-    hipLaunchKernelGGL(k_place_lower, dim3(nbr), dim3(kT), 0, st, (const uint64_t*)mk1,
+    hipLaunchKernelGGL(k_place_lower, dim3(nbr), dim3(kT), 0, st, (const uint32_t*)mk1,
                        (const uint32_t*)mi1, (const uint64_t*)ukey, (const float*)uw, (int64_t)runs,
                        jbits, (const int32_t*)c_row_ptr, (const int32_t*)lfirst, c_col, c_w);
     GR_LAUNCHED("place lower");

@@ -103,6 +103,9 @@ int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tota
 // Results land in keys_out/vals_out; the inputs are used as scratch.
 int radix_sort_pairs(uint64_t* keys_in, uint32_t* vals_in, uint64_t* keys_out,
                      uint32_t* vals_out, int64_t n, int bits, Arena& ws, hipStream_t st);
+// The same for keys of at most 32 bits.
+int radix_sort_pairs32(uint32_t* keys_in, uint32_t* vals_in, uint32_t* keys_out,
+                       uint32_t* vals_out, int64_t n, int bits, Arena& ws, hipStream_t st);
 
 // Deterministic FP64 sum of n values into *out (device).
 int sum_f64(const double* in, int64_t n, double* out, Arena& ws, hipStream_t st);

@@ -174,7 +174,8 @@ __device__ inline int degree_bits(int32_t maxdeg) {
 // below it (ties of the truncated key are detected after the sort).
 __global__ void k_prio_keys(const int32_t* __restrict__ rp, int64_t n, uint64_t seed, int mode,
                             int hb, const int32_t* __restrict__ maxdeg,
-                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ keys32,
+                            uint32_t* __restrict__ vals) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     uint64_t k = splitmix64(seed, (uint64_t)v);
@@ -183,7 +184,7 @@ __global__ void k_prio_keys(const int32_t* __restrict__ rp, int64_t n, uint64_t 
         k = ((uint64_t)(rp[v + 1] - rp[v]) << (64 - bd)) | (k >> bd);
         keys[v] = ~k;
     } else {
-        keys[v] = ~(k >> (64 - hb)) & ((1ull << hb) - 1ull);
+        keys32[v] = (uint32_t)(~(k >> (64 - hb)) & ((1ull << hb) - 1ull));
     }
     vals[v] = (uint32_t)v;
 }
@@ -191,7 +192,7 @@ __global__ void k_prio_keys(const int32_t* __restrict__ rp, int64_t n, uint64_t 
 // mode 0 after the sort: every run of equal truncated keys (a thread at the
 // head of each run) in decreasing full h(v), by insertion sort (runs are
 // short: a few nodes share the top 32 bits of h in millions)
-__global__ void k_order_ties(const uint64_t* __restrict__ keys, uint32_t* __restrict__ order,
+__global__ void k_order_ties(const uint32_t* __restrict__ keys, uint32_t* __restrict__ order,
                              int64_t n, uint64_t seed) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i + 1 >= n || keys[i] != keys[i + 1] || (i > 0 && keys[i - 1] == keys[i])) return;
@@ -670,12 +671,16 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         GR_LAUNCHED("colour max degree");
         // the priority order
         const int mode = (ldf && !exact) ? 1 : 0;
+        // (the plain order's keys are 32-bit, in the same buffers)
+        uint32_t* ka32 = reinterpret_cast<uint32_t*>(ka);
+        uint32_t* kb32 = reinterpret_cast<uint32_t*>(kb);
         hipLaunchKernelGGL(k_prio_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, n, seed, mode,
-                           hbits, (const int32_t*)small, ka, va);
+                           hbits, (const int32_t*)small, ka, ka32, va);
         GR_LAUNCHED("colour keys");
-        GR_TRY(radix_sort_pairs(ka, va, kb, order, n, mode ? 64 : hbits, ws, st));
+        if (mode) GR_TRY(radix_sort_pairs(ka, va, kb, order, n, 64, ws, st));
+        else GR_TRY(radix_sort_pairs32(ka32, va, kb32, order, n, hbits, ws, st));
         if (!mode) {
-            hipLaunchKernelGGL(k_order_ties, dim3(nb), dim3(kThreads), 0, st, (const uint64_t*)kb,
+            hipLaunchKernelGGL(k_order_ties, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)kb32,
                                order, n, seed);
             GR_LAUNCHED("colour key ties (exact order)");
         }
@@ -804,21 +809,21 @@ int validate_colouring(const gr_graph* g, const int32_t* colours, int32_t n_colo
 // one colour become a contiguous range, in decreasing degree tiers, so that
 // one smoothing launch can give every tier its own lanes-per-row.
 __global__ void k_bucket_keys(const int32_t* __restrict__ rp, const int32_t* __restrict__ colours,
-                              int64_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                              int64_t n, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int32_t deg = rp[v + 1] - rp[v];
-    uint64_t b = (uint64_t)colours[v] * kNT + (uint64_t)degree_tier(deg);
+    uint32_t b = (uint32_t)colours[v] * kNT + (uint32_t)degree_tier(deg);
     keys[v] = b;
     vals[v] = (uint32_t)v;
 }
 
 // first and one-past-last row of every bucket present in the sorted keys
-__global__ void k_bucket_bounds(const uint64_t* __restrict__ keys, int64_t n,
+__global__ void k_bucket_bounds(const uint32_t* __restrict__ keys, int64_t n,
                                 int32_t* __restrict__ bfirst, int32_t* __restrict__ bend) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint64_t k = keys[i];
+    const uint32_t k = keys[i];
     if (i == 0 || keys[i - 1] != k) bfirst[k] = (int32_t)i;
     if (i == n - 1 || keys[i + 1] != k) bend[k] = (int32_t)(i + 1);
 }
@@ -899,9 +904,9 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (relabel)");
     size_t mark = ws.used;
     const int32_t nb = kNT * n_colours;
-    uint64_t* k0 = ws.take<uint64_t>(n);
+    uint32_t* k0 = ws.take<uint32_t>(n);
     uint32_t* v0 = ws.take<uint32_t>(n);
-    uint64_t* k1 = ws.take<uint64_t>(n);
+    uint32_t* k1 = ws.take<uint32_t>(n);
     int32_t* bfirst = ws.take<int32_t>(nb + 1);
     int32_t* bend = ws.take<int32_t>(nb + 1);
     int64_t* sizes = ws.take<int64_t>(2 * (int64_t)nb + 2);
@@ -914,10 +919,10 @@ int order_by_colour(const gr_graph* g, const int32_t* colours, int32_t n_colours
                            g->row_ptr, colours, n, k0, v0);
         GR_LAUNCHED("bucket keys");
     }
-    GR_TRY(radix_sort_pairs(k0, v0, k1, (uint32_t*)og->perm, n, bits_for(nb), ws, st));
+    GR_TRY(radix_sort_pairs32(k0, v0, k1, (uint32_t*)og->perm, n, bits_for(nb), ws, st));
     if (n > 0) {
         hipLaunchKernelGGL(k_bucket_bounds, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st,
-                           (const uint64_t*)k1, n, bfirst, bend);
+                           (const uint32_t*)k1, n, bfirst, bend);
         GR_LAUNCHED("bucket bounds");
         hipLaunchKernelGGL(k_perm_degrees, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st,
                            g->row_ptr, (const uint32_t*)og->perm, n, og->iperm, deg);
