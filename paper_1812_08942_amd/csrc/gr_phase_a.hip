@@ -166,32 +166,33 @@ __device__ inline int degree_bits(int32_t maxdeg) {
     return maxdeg > 0 ? 32 - __clz(maxdeg) : 1;
 }
 
-// Sort keys whose ascending order is decreasing priority.  mode 0: the top
-// hb bits of h(v), complemented, in the low bits of the key (h is a
-// bijection of v, so nodes tie only on the truncated key; k_order_ties puts
-// each run of equal keys in decreasing h after the sort); mode 1 (largest
-// degree first): the degree in the top bd bits, the top 64 - bd bits of h(v)
-// below it (ties of the truncated key are detected after the sort).
+// 32-bit sort keys whose ascending order is decreasing priority.  mode 0:
+// the top hb bits of h(v), complemented; mode 1 (largest degree first): the
+// degree above the top hl = max(hb - bd, 1) bits of h(v), bd the degree's
+// bit width, complemented.  h is a bijection of v, so nodes tie only on the
+// truncated h, and only with nodes of their own degree: k_order_ties puts
+// each run of equal keys in decreasing full h after the sort.
 __global__ void k_prio_keys(const int32_t* __restrict__ rp, int64_t n, uint64_t seed, int mode,
                             int hb, const int32_t* __restrict__ maxdeg,
-                            uint64_t* __restrict__ keys, uint32_t* __restrict__ keys32,
-                            uint32_t* __restrict__ vals) {
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    uint64_t k = splitmix64(seed, (uint64_t)v);
+    const uint64_t h = splitmix64(seed, (uint64_t)v);
+    uint64_t k;
     if (mode) {
         const int bd = degree_bits(*maxdeg);
-        k = ((uint64_t)(rp[v + 1] - rp[v]) << (64 - bd)) | (k >> bd);
-        keys[v] = ~k;
+        const int hl = hb - bd > 1 ? hb - bd : 1;
+        k = ((uint64_t)(rp[v + 1] - rp[v]) << hl) | (h >> (64 - hl));
     } else {
-        keys32[v] = (uint32_t)(~(k >> (64 - hb)) & ((1ull << hb) - 1ull));
+        k = h >> (64 - hb);
     }
+    keys[v] = ~(uint32_t)k;
     vals[v] = (uint32_t)v;
 }
 
-// mode 0 after the sort: every run of equal truncated keys (a thread at the
-// head of each run) in decreasing full h(v), by insertion sort (runs are
-// short: a few nodes share the top 32 bits of h in millions)
+// after the sort: every run of equal truncated keys (a thread at the head of
+// each run) in decreasing full h(v), by insertion sort (runs are short: a
+// few nodes of one degree share the top bits of h)
 __global__ void k_order_ties(const uint32_t* __restrict__ keys, uint32_t* __restrict__ order,
                              int64_t n, uint64_t seed) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -218,11 +219,6 @@ __global__ void k_degree_keys(const int32_t* __restrict__ rp, const uint32_t* __
     if (i >= n) return;
     const uint32_t v = order[i];
     keys[i] = ~(uint64_t)(uint32_t)(rp[v + 1] - rp[v]);
-}
-
-__global__ void k_adjacent_ties(const uint64_t* __restrict__ keys, int64_t n, int32_t* flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i + 1 < n && keys[i] == keys[i + 1]) atomicOr(flag, 1);
 }
 
 __global__ void k_rank_of(const uint32_t* __restrict__ order, int64_t n, int32_t* __restrict__ rank) {
@@ -630,17 +626,18 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     const int64_t ngroups = (n + kFlowBatch - 1) / kFlowBatch;
     int32_t* nbat = ws.take<int32_t>(ngroups);
     int32_t* boff = ws.take<int32_t>(ngroups);
-    // [0] largest degree, [1] tie flag, [2] wide count, [3] abort flag,
+    // [0] largest degree, [1] unused, [2] wide count, [3] abort flag,
     // [4] largest colour, [5] batches, [6] first batch of the device-wide flow
     int32_t* small = ws.take<int32_t>(8);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
     const int nblk = flow_blocks(n);
     if (nblk < 0) return nblk;
     const unsigned nb = blocks_for(n, kThreads);
-    // GR_COLOUR_EXACT_ORDER=1 takes the exact two-key order from the start
-    // (the path that ties of truncated keys take; tests use it)
+    // GR_COLOUR_EXACT_ORDER=1 builds the largest-degree-first order in two
+    // sorts instead (by h, then stably by degree): a second route to the
+    // same order, which tests compare with the oracle
     const char* force = getenv("GR_COLOUR_EXACT_ORDER");
-    const int first = (ldf && force && force[0] == '1') ? 1 : 0;
+    const int exact = (ldf && force && force[0] == '1') ? 1 : 0;
     // GR_COLOUR_SPIN_LIMIT=k shortens every wait to k polls (tests of the
     // timed-out path: every wave then leaves early and the call fails)
     unsigned spin_limit = kFlowSpinLimit;
@@ -654,9 +651,9 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     // not, the bounded waits would end the call with GR_EHIP, never hang).
     // It exists for profiling: rocprofv3 faults in its own exit handlers
     // after a cooperative launch, once its results are written.
-    // bits of h in the sort key of the plain priority order (32; the
-    // variable GR_COLOUR_KEY_BITS=b, 8 <= b <= 32, makes ties of the
-    // truncated keys frequent, for tests of their exact order)
+    // width of the priority sort key (32; the variable GR_COLOUR_KEY_BITS=b,
+    // 8 <= b <= 32, keeps fewer bits of h, which makes ties of the truncated
+    // keys frequent, for tests of their exact order)
     int hbits = 32;
     if (const char* kb_env = getenv("GR_COLOUR_KEY_BITS")) {
         const int b = atoi(kb_env);
@@ -664,31 +661,24 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     }
     const char* plain_env = getenv("GR_COLOUR_PLAIN_LAUNCH");
     const bool plain = plain_env && plain_env[0] == '1';
-    for (int exact = first; exact < 2; ++exact) {
+    {
         GR_HIP(hipMemsetAsync(small, 0, sizeof(int32_t) * 8, st));
         GR_HIP(hipMemsetAsync(small + 4, 0xff, sizeof(int32_t), st));
         hipLaunchKernelGGL(k_max_degree, dim3(256), dim3(kThreads), 0, st, g->row_ptr, n, small);
         GR_LAUNCHED("colour max degree");
         // the priority order
         const int mode = (ldf && !exact) ? 1 : 0;
-        // (the plain order's keys are 32-bit, in the same buffers)
+        // (the 32-bit keys share the buffers of the 64-bit ones)
         uint32_t* ka32 = reinterpret_cast<uint32_t*>(ka);
         uint32_t* kb32 = reinterpret_cast<uint32_t*>(kb);
         hipLaunchKernelGGL(k_prio_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr, n, seed, mode,
-                           hbits, (const int32_t*)small, ka, ka32, va);
+                           hbits, (const int32_t*)small, ka32, va);
         GR_LAUNCHED("colour keys");
-        if (mode) GR_TRY(radix_sort_pairs(ka, va, kb, order, n, 64, ws, st));
-        else GR_TRY(radix_sort_pairs32(ka32, va, kb32, order, n, hbits, ws, st));
-        if (!mode) {
-            hipLaunchKernelGGL(k_order_ties, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)kb32,
-                               order, n, seed);
-            GR_LAUNCHED("colour key ties (exact order)");
-        }
-        if (ldf && !exact) {
-            hipLaunchKernelGGL(k_adjacent_ties, dim3(nb), dim3(kThreads), 0, st, (const uint64_t*)kb,
-                               n, small + 1);
-            GR_LAUNCHED("colour key ties");
-        } else if (ldf) {
+        GR_TRY(radix_sort_pairs32(ka32, va, kb32, order, n, mode ? 32 : hbits, ws, st));
+        hipLaunchKernelGGL(k_order_ties, dim3(nb), dim3(kThreads), 0, st, (const uint32_t*)kb32, order,
+                           n, seed);
+        GR_LAUNCHED("colour key ties (exact order)");
+        if (ldf && exact) {
             hipLaunchKernelGGL(k_degree_keys, dim3(nb), dim3(kThreads), 0, st, g->row_ptr,
                                (const uint32_t*)order, n, ka);
             GR_LAUNCHED("colour degree keys");
@@ -751,10 +741,8 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
         GR_HIP(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
         if (hs[3]) return set_error(GR_EHIP, "colouring wait timed out");
-        if (ldf && !exact && hs[1]) continue;  // truncated keys tied: again with the exact order
         if (hs[4] < 0) return set_error(GR_EHIP, "colouring left nodes uncoloured");
         *n_colours_host = hs[4] + 1;
-        break;
     }
     ws.used = mark;
     return GR_OK;

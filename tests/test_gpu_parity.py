@@ -163,19 +163,20 @@ def test_greedy_colouring_exact_order_path(monkeypatch):
         assert np.array_equal(c.cpu().numpy(), rc)
 
 
-@pytest.mark.parametrize("bits", [8, 13, 20])
-def test_greedy_colouring_truncated_key_ties(bits, monkeypatch):
-    """The plain priority order sorts a truncated h(v) and then puts each run
-    of equal keys in exact order; with the key cut to `bits` bits (runs of
-    tens of nodes at 8 bits) the colouring is still the oracle's, bit for
-    bit."""
+@pytest.mark.parametrize("ldf,bits", [(False, 8), (False, 13), (False, 20), (True, 13),
+                                      (True, 20)])
+def test_greedy_colouring_truncated_key_ties(ldf, bits, monkeypatch):
+    """The priority orders sort a 32-bit key holding the degree (largest
+    degree first) and the top bits of h(v), then put each run of equal keys
+    in exact order; with the key cut to `bits` bits (runs of tens to
+    hundreds of nodes) the colouring is still the oracle's, bit for bit."""
     dev = _dev()
     G = _G()
     monkeypatch.setenv("GR_COLOUR_KEY_BITS", str(bits))
     for name, g in colouring_graphs().items():
-        say(f"colour (key of {bits} bits) {name}")
-        c, nc = G.gr_colour_greedy(dgraph(g, dev), 2024, False)
-        rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 2024, False)
+        say(f"colour (key of {bits} bits) {name} ldf={ldf}")
+        c, nc = G.gr_colour_greedy(dgraph(g, dev), 2024, ldf)
+        rc, rnc = O.colour_greedy(g.n, g.row_ptr, g.col, 2024, ldf)
         assert nc == rnc
         assert np.array_equal(c.cpu().numpy(), rc)
 
