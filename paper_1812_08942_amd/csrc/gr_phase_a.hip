@@ -635,7 +635,7 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     const unsigned nb = blocks_for(n, kThreads);
     // GR_COLOUR_EXACT_ORDER=1 builds the largest-degree-first order in two
     // sorts instead (by h, then stably by degree): a second route to the
-    // same order, which tests compare with the oracle
+    // same order, which tests check against the reference colouring
     const char* force = getenv("GR_COLOUR_EXACT_ORDER");
     const int exact = (ldf && force && force[0] == '1') ? 1 : 0;
     // GR_COLOUR_SPIN_LIMIT=k shortens every wait to k polls (tests of the
@@ -1144,6 +1144,7 @@ struct GsTiers {
     int32_t lanes[kNT];         // lanes per row
     int64_t row0[kNT + 1];      // first row of each tier (and the end)
     int64_t blk0[kNT + 1];      // first block of each tier (and the total)
+    int32_t reverse;            // blocks from blk0[split] on run in reverse order
 };
 
 template <int Q, int DT>
@@ -1301,7 +1302,10 @@ __global__ void __launch_bounds__(kBig) k_gs_step(const int32_t* __restrict__ rp
                                                   int32_t* __restrict__ splitcnt) {
     __shared__ float sacc[kBig / kWave][Q][Chunk<DT>::E];
     __shared__ float sd[kBig / kWave];
-    gs_block<Q, DT>(rp, col, w, X, K, tt, blockIdx.x, part, splitcnt, sacc, sd);
+    int64_t b = blockIdx.x;
+    const int64_t b0 = tt.blk0[tt.split], nb = tt.blk0[tt.nt];
+    if (tt.reverse && b >= b0) b = b0 + (nb - 1 - b);
+    gs_block<Q, DT>(rp, col, w, X, K, tt, b, part, splitcnt, sacc, sd);
 }
 
 // lanes per row of tier t: about half the tier's largest degree times
@@ -1368,10 +1372,22 @@ static int smooth_q(const OrderedGraph* og, int K, int sweeps, void* X, Arena& w
     // the profiler brackets all steps of the level at once (events between
     // the launches would stall the launch queue)
     if (pr) prof::begin(st);
+    // where the vectors exceed half the Infinity Cache, every other step runs
+    // its blocks in reverse, so that it starts on the rows whose neighbours
+    // the step before touched last (still on chip; grid smoothing 13.4 ->
+    // 13.25 ms per reduction; on smaller vectors, which stay on chip, it
+    // only moved the widest tiers to the back).  GR_GS_ALTERNATE=0 / 1
+    // turns it off / on at any size, for comparison and tests.
+    const char* alt_env = getenv("GR_GS_ALTERNATE");
+    const bool alternate = alt_env ? alt_env[0] == '1'
+                                   : (double)og->g.n * K * xs > 128.0 * 1024 * 1024;
+    int64_t launched = 0;
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < C; ++c) {
-            const GsTiers& tt = plan[c];
+            GsTiers tt = plan[c];
             if (tt.nt == 0) continue;
+            tt.reverse = alternate ? (int32_t)(launched & 1) : 0;
+            ++launched;
             hipLaunchKernelGGL((k_gs_step<Q, DT>), dim3((unsigned)tt.blk0[tt.nt]), dim3(kBig), 0, st,
                                og->g.row_ptr, og->g.col, og->g.w, X, K, tt, part, splitcnt);
             GR_LAUNCHED("gs step");

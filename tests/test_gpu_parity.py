@@ -265,6 +265,37 @@ def test_smoothing_matches_oracle(dtype):
                     f"{name}: max rel {np.max(err / (scale + 1e-30))}"
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_smoothing_block_order_bit_identical(dtype, monkeypatch):
+    """Colour steps with every other step's blocks in reverse order (the
+    default) give the same bits as all steps in launch order: tiers of every
+    width, split hub rows (kept at the front), isolated rows, odd block
+    counts."""
+    dev = _dev()
+    G = _G()
+    cases = {
+        "grid3d_40": W.grid3d(40, seed=3),
+        "chunglu_hubs_10000": W.chung_lu(10000, mean_deg=700.0, seed=7),
+        "er_40_isolated": W.with_isolated(W.random_weighted(40, 0.15, seed=9), 3),
+        "knn2d_3000": W.knn2d(3000, 10, seed=2),
+    }
+    for name, g in cases.items():
+        c, nc = _colour(g)
+        for K in ((8, 16) if dtype == "f32" else (8, 32)):
+            X0 = torch.from_numpy(O.init_vectors(g.n, K, 17)).to(dev).to(
+                torch.float32 if dtype == "f32" else torch.bfloat16).contiguous()
+            out = {}
+            for mode in ("0", "1"):
+                say(f"smooth {name} K={K} {dtype} alternate={mode}")
+                monkeypatch.setenv("GR_GS_ALTERNATE", mode)
+                X = X0.clone()
+                G.gr_smooth(dgraph(g, dev), torch.from_numpy(c).to(dev), nc, X, 3)
+                torch.cuda.synchronize()
+                out[mode] = X.view(torch.int16 if dtype == "bf16" else torch.int32).cpu().numpy()
+            monkeypatch.delenv("GR_GS_ALTERNATE")
+            assert np.array_equal(out["0"], out["1"]), name
+
+
 def test_affinity_matches_oracle_and_is_symmetric():
     """a within 1e-5 absolute; the algebraic distance d = 1 - a within the
     error of its cancellation-free float32 evaluation: about 6 u / theta
