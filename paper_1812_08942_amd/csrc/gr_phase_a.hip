@@ -1021,48 +1021,91 @@ int permute_rows(const void* src, void* dst, const int32_t* perm, int64_t n, siz
 }
 
 // ------------------------------------------------------------ test vectors
-__device__ inline double rand_entry(uint64_t seed, uint64_t idx) {
-    uint64_t r = splitmix64(seed, idx);
-    int64_t m = (int64_t)(r >> 40);
-    return (double)(2 * m + 1 - (1ll << 24)) * (1.0 / 16777216.0);
+// Entry (v, k) of the raw vectors: t = 2m + 1 - 2^24 for m the top 24 bits of
+// splitmix64 output id(v) * K + k, the value being t / 2^24.  The counter
+// of splitmix64 advances by a fixed odd constant per output, so the E
+// consecutive entries of a 16-byte chunk start from one product and add the
+// constant; only the top 24 bits of the last multiplication are used.
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+template <int E>
+__device__ inline void rand_chunk(uint64_t seed, uint64_t first, int32_t* t) {
+    uint64_t z = seed + (first + 1ull) * kGolden;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uint64_t y = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        y = (y ^ (y >> 27)) * 0x94D049BB133111EBull;
+        // the final y ^ (y >> 31) leaves the top 24 bits as they are
+        const int32_t m = (int32_t)(y >> 40);
+        t[e] = 2 * m + 1 - (1 << 24);
+        z += kGolden;
+    }
 }
 
-constexpr int kInitBlocks = 240;
+constexpr int kInitBlocks = 2048;  // at most; a multiple of K / 4 in use
+constexpr int kInitE = 4;  // entries per chunk in the column sums (K % 4 == 0)
 
+// Column sums of the raw vectors.  Thread g takes the chunks g, g + G, ... of
+// the n * K / 4 chunks (G a multiple of K / 4, so a thread keeps one chunk
+// column q); the sums are of multiples of 2^-24 below n in magnitude, exact
+// in FP64 for n < 2^29, so their order does not matter.  part[k * B + b]:
+// block b's sum of column k.
 __global__ void __launch_bounds__(kThreads) k_init_colsum(int64_t n, int32_t K, uint64_t seed,
                                                           const int32_t* __restrict__ ids,
                                                           double* __restrict__ part) {
-    // grid (kInitBlocks, K): block (b, k) sums column k over rows b, b+B, ...
-    const int k = blockIdx.y;
-    double s = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * kThreads) {
-        int64_t id = ids ? ids[r] : r;
-        s += rand_entry(seed, (uint64_t)id * (uint64_t)K + (uint64_t)k);
-    }
-    __shared__ double wsum[kThreads / kWave];
+    __shared__ double red[kThreads][kInitE];
+    const int Qc = K / kInitE;
+    const int tid = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * kThreads + tid;
+    const int64_t G = (int64_t)gridDim.x * kThreads;
+    const int q = (int)(g % Qc);
+    double acc[kInitE];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = s;
+    for (int e = 0; e < kInitE; ++e) acc[e] = 0.0;
+    const int64_t items = n * Qc;
+    const bool narrow = items <= 0xffffffffll;
+    for (int64_t i = g; i < items; i += G) {
+        const int64_t r = narrow ? (int64_t)((uint32_t)i / (uint32_t)Qc) : i / Qc;
+        const int64_t id = ids ? ids[r] : r;
+        int32_t t[kInitE];
+        rand_chunk<kInitE>(seed, (uint64_t)id * (uint64_t)K + (uint64_t)(q * kInitE), t);
+#pragma unroll
+        for (int e = 0; e < kInitE; ++e) acc[e] += (double)t[e];
+    }
+#pragma unroll
+    for (int e = 0; e < kInitE; ++e) red[tid][e] = acc[e];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kThreads / kWave; ++w) t += wsum[w];
-        part[(int64_t)k * gridDim.x + blockIdx.x] = t;
+    // column k = q * 4 + e: the threads of chunk column q (tid = q mod Qc,
+    // the block's first thread being of column blockIdx.x * kThreads mod Qc)
+    for (int k = tid; k < K; k += kThreads) {
+        const int qq = k / kInitE, e = k % kInitE;
+        const int t0 = (int)(((int64_t)qq - (int64_t)blockIdx.x * kThreads) % Qc + Qc) % Qc;
+        double sum = 0.0;
+        for (int u = t0; u < kThreads; u += Qc) sum += red[u][e];
+        part[(int64_t)k * gridDim.x + blockIdx.x] = sum * (1.0 / 16777216.0);
     }
 }
 
-__global__ void k_init_mean(const double* __restrict__ part, int nb, int64_t n, int32_t K,
-                            double* __restrict__ mean) {
-    int k = threadIdx.x;
-    if (k >= K) return;
+// a block per column: the sum of its nb partial sums (exact, see above)
+__global__ void __launch_bounds__(kThreads) k_init_mean(const double* __restrict__ part, int nb,
+                                                        int64_t n, double* __restrict__ mean) {
+    __shared__ double ws[kThreads / kWave];
+    const int k = blockIdx.x;
     double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part[(int64_t)k * nb + b];
-    mean[k] = t / (double)n;
+    for (int b = threadIdx.x; b < nb; b += kThreads) t += part[(int64_t)k * nb + b];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double u = 0.0;
+        for (int w = 0; w < kThreads / kWave; ++w) u += ws[w];
+        mean[k] = u / (double)n;
+    }
 }
 
 // one 16-byte chunk (4 float32 or 8 bfloat16 values) per thread, stored
-// with one vector store; the same arithmetic per value as the column sums
+// with one vector store: (value - column mean) in FP64, rounded once
 template <int DT>
 __global__ void k_init_write(int64_t n, int32_t K, uint64_t seed, const int32_t* __restrict__ ids,
                              const double* __restrict__ mean, void* __restrict__ X) {
@@ -1076,12 +1119,12 @@ __global__ void k_init_write(int64_t n, int32_t K, uint64_t seed, const int32_t*
     else r = c / Qc;
     const int q = (int)(c - r * Qc);
     const int64_t id = ids ? ids[r] : r;
+    int32_t t[E];
+    rand_chunk<E>(seed, (uint64_t)id * (uint64_t)K + (uint64_t)(q * E), t);
     float v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = q * E + e;
-        v[e] = (float)(rand_entry(seed, (uint64_t)id * (uint64_t)K + (uint64_t)k) - mean[k]);
-    }
+    for (int e = 0; e < E; ++e)
+        v[e] = (float)((double)t[e] * (1.0 / 16777216.0) - mean[q * E + e]);
     Chunk<DT>::store(X, r, K, q, v);
 }
 
@@ -1089,13 +1132,17 @@ int init_vectors(int64_t n, int32_t K, uint64_t seed, int32_t dtype, const int32
                  Arena& ws, hipStream_t st) {
     if (n == 0) return GR_OK;
     size_t mark = ws.used;
-    double* part = ws.take<double>((size_t)kInitBlocks * K);
+    double* part = ws.take<double>((size_t)(kInitBlocks + 64) * K);
     double* mean = ws.take<double>(K);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (init)");
-    hipLaunchKernelGGL(k_init_colsum, dim3(kInitBlocks, K), dim3(kThreads), 0, st, n, K, seed, ids,
-                       part);
+    if (K % kInitE != 0) return set_error(GR_EUNSUP, "K=%d is not a multiple of 4", K);
+    // a multiple of K / 4 blocks, so that every thread keeps one chunk column
+    const int Qc = K / kInitE;
+    const int64_t want = std::min<int64_t>(kInitBlocks, blocks_for(n * Qc, kThreads));
+    const int nbk = (int)std::max<int64_t>(Qc, want / Qc * Qc);
+    hipLaunchKernelGGL(k_init_colsum, dim3(nbk), dim3(kThreads), 0, st, n, K, seed, ids, part);
     GR_LAUNCHED("init colsum");
-    hipLaunchKernelGGL(k_init_mean, dim3(1), dim3(64), 0, st, (const double*)part, kInitBlocks, n, K,
+    hipLaunchKernelGGL(k_init_mean, dim3(K), dim3(kThreads), 0, st, (const double*)part, nbk, n,
                        mean);
     GR_LAUNCHED("init mean");
     const int E = dtype == GR_BF16 ? Chunk<GR_BF16>::E : Chunk<GR_F32>::E;
