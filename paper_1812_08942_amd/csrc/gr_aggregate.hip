@@ -151,8 +151,9 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
     GR_HIP(hipMemcpyAsync(&nf, pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GR_HIP(hipStreamSynchronize(st));
     if (n_forest) *n_forest = nf;
+    const int32_t* accepted = acc;  // the forest edges taken
     if (n - nf >= target) {
-        GR_HIP(hipMemcpyAsync(acc, own, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+        accepted = own;  // all of them
     } else {
         // accept only the first m = n - target forest edges in the total order
         int64_t m = n - target;
@@ -184,7 +185,7 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
             ws.used = mark2;
         }
     }
-    hipLaunchKernelGGL(k_parent, dim3(gb), dim3(kT), 0, st, best, ids, acc, n, pa);
+    hipLaunchKernelGGL(k_parent, dim3(gb), dim3(kT), 0, st, best, ids, accepted, n, pa);
     GR_LAUNCHED("parent");
     // pointer jumping to the roots, in place, kHops links per node and
     // launch (a launch at least multiplies the distance covered by kHops).
@@ -1025,11 +1026,27 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         GR_LAUNCHED("long segment run counts");
         ws.used = mk;
     }
-    // all runs in (I, J) order, then the mirrored entries by a stable sort on J
+    // all runs in (I, J) order, then the mirrored entries by a stable sort on J;
+    // the rows of more than 64 kept entries (LDS and hub classes) compact
+    // their runs a thread per run, at offsets of their own (one host read
+    // brings both totals)
     GR_TRY(scan_exclusive_i32(rc, roff, n_c, small + 10, ws, st));
-    int32_t runs = 0;
-    GR_HIP(hipMemcpyAsync(&runs, small + 10, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    const int32_t nh = cs[kGalClasses] - cs[kGalLds];
+    int32_t* hoff = nullptr;
+    if (nh > 0) {
+        int32_t* hrc = ws.take<int32_t>(nh + 1);
+        hoff = ws.take<int32_t>(nh + 1);
+        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin long rows)");
+        hipLaunchKernelGGL(k_long_runs, dim3(blocks_for(nh, kT)), dim3(kT), 0, st,
+                           cls_list(kGalLds), nh, (const int32_t*)rc, hrc);
+        GR_LAUNCHED("long row run counts");
+        GR_TRY(scan_exclusive_i32(hrc, hoff, nh, small + 11, ws, st));
+    }
+    int32_t tot[2] = {0, 0};  // runs, runs of the long rows
+    GR_HIP(hipMemcpyAsync(tot, small + 10, sizeof(tot), hipMemcpyDeviceToHost, st));
     GR_HIP(hipStreamSynchronize(st));
+    const int32_t runs = tot[0];
+    const int32_t hr = nh > 0 ? tot[1] : 0;
     uint64_t* ukey = ws.take<uint64_t>(runs);
     float* uw = ws.take<float>(runs);
     uint32_t* mk0 = ws.take<uint32_t>(runs);
@@ -1042,27 +1059,12 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
                        (const int32_t*)roff, n_c, jbits, (const int32_t*)rj, (const float*)rw, ukey,
                        uw, mk0, mi0);
     GR_LAUNCHED("compact runs");
-    const int32_t nh = cs[kGalClasses] - cs[kGalLds];  // LDS and hub rows
-    if (nh > 0) {
-        const size_t mk = ws.used;
-        int32_t* hrc = ws.take<int32_t>(nh + 1);
-        int32_t* hoff = ws.take<int32_t>(nh + 1);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin long rows)");
-        hipLaunchKernelGGL(k_long_runs, dim3(blocks_for(nh, kT)), dim3(kT), 0, st,
-                           cls_list(kGalLds), nh, (const int32_t*)rc, hrc);
-        GR_LAUNCHED("long row run counts");
-        GR_TRY(scan_exclusive_i32(hrc, hoff, nh, small + 11, ws, st));
-        int32_t hr = 0;
-        GR_HIP(hipMemcpyAsync(&hr, small + 11, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));
-        if (hr > 0) {
-            hipLaunchKernelGGL(k_compact_long, dim3(blocks_for(hr, kT)), dim3(kT), 0, st,
-                               cls_list(kGalLds), nh, (const int32_t*)hoff, (int64_t)hr,
-                               (const int32_t*)uoff, (const int32_t*)roff, jbits, (const int32_t*)rj,
-                               (const float*)rw, ukey, uw, mk0, mi0);
-            GR_LAUNCHED("compact runs (long rows)");
-        }
-        ws.used = mk;
+    if (hr > 0) {
+        hipLaunchKernelGGL(k_compact_long, dim3(blocks_for(hr, kT)), dim3(kT), 0, st,
+                           cls_list(kGalLds), nh, (const int32_t*)hoff, (int64_t)hr,
+                           (const int32_t*)uoff, (const int32_t*)roff, jbits, (const int32_t*)rj,
+                           (const float*)rw, ukey, uw, mk0, mi0);
+        GR_LAUNCHED("compact runs (long rows)");
     }
     GR_TRY(radix_sort_pairs32(mk0, mi0, mk1, mi1, runs, jbits, ws, st));
     const unsigned nbr = blocks_for(runs, kT);
