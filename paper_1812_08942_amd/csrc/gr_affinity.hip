@@ -18,9 +18,18 @@ constexpr int kThreads = 256;
 constexpr int kBig = GR_AFF_BLOCK;
 
 // ---------------------------------------------------------------- affinity
-// (d, id) ordering of candidates: smaller algebraic distance, then smaller id.
+// (d, id) ordering of candidates: smaller algebraic distance, then smaller
+// original id.
 __device__ inline bool closer(float d1, int32_t id1, float d2, int32_t id2) {
     return d1 < d2 || (d1 == d2 && id1 < id2);
+}
+__device__ inline int32_t idof(const int32_t* ids, int32_t j) { return ids ? ids[j] : j; }
+// Candidate j (row index) beats the current best bj when its distance is
+// smaller, or equal with a smaller id; the ids are read only for such exact
+// ties.  (The search starts from bd = 2 above every distance, so a tie
+// always has a best bj >= 0.)
+__device__ inline bool beats(float d, int32_t j, float bd, int32_t bj, const int32_t* ids) {
+    return d < bd || (d == bd && idof(ids, j) < idof(ids, bj));
 }
 
 // Per row-group: a = (x_v . x_j)^2 / (|x_v|^2 |x_j|^2) and the algebraic
@@ -82,6 +91,11 @@ __device__ inline void row_entries(const int32_t* __restrict__ col, const void* 
                                    float* __restrict__ dist, float& bd, int32_t& bj,
                                    int32_t& bid) {
     constexpr int E = Chunk<DT>::E;
+    // with bfloat16 storage (8-bit mantissas) equal smoothed rows, and so
+    // exact ties of d, are common: the ids then travel with the rows' loads
+    // (a tie otherwise stops the loop for two dependent loads); with float32
+    // they are read only on a tie, and the best one's at the end
+    constexpr bool kEagerIds = DT == GR_BF16;
     float xv[E], uv[E];
     Chunk<DT>::load(X, r, K, q, xv);
     const float2 nrv = row_norm<Q, E>(xv);
@@ -99,7 +113,7 @@ __device__ inline void row_entries(const int32_t* __restrict__ col, const void* 
 #pragma unroll
         for (int u = 0; u < kAU; ++u) {
             Chunk<DT>::load(X, j[u], K, q, xj[u]);
-            jid[u] = ids ? ids[j[u]] : j[u];
+            if constexpr (kEagerIds) jid[u] = idof(ids, j[u]);
         }
 #pragma unroll
         for (int u = 0; u < kAU; ++u) {
@@ -110,10 +124,20 @@ __device__ inline void row_entries(const int32_t* __restrict__ col, const void* 
                     if (a) a[e[u]] = av;
                     if (dist) dist[e[u]] = dv;
                 }
-                if (closer(dv, jid[u], bd, bid)) { bd = dv; bj = j[u]; bid = jid[u]; }
+                if constexpr (kEagerIds) {
+                    if (closer(dv, jid[u], bd, bid)) {
+                        bd = dv;
+                        bj = j[u];
+                        bid = jid[u];
+                    }
+                } else if (beats(dv, j[u], bd, bj, ids)) {
+                    bd = dv;
+                    bj = j[u];
+                }
             }
         }
     }
+    if constexpr (!kEagerIds) bid = bj >= 0 ? idof(ids, bj) : 0x7fffffff;
 }
 
 // Rows with degree <= kLongRow: L = Q*P lanes per row.
