@@ -247,17 +247,18 @@ enum {
 };
 
 // 8 lanes per fine row: the number of the row's kept entries
+// G lanes per row (G a power of two up to 8, sized to the mean degree)
+template <int G>
 __global__ void k_rap_count(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                             const int32_t* __restrict__ agg, int64_t n, int32_t* __restrict__ cnt) {
-    const int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
-    const int l = threadIdx.x & 7;
-    if (v >= n || rp[v + 1] - rp[v] > kLongRow) return;  // the 8 lanes of a row leave together
+    const int64_t v = ((int64_t)blockIdx.x * kT + threadIdx.x) / G;
+    const int l = threadIdx.x % G;
+    if (v >= n || rp[v + 1] - rp[v] > kLongRow) return;  // the G lanes of a row leave together
     const int32_t I = agg[v];
     int32_t c = 0;
-    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += 8) c += agg[col[e]] > I ? 1 : 0;
-    c += __shfl_xor(c, 1, kWave);
-    c += __shfl_xor(c, 2, kWave);
-    c += __shfl_xor(c, 4, kWave);
+    for (int32_t e = rp[v] + l; e < rp[v + 1]; e += G) c += agg[col[e]] > I ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) c += __shfl_xor(c, off, kWave);
     if (l == 0) cnt[v] = c;
 }
 
@@ -376,26 +377,28 @@ __global__ void k_class_starts(const int32_t* __restrict__ boffs, int32_t nblk, 
 }
 
 // Kept entries of the sorted rows at their segment positions: column
-// aggregate J and weight.  8 lanes per row; rows above kLongRow are skipped
-// (k_place_long takes them).
+// aggregate J and weight.  G lanes per row (as in the count); rows above
+// kLongRow are skipped (k_place_long takes them).
+template <int G>
 __global__ void k_place_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                              const float* __restrict__ w, const int32_t* __restrict__ agg,
                              const uint32_t* __restrict__ rows, const int32_t* __restrict__ pos_s,
                              int64_t n, int32_t* __restrict__ ej, float* __restrict__ ew) {
-    const int64_t t = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 3;
-    const int l = threadIdx.x & 7;
-    const int grp = (threadIdx.x & (kWave - 1)) >> 3;
+    const int64_t t = ((int64_t)blockIdx.x * kT + threadIdx.x) / G;
+    const int l = threadIdx.x % G;
+    const int grp = (threadIdx.x & (kWave - 1)) / G;
     if (t >= n) return;
     const int32_t v = (int32_t)rows[t];
     const int32_t e1 = rp[v + 1];
-    if (e1 - rp[v] > kLongRow) return;  // the 8 lanes of a row leave together
+    if (e1 - rp[v] > kLongRow) return;  // the G lanes of a row leave together
     const int32_t I = agg[v];
     int64_t out = pos_s[t];
-    for (int32_t e0 = rp[v]; e0 < e1; e0 += 8) {  // the same trip count for the row's lanes
+    constexpr uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    for (int32_t e0 = rp[v]; e0 < e1; e0 += G) {  // the same trip count for the row's lanes
         const int32_t e = e0 + l;
         const int32_t J = e < e1 ? agg[col[e]] : -1;
         const bool keep = J > I;
-        const uint32_t bits = (uint32_t)(__ballot(keep) >> (8 * grp)) & 0xffu;
+        const uint32_t bits = (uint32_t)((__ballot(keep) >> (G * grp)) & gmask);
         if (keep) {
             const int64_t s = out + __popc(bits & ((1u << l) - 1u));
             ej[s] = J;
@@ -849,11 +852,24 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     int32_t* lend = ws.take<int32_t>(n_c + 1);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin)");
     const unsigned nb = blocks_for(n, kT);
+    // lanes per fine row in the count and the placement: a power of two up
+    // to 8, about the mean degree (GR_GAL_LANES=g forces g)
+    int rl = 1;
+    while (rl < 8 && rl * 2 <= (nnz + n - 1) / std::max<int64_t>(n, 1)) rl *= 2;
+    if (const char* gl = getenv("GR_GAL_LANES")) {
+        const int v = atoi(gl);
+        if (v == 1 || v == 2 || v == 4 || v == 8) rl = v;
+    }
     // kept entries per fine row, the rows in aggregate order, and each coarse
     // row's segment
     if (nnz > 0) {
-        const unsigned rb = blocks_for(n * 8, kT);
-        hipLaunchKernelGGL(k_rap_count, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt);
+        const unsigned rb = blocks_for(n * rl, kT);
+        switch (rl) {
+            case 1: hipLaunchKernelGGL(k_rap_count<1>, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt); break;
+            case 2: hipLaunchKernelGGL(k_rap_count<2>, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt); break;
+            case 4: hipLaunchKernelGGL(k_rap_count<4>, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt); break;
+            default: hipLaunchKernelGGL(k_rap_count<8>, dim3(rb), dim3(kT), 0, st, g->row_ptr, g->col, agg, n, rcnt); break;
+        }
         GR_LAUNCHED("rap count");
         if (n_long > 0) {
             hipLaunchKernelGGL(k_rap_count_long, dim3((unsigned)n_long), dim3(kT), 0, st, g->row_ptr,
@@ -918,8 +934,16 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
     float* rw = ws.take<float>(m);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin entries)");
     // the kept entries in segment order
-    hipLaunchKernelGGL(k_place_rows, dim3(blocks_for(n * 8, kT)), dim3(kT), 0, st, g->row_ptr, g->col,
-                       g->w, agg, (const uint32_t*)rows, (const int32_t*)pos_s, n, ej, ew);
+#define GR_PLACE(GG)                                                                               \
+    hipLaunchKernelGGL(k_place_rows<GG>, dim3(blocks_for(n * GG, kT)), dim3(kT), 0, st, g->row_ptr, \
+                       g->col, g->w, agg, (const uint32_t*)rows, (const int32_t*)pos_s, n, ej, ew)
+    switch (rl) {
+        case 1: GR_PLACE(1); break;
+        case 2: GR_PLACE(2); break;
+        case 4: GR_PLACE(4); break;
+        default: GR_PLACE(8); break;
+    }
+#undef GR_PLACE
     GR_LAUNCHED("place rows");
     if (n_long > 0) {
         hipLaunchKernelGGL(k_place_long, dim3((unsigned)n_long), dim3(kT), 0, st, g->row_ptr, g->col,
