@@ -286,12 +286,17 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const KT* __restric
 }
 
 // One pass of the stable LSD sort on digit (key >> shift) & 0xff (keys of 64
-// or 32 bits; the narrow form moves a third fewer bytes).  The block
-// first ranks its tile in LDS (digit-major, original order inside a digit:
-// ballots give the rank inside a wave, per-wave counts the order of the
-// waves, a running count the order of the rounds), then writes the tile out
-// digit by digit, so that the elements of one digit leave as a contiguous
-// run (coalesced stores) at the digit's global offset for this tile.
+// or 32 bits; the narrow form moves a third fewer bytes).  Wave w of the
+// block owns the kSortIters * 64 consecutive keys of its part of the tile
+// and keeps them in registers.  It first counts its digits (a ballot match
+// per round gives each digit's lanes; the lowest lane adds their number to
+// the wave's own counter in LDS), the block then turns the counts into each
+// wave's starting place per digit (digit-major, waves in order), and each
+// wave walks its keys again in the same order, placing them at its running
+// place plus their rank among the round's lanes of the same digit.  The
+// order inside a digit is the input order (stable).  The tile is then
+// written out digit by digit, each digit's keys as one contiguous run
+// (coalesced stores) at the digit's global offset for this tile.
 template <class KT>
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const KT* __restrict__ kin, const uint32_t* __restrict__ vin, KT* __restrict__ kout,
@@ -302,72 +307,89 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     __shared__ uint32_t sval[kSortTile];
     __shared__ int32_t gbase[kRadix];
     __shared__ int32_t lbase[kRadix];
-    __shared__ int32_t run[kRadix];
-    __shared__ int32_t wsum[kW];
-    __shared__ int32_t wcnt[kW][kRadix];
+    __shared__ int32_t wcnt[kW][kRadix];  // per wave: its count, then its place
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wid = tid / kWave;
-    gbase[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
-    // exclusive scan of the tile's digit counts: the digits' local offsets
-    const int32_t c = hist[(int64_t)tid * nblocks + blockIdx.x];
-    int32_t x = c;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int32_t y = __shfl_up(x, off, kWave);
-        if (lane >= off) x += y;
-    }
-    if (lane == kWave - 1) wsum[wid] = x;
-    run[tid] = 0;
-#pragma unroll
     for (int w = 0; w < kW; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
-    int32_t pre_w = 0;
-    for (int w = 0; w < wid; ++w) pre_w += wsum[w];
-    lbase[tid] = pre_w + x - c;
-    __syncthreads();
+    gbase[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const int64_t tbase = (int64_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortIters; ++it) {
-        const int64_t i = tbase + it * kSortThreads + tid;
-        const bool valid = i < n;
-        const KT key = valid ? kin[i] : KT(0);
-        const uint32_t val = valid ? vin[i] : 0u;
-        const int d = valid ? (int)((key >> shift) & 0xff) : 0;
-        // lanes of this wave holding the same digit (and validity)
-        uint64_t peers = __ballot(valid);
-        if (!valid) peers = ~peers;
+    const int64_t wbase = tbase + (int64_t)wid * kSortIters * kWave;
+    KT key[kSortIters];
+    uint32_t val[kSortIters];
+    int dig[kSortIters];
+    uint64_t peer[kSortIters];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+    for (int it = 0; it < kSortIters; ++it) {
+        const int64_t i = wbase + it * kWave + lane;
+        const bool valid = i < n;
+        key[it] = valid ? kin[i] : KT(0);
+        val[it] = valid ? vin[i] : 0u;
+        // invalid lanes take digit 256: they match only each other
+        dig[it] = valid ? (int)((key[it] >> shift) & 0xff) : kRadix;
+    }
+    __syncthreads();  // counters cleared
+#pragma unroll
+    for (int it = 0; it < kSortIters; ++it) {
+        const int d = dig[it];
+        uint64_t peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
             const uint64_t bb = __ballot((d >> b) & 1);
             peers &= ((d >> b) & 1) ? bb : ~bb;
         }
-        const int rank = __popcll(peers & lt);
-        if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int pre = 0;
-            for (int w = 0; w < wid; ++w) pre += wcnt[w][d];
-            const int lpos = lbase[d] + run[d] + pre + rank;
-            skey[lpos] = key;
-            sval[lpos] = val;
+        peer[it] = peers;
+        if (d < kRadix && (peers & lt) == 0) wcnt[wid][d] += __popcll(peers);
+    }
+    __syncthreads();
+    {
+        // digit tid: the tile's count, its local base (exclusive scan over
+        // digits), and each wave's place
+        int32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) c += wcnt[w][tid];
+        int32_t x = c;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t y = __shfl_up(x, off, kWave);
+            if (lane >= off) x += y;
         }
+        __shared__ int32_t wsum[kW];
+        if (lane == kWave - 1) wsum[wid] = x;
         __syncthreads();
-        int add = 0;
+        int32_t pre = 0;
+        for (int w = 0; w < wid; ++w) pre += wsum[w];
+        int32_t place = pre + x - c;
+        lbase[tid] = place;
 #pragma unroll
         for (int w = 0; w < kW; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
+            const int32_t cw = wcnt[w][tid];
+            wcnt[w][tid] = place;
+            place += cw;
         }
-        run[tid] += add;
-        __syncthreads();
     }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSortIters; ++it) {
+        const int d = dig[it];
+        if (d < kRadix) {
+            const uint64_t peers = peer[it];
+            const int lpos = wcnt[wid][d] + __popcll(peers & lt);
+            skey[lpos] = key[it];
+            sval[lpos] = val[it];
+            // the digit's lowest lane moves the wave's place on, after every
+            // lane of the digit has read it (a wave's LDS accesses are in order)
+            if ((peers & lt) == 0) wcnt[wid][d] += __popcll(peers);
+        }
+    }
+    __syncthreads();
     const int cnt = (int)(n - tbase < kSortTile ? n - tbase : kSortTile);
     for (int j = tid; j < cnt; j += kSortThreads) {
-        const KT key = skey[j];
-        const int d = (int)((key >> shift) & 0xff);
+        const KT k = skey[j];
+        const int d = (int)((k >> shift) & 0xff);
         const int64_t pos = (int64_t)gbase[d] + (j - lbase[d]);
-        kout[pos] = key;
+        kout[pos] = k;
         vout[pos] = sval[j];
     }
 }
