@@ -138,9 +138,17 @@ constexpr unsigned kFlowSpinLimit = 1u << 21;  // polls of one neighbour at most
 constexpr int kFlowG = 8;                      // lanes per position of a narrow batch
 constexpr int kFlowBatch = kWave / kFlowG;     // positions of a batch
 constexpr int32_t kFlowNarrow = 64;            // listed neighbours per position of a narrow batch
+// resident workgroups per CU of the flow: more waves take more batches at
+// once where the dependence chains are short (sparse graphs: grid colour
+// phase 3.5 -> 3.07 ms with 8), fewer where long chains keep most waves
+// polling (power law: 3.16 ms with 2, 3.66 with 8)
 #ifndef GR_FLOW_BLOCKS_PER_CU
 #define GR_FLOW_BLOCKS_PER_CU 2
 #endif
+#ifndef GR_FLOW_BLOCKS_PER_CU_SPARSE
+#define GR_FLOW_BLOCKS_PER_CU_SPARSE 8
+#endif
+constexpr double kFlowSparseDegree = 32.0;  // mean degree up to which a graph counts as sparse
 #ifndef GR_FLOW_SLEEP
 #define GR_FLOW_SLEEP 2  // s_sleep units (64 cycles) between polls
 #endif
@@ -595,13 +603,14 @@ __global__ void __launch_bounds__(kThreads) k_flow_colours(const int32_t* __rest
     }
 }
 
-static int flow_blocks(int64_t n) {
+static int flow_blocks(int64_t n, int64_t nnz) {
     int dev = 0, cus = 0, per_cu = 0;
     GR_HIP(hipGetDevice(&dev));
     GR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     GR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_jp_flow,
                                                         kFlowThreads, 0));
-    per_cu = std::min(per_cu, GR_FLOW_BLOCKS_PER_CU);
+    const bool sparse = n > 0 && (double)nnz <= kFlowSparseDegree * (double)n;
+    per_cu = std::min(per_cu, sparse ? GR_FLOW_BLOCKS_PER_CU_SPARSE : GR_FLOW_BLOCKS_PER_CU);
     if (per_cu < 1 || cus < 1) return set_error(GR_EHIP, "colouring kernel does not fit a CU");
     const int64_t want = (n + kFlowWaves - 1) / kFlowWaves;
     return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * cus, want));
@@ -630,7 +639,7 @@ static int colour_flow(const gr_graph* g, uint64_t seed, int ldf, int32_t* colou
     // [4] largest colour, [5] batches, [6] first batch of the device-wide flow
     int32_t* small = ws.take<int32_t>(8);
     if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (colouring)");
-    const int nblk = flow_blocks(n);
+    const int nblk = flow_blocks(n, nnz);
     if (nblk < 0) return nblk;
     const unsigned nb = blocks_for(n, kThreads);
     // GR_COLOUR_EXACT_ORDER=1 builds the largest-degree-first order in two
