@@ -300,8 +300,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const KT* __restric
 template <class KT>
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const KT* __restrict__ kin, const uint32_t* __restrict__ vin, KT* __restrict__ kout,
-    uint32_t* __restrict__ vout, int64_t n, int shift, const int32_t* __restrict__ hist,
-    const int32_t* __restrict__ offs, int nblocks) {
+    uint32_t* __restrict__ vout, int64_t n, int shift, const int32_t* __restrict__ offs,
+    int nblocks) {
     constexpr int kW = kSortThreads / kWave;
     __shared__ KT skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
@@ -419,7 +419,7 @@ static int radix_sort(KT* keys_in, uint32_t* vals_in, KT* keys_out, uint32_t* va
         GR_LAUNCHED("radix hist");
         GR_TRY(scan_exclusive_i32(hist, offs, (int64_t)kRadix * nb, nullptr, ws, st));
         hipLaunchKernelGGL(k_radix_scatter<KT>, dim3(nb), dim3(kSortThreads), 0, st, ks, vs, kd, vd,
-                           n, shift, (const int32_t*)hist, (const int32_t*)offs, (int)nb);
+                           n, shift, (const int32_t*)offs, (int)nb);
         GR_LAUNCHED("radix scatter");
         KT* tk = ks; ks = kd; kd = tk;
         uint32_t* tv = vs; vs = vd; vd = tv;
