@@ -44,8 +44,9 @@ __global__ void k_forest_keys(const int32_t* __restrict__ best, const float* __r
     owner[s] = (int32_t)v;
 }
 
-__global__ void k_gather_keys(const uint64_t* __restrict__ src, const uint32_t* __restrict__ idx,
-                              int64_t m, uint64_t* __restrict__ dst) {
+template <class KT>
+__global__ void k_gather_keys(const KT* __restrict__ src, const uint32_t* __restrict__ idx,
+                              int64_t m, KT* __restrict__ dst) {
     int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i < m) dst[i] = src[idx[i]];
 }
@@ -175,7 +176,7 @@ int aggregate(const gr_graph* g, const int32_t* best, const float* dbest, const 
             // LSD order: stable by max id first, then stable by k1
             GR_TRY(radix_sort_pairs(k2, sa, ka, sb, nf, idb, ws, st));
             const unsigned fb = blocks_for(nf, kT);
-            hipLaunchKernelGGL(k_gather_keys, dim3(fb), dim3(kT), 0, st, k1, sb, (int64_t)nf, kb);
+            hipLaunchKernelGGL(k_gather_keys<uint64_t>, dim3(fb), dim3(kT), 0, st, k1, sb, (int64_t)nf, kb);
             GR_LAUNCHED("gather keys");
             GR_TRY(radix_sort_pairs(kb, sb, ka, sa, nf, 30 + idb, ws, st));
             hipLaunchKernelGGL(k_accept_first, dim3(blocks_for(m, kT)), dim3(kT), 0, st, sa, owner,
@@ -599,16 +600,17 @@ __device__ inline int32_t seg_of(const int32_t* __restrict__ off, int32_t cnt, i
 
 // the entries of the long segments, concatenated in list order: key
 // (list rank << jbits | J), value the weight's bits; a thread per entry
+template <class KT>
 __global__ void k_big_gather(const int32_t* __restrict__ list, int32_t nbig,
                              const int32_t* __restrict__ boff, int64_t mb,
                              const int32_t* __restrict__ uoff, const int32_t* __restrict__ ej,
-                             const float* __restrict__ ew, int jbits, uint64_t* __restrict__ bk,
+                             const float* __restrict__ ew, int jbits, KT* __restrict__ bk,
                              uint32_t* __restrict__ bv) {
     const int64_t d = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (d >= mb) return;
     const int32_t b = seg_of(boff, nbig, d);
     const int64_t src = (int64_t)uoff[list[b]] + (d - boff[b]);
-    bk[d] = ((uint64_t)(uint32_t)b << jbits) | (uint64_t)(uint32_t)ej[src];
+    bk[d] = ((KT)(uint32_t)b << jbits) | (KT)(uint32_t)ej[src];
     bv[d] = __float_as_uint(ew[src]);
 }
 
@@ -618,7 +620,8 @@ __global__ void k_big_sizes(const int32_t* __restrict__ list, int32_t nbig,
     if (b < nbig) sz[b] = ucnt[list[b]];
 }
 
-__global__ void k_run_heads(const uint64_t* __restrict__ keys, int64_t m, int32_t* __restrict__ head) {
+template <class KT>
+__global__ void k_run_heads(const KT* __restrict__ keys, int64_t m, int32_t* __restrict__ head) {
     int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= m) return;
     head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
@@ -693,7 +696,8 @@ __global__ void __launch_bounds__(kT) k_seg_tile(const uint32_t* __restrict__ va
 
 // pass 2 for the long segments: one thread per run adds the run's pieces in
 // tile order and writes (J, sum) at the run's rank inside its coarse row
-__global__ void k_big_runs(const uint64_t* __restrict__ keys, const int32_t* __restrict__ start,
+template <class KT>
+__global__ void k_big_runs(const KT* __restrict__ keys, const int32_t* __restrict__ start,
                            const float* __restrict__ piece, int64_t runs, int64_t m, int jbits,
                            const int32_t* __restrict__ list, const int32_t* __restrict__ uoff,
                            const int32_t* __restrict__ bfirst, int32_t* __restrict__ rj,
@@ -707,7 +711,7 @@ __global__ void k_big_runs(const uint64_t* __restrict__ keys, const int32_t* __r
         int64_t pe = min(e, (t + 1) * (int64_t)kSegTile) - 1;
         acc += piece[pe];
     }
-    const uint64_t k = keys[s];
+    const uint64_t k = (uint64_t)keys[s];
     const int32_t b = (int32_t)(k >> jbits);
     const int32_t I = list[b];
     const int64_t pos = (int64_t)uoff[I] + (r - bfirst[b]);
@@ -822,6 +826,73 @@ __global__ void k_place_lower(const uint32_t* __restrict__ mkey, const uint32_t*
     const int64_t p = (int64_t)c_row_ptr[J] + (t - lfirst[J]);
     c_col[p] = (int32_t)(ukey[r] >> jbits);
     c_w[p] = uw[r];
+}
+
+// the stable radix sort for either key width
+static int sort_pairs(uint32_t* a, uint32_t* av, uint32_t* b, uint32_t* bv, int64_t n, int bits,
+                      Arena& ws, hipStream_t st) {
+    return radix_sort_pairs32(a, av, b, bv, n, bits, ws, st);
+}
+static int sort_pairs(uint64_t* a, uint32_t* av, uint64_t* b, uint32_t* bv, int64_t n, int bits,
+                      Arena& ws, hipStream_t st) {
+    return radix_sort_pairs(a, av, b, bv, n, bits, ws, st);
+}
+
+// The runs of the hub segments (more than kGalCap kept entries): their
+// entries gathered in segment order, sorted by (segment rank, J) with the
+// stable radix sort, summed by fixed tiles; keys of 32 bits where they fit.
+template <class KT>
+static int hub_runs(const int32_t* blist, int32_t nbig, const int32_t* boff, int32_t mb,
+                    const int32_t* uoff, const int32_t* ej, const float* ew, int jbits, int bbits,
+                    int32_t* small, int32_t* bfirst, int32_t* bend, int32_t* rj, float* rw,
+                    int32_t* rc, Arena& ws, hipStream_t st) {
+    KT* bk0 = ws.take<KT>(mb);
+    uint32_t* bv0 = ws.take<uint32_t>(mb);
+    KT* bk1 = ws.take<KT>(mb);
+    uint32_t* bv1 = ws.take<uint32_t>(mb);
+    int32_t* head = ws.take<int32_t>(mb);
+    int32_t* ridx = ws.take<int32_t>(mb);
+    int32_t* start = ws.take<int32_t>(mb);
+    float* piece = ws.take<float>(mb);
+    if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin long rows)");
+    hipLaunchKernelGGL(k_big_gather<KT>, dim3(blocks_for(mb, kT)), dim3(kT), 0, st, blist, nbig,
+                       (const int32_t*)boff, (int64_t)mb, (const int32_t*)uoff,
+                       (const int32_t*)ej, (const float*)ew, jbits, bk0, bv0);
+    GR_LAUNCHED("long segments gather");
+    GR_TRY(sort_pairs(bk0, bv0, bk1, bv1, mb, bbits + jbits, ws, st));
+    const unsigned mbb = blocks_for(mb, kT);
+    hipLaunchKernelGGL(k_run_heads<KT>, dim3(mbb), dim3(kT), 0, st, (const KT*)bk1, (int64_t)mb,
+                       head);
+    GR_LAUNCHED("run heads");
+    GR_TRY(scan_exclusive_i32(head, ridx, mb, small + 9, ws, st));
+    hipLaunchKernelGGL(k_run_starts, dim3(mbb), dim3(kT), 0, st, (const int32_t*)head,
+                       (const int32_t*)ridx, (int64_t)mb, start);
+    GR_LAUNCHED("run starts");
+    hipLaunchKernelGGL(k_seg_tile, dim3(blocks_for(mb, kSegTile)), dim3(kT), 0, st,
+                       (const uint32_t*)bv1, (const int32_t*)head, (int64_t)mb, piece);
+    GR_LAUNCHED("segment tiles");
+    int32_t bruns = 0;
+    GR_HIP(hipMemcpyAsync(&bruns, small + 9, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GR_HIP(hipStreamSynchronize(st));
+    // each long segment's first run: the run keys' segment bits
+    KT* rkey = bk0;  // free again
+    hipLaunchKernelGGL(k_gather_keys<KT>, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
+                       (const KT*)bk1, (const uint32_t*)start, (int64_t)bruns, rkey);
+    GR_LAUNCHED("run keys");
+    GR_TRY(fill_i32(bfirst, -1, nbig, st));
+    GR_TRY(fill_i32(bend, -1, nbig, st));
+    hipLaunchKernelGGL(k_row_bounds<KT>, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
+                       (const KT*)rkey, (int64_t)bruns, jbits, bfirst, bend);
+    GR_LAUNCHED("long segment run bounds");
+    hipLaunchKernelGGL(k_big_runs<KT>, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
+                       (const KT*)bk1, (const int32_t*)start, (const float*)piece,
+                       (int64_t)bruns, (int64_t)mb, jbits, blist, (const int32_t*)uoff,
+                       (const int32_t*)bfirst, rj, rw);
+    GR_LAUNCHED("long segment runs");
+    hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(nbig, kT)), dim3(kT), 0, st, blist, nbig,
+                       (const int32_t*)bfirst, (const int32_t*)bend, rc);
+    GR_LAUNCHED("long segment run counts");
+    return GR_OK;
 }
 
 int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_ptr,
@@ -1001,53 +1072,14 @@ int galerkin(const gr_graph* g, const int32_t* agg, int64_t n_c, int32_t* c_row_
         int32_t mb = 0;
         GR_HIP(hipMemcpyAsync(&mb, small + 8, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         GR_HIP(hipStreamSynchronize(st));
-        uint64_t* bk0 = ws.take<uint64_t>(mb);
-        uint32_t* bv0 = ws.take<uint32_t>(mb);
-        uint64_t* bk1 = ws.take<uint64_t>(mb);
-        uint32_t* bv1 = ws.take<uint32_t>(mb);
-        int32_t* head = ws.take<int32_t>(mb);
-        int32_t* ridx = ws.take<int32_t>(mb);
-        int32_t* start = ws.take<int32_t>(mb);
-        float* piece = ws.take<float>(mb);
-        if (ws.overflow) return set_error(GR_ENOMEM, "workspace too small (galerkin long rows)");
-        hipLaunchKernelGGL(k_big_gather, dim3(blocks_for(mb, kT)), dim3(kT), 0, st, blist, nbig,
-                           (const int32_t*)boff, (int64_t)mb, (const int32_t*)uoff,
-                           (const int32_t*)ej, (const float*)ew, jbits, bk0, bv0);
-        GR_LAUNCHED("long segments gather");
+        // keys (segment rank << jbits | J) of 32 bits where they fit
         const int bbits = bits_for(nbig);
-        GR_TRY(radix_sort_pairs(bk0, bv0, bk1, bv1, mb, bbits + jbits, ws, st));
-        const unsigned mbb = blocks_for(mb, kT);
-        hipLaunchKernelGGL(k_run_heads, dim3(mbb), dim3(kT), 0, st, (const uint64_t*)bk1, (int64_t)mb,
-                           head);
-        GR_LAUNCHED("run heads");
-        GR_TRY(scan_exclusive_i32(head, ridx, mb, small + 9, ws, st));
-        hipLaunchKernelGGL(k_run_starts, dim3(mbb), dim3(kT), 0, st, (const int32_t*)head,
-                           (const int32_t*)ridx, (int64_t)mb, start);
-        GR_LAUNCHED("run starts");
-        hipLaunchKernelGGL(k_seg_tile, dim3(blocks_for(mb, kSegTile)), dim3(kT), 0, st,
-                           (const uint32_t*)bv1, (const int32_t*)head, (int64_t)mb, piece);
-        GR_LAUNCHED("segment tiles");
-        int32_t bruns = 0;
-        GR_HIP(hipMemcpyAsync(&bruns, small + 9, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GR_HIP(hipStreamSynchronize(st));
-        // each long segment's first run: the run keys' segment bits
-        uint64_t* rkey = bk0;  // free again
-        hipLaunchKernelGGL(k_gather_keys, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
-                           (const uint64_t*)bk1, (const uint32_t*)start, (int64_t)bruns, rkey);
-        GR_LAUNCHED("run keys");
-        GR_TRY(fill_i32(bfirst, -1, nbig, st));
-        GR_TRY(fill_i32(bend, -1, nbig, st));
-        hipLaunchKernelGGL(k_row_bounds<uint64_t>, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
-                           (const uint64_t*)rkey, (int64_t)bruns, jbits, bfirst, bend);
-        GR_LAUNCHED("long segment run bounds");
-        hipLaunchKernelGGL(k_big_runs, dim3(blocks_for(bruns, kT)), dim3(kT), 0, st,
-                           (const uint64_t*)bk1, (const int32_t*)start, (const float*)piece,
-                           (int64_t)bruns, (int64_t)mb, jbits, blist, (const int32_t*)uoff,
-                           (const int32_t*)bfirst, rj, rw);
-        GR_LAUNCHED("long segment runs");
-        hipLaunchKernelGGL(k_big_counts, dim3(blocks_for(nbig, kT)), dim3(kT), 0, st, blist, nbig,
-                           (const int32_t*)bfirst, (const int32_t*)bend, rc);
-        GR_LAUNCHED("long segment run counts");
+        if (bbits + jbits <= 32)
+            GR_TRY((hub_runs<uint32_t>(blist, nbig, boff, mb, uoff, ej, ew, jbits, bbits, small, bfirst,
+                                       bend, rj, rw, rc, ws, st)));
+        else
+            GR_TRY((hub_runs<uint64_t>(blist, nbig, boff, mb, uoff, ej, ew, jbits, bbits, small, bfirst,
+                                       bend, rj, rw, rc, ws, st)));
         ws.used = mk;
     }
     // all runs in (I, J) order, then the mirrored entries by a stable sort on J;
