@@ -73,6 +73,13 @@ __global__ void k_iota_i32(int32_t* p, int64_t n) {
     if (i < n) p[i] = (int32_t)i;
 }
 
+// out[i] = perm[in[i]]: relabelled row ids back to the level's own
+__global__ void k_map_ids(const int32_t* __restrict__ in, const int32_t* __restrict__ perm,
+                          int64_t n, int32_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = perm[in[i]];
+}
+
 // agg_orig[perm[r]] = aggp[r]
 __global__ void k_unpermute(const int32_t* __restrict__ aggp, const int32_t* __restrict__ perm,
                             int64_t n, int32_t* __restrict__ agg) {
@@ -389,8 +396,19 @@ static int reduce_impl(const gr_graph* g, const gr_params* p_in, gr_result* res,
         next.w = gbuf_w[which];
         int64_t nnzc = 0;
         if (pr) prof::begin(st);
-        GR_TRY(galerkin(&og.g, aggp, ncoarse, gbuf_rp[which], gbuf_col[which], gbuf_w[which], &nnzc,
-                        og.long_rows, og.n_long, A, st));
+        // the collapse runs on the level's graph in its own order, where an
+        // aggregate's members lie close together (in the colour-major order
+        // they sit in different classes, far apart)
+        int32_t* long_own = nullptr;
+        if (og.n_long > 0) {
+            long_own = A.take<int32_t>(og.n_long);
+            if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (long rows)");
+            hipLaunchKernelGGL(k_map_ids, dim3(blocks_for(og.n_long, 256)), dim3(256), 0, st,
+                               og.long_rows, og.perm, og.n_long, long_own);
+            GR_LAUNCHED("long rows, own order");
+        }
+        GR_TRY(galerkin(&cur, aggl, ncoarse, gbuf_rp[which], gbuf_col[which], gbuf_w[which], &nnzc,
+                        long_own, og.n_long, A, st));
         if (pr) prof::end(st, prof::GALERKIN, 0.0, 1);
         next.nnz = nnzc;
         hipLaunchKernelGGL(k_compose, dim3(blocks_for(n0, 256)), dim3(256), 0, st, aggl, n0,
