@@ -52,7 +52,7 @@ static size_t plan_bytes(int64_t n, int64_t nnz, int32_t K, int32_t dtype) {
     size_t relabel = 36 * N + 8 * 1024 + sort_scratch(N);
     // colouring: sort keys and values, ranks, positions, batches, up-lists
     size_t colour = 46 * N + 4 * M + sort_scratch(N) + 8192;
-    size_t agg = 24 * N + 44 * N + sort_scratch(N);
+    size_t agg = 8 * N + 24 * N + 44 * N + sort_scratch(N);  // (+ best in own order)
     // per fine row: counts, positions, sort keys and values (twice);
     // per coarse row: bounds, segments, lists, runs, counts; per kept entry
     // (at most M/2): column, weight, run column, run sum, and for hub rows
@@ -73,18 +73,23 @@ __global__ void k_iota_i32(int32_t* p, int64_t n) {
     if (i < n) p[i] = (int32_t)i;
 }
 
+// the strongest neighbour of relabelled row r, moved to the level's own
+// order: entry perm[r] names perm[best[r]]
+__global__ void k_best_own(const int32_t* __restrict__ best, const float* __restrict__ dbest,
+                           const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ obest,
+                           float* __restrict__ odbest) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t b = best[r], o = perm[r];
+    obest[o] = b >= 0 ? perm[b] : -1;
+    odbest[o] = dbest[r];
+}
+
 // out[i] = perm[in[i]]: relabelled row ids back to the level's own
 __global__ void k_map_ids(const int32_t* __restrict__ in, const int32_t* __restrict__ perm,
                           int64_t n, int32_t* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = perm[in[i]];
-}
-
-// agg_orig[perm[r]] = aggp[r]
-__global__ void k_unpermute(const int32_t* __restrict__ aggp, const int32_t* __restrict__ perm,
-                            int64_t n, int32_t* __restrict__ agg) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) agg[perm[r]] = aggp[r];
 }
 
 // total[v] = lvl[total[v]]
@@ -329,7 +334,6 @@ static int reduce_impl(const gr_graph* g, const gr_params* p_in, gr_result* res,
     void* X = A.take<char>(vec_bytes(n0, p.K, p.vec_dtype) + 256);
     int32_t* best = A.take<int32_t>(n0 + 1);
     float* dbest = A.take<float>(n0 + 1);
-    int32_t* aggp = A.take<int32_t>(n0 + 1);
     int32_t* aggl = A.take<int32_t>(n0 + 1);
     int32_t* gbuf_rp[2] = {A.take<int32_t>(n0 + 1), A.take<int32_t>(n0 + 1)};
     int32_t* gbuf_col[2] = {A.take<int32_t>(g->nnz + 1), A.take<int32_t>(g->nnz + 1)};
@@ -384,10 +388,17 @@ static int reduce_impl(const gr_graph* g, const gr_params* p_in, gr_result* res,
                       1);
         int64_t ncoarse = 0, nforest = 0;
         if (pr) prof::begin(st);
-        GR_TRY(aggregate(&og.g, best, dbest, og.perm, target, aggp, &ncoarse, &nforest, A, st));
-        hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(cur.n, 256)), dim3(256), 0, st, aggp,
-                           og.perm, cur.n, aggl);
-        GR_LAUNCHED("unpermute");
+        // the aggregation runs in the level's own order (a node's strongest
+        // neighbour is near it there, and ids are the rows themselves)
+        const size_t mark_own = A.used;
+        int32_t* obest = A.take<int32_t>(cur.n + 1);
+        float* odbest = A.take<float>(cur.n + 1);
+        if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (aggregation)");
+        hipLaunchKernelGGL(k_best_own, dim3(blocks_for(cur.n, 256)), dim3(256), 0, st, best, dbest,
+                           og.perm, cur.n, obest, odbest);
+        GR_LAUNCHED("best, own order");
+        GR_TRY(aggregate(&cur, obest, odbest, nullptr, target, aggl, &ncoarse, &nforest, A, st));
+        A.used = mark_own;  // stream order keeps them valid for the launches above
         if (pr) prof::end(st, prof::AGGREGATE, 0.0, 1);
         gr_graph next;
         next.n = ncoarse;
