@@ -85,6 +85,13 @@ __global__ void k_best_own(const int32_t* __restrict__ best, const float* __rest
     odbest[o] = dbest[r];
 }
 
+// agg_own[perm[r]] = aggp[r]
+__global__ void k_unpermute(const int32_t* __restrict__ aggp, const int32_t* __restrict__ perm,
+                            int64_t n, int32_t* __restrict__ agg) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) agg[perm[r]] = aggp[r];
+}
+
 // out[i] = perm[in[i]]: relabelled row ids back to the level's own
 __global__ void k_map_ids(const int32_t* __restrict__ in, const int32_t* __restrict__ perm,
                           int64_t n, int32_t* __restrict__ out) {
@@ -388,16 +395,27 @@ static int reduce_impl(const gr_graph* g, const gr_params* p_in, gr_result* res,
                       1);
         int64_t ncoarse = 0, nforest = 0;
         if (pr) prof::begin(st);
-        // the aggregation runs in the level's own order (a node's strongest
-        // neighbour is near it there, and ids are the rows themselves)
+        // on sparse levels the aggregation runs in the level's own order (a
+        // node's strongest neighbour is near it there, and ids are the rows
+        // themselves); on dense ones, without that locality, on the relabel
         const size_t mark_own = A.used;
-        int32_t* obest = A.take<int32_t>(cur.n + 1);
-        float* odbest = A.take<float>(cur.n + 1);
-        if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (aggregation)");
-        hipLaunchKernelGGL(k_best_own, dim3(blocks_for(cur.n, 256)), dim3(256), 0, st, best, dbest,
-                           og.perm, cur.n, obest, odbest);
-        GR_LAUNCHED("best, own order");
-        GR_TRY(aggregate(&cur, obest, odbest, nullptr, target, aggl, &ncoarse, &nforest, A, st));
+        if (cur.nnz <= 32 * cur.n) {
+            int32_t* obest = A.take<int32_t>(cur.n + 1);
+            float* odbest = A.take<float>(cur.n + 1);
+            if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (aggregation)");
+            hipLaunchKernelGGL(k_best_own, dim3(blocks_for(cur.n, 256)), dim3(256), 0, st, best,
+                               dbest, og.perm, cur.n, obest, odbest);
+            GR_LAUNCHED("best, own order");
+            GR_TRY(aggregate(&cur, obest, odbest, nullptr, target, aggl, &ncoarse, &nforest, A,
+                             st));
+        } else {
+            int32_t* aggp = A.take<int32_t>(cur.n + 1);
+            if (A.overflow) return set_error(GR_ENOMEM, "workspace too small (aggregation)");
+            GR_TRY(aggregate(&og.g, best, dbest, og.perm, target, aggp, &ncoarse, &nforest, A, st));
+            hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(cur.n, 256)), dim3(256), 0, st, aggp,
+                               og.perm, cur.n, aggl);
+            GR_LAUNCHED("unpermute");
+        }
         A.used = mark_own;  // stream order keeps them valid for the launches above
         if (pr) prof::end(st, prof::AGGREGATE, 0.0, 1);
         gr_graph next;
