@@ -103,6 +103,14 @@ __global__ void k_jump(int32_t* __restrict__ pa, int64_t n, int32_t* __restrict_
 __global__ void k_min_member(const int32_t* __restrict__ root, const int32_t* __restrict__ ids,
                              int64_t n, int32_t* __restrict__ minid) {
     int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (!ids) {
+        // ids are the rows: of a run of lanes with one root (members next to
+        // each other) the first has the smallest id; the others stay out of
+        // the atomics on that address
+        const int32_t r = v < n ? root[v] : -1;
+        const int32_t rp = __shfl_up(r, 1, kWave);
+        if ((threadIdx.x & (kWave - 1)) > 0 && rp == r) return;
+    }
     if (v >= n) return;
     // read first: once a small id has arrived, the larger ones of a big
     // aggregate skip the atomic (same-address atomics serialise); a stale
