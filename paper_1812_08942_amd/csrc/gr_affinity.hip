@@ -4,6 +4,8 @@
 //
 // Layout as in the smoothing: node-major rows of K values in 16-byte chunks;
 // Q lanes hold one row, the P slots of a row-group walk the neighbours.
+#include <cstdlib>
+
 #include "gr_internal.hpp"
 #include "gr_device.hpp"
 
@@ -216,6 +218,24 @@ __device__ inline void aff_long(const int32_t* __restrict__ rp, const int32_t* _
     }
 }
 
+// Workgroups are handed to the 8 XCDs in turn (block b to XCD b mod 8),
+// and each XCD has its own L2.  With chunk C > 0 the blocks are renumbered
+// so that each XCD runs C consecutive row blocks of every 8C: neighbouring
+// rows, whose gathered neighbour rows overlap, then share one L2.  The tail
+// beyond the last whole group of 8C blocks keeps its order.  C = 0 keeps
+// the launch order; C < 0 takes C = T / 8, one contiguous range per XCD.
+// A bijection of [0, T) for any T; an offset o added to b and the result
+// keeps the property (block o + b runs on XCD (o + b) mod 8).
+__device__ inline int64_t xcd_block(int64_t b, int64_t T, int32_t C) {
+    if (C < 0) C = (int32_t)(T >> 3);
+    if (C <= 0) return b;
+    const int64_t span = 8 * (int64_t)C;
+    const int64_t s = b / span;
+    if ((s + 1) * span > T) return b;
+    const int64_t w = b - s * span;
+    return s * span + (w & 7) * C + (w >> 3);
+}
+
 template <int Q, int P, int DT>
 __global__ void __launch_bounds__(kBig) k_affinity(const int32_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col,
@@ -225,8 +245,10 @@ __global__ void __launch_bounds__(kBig) k_affinity(const int32_t* __restrict__ r
                                                    int64_t n_long, float* __restrict__ a,
                                                    float* __restrict__ dist,
                                                    int32_t* __restrict__ best,
-                                                   float* __restrict__ dbest) {
-    const int64_t b = blockIdx.x;
+                                                   float* __restrict__ dbest, int32_t chunk) {
+    // the workgroup-wide rows keep the launch order (spread over the XCDs)
+    int64_t b = blockIdx.x;
+    if (b >= n_long) b = n_long + xcd_block(b - n_long, (int64_t)gridDim.x - n_long, chunk);
     if (b < n_long) aff_long<Q, DT>(rp, col, X, K, long_rows[b], ids, a, dist, best, dbest);
     else aff_normal<Q, P, DT>(rp, col, X, K, n, ids, a, dist, best, dbest, b - n_long);
 }
@@ -244,12 +266,21 @@ static int launch_aff(const gr_graph* g, int K, const void* X, const int32_t* id
     while (P * 16 <= md && Q * P * 2 <= kWave) P *= 2;
     const int64_t waves = (g->n * Q * P + kWave - 1) / kWave;
     const int64_t grid = n_long + (waves * kWave + kBig - 1) / kBig;
+    // Where the vectors exceed half the Infinity Cache, each XCD takes one
+    // contiguous range of the row blocks (256^3 grid, bfloat16: level-0
+    // affinity 1.80 -> 1.53 ms).  Vectors that stay on chip gain nothing
+    // (the power-law graph's affinity, 27 MB of vectors, went 0.65 -> 0.74
+    // ms with it).  GR_AFF_XCD_CHUNK sets the chunk instead (0 = launch
+    // order, -1 = contiguous ranges, C > 0 = C blocks at a time).
+    const double vbytes = (double)g->n * K * (DT == GR_BF16 ? 2 : 4);
+    int32_t chunk = vbytes > 128.0 * 1024 * 1024 ? -1 : 0;
+    if (const char* e = getenv("GR_AFF_XCD_CHUNK")) chunk = atoi(e);
 #define GR_AF(PP)                                                                                  \
     case PP:                                                                                      \
         if constexpr (Q * PP <= kWave)                                                            \
             hipLaunchKernelGGL((k_affinity<Q, PP, DT>), dim3((unsigned)grid), dim3(kBig), 0, st,    \
                                g->row_ptr, g->col, X, K, g->n, ids, long_rows, n_long, a, dist,    \
-                               best, dbest);                                                      \
+                               best, dbest, chunk);                                               \
         break;
     switch (P) {
         GR_AF(1) GR_AF(2) GR_AF(4) GR_AF(8) GR_AF(16) GR_AF(32) GR_AF(64)

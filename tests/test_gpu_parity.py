@@ -360,6 +360,35 @@ def test_candidates_do_not_depend_on_requested_outputs(dtype):
                 assert int((b1 < 0).sum()) >= 3
 
 
+def test_affinity_block_order_bit_identical(monkeypatch):
+    """The workgroup renumbering over the XCDs (GR_AFF_XCD_CHUNK: contiguous
+    ranges, chunks of 16 and 3 blocks) changes only which XCD runs a row:
+    a, d, best and dbest equal, bit for bit, those of the launch order, on
+    a graph with workgroup-wide hub rows ahead of the renumbered blocks and
+    on block counts that leave a ragged tail."""
+    dev = _dev()
+    G = _G()
+    graphs = {"chunglu_hubs_10000": W.chung_lu(10000, mean_deg=700.0, seed=7),
+              "grid2d_300x211": W.grid2d(300, 211, weights="lognormal", seed=5)}
+    for name, g in graphs.items():
+        dg = dgraph(g, dev)
+        c, nc = _colour(g)
+        for dtype, tdt, K in (("f32", torch.float32, 16), ("bf16", torch.bfloat16, 32)):
+            say(f"affinity block order {name} {dtype}")
+            X = torch.from_numpy(O.init_vectors(g.n, K, 29)).to(dev).to(tdt).contiguous()
+            G.gr_smooth(dg, torch.from_numpy(c).to(dev), nc, X, 2)
+            out = {}
+            for chunk in ("0", "-1", "16", "3"):
+                monkeypatch.setenv("GR_AFF_XCD_CHUNK", chunk)
+                a, d, b, db = G.gr_affinity(dg, X, want_a=True, want_d=True)
+                torch.cuda.synchronize()
+                out[chunk] = [t.view(torch.int32).cpu().numpy() for t in (a, d, b, db)]
+            monkeypatch.delenv("GR_AFF_XCD_CHUNK")
+            for chunk in ("-1", "16", "3"):
+                for ref, got in zip(out["0"], out[chunk]):
+                    assert np.array_equal(ref, got), (name, dtype, chunk)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_affinity_extreme_angles(dtype):
     """Rows at angles where a rounds to 0 or 1 in float32: nearly parallel
