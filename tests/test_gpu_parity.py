@@ -554,6 +554,44 @@ def test_galerkin_segment_classes():
             assert torch.equal(c1.w.view(torch.int32), c2.w.view(torch.int32))
 
 
+def test_galerkin_lane_counts(monkeypatch):
+    """GR_GAL_LANES forces 1, 2, 4 or 8 lanes per fine row in the count and
+    the placement (normally about the mean degree): every choice gives the
+    oracle's coarse structure exactly, its weights within the float32 sum
+    tolerance, and bitwise-symmetric weights; the placement positions do
+    not depend on the lane count, so the weights agree bit for bit across
+    the choices."""
+    dev = _dev()
+    G = _G()
+    rng = np.random.default_rng(23)
+    graphs = {"chunglu_20000": W.chung_lu(20000, mean_deg=40.0, seed=6),
+              "grid2d_200x150": W.grid2d(200, 150, "lognormal", 8),
+              "knn2d_3000": W.knn2d(3000, 10, seed=2)}
+    for name, g in graphs.items():
+        nc = max(1, g.n // 7)
+        agg = np.concatenate([np.arange(nc), rng.integers(0, nc, g.n - nc)])
+        rng.shuffle(agg)
+        agg = agg.astype(np.int32)
+        rp, cl, w = O.galerkin(g.n, g.row_ptr, g.col, g.w.astype(np.float64), agg, nc)
+        dg = dgraph(g, dev)
+        da = torch.from_numpy(agg).to(dev)
+        first = None
+        for lanes in ("1", "2", "4", "8"):
+            say(f"galerkin lanes={lanes} {name} n_c={nc}")
+            monkeypatch.setenv("GR_GAL_LANES", lanes)
+            cg = G.gr_galerkin(dg, da, nc)
+            torch.cuda.synchronize()
+            assert np.array_equal(cg.row_ptr.cpu().numpy(), rp), (name, lanes)
+            assert np.array_equal(cg.col.cpu().numpy(), cl), (name, lanes)
+            cw = cg.w.cpu().numpy()
+            assert np.allclose(cw, w, rtol=1e-5, atol=0), (name, lanes)
+            assert_bitwise_symmetric(rp, cl, cw)
+            if first is None:
+                first = cw
+            assert np.array_equal(cw.view(np.uint32), first.view(np.uint32)), (name, lanes)
+        monkeypatch.delenv("GR_GAL_LANES")
+
+
 def assert_bitwise_symmetric(rp, cl, w):
     """Both stored directions of every coarse edge carry the same bits."""
     n = rp.size - 1
