@@ -119,6 +119,9 @@ def main():
     }
     result.update({k: v for k, v in res.items() if k not in result})
     result["paper_reference"] = PAPER_REFERENCE
+    result["copy_bandwidth"] = copy_bandwidth()
+    result["roofline"]["frac_of_copy"] = (result["roofline"]["achieved"]
+                                          / result["copy_bandwidth"]["GB_per_s"])
     g, wl, r, dg = keep
     if not args.no_eig:
         result.update(eig_report(G, r, args.workload, res["storage"]))
@@ -578,6 +581,32 @@ def calibrate_copy():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
+
+
+def copy_bandwidth(copies=5):
+    """What a plain device-to-device copy of 1 GiB reaches (bytes read plus
+    bytes written over its event-measured time): the memory system's
+    practical rate, as context for the roofline fraction.  Outside the timed
+    steps; the copies run on torch's current stream, where the events are."""
+    import torch
+
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(2):
+        dst.copy_(src)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(copies):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    ms = t0.elapsed_time(t1) / copies
+    del src, dst
+    return {"GB_per_s": 2 * COPY_BYTES / (ms * 1e-3) / 1e9, "ms_per_copy": ms,
+            "bytes_per_copy": COPY_BYTES, "copies": copies,
+            "kind": "device-to-device copy, read + write bytes"}
 
 
 GS_SECTION = "// ----------------------------------------------------------- GS colour step"
